@@ -1,0 +1,182 @@
+"""Benchmark: chain-steps/s of the parallel Newton MALA solve on one MI355X,
+against the same chain run by the same-GPU sequential sampler.
+
+Workload (one "step" = one full parallel solve to the convergence tolerance):
+MALA on the synthetic Bayesian logistic-regression posterior, X 1000 x 25
+from N(0,1), w* ~ N(0, I), y ~ Bernoulli(sigmoid(X w*)), prior N(0, I), FP32
+states, T = 65536, quasi-DEER (diagonal Jacobians).  The step size is 0.0015
+(the paper's value for its logistic-regression MALA runs); the specified 0.02
+puts the sampler at the Langevin stability edge (acceptance ~0.2 %) and is run
+and reported separately under "as_specified".  Inputs are resident in HBM when
+the timed region starts.
+
+Prints one JSON line.  --gpus > 1 is rejected: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--T", type=int, default=65536)
+    ap.add_argument("--eps", type=float, default=0.0015)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-as-specified", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2508_18413_amd as pm
+    from paper_2508_18413_amd import workloads as W
+
+    dev = "cuda:0"
+    T, eps = args.T, args.eps
+    ch = W.logreg_chain(T=T, seed=0, eps=eps)
+    ctx = pm.Context(0)
+    tg = pm.Target(ctx, ch.target)
+    # burn-in (3 MALA steps) by the GPU sequential sampler, outside the timed region
+    b = pm.sample_sequential(ctx, tg, eps, torch.tensor(ch.x0, device=dev),
+                             torch.tensor(ch.burn_xi, device=dev), torch.tensor(ch.burn_u, device=dev))
+    s0 = b.states[-1].clone()
+    xi = torch.tensor(ch.xi, device=dev)
+    u = torch.tensor(ch.u, device=dev)
+    torch.cuda.synchronize()
+    solve_kw = dict(variant="diag", max_iter=T + 1, profile_kernels=True)
+
+    for _ in range(args.warmup):
+        pm.solve(ctx, tg, eps, s0, xi, u, **solve_kw)
+        pm.sample_sequential(ctx, tg, eps, s0, xi, u)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K parallel solves
+    t0 = time.perf_counter()
+    results = [pm.solve(ctx, tg, eps, s0, xi, u, **solve_kw) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    r = results[-1]
+    ms_step = 1e3 * wall
+    value = T / wall
+
+    # same-GPU sequential sampler on the same chain
+    seq_ms = []
+    for _ in range(max(1, args.steps)):
+        t1 = time.perf_counter()
+        rs = pm.sample_sequential(ctx, tg, eps, s0, xi, u)
+        torch.cuda.synchronize()
+        seq_ms.append(1e3 * (time.perf_counter() - t1))
+    seq_ms = min(seq_ms)
+    seq_value = T / (seq_ms / 1e3)
+    par_vs_seq = (r.states - rs.states).abs().max().item()
+
+    # roofline of the dominant kernel (the evaluation kernel), live HIP events
+    N, D = ch.target["X"].shape
+    flops_per_step = 10.0 * N * D  # grad at x and x~ (4ND each) + Hessian diagonal (2ND)
+    eval_avg_ms = sum(x.eval_ms for x in results) / sum(x.sweeps for x in results)
+    steps_per_launch = sum(x.eval_steps for x in results) / sum(x.sweeps for x in results)
+    achieved = flops_per_step * steps_per_launch / (eval_avg_ms * 1e-3) / 1e12
+    scan_avg_ms = sum(x.scan_ms for x in results) / sum(x.sweeps for x in results)
+    scan_bytes = 16.0 * D * steps_per_launch  # J, F, S read + S written, FP32 per element
+    out = {
+        "metric": "chain-steps/sec at converged tol vs same-GPU sequential sampler; Newton iters",
+        "value": value,
+        "unit": "chain-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"mala-logreg-d{D}-n{N}-T{T}-eps{eps}-quasi-deer",
+                   "T": T, "D": D, "n_data": N, "eps": eps, "variant": "diag",
+                   "atol": 1e-6, "rtol": 1e-6, "chains": 1},
+        "newton_iters": r.sweeps,
+        "n_converged": r.n_converged,
+        "n_floor": r.n_floor,
+        "max_ratio": r.max_ratio,
+        "resid_inf": r.resid_inf,
+        "sequential": {"value": seq_value, "unit": "chain-steps/s", "ms": seq_ms},
+        "speedup_vs_sequential": value / seq_value,
+        "max_abs_parallel_minus_sequential": par_vs_seq,
+        "acceptance": r.n_accept / T,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": None, "kernel": "k_eval_logreg",
+                     "avg_launch_ms": eval_avg_ms, "steps_per_launch": steps_per_launch},
+        "roofline_scan_in_solve": {"bound": "hbm", "achieved": scan_bytes / (scan_avg_ms * 1e-3) / 1e9,
+                                   "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": scan_bytes / (scan_avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                   "avg_launch_ms": scan_avg_ms, "kernel": "k_scan<DiagNewtonIO>"},
+    }
+
+    # ---- the step size as specified (0.02): run and report
+    if not args.no_as_specified:
+        ch2 = W.logreg_chain(T=T, seed=0, eps=0.02)
+        b2 = pm.sample_sequential(ctx, tg, 0.02, torch.tensor(ch2.x0, device=dev),
+                                  torch.tensor(ch2.burn_xi, device=dev),
+                                  torch.tensor(ch2.burn_u, device=dev))
+        s02 = b2.states[-1].clone()
+        xi2, u2 = torch.tensor(ch2.xi, device=dev), torch.tensor(ch2.u, device=dev)
+        t2 = time.perf_counter()
+        r2 = pm.solve(ctx, tg, 0.02, s02, xi2, u2, variant="diag", max_iter=300)
+        torch.cuda.synchronize()
+        w2 = time.perf_counter() - t2
+        rs2 = pm.sample_sequential(ctx, tg, 0.02, s02, xi2, u2)
+        out["as_specified"] = {"eps": 0.02, "status": int(r2.status), "sweeps": r2.sweeps,
+                               "max_iter": 300, "converged": r2.n_converged == 1,
+                               "max_ratio": r2.max_ratio, "ms": 1e3 * w2,
+                               "acceptance": r2.n_accept / T,
+                               "max_abs_parallel_minus_sequential":
+                                   (r2.states - rs2.states).abs().max().item(),
+                               "sequential_ms": rs2.elapsed_ms}
+
+    # ---- CPU baseline: the FP64 oracle on the same chain, and parity of the solve
+    if not args.no_cpu_baseline:
+        import oracle
+        otg = oracle.Target(oracle.LOGREG, D, X=ch.target["X"], y=ch.target["y"])
+        s0h = s0.cpu().numpy().astype(np.float64)
+        t3 = time.perf_counter()
+        ref, acc, gt = oracle.mala_chain(otg, eps, s0h, ch.xi, ch.u)
+        cpu_s = time.perf_counter() - t3
+        got = r.states.cpu().numpy().astype(np.float64)
+        den = np.maximum(1.0, np.abs(ref).max(axis=1))
+        err = float(np.max(np.abs(got - ref).max(axis=1) / den))
+        gacc = r.accept.cpu().numpy()
+        mism = np.nonzero(gacc != acc)[0]
+        out["cpu_baseline"] = {"value": T / cpu_s, "unit": "chain-steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the full chain (T={T}), FP64, single thread, {cpu_s:.1f} s"}
+        out["parity_vs_oracle"] = {"state_error": err, "first_accept_mismatch":
+                                   int(mism[0]) if mism.size else None,
+                                   "gtilde_at_first_mismatch": float(gt[mism[0]]) if mism.size else None,
+                                   "n_accept_mismatch": int(mism.size)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * pmcmc.h -- C ABI of libpmcmc: parallel-in-sequence MCMC on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates an MCMC chain s_t = f_t(s_{t-1}), t = 1..T, from s_0 as
+ * the solution of the fixed-point problem r(s_{1:T}) = 0 (Sec. 2 eq. 1) by the
+ * parallel Newton iteration of Sec. 2 eq. 2-3 (DEER), its diagonal quasi-Newton
+ * form eq. 4 (quasi-DEER), the block quasi-Newton form for leapfrog
+ * integration (Sec. 3.3, Appendix A.3), or Picard iteration (J = 0), looping as
+ * Algorithm 1 (Appendix A.1) does until successive iterates agree.  f_t is a
+ * built-in sampler transition (MALA or ULA, Sec. 3.2; leapfrog, Sec. 3.3) on a
+ * built-in target, chosen by enum: arbitrary device code cannot cross a C ABI.
+ *
+ * Conventions (all entry points):
+ *  - Pointers documented DEVICE point to device memory owned by the caller;
+ *    pointers documented HOST point to host memory owned by the caller.  The
+ *    library never frees caller memory.  Arrays are C-contiguous, row-major.
+ *  - All GPU work is enqueued on the context's stream.  Every entry point
+ *    returns only after its outputs (device and host) are complete.
+ *  - Each call returns a pmc_status and, on failure, sets a thread-local
+ *    message readable with pmc_last_error().  PMC_NOT_CONVERGED is a soft
+ *    status: all outputs are written and valid (the last Newton iterate).
+ *    pmc_solve returns PMC_OK when every chain met the tolerance or stopped at
+ *    its rounding floor (pmc_result.n_floor counts the latter).
+ *  - Floating-point types: PMC_F32 arrays are float, PMC_F64 arrays double.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef PMCMC_H
+#define PMCMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMC_OK = 0,
+    PMC_ERR_INVALID = 1,     /* bad argument (null pointer, size, enum, layout)      */
+    PMC_ERR_UNSUPPORTED = 2, /* valid request that this build does not implement     */
+    PMC_ERR_OOM = 3,         /* device allocation failed or workspace too small      */
+    PMC_ERR_HIP = 4,         /* HIP runtime error (no device, launch failure, ...)   */
+    PMC_NOT_CONVERGED = 5,   /* soft: max_iter reached; outputs hold the last iterate */
+    PMC_ERR_NONFINITE = 6    /* non-finite value in an input array                    */
+} pmc_status;
+
+typedef enum { PMC_F32 = 0, PMC_F64 = 1 } pmc_dtype;
+
+/* Transition f_t.  MALA: the MALA function of Sec. 3.2 with noise xi_t and
+ * uniform u_t; ULA: the same proposal, always kept. */
+typedef enum { PMC_SAMPLER_MALA = 0, PMC_SAMPLER_ULA = 1 } pmc_sampler;
+
+typedef enum {
+    PMC_TARGET_GAUSSIAN = 0, /* log p = -(x-mu)^T P (x-mu) / 2                          */
+    PMC_TARGET_BANANA = 1,   /* D = 2: log p = -x1^2/2 - (x2 - x1^2)^2/2                */
+    PMC_TARGET_LOGREG = 2,   /* sum_n [y_n z_n - log(1+e^{z_n})] - |x|^2/(2 prior_var), z = X x */
+    PMC_TARGET_FUNNEL = 3    /* x1 ~ N(0, e^{2 theta}), x_d | x1 ~ N(0, e^{x1}), d >= 2 */
+} pmc_target_kind;
+
+/* Jacobian structure of the Newton update. */
+typedef enum {
+    PMC_DEER_DENSE = 0,   /* full D x D J_t (Sec. 2 eq. 2-3)                         */
+    PMC_QDEER_DIAG = 1,   /* diag(J_t) (Sec. 2 eq. 4)                                 */
+    PMC_QDEER_BLOCK2 = 2, /* diagonal of each D x D block (leapfrog only, App. A.3)   */
+    PMC_PICARD = 3        /* J_t = 0                                                  */
+} pmc_variant;
+
+/* Storage/compute precision of dense Jacobian compositions (PMC_DEER_DENSE). */
+typedef enum { PMC_JAC_F32 = 0, PMC_JAC_BF16 = 1 } pmc_jac_prec;
+
+/* How the accept gate enters the Jacobian: FROZEN treats the decision as a
+ * constant; SURROGATE is the stop-gradient relaxation of Sec. 3.2, adding
+ * sigma'(g~) (x~ - x) (d g~/dx)^T. */
+typedef enum { PMC_GATE_FROZEN = 0, PMC_GATE_SURROGATE = 1 } pmc_gate;
+
+typedef struct pmc_context pmc_context; /* opaque: device, stream, workspace pool, tuning table */
+typedef struct pmc_target pmc_target;   /* opaque: device copy of a target's parameters        */
+
+/* Target description.  All pointers DEVICE, read only during pmc_target_create,
+ * in the dtype given (the library copies them). */
+typedef struct {
+    pmc_target_kind kind;
+    int dim;             /* D */
+    pmc_dtype dtype;
+    const void *mean;    /* GAUSSIAN: [D]                          */
+    const void *prec;    /* GAUSSIAN: [D, D] symmetric precision   */
+    const void *X;       /* LOGREG:   [n_data, D] design           */
+    const void *y;       /* LOGREG:   [n_data] labels in {0, 1}    */
+    int n_data;          /* LOGREG                                 */
+    double prior_var;    /* LOGREG:   prior N(0, prior_var I)      */
+    double theta;        /* FUNNEL:   neck log-scale               */
+} pmc_target_desc;
+
+/* One or more independent chains on one target, concatenated along time.
+ * Chain c owns global steps offsets[c] .. offsets[c+1]-1 (CSR form). */
+typedef struct {
+    pmc_sampler sampler;
+    const pmc_target *target;
+    double step_size;         /* eps */
+    int n_chains;             /* >= 1 */
+    const int64_t *offsets;   /* HOST [n_chains+1], offsets[0] = 0, non-decreasing; NULL => one
+                                 chain of length n_steps */
+    int64_t n_steps;          /* sum of chain lengths (= offsets[n_chains] when offsets given) */
+    const void *s0;           /* DEVICE [n_chains, D] initial states                        */
+    const void *noise;        /* DEVICE [n_steps, D]  xi_t                                  */
+    const void *uniforms;     /* DEVICE [n_steps]     u_t in (0, 1) (MALA only; may be NULL for ULA) */
+    const void *init_guess;   /* DEVICE [n_steps, D] initial Newton guess, or NULL => each chain's
+                                 s0 broadcast over its steps (the paper's choice)            */
+    void *out_states;         /* DEVICE [n_steps, D] written: the trajectory                */
+    uint8_t *out_accept;      /* DEVICE [n_steps] or NULL: accept decision of each step     */
+    float *out_gtilde;        /* DEVICE [n_steps] or NULL: g~ = log alpha - log u (MALA)     */
+} pmc_problem;
+
+typedef struct {
+    pmc_variant variant;
+    pmc_jac_prec jac_prec;    /* PMC_DEER_DENSE only                                          */
+    pmc_gate gate;
+    double atol, rtol;        /* stop when max_{t,d} |s^{i+1} - s^i| / (atol + rtol |s^{i+1}|) <= 1 */
+    int max_iter;             /* <= 0: min(T + 1, 50 + 5e-4 T), T the longest chain          */
+    double damping;           /* J <- damping * J before clipping (1 = none)                  */
+    double clip;              /* > 0: clip entries of J to [-clip, clip] (clip_inf_norm = 0), or
+                                 rescale J so that |J|_inf <= clip (clip_inf_norm = 1)        */
+    int clip_inf_norm;
+    int skip_converged_prefix;/* sliding window: each sweep starts at the chain's first
+                                 unconverged step                                            */
+    int graph_sweeps;         /* > 0: replay a captured HIP graph of this many sweeps between
+                                 host convergence checks; 0: one host check per sweep       */
+    void *trace_out;          /* DEVICE or NULL: iterate after every sweep, [max_iter, n_steps, D] */
+    size_t trace_bytes;       /* size of trace_out                                           */
+    int floor_stall;          /* > 0: stop a chain at its rounding floor after this many sweeps
+                                 without progress (no 2x drop of its best ratio and no advance
+                                 of its converged front) while its ratio is <= 100; 0: never */
+    int profile_kernels;      /* != 0 (graph_sweeps = 0 only): time every eval and scan launch
+                                 with HIP events on the context's stream (pmc_result.*_ms)    */
+} pmc_options;
+
+typedef struct {
+    int32_t *sweeps_per_chain;/* HOST [n_chains] or NULL: sweeps (Alg. 1 count) per chain   */
+    int n_converged;          /* chains that met the tolerance                               */
+    int sweeps_total;         /* sweeps executed (max over chains)                           */
+    int n_floor;              /* chains stopped at their rounding floor (see floor_stall)      */
+    int64_t n_accept;         /* accepted steps (MALA), from the last sweep's decisions      */
+    double resid_inf;         /* max |s_t - f_t(s_{t-1})| at the last linearisation point      */
+    double resid_l2;          /* its Euclidean norm, accumulated in FP64                      */
+    double max_ratio;         /* final Delta-ratio (<= 1 means converged)                     */
+    int64_t nonfinite;        /* count of non-finite iterate elements seen in the last sweep  */
+    float elapsed_ms;         /* device time of the call, HIP events                          */
+    float eval_ms;            /* with profile_kernels: summed duration of the eval launches   */
+    float scan_ms;            /* with profile_kernels: summed duration of the scan launches   */
+    int64_t eval_steps;       /* with profile_kernels: steps evaluated over all sweeps        */
+} pmc_result;
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  Fails with PMC_ERR_HIP
+ * when no usable device exists. */
+pmc_status pmc_create(pmc_context **out, int device, void *hip_stream);
+pmc_status pmc_destroy(pmc_context *ctx);
+pmc_status pmc_set_stream(pmc_context *ctx, void *hip_stream);
+
+/* ---- targets ------------------------------------------------------------ */
+/* Copies the target's parameters to library-owned device memory. */
+pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *desc, pmc_target **out);
+pmc_status pmc_target_destroy(pmc_target *tgt);
+
+/* ---- parallel Newton solve (Algorithm 1) --------------------------------- */
+/* Device workspace pmc_solve needs for this problem and options. */
+pmc_status pmc_workspace_size(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                              size_t *bytes);
+/* Fills *opts with the defaults: quasi-DEER diagonal, frozen gate,
+ * atol = rtol = 1e-6 (1e-12 for F64), max_iter auto, no damping or clipping,
+ * floor_stall 16. */
+pmc_status pmc_default_options(pmc_options *opts, pmc_dtype dtype);
+/* Solves every chain of `prob` by parallel Newton iterations.  `workspace`
+ * is DEVICE memory of at least pmc_workspace_size bytes, or NULL to use the
+ * context's pool.  res (HOST) may be NULL. */
+pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                     void *workspace, size_t ws_bytes, pmc_result *res);
+
+/* ---- same-GPU sequential sampler ------------------------------------------ */
+/* Evaluates s_t = f_t(s_{t-1}) step by step on the device (one workgroup per
+ * chain): the baseline the parallel solve is measured against (Sec. 2). */
+pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *prob, pmc_result *res);
+
+/* ---- HMC with parallel leapfrog (Appendix A.2 algorithm) ------------------ */
+/* n_prop sequential HMC proposals with L leapfrog steps of size step_size on
+ * `target` (F32 only).  Each proposal draws momentum momenta[p] (DEVICE
+ * [n_prop, D]), half-steps it, integrates, reverse half-steps and accepts iff
+ * log unif[p] < H0 - HL (DEVICE [n_prop]).  parallel_leapfrog != 0 solves the
+ * L-step leapfrog recursion on s = [x, v] in R^{2D} by Newton iterations with
+ * opts->variant (PMC_QDEER_BLOCK2, PMC_QDEER_DIAG or PMC_PICARD) and tolerance;
+ * 0 integrates sequentially.  out_chain: DEVICE [n_prop+1, D] (row 0 = x0);
+ * accept: DEVICE [n_prop] or NULL; sweeps: HOST [n_prop] or NULL (Newton
+ * sweeps per proposal). */
+pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target, double step_size, int L,
+                          int n_prop, const void *x0, const void *momenta, const void *unif,
+                          const pmc_options *opts, int parallel_leapfrog, void *out_chain,
+                          uint8_t *accept, int32_t *sweeps, pmc_result *res);
+
+/* ---- derivatives through a converged chain ---------------------------------- */
+/* Reverse (adjoint) scan lambda_t = dF/ds_t + J_{t+1}^T lambda_{t+1} over the
+ * transposed step Jacobians at the trajectory `states` (DEVICE [T, D], the
+ * converged output of pmc_solve with accept decisions `accept`, DEVICE [T]),
+ * then dF/dtheta = sum_t lambda_t . df_t/dtheta and dF/deps likewise, FP64
+ * sums.  dF_ds: DEVICE [T, D].  Single chain, F32, frozen gate.  Results are
+ * written to the HOST scalars. */
+pmc_status pmc_adjoint(pmc_context *ctx, const pmc_problem *prob, const void *states,
+                       const uint8_t *accept, const void *dF_ds, double *dF_dtheta,
+                       double *dF_dstep);
+
+/* ---- linear recursions on their own (the scans of the Newton update) ------- */
+/* delta_t = a_t * delta_{t-1} + b_t, delta_0 = 0, for n_lanes independent
+ * lanes.  a, b, out: DEVICE [n_lanes, T] (each lane's sequence contiguous).
+ * Quasi-DEER's recursion (Sec. 2 eq. 4). */
+pmc_status pmc_linrec_diag(pmc_context *ctx, pmc_dtype dtype, int n_lanes, int64_t T,
+                           const void *a, const void *b, void *out);
+/* Block form of Appendix A.3: per lane [p; q]_t = [[a, b], [c, d]]_t [p; q]_{t-1}
+ * + [e; f]_t.  coef: DEVICE [4, n_lanes, T] (planes a, b, c, d); rhs: DEVICE
+ * [2, n_lanes, T] (planes e, f); out: DEVICE [2, n_lanes, T] (planes p, q). F32. */
+pmc_status pmc_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
+                             const void *rhs, void *out);
+/* Dense form (Sec. 2 eq. 3): delta_t = A_t delta_{t-1} + b_t.  A: DEVICE
+ * [T, D, D]; b, out: DEVICE [T, D].  F64 for D <= 4 (VALU); F32 with
+ * jac_prec BF16 or F32 for D <= 32 (matrix cores). */
+pmc_status pmc_linrec_dense(pmc_context *ctx, pmc_dtype dtype, pmc_jac_prec jac_prec, int D,
+                            int64_t T, const void *A, const void *b, void *out);
+
+/* ---- tuning --------------------------------------------------------------- */
+/* Times the scan tile configurations for this problem's shape on the device
+ * and stores the fastest in the context (and, if cache_path != NULL, in a
+ * JSON file keyed by the device's architecture name).  If the file exists
+ * and holds an entry for this shape, it is loaded instead of timing. */
+pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                        const char *cache_path);
+
+/* Thread-local description of the last failure on this thread. */
+const char *pmc_last_error(void);
+const char *pmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMCMC_H */

@@ -1,0 +1,73 @@
+// C entry points for the standalone linear recursions and the tuning table.
+#include <string.h>
+
+#include "pmc_internal.hpp"
+
+using namespace pmc;
+
+extern "C" {
+
+pmc_status pmc_linrec_diag(pmc_context *ctx, pmc_dtype dtype, int n_lanes, int64_t T, const void *a,
+                           const void *b, void *out)
+{
+    PMC_REQUIRE(ctx, "pmc_linrec_diag: ctx is NULL");
+    PMC_REQUIRE(dtype == PMC_F32 || dtype == PMC_F64, "pmc_linrec_diag: bad dtype");
+    PMC_REQUIRE(n_lanes >= 0 && T >= 0, "pmc_linrec_diag: negative size");
+    if (n_lanes == 0 || T == 0) return PMC_OK;
+    PMC_REQUIRE(is_device_ptr(a) && is_device_ptr(b) && is_device_ptr(out),
+                "pmc_linrec_diag: a, b, out must be device pointers");
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    PMC_TRY(launch_linrec_diag(ctx, dtype, n_lanes, T, a, b, out));
+    PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    return check_scan_health(ctx);
+}
+
+pmc_status pmc_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
+                             const void *rhs, void *out)
+{
+    PMC_REQUIRE(ctx, "pmc_linrec_block2: ctx is NULL");
+    PMC_REQUIRE(n_lanes >= 0 && T >= 0, "pmc_linrec_block2: negative size");
+    if (n_lanes == 0 || T == 0) return PMC_OK;
+    PMC_REQUIRE(is_device_ptr(coef) && is_device_ptr(rhs) && is_device_ptr(out),
+                "pmc_linrec_block2: coef, rhs, out must be device pointers");
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    PMC_TRY(launch_linrec_block2(ctx, n_lanes, T, coef, rhs, out));
+    PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    return check_scan_health(ctx);
+}
+
+pmc_status pmc_linrec_dense(pmc_context *ctx, pmc_dtype dtype, pmc_jac_prec jac_prec, int D,
+                            int64_t T, const void *A, const void *b, void *out)
+{
+    PMC_REQUIRE(ctx, "pmc_linrec_dense: ctx is NULL");
+    PMC_REQUIRE(D >= 1 && T >= 0, "pmc_linrec_dense: D >= 1, T >= 0");
+    if (T == 0) return PMC_OK;
+    PMC_REQUIRE(is_device_ptr(A) && is_device_ptr(b) && is_device_ptr(out),
+                "pmc_linrec_dense: A, b, out must be device pointers");
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    if (dtype == PMC_F64) {
+        PMC_TRY(launch_linrec_dense_small(ctx, D, T, (const double *)A, (const double *)b, (double *)out));
+    } else {
+        (void)jac_prec;
+        set_error("pmc_linrec_dense: F32 matrix-core path not built");
+        return PMC_ERR_UNSUPPORTED;
+    }
+    PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    return check_scan_health(ctx);
+}
+
+pmc_status pmc_adjoint(pmc_context *ctx, const pmc_problem *prob, const void *states,
+                       const uint8_t *accept, const void *dF_ds, double *dF_dtheta, double *dF_dstep)
+{
+    set_error("pmc_adjoint: not built");
+    return PMC_ERR_UNSUPPORTED;
+}
+
+pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                        const char *cache_path)
+{
+    set_error("pmc_autotune: not built");
+    return PMC_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

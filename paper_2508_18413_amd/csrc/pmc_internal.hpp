@@ -1,0 +1,273 @@
+// Internal declarations of libpmcmc (HIP, gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pmcmc.h"
+
+namespace pmc {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+const char *last_error();
+
+#define PMC_TRY_HIP(call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            pmc::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                           __LINE__);                                                      \
+            return PMC_ERR_HIP;                                                            \
+        }                                                                                  \
+    } while (0)
+
+#define PMC_TRY(call)                       \
+    do {                                    \
+        pmc_status s_ = (call);             \
+        if (s_ != PMC_OK) return s_;        \
+    } while (0)
+
+#define PMC_REQUIRE(cond, ...)              \
+    do {                                    \
+        if (!(cond)) {                      \
+            pmc::set_error(__VA_ARGS__);    \
+            return PMC_ERR_INVALID;         \
+        }                                   \
+    } while (0)
+
+// ------------------------------------------------------------ tiling
+// A contiguous run of one chain's steps handled by one workgroup.
+struct SegTile {
+    int64_t start;  // global step index of the first step
+    int32_t len;    // number of steps (>= 1)
+    int32_t chain;  // owning chain
+};
+
+// Per-tile convergence partials, written by every scan tile (neutral when the
+// tile does no work) and folded per chain by the status kernel.
+struct TilePartial {
+    float max_ratio;     // max |delta| / (atol + rtol |s_new|)
+    uint32_t nonfinite;  // count of non-finite new iterate elements
+    int64_t first_bad;   // smallest global step index with ratio > 1 (INT64_MAX if none)
+    double resid_sq;     // sum of squared residuals b_t = f_t(s_{t-1}) - s_t, FP64
+    double resid_inf;    // max |b_t|
+};
+
+// Per-chain Newton state, device resident.
+struct ChainStatus {
+    int64_t win_start;   // first step of the active window (sliding window)
+    int64_t first_bad;   // first unconverged step of the last sweep
+    double resid_sq;
+    double resid_inf;
+    float max_ratio;
+    int32_t sweeps;      // sweeps run on this chain
+    int32_t active;      // 1 while the chain iterates
+    int32_t converged;   // 1 once the tolerance is met
+    int32_t stall;       // sweeps without progress (floor guard)
+    float best_ratio;
+    uint32_t nonfinite;
+    int32_t at_floor;    // 1 if stopped at the rounding floor
+    int64_t best_front;  // furthest converged front seen
+};
+
+// Whole-problem status, read by the host after each sweep or graph replay.
+struct GlobalStatus {
+    int32_t n_active;
+    int32_t n_converged;
+    int32_t sweeps;      // sweeps executed
+    int32_t n_floor;     // chains stopped at the rounding floor
+    double resid_sq;
+    double resid_inf;
+    float max_ratio;
+    uint32_t nonfinite;
+    int64_t n_accept;
+};
+
+// Synchronisation words of the single-pass scans.  The last workgroup of a
+// launch resets the tile counter and advances the epoch that tags every
+// look-back descriptor, so descriptors never need clearing and captured
+// graphs can replay the scan.
+struct ScanSync {
+    uint32_t tile_ctr;
+    uint32_t done_ctr;
+    uint32_t epoch;
+    uint32_t pad;
+};
+
+// ------------------------------------------------------------ targets
+struct DevTarget {
+    pmc_target_kind kind;
+    pmc_dtype dtype;
+    int dim;
+    int n_data;
+    int ldx;           // padded row stride of X (logreg)
+    double prior_var;
+    double theta;
+    void *mean = nullptr;  // [D]
+    void *prec = nullptr;  // [D*D]
+    void *X = nullptr;     // [n_data * ldx], zero padded
+    void *y = nullptr;     // [n_data]
+};
+
+}  // namespace pmc
+
+struct pmc_target {
+    pmc::DevTarget t;
+    int device;
+};
+
+struct pmc_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string arch;
+    int n_cu = 0;
+    // persistent device state
+    pmc::ScanSync *sync = nullptr;   // [kMaxSyncSlots]
+    void *lb_desc = nullptr;         // look-back descriptors
+    size_t lb_desc_bytes = 0;
+    void *pool = nullptr;            // workspace pool
+    size_t pool_bytes = 0;
+    pmc::GlobalStatus *h_status = nullptr;  // pinned host mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t kev[3] = {nullptr, nullptr, nullptr};  // per-kernel timing
+    // tuning: items per thread of the diagonal scan (0 = default)
+    int diag_items = 0;
+    int diag_block = 0;
+};
+
+namespace pmc {
+
+// bytes helper
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Layout helpers: row-major [n, D] <-> dimension-major planes [D, ld].
+pmc_status rows_to_planes(pmc_context *ctx, pmc_dtype dt, const void *rows, void *planes, int64_t n,
+                          int D, int64_t ld);
+pmc_status planes_to_rows(pmc_context *ctx, pmc_dtype dt, const void *planes, void *rows, int64_t n,
+                          int D, int64_t ld);
+// planes[d][t] = s0[chain(t)][d] (d_offsets: device [n_chains+1])
+pmc_status broadcast_s0(pmc_context *ctx, pmc_dtype dt, const void *s0, const int64_t *d_offsets,
+                        int n_chains, void *planes, int64_t n, int D, int64_t ld);
+bool is_device_ptr(const void *p);
+
+// Ensures ctx->lb_desc holds at least `bytes` (zero filled on growth).
+pmc_status ensure_lb_desc(pmc_context *ctx, size_t bytes);
+pmc_status ensure_pool(pmc_context *ctx, size_t bytes);
+
+// ------------------------------------------------------ scan launchers
+// Newton-update scans over dimension-major planes of length ld (stride between
+// planes).  For every active tile: b_t = F_t - S_t; delta_t = J_t delta_{t-1} + b_t
+// (delta = 0 before a chain's or window's first step); S_t <- F_t + J_t delta_{t-1};
+// partials[lane * n_tiles + tile] receives the convergence partials.
+struct NewtonScanArgs {
+    int n_lanes;            // planes (D for diag, D for block2 with x/v pairs)
+    int64_t ld;             // plane stride
+    const SegTile *tiles;   // [n_tiles]
+    int n_tiles;
+    const int64_t *offsets; // [n_chains+1] device
+    const ChainStatus *chains;
+    const int32_t *chain_tile_begin;  // [n_chains+1] first scan tile of each chain
+    const void *J;          // diag: [n_lanes, ld]; block2 (leapfrog): h [n_lanes, ld]
+    const void *F;          // [n_lanes, ld] (block2: [2*n_lanes, ld], x planes then v planes)
+    void *S;                // [n_lanes, ld] in/out (block2: [2*n_lanes, ld])
+    TilePartial *partials;  // [n_lanes * n_tiles]
+    double atol, rtol;
+    double eps;             // leapfrog step (block2)
+    void *trace;            // optional copy of S after the update, or nullptr
+};
+
+// Steps per scan tile for a configuration (the host builds its tile map with it).
+int scan_tile_steps(pmc_dtype dt, int variant_m, int items, int block);
+pmc_status launch_newton_scan_diag(pmc_context *ctx, pmc_dtype dt, const NewtonScanArgs &a,
+                                   int items, int block);
+pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64_t T, const void *a,
+                              const void *b, void *out);
+pmc_status launch_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
+                                const void *rhs, void *out);
+pmc_status launch_linrec_dense_small(pmc_context *ctx, int D, int64_t T, const double *A,
+                                     const double *b, double *out);
+
+// Dense Newton scan (small D, VALU, F64 or F32): J as [ld, D, D] row-major per step.
+pmc_status launch_newton_scan_dense_small(pmc_context *ctx, pmc_dtype dt, int D,
+                                          const NewtonScanArgs &a);
+
+// ------------------------------------------------------ evaluation
+// Jacobian output formats of the eval kernels.
+enum JacMode {
+    JM_DIAG = 0,       // diag(J_t) in planes [D, ld]
+    JM_DENSE_ROW = 1,  // J_t row-major [n_steps, D, D] in the state dtype (VALU dense scan)
+    JM_DENSE_BF16 = 2, // J_t padded to 32x32, bf16, matrix-core A-operand order, 2 KB per step
+    JM_DENSE_F32 = 3,  // J_t padded to 32x32, f32, matrix-core A-operand order, 4 KB per step
+    JM_NONE = 4        // Picard: J_t = 0, nothing written
+};
+
+struct EvalArgs {
+    const SegTile *tiles;     // eval tile map (tile length <= block size)
+    int n_tiles;
+    const int64_t *offsets;   // [n_chains+1]
+    const ChainStatus *chains;
+    int D;
+    int64_t ld;               // plane stride of S and F (and diag J)
+    const void *s0;           // [n_chains, D]
+    const void *S;            // [D, ld] current iterate
+    const void *noise;        // [n_steps, D]
+    const void *unif;         // [n_steps]
+    void *F;                  // [D, ld] f_t(s_{t-1})
+    void *J;                  // per JacMode
+    uint8_t *accept;          // [n_steps]
+    float *gtilde;            // [n_steps]
+    double eps;
+    int ula;
+    int gate;                 // pmc_gate
+    double damping;
+    double clip;
+    int clip_inf;
+    int jmode;
+    const pmc::DevTarget *tg; // host copy of the target description (fields passed by value)
+};
+pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
+// Tile length the eval kernel for this target expects.
+int eval_tile_steps(const DevTarget &tg);
+
+// Same-GPU sequential sampler: one workgroup (or lane) per chain, T-step loop
+// on the device.  Writes out_states [n_steps, D], accept, gtilde.
+struct SeqArgs {
+    int n_chains;
+    const int64_t *offsets;
+    int D;
+    const void *s0, *noise, *unif;
+    void *out;
+    uint8_t *accept;
+    float *gtilde;
+    double eps;
+    int ula;
+};
+pmc_status launch_sequential(pmc_context *ctx, const DevTarget &tg, const SeqArgs &a);
+
+// Chain status fold (one launch per sweep).
+struct StatusArgs {
+    int n_chains;
+    int n_lanes;
+    const SegTile *tiles;
+    int n_tiles;
+    const int32_t *chain_tile_begin;  // [n_chains+1] scan-tile ranges per chain
+    const TilePartial *partials;
+    ChainStatus *chains;
+    GlobalStatus *global;
+    const uint8_t *accept;            // [n_steps] or nullptr
+    const int64_t *offsets;
+    int max_iter;
+    int skip_prefix;
+    int floor_stall;                  // > 0: stop a chain whose ratio has not improved for this
+                                      // many sweeps while within 100x of the tolerance
+    int64_t n_steps;
+};
+pmc_status launch_status(pmc_context *ctx, const StatusArgs &a);
+// PMC_ERR_HIP if any scan's look-back gave up since the context was created.
+pmc_status check_scan_health(pmc_context *ctx);
+
+}  // namespace pmc

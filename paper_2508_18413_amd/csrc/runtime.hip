@@ -1,0 +1,320 @@
+// Context, targets, errors and small layout kernels of libpmcmc.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "pmc_internal.hpp"
+
+namespace pmc {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+const char *last_error() { return g_err; }
+
+pmc_status ensure_lb_desc(pmc_context *ctx, size_t bytes)
+{
+    if (bytes <= ctx->lb_desc_bytes) return PMC_OK;
+    size_t nb = align_up(bytes + bytes / 4, 1 << 20);
+    if (ctx->lb_desc) {
+        PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+        PMC_TRY_HIP(hipFree(ctx->lb_desc));
+        ctx->lb_desc = nullptr;
+        ctx->lb_desc_bytes = 0;
+    }
+    if (hipMalloc(&ctx->lb_desc, nb) != hipSuccess) {
+        ctx->lb_desc = nullptr;
+        set_error("out of device memory for %zu bytes of look-back descriptors", nb);
+        return PMC_ERR_OOM;
+    }
+    PMC_TRY_HIP(hipMemsetAsync(ctx->lb_desc, 0, nb, ctx->stream));
+    ctx->lb_desc_bytes = nb;
+    return PMC_OK;
+}
+
+pmc_status ensure_pool(pmc_context *ctx, size_t bytes)
+{
+    if (bytes <= ctx->pool_bytes) return PMC_OK;
+    if (ctx->pool) {
+        PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+        PMC_TRY_HIP(hipFree(ctx->pool));
+        ctx->pool = nullptr;
+        ctx->pool_bytes = 0;
+    }
+    size_t nb = align_up(bytes, 1 << 20);
+    if (hipMalloc(&ctx->pool, nb) != hipSuccess) {
+        ctx->pool = nullptr;
+        set_error("out of device memory for a %zu-byte workspace", nb);
+        return PMC_ERR_OOM;
+    }
+    ctx->pool_bytes = nb;
+    return PMC_OK;
+}
+
+// ------------------------------------------------------------ layout kernels
+namespace {
+template <typename R>
+__global__ void k_rows_to_planes(const R *rows, R *planes, int64_t n, int D, int64_t ld)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * D) return;
+    const int64_t t = i / D;
+    const int d = (int)(i % D);
+    planes[(size_t)d * ld + t] = rows[i];
+}
+template <typename R>
+__global__ void k_planes_to_rows(const R *planes, R *rows, int64_t n, int D, int64_t ld)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * D) return;
+    const int64_t t = i / D;
+    const int d = (int)(i % D);
+    rows[i] = planes[(size_t)d * ld + t];
+}
+// planes[d][t] = s0[chain(t)][d]
+template <typename R>
+__global__ void k_broadcast_s0(const R *s0, const int64_t *offsets, int n_chains, R *planes,
+                               int64_t n, int D, int64_t ld)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int lo = 0, hi = n_chains - 1;
+    while (lo < hi) {  // last chain with offsets[c] <= t
+        const int mid = (lo + hi + 1) / 2;
+        if (offsets[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    for (int d = 0; d < D; d++) planes[(size_t)d * ld + t] = s0[(size_t)lo * D + d];
+}
+}  // namespace
+
+pmc_status rows_to_planes(pmc_context *ctx, pmc_dtype dt, const void *rows, void *planes, int64_t n,
+                          int D, int64_t ld)
+{
+    const int64_t tot = n * D;
+    if (tot == 0) return PMC_OK;
+    dim3 g((unsigned)((tot + 255) / 256)), b(256);
+    if (dt == PMC_F64)
+        hipLaunchKernelGGL(k_rows_to_planes<double>, g, b, 0, ctx->stream, (const double *)rows,
+                           (double *)planes, n, D, ld);
+    else
+        hipLaunchKernelGGL(k_rows_to_planes<float>, g, b, 0, ctx->stream, (const float *)rows,
+                           (float *)planes, n, D, ld);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+pmc_status planes_to_rows(pmc_context *ctx, pmc_dtype dt, const void *planes, void *rows, int64_t n,
+                          int D, int64_t ld)
+{
+    const int64_t tot = n * D;
+    if (tot == 0) return PMC_OK;
+    dim3 g((unsigned)((tot + 255) / 256)), b(256);
+    if (dt == PMC_F64)
+        hipLaunchKernelGGL(k_planes_to_rows<double>, g, b, 0, ctx->stream, (const double *)planes,
+                           (double *)rows, n, D, ld);
+    else
+        hipLaunchKernelGGL(k_planes_to_rows<float>, g, b, 0, ctx->stream, (const float *)planes,
+                           (float *)rows, n, D, ld);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+pmc_status broadcast_s0(pmc_context *ctx, pmc_dtype dt, const void *s0, const int64_t *d_offsets,
+                        int n_chains, void *planes, int64_t n, int D, int64_t ld)
+{
+    if (n == 0) return PMC_OK;
+    dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (dt == PMC_F64)
+        hipLaunchKernelGGL(k_broadcast_s0<double>, g, b, 0, ctx->stream, (const double *)s0,
+                           d_offsets, n_chains, (double *)planes, n, D, ld);
+    else
+        hipLaunchKernelGGL(k_broadcast_s0<float>, g, b, 0, ctx->stream, (const float *)s0,
+                           d_offsets, n_chains, (float *)planes, n, D, ld);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+bool is_device_ptr(const void *p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace pmc
+
+using namespace pmc;
+
+extern "C" {
+
+const char *pmc_last_error(void) { return pmc::last_error(); }
+const char *pmc_version(void) { return "libpmcmc 0.1 (gfx950)"; }
+
+pmc_status pmc_create(pmc_context **out, int device, void *hip_stream)
+{
+    if (!out) {
+        set_error("pmc_create: out is NULL");
+        return PMC_ERR_INVALID;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        set_error("pmc_create: no HIP device available (%s)", hipGetErrorString(e));
+        return PMC_ERR_HIP;
+    }
+    if (device < 0 || device >= n) {
+        set_error("pmc_create: device %d out of range [0, %d)", device, n);
+        return PMC_ERR_INVALID;
+    }
+    PMC_TRY_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    PMC_TRY_HIP(hipGetDeviceProperties(&prop, device));
+    pmc_context *ctx = new pmc_context();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->arch = prop.gcnArchName;
+    ctx->n_cu = prop.multiProcessorCount;
+    if (hipMalloc((void **)&ctx->sync, sizeof(ScanSync) * 4) != hipSuccess ||
+        hipMemset(ctx->sync, 0, sizeof(ScanSync) * 4) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_status, sizeof(GlobalStatus)) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipEventCreate(&ctx->kev[0]) != hipSuccess || hipEventCreate(&ctx->kev[1]) != hipSuccess ||
+        hipEventCreate(&ctx->kev[2]) != hipSuccess) {
+        set_error("pmc_create: device initialisation failed");
+        pmc_destroy(ctx);
+        return PMC_ERR_HIP;
+    }
+    *out = ctx;
+    return PMC_OK;
+}
+
+pmc_status pmc_destroy(pmc_context *ctx)
+{
+    if (!ctx) return PMC_OK;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    (void)hipDeviceSynchronize();
+    if (ctx->sync) (void)hipFree(ctx->sync);
+    if (ctx->lb_desc) (void)hipFree(ctx->lb_desc);
+    if (ctx->pool) (void)hipFree(ctx->pool);
+    if (ctx->h_status) (void)hipHostFree(ctx->h_status);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (hipEvent_t e : ctx->kev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return PMC_OK;
+}
+
+pmc_status pmc_set_stream(pmc_context *ctx, void *hip_stream)
+{
+    if (!ctx) {
+        set_error("pmc_set_stream: ctx is NULL");
+        return PMC_ERR_INVALID;
+    }
+    ctx->stream = (hipStream_t)hip_stream;
+    return PMC_OK;
+}
+
+pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *d, pmc_target **out)
+{
+    PMC_REQUIRE(ctx && d && out, "pmc_target_create: NULL argument");
+    *out = nullptr;
+    PMC_REQUIRE(d->dim >= 1, "pmc_target_create: dim must be >= 1 (got %d)", d->dim);
+    PMC_REQUIRE(d->dtype == PMC_F32 || d->dtype == PMC_F64, "pmc_target_create: bad dtype");
+    const size_t es = d->dtype == PMC_F64 ? 8 : 4;
+    DevTarget t;
+    t.kind = d->kind;
+    t.dtype = d->dtype;
+    t.dim = d->dim;
+    t.n_data = 0;
+    t.ldx = 0;
+    t.prior_var = d->prior_var;
+    t.theta = d->theta;
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    switch (d->kind) {
+    case PMC_TARGET_BANANA:
+        PMC_REQUIRE(d->dim == 2, "banana target has dim 2 (got %d)", d->dim);
+        break;
+    case PMC_TARGET_FUNNEL:
+        PMC_REQUIRE(d->dim >= 2 && d->dim <= 32, "funnel target: 2 <= dim <= 32 (got %d)", d->dim);
+        break;
+    case PMC_TARGET_GAUSSIAN: {
+        PMC_REQUIRE(d->dim <= 32, "gaussian target: dim <= 32 (got %d)", d->dim);
+        PMC_REQUIRE(is_device_ptr(d->mean) && is_device_ptr(d->prec),
+                    "gaussian target: mean and prec must be device pointers");
+        PMC_TRY_HIP(hipMalloc(&t.mean, es * d->dim));
+        PMC_TRY_HIP(hipMalloc(&t.prec, es * d->dim * d->dim));
+        PMC_TRY_HIP(hipMemcpyAsync(t.mean, d->mean, es * d->dim, hipMemcpyDeviceToDevice, ctx->stream));
+        PMC_TRY_HIP(hipMemcpyAsync(t.prec, d->prec, es * d->dim * d->dim, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        break;
+    }
+    case PMC_TARGET_LOGREG: {
+        PMC_REQUIRE(d->dtype == PMC_F32, "logreg target runs in F32");
+        PMC_REQUIRE(d->n_data >= 1, "logreg target: n_data >= 1");
+        PMC_REQUIRE(d->prior_var > 0, "logreg target: prior_var > 0");
+        PMC_REQUIRE(is_device_ptr(d->X) && is_device_ptr(d->y),
+                    "logreg target: X and y must be device pointers");
+        int ldx = 0;
+        for (int c : {4, 8, 16, 25, 32})
+            if (d->dim <= c) {
+                ldx = c;
+                break;
+            }
+        if (!ldx) {
+            set_error("logreg target: dim <= 32 (got %d)", d->dim);
+            return PMC_ERR_UNSUPPORTED;
+        }
+        t.ldx = ldx;
+        t.n_data = d->n_data;
+        PMC_TRY_HIP(hipMalloc(&t.X, 4 * (size_t)ldx * d->n_data));
+        PMC_TRY_HIP(hipMalloc(&t.y, 4 * (size_t)d->n_data));
+        PMC_TRY_HIP(hipMemsetAsync(t.X, 0, 4 * (size_t)ldx * d->n_data, ctx->stream));
+        PMC_TRY_HIP(hipMemcpy2DAsync(t.X, 4 * ldx, d->X, 4 * d->dim, 4 * d->dim, d->n_data,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+        PMC_TRY_HIP(hipMemcpyAsync(t.y, d->y, 4 * (size_t)d->n_data, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        break;
+    }
+    default:
+        set_error("pmc_target_create: unknown kind %d", (int)d->kind);
+        return PMC_ERR_INVALID;
+    }
+    PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    pmc_target *o = new pmc_target();
+    o->t = t;
+    o->device = ctx->device;
+    *out = o;
+    return PMC_OK;
+}
+
+pmc_status pmc_target_destroy(pmc_target *tgt)
+{
+    if (!tgt) return PMC_OK;
+    (void)hipDeviceSynchronize();
+    if (tgt->t.mean) (void)hipFree(tgt->t.mean);
+    if (tgt->t.prec) (void)hipFree(tgt->t.prec);
+    if (tgt->t.X) (void)hipFree(tgt->t.X);
+    if (tgt->t.y) (void)hipFree(tgt->t.y);
+    delete tgt;
+    return PMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,951 @@
+// Single-pass scans of the linearised recursion of the Newton update
+// (Sec. 2 eq. 2-4, Appendix A.3) for gfx950.
+//
+// The recursion delta_t = A_t delta_{t-1} + b_t is a composition of affine
+// maps (A, b); compositions of affine maps are affine (Sec. 2), so a tile of C
+// consecutive steps reduces to one map.  One kernel launch does the whole
+// scan:
+//   1. each thread composes ITEMS consecutive steps held in registers;
+//   2. a wavefront inclusive scan of the thread aggregates (cross-lane shuffles);
+//   3. wave aggregates combine through LDS into the tile aggregate;
+//   4. decoupled look-back: the tile publishes its aggregate, then wave 0 reads
+//      up to 64 predecessor descriptors at once and folds aggregates back to the
+//      nearest published inclusive value;
+//   5. every thread re-applies its steps from its exact carry and writes the
+//      new iterate, fusing the convergence partials (Algorithm 1's Delta test,
+//      residual norms in FP64, first unconverged step, non-finite count).
+//
+// Descriptor words are 64-bit (tag << 32 | 32-bit payload piece) written and
+// read with agent-scope atomics, so every word validates itself and no memory
+// fence is needed between payload and flag.  Tags carry a per-launch epoch
+// that the last workgroup of each launch advances (descriptors never need
+// clearing; captured graphs can replay the scan).  Tile ids come from an
+// atomic counter so a tile's predecessors were scheduled before it.
+#include <float.h>
+#include <math.h>
+
+#include "pmc_internal.hpp"
+
+namespace pmc {
+namespace {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------- affine maps
+template <typename R, int M>
+struct Aff {
+    R a[M][M];
+    R b[M];
+};
+
+template <typename R, int M>
+__device__ __forceinline__ Aff<R, M> aff_identity()
+{
+    Aff<R, M> e;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int j = 0; j < M; j++) e.a[i][j] = (i == j) ? R(1) : R(0);
+        e.b[i] = R(0);
+    }
+    return e;
+}
+
+// later o earlier: x -> L.a (E.a x + E.b) + L.b
+template <typename R, int M>
+__device__ __forceinline__ Aff<R, M> compose(const Aff<R, M> &L, const Aff<R, M> &E)
+{
+    Aff<R, M> c;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int j = 0; j < M; j++) {
+            R s = R(0);
+#pragma unroll
+            for (int k = 0; k < M; k++) s = fma(L.a[i][k], E.a[k][j], s);
+            c.a[i][j] = s;
+        }
+        R s = L.b[i];
+#pragma unroll
+        for (int k = 0; k < M; k++) s = fma(L.a[i][k], E.b[k], s);
+        c.b[i] = s;
+    }
+    return c;
+}
+
+template <typename R, int M>
+__device__ __forceinline__ void apply(const Aff<R, M> &e, const R (&x)[M], R (&y)[M])
+{
+    R t[M];
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        R s = e.b[i];
+#pragma unroll
+        for (int k = 0; k < M; k++) s = fma(e.a[i][k], x[k], s);
+        t[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < M; i++) y[i] = t[i];
+}
+
+template <typename R, int M>
+__device__ __forceinline__ Aff<R, M> shfl_up_aff(const Aff<R, M> &e, int off)
+{
+    Aff<R, M> o;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int j = 0; j < M; j++) o.a[i][j] = __shfl_up(e.a[i][j], off, kWave);
+        o.b[i] = __shfl_up(e.b[i], off, kWave);
+    }
+    return o;
+}
+
+template <typename R, int M>
+__device__ __forceinline__ Aff<R, M> shfl_down_aff(const Aff<R, M> &e, int off)
+{
+    Aff<R, M> o;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int j = 0; j < M; j++) o.a[i][j] = __shfl_down(e.a[i][j], off, kWave);
+        o.b[i] = __shfl_down(e.b[i], off, kWave);
+    }
+    return o;
+}
+
+// ---------------------------------------------------- look-back descriptors
+template <typename R>
+struct Pieces;
+template <>
+struct Pieces<float> {
+    static constexpr int n = 1;
+    __device__ static void split(float v, uint32_t *p) { p[0] = __float_as_uint(v); }
+    __device__ static float join(const uint32_t *p) { return __uint_as_float(p[0]); }
+};
+template <>
+struct Pieces<double> {
+    static constexpr int n = 2;
+    __device__ static void split(double v, uint32_t *p)
+    {
+        uint64_t u = __double_as_longlong(v);
+        p[0] = (uint32_t)u;
+        p[1] = (uint32_t)(u >> 32);
+    }
+    __device__ static double join(const uint32_t *p)
+    {
+        return __longlong_as_double(((uint64_t)p[1] << 32) | p[0]);
+    }
+};
+
+template <typename R, int M>
+struct Desc {
+    static constexpr int P = Pieces<R>::n;
+    static constexpr int kInc = M * P;            // words of the inclusive value
+    static constexpr int kAgg = (M * M + M) * P;  // words of the aggregate
+    static constexpr int kWords = kInc + kAgg;
+};
+
+__device__ __forceinline__ void word_store(uint64_t *w, uint32_t tag, uint32_t v)
+{
+    __hip_atomic_store(w, ((uint64_t)tag << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t word_load(const uint64_t *w)
+{
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t kAggState = 1, kIncState = 2;
+__device__ __forceinline__ uint32_t make_tag(uint32_t epoch, uint32_t st) { return (epoch << 2) | st; }
+
+template <typename R, int M>
+__device__ void publish_agg(uint64_t *d, uint32_t epoch, const Aff<R, M> &e)
+{
+    using DS = Desc<R, M>;
+    uint32_t tag = make_tag(epoch, kAggState);
+    uint32_t p[Pieces<R>::n];
+    int w = DS::kInc;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int j = 0; j < M; j++) {
+            Pieces<R>::split(e.a[i][j], p);
+#pragma unroll
+            for (int k = 0; k < Pieces<R>::n; k++) word_store(d + w++, tag, p[k]);
+        }
+        Pieces<R>::split(e.b[i], p);
+#pragma unroll
+        for (int k = 0; k < Pieces<R>::n; k++) word_store(d + w++, tag, p[k]);
+    }
+}
+
+template <typename R, int M>
+__device__ void publish_inc(uint64_t *d, uint32_t epoch, const R (&v)[M])
+{
+    uint32_t tag = make_tag(epoch, kIncState);
+    uint32_t p[Pieces<R>::n];
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        Pieces<R>::split(v[i], p);
+#pragma unroll
+        for (int k = 0; k < Pieces<R>::n; k++) word_store(d + w++, tag, p[k]);
+    }
+}
+
+// Reads one descriptor.  Returns 2 with the inclusive value as a constant map
+// (a = 0, b = value), 1 with the aggregate, or 0 if not yet published.
+template <typename R, int M>
+__device__ int read_desc(const uint64_t *d, uint32_t epoch, Aff<R, M> &out)
+{
+    using DS = Desc<R, M>;
+    constexpr int P = Pieces<R>::n;
+    uint32_t ti = make_tag(epoch, kIncState), ta = make_tag(epoch, kAggState);
+    uint32_t p[P];
+    bool ok = true;
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            uint64_t x = word_load(d + w++);
+            ok &= (uint32_t)(x >> 32) == ti;
+            p[k] = (uint32_t)x;
+        }
+        out.b[i] = Pieces<R>::join(p);
+    }
+    if (ok) {
+#pragma unroll
+        for (int i = 0; i < M; i++)
+#pragma unroll
+            for (int j = 0; j < M; j++) out.a[i][j] = R(0);
+        return 2;
+    }
+    ok = true;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+#pragma unroll
+        for (int j = 0; j < M; j++) {
+#pragma unroll
+            for (int k = 0; k < P; k++) {
+                uint64_t x = word_load(d + w++);
+                ok &= (uint32_t)(x >> 32) == ta;
+                p[k] = (uint32_t)x;
+            }
+            out.a[i][j] = Pieces<R>::join(p);
+        }
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            uint64_t x = word_load(d + w++);
+            ok &= (uint32_t)(x >> 32) == ta;
+            p[k] = (uint32_t)x;
+        }
+        out.b[i] = Pieces<R>::join(p);
+    }
+    return ok ? 1 : 0;
+}
+
+// Wave-parallel look-back (wave 0 only).  `self` is this tile's descriptor id,
+// `head` the id of the first tile of its sequence (which publishes an
+// inclusive value without looking back).  Returns the carry entering the tile.
+// A predecessor that never publishes is a bug; after kSpinLimit polls the
+// look-back gives up, raises sync->pad and uses a zero carry, so the launch
+// ends and the host reports the failure instead of hanging the device.
+constexpr uint32_t kSpinLimit = 1u << 21;
+
+template <typename R, int M>
+__device__ void lookback(uint64_t *desc, int64_t self, int64_t head, uint32_t epoch, R (&carry)[M],
+                         ScanSync *sync)
+{
+    using DS = Desc<R, M>;
+    const int lid = threadIdx.x % kWave;
+    Aff<R, M> acc = aff_identity<R, M>();
+    int64_t p = self - 1;
+    uint32_t spins = 0;
+    for (;;) {
+        const int64_t q = p - lid;
+        Aff<R, M> m;
+        int st = 3;  // 3: beyond the sequence head, never needed
+        if (q >= head) st = read_desc<R, M>(desc + (size_t)q * DS::kWords, epoch, m);
+        const uint64_t incmask = __ballot(st == 2);
+        const int first_inc = incmask ? __ffsll((unsigned long long)incmask) - 1 : kWave;
+        const uint64_t waitmask = __ballot(st == 0 && lid <= first_inc);
+        if (waitmask) {
+            if (++spins >= kSpinLimit) {
+                if (lid == 0) atomicOr(&sync->pad, 1u);
+#pragma unroll
+                for (int i = 0; i < M; i++) carry[i] = R(0);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        // ordered fold m_0 o m_1 o ... o m_first_inc (lane 0 is the nearest tile)
+        if (lid > first_inc || st == 3) m = aff_identity<R, M>();
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            Aff<R, M> o = shfl_down_aff(m, off);
+            if ((lid & (2 * off - 1)) == 0 && lid + off < kWave) m = compose(m, o);
+        }
+        // lane 0 holds the fold; broadcast it
+#pragma unroll
+        for (int i = 0; i < M; i++) {
+#pragma unroll
+            for (int j = 0; j < M; j++) m.a[i][j] = __shfl(m.a[i][j], 0, kWave);
+            m.b[i] = __shfl(m.b[i], 0, kWave);
+        }
+        acc = compose(acc, m);
+        if (first_inc < kWave) break;
+        p -= kWave;
+    }
+#pragma unroll
+    for (int i = 0; i < M; i++) carry[i] = acc.b[i];
+}
+
+// ------------------------------------------------------------ partials
+struct Part {
+    float ratio;
+    uint32_t nonfinite;
+    int64_t first_bad;
+    double rsq;
+    double rinf;
+};
+
+__device__ __forceinline__ Part part_neutral()
+{
+    Part p;
+    p.ratio = 0.f;
+    p.nonfinite = 0;
+    p.first_bad = INT64_MAX;
+    p.rsq = 0.0;
+    p.rinf = 0.0;
+    return p;
+}
+
+__device__ __forceinline__ void part_merge(Part &a, const Part &b)
+{
+    a.ratio = fmaxf(a.ratio, b.ratio);
+    a.nonfinite += b.nonfinite;
+    a.first_bad = min(a.first_bad, b.first_bad);
+    a.rsq += b.rsq;
+    a.rinf = fmax(a.rinf, b.rinf);
+}
+
+__device__ __forceinline__ Part part_shfl_xor(const Part &p, int m)
+{
+    Part o;
+    o.ratio = __shfl_xor(p.ratio, m, kWave);
+    o.nonfinite = __shfl_xor(p.nonfinite, m, kWave);
+    o.first_bad = __shfl_xor(p.first_bad, m, kWave);
+    o.rsq = __shfl_xor(p.rsq, m, kWave);
+    o.rinf = __shfl_xor(p.rinf, m, kWave);
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ void part_add(Part &p, int64_t t, R delta, R snew, R b, double atol,
+                                         double rtol)
+{
+    float r = (float)(fabs((double)delta) / (atol + rtol * fabs((double)snew)));
+    if (!(r == r)) r = INFINITY;
+    if (!isfinite(snew)) p.nonfinite++;
+    if (r > 1.f && t < p.first_bad) p.first_bad = t;
+    p.ratio = fmaxf(p.ratio, r);
+    double bb = (double)b;
+    p.rsq += bb * bb;
+    double ab = fabs(bb);
+    if (!(ab == ab)) ab = INFINITY;
+    p.rinf = fmax(p.rinf, ab);
+}
+
+// ------------------------------------------------------------ IO policies
+// Geometry shared by the Newton-update policies: tiles of one chain (or one
+// sliding window of it) in a SegTile map.
+struct SegGeom {
+    const SegTile *tiles;
+    int n_tiles;
+    const int64_t *offsets;
+    const ChainStatus *chains;
+    const int32_t *chain_tile_begin;
+
+    // [t0, t1) of the tile, its sequence head tile, false if the tile is idle.
+    __device__ bool range(int ti, int C, int64_t &t0, int64_t &t1, int &head_ti) const
+    {
+        const SegTile st = tiles[ti];
+        const ChainStatus &cs = chains[st.chain];
+        if (!cs.active) return false;
+        const int64_t off = offsets[st.chain];
+        const int64_t ws = cs.win_start > off ? cs.win_start : off;
+        t1 = st.start + st.len;
+        if (ws >= t1) return false;
+        t0 = st.start > ws ? st.start : ws;
+        head_ti = chain_tile_begin[st.chain] + (int)((ws - off) / C);
+        return true;
+    }
+};
+
+// Quasi-DEER (eq. 4) over dimension-major planes.
+template <typename R>
+struct DiagNewtonIO {
+    using Real = R;
+    static constexpr int M = 1;
+    SegGeom g;
+    int64_t ld;
+    const R *J, *F;
+    R *S;
+    R *trace;
+    double atol, rtol;
+    struct Extra {
+        R f[1];
+    };
+    __device__ void load(int lane, int64_t t, Aff<R, 1> &e, Extra &x) const
+    {
+        const size_t i = (size_t)lane * ld + t;
+        const R f = F[i];
+        e.a[0][0] = J[i];
+        e.b[0] = f - S[i];
+        x.f[0] = f;
+    }
+    __device__ void store(int lane, int64_t t, const Aff<R, 1> &e, const Extra &x, const R (&dp)[1],
+                          const R (&dc)[1], Part &p) const
+    {
+        const size_t i = (size_t)lane * ld + t;
+        const R s = fma(e.a[0][0], dp[0], x.f[0]);
+        S[i] = s;
+        if (trace) trace[i] = s;
+        part_add<R>(p, t, dc[0], s, e.b[0], atol, rtol);
+    }
+};
+
+// Small dense DEER (eq. 3): J_t row-major [ld, M, M], states in planes.
+template <typename R, int MM>
+struct DenseNewtonIO {
+    using Real = R;
+    static constexpr int M = MM;
+    SegGeom g;
+    int64_t ld;
+    const R *J, *F;
+    R *S;
+    R *trace;
+    double atol, rtol;
+    struct Extra {
+        R f[MM];
+    };
+    __device__ void load(int lane, int64_t t, Aff<R, MM> &e, Extra &x) const
+    {
+        const R *Jt = J + (size_t)t * MM * MM;
+#pragma unroll
+        for (int i = 0; i < MM; i++) {
+#pragma unroll
+            for (int j = 0; j < MM; j++) e.a[i][j] = Jt[i * MM + j];
+            const size_t k = (size_t)i * ld + t;
+            x.f[i] = F[k];
+            e.b[i] = x.f[i] - S[k];
+        }
+    }
+    __device__ void store(int lane, int64_t t, const Aff<R, MM> &e, const Extra &x,
+                          const R (&dp)[MM], const R (&dc)[MM], Part &p) const
+    {
+#pragma unroll
+        for (int i = 0; i < MM; i++) {
+            R s = x.f[i];
+#pragma unroll
+            for (int j = 0; j < MM; j++) s = fma(e.a[i][j], dp[j], s);
+            const size_t k = (size_t)i * ld + t;
+            S[k] = s;
+            if (trace) trace[k] = s;
+            part_add<R>(p, t, dc[i], s, e.b[i], atol, rtol);
+        }
+    }
+};
+
+// Standalone linear recursions: one sequence per lane, no chains.
+struct LinGeom {
+    int64_t T;
+    int n_tiles;
+    __device__ bool range(int ti, int C, int64_t &t0, int64_t &t1, int &head_ti) const
+    {
+        t0 = (int64_t)ti * C;
+        t1 = t0 + C < T ? t0 + C : T;
+        head_ti = 0;
+        return t0 < T;
+    }
+};
+
+template <typename R>
+struct DiagLinIO {
+    using Real = R;
+    static constexpr int M = 1;
+    LinGeom g;
+    const R *a, *b;
+    R *out;
+    struct Extra {};
+    __device__ void load(int lane, int64_t t, Aff<R, 1> &e, Extra &) const
+    {
+        const size_t i = (size_t)lane * g.T + t;
+        e.a[0][0] = a[i];
+        e.b[0] = b[i];
+    }
+    __device__ void store(int lane, int64_t t, const Aff<R, 1> &, const Extra &, const R (&)[1],
+                          const R (&dc)[1], Part &) const
+    {
+        out[(size_t)lane * g.T + t] = dc[0];
+    }
+};
+
+struct Block2LinIO {
+    using Real = float;
+    static constexpr int M = 2;
+    LinGeom g;
+    int n_lanes;
+    const float *coef, *rhs;
+    float *out;
+    struct Extra {};
+    __device__ void load(int lane, int64_t t, Aff<float, 2> &e, Extra &) const
+    {
+        const size_t pl = (size_t)n_lanes * g.T;
+        const size_t i = (size_t)lane * g.T + t;
+        e.a[0][0] = coef[i];
+        e.a[0][1] = coef[pl + i];
+        e.a[1][0] = coef[2 * pl + i];
+        e.a[1][1] = coef[3 * pl + i];
+        e.b[0] = rhs[i];
+        e.b[1] = rhs[pl + i];
+    }
+    __device__ void store(int lane, int64_t t, const Aff<float, 2> &, const Extra &,
+                          const float (&)[2], const float (&dc)[2], Part &) const
+    {
+        const size_t pl = (size_t)n_lanes * g.T;
+        const size_t i = (size_t)lane * g.T + t;
+        out[i] = dc[0];
+        out[pl + i] = dc[1];
+    }
+};
+
+template <typename R, int MM>
+struct DenseLinIO {
+    using Real = R;
+    static constexpr int M = MM;
+    LinGeom g;
+    const R *A, *b;
+    R *out;
+    struct Extra {};
+    __device__ void load(int, int64_t t, Aff<R, MM> &e, Extra &) const
+    {
+#pragma unroll
+        for (int i = 0; i < MM; i++) {
+#pragma unroll
+            for (int j = 0; j < MM; j++) e.a[i][j] = A[((size_t)t * MM + i) * MM + j];
+            e.b[i] = b[(size_t)t * MM + i];
+        }
+    }
+    __device__ void store(int, int64_t t, const Aff<R, MM> &, const Extra &, const R (&)[MM],
+                          const R (&dc)[MM], Part &) const
+    {
+#pragma unroll
+        for (int i = 0; i < MM; i++) out[(size_t)t * MM + i] = dc[i];
+    }
+};
+
+template <class IO>
+struct HasPartials {
+    static constexpr bool value = false;
+};
+template <typename R>
+struct HasPartials<DiagNewtonIO<R>> {
+    static constexpr bool value = true;
+};
+template <typename R, int MM>
+struct HasPartials<DenseNewtonIO<R, MM>> {
+    static constexpr bool value = true;
+};
+
+// ------------------------------------------------------------ the kernel
+template <class IO, int BLOCK, int ITEMS>
+__global__ void __launch_bounds__(BLOCK)
+k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials)
+{
+    using R = typename IO::Real;
+    constexpr int M = IO::M;
+    constexpr int NW = BLOCK / kWave;
+    constexpr int C = BLOCK * ITEMS;
+    using A = Aff<R, M>;
+    using DS = Desc<R, M>;
+
+    __shared__ uint32_t s_id, s_epoch;
+    __shared__ A s_wagg[NW];
+    __shared__ R s_carry[M];
+    __shared__ Part s_part[NW];
+
+    const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
+    if (tid == 0) {
+        s_id = atomicAdd(&sync->tile_ctr, 1u);
+        s_epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t id = s_id, epoch = s_epoch;
+    const int lane = (int)(id / (uint32_t)n_tiles), ti = (int)(id % (uint32_t)n_tiles);
+
+    int64_t t0 = 0, t1 = 0;
+    int head_ti = 0;
+    const bool active = io.g.range(ti, C, t0, t1, head_ti);
+    Part part = part_neutral();
+
+    if (active) {
+        A e[ITEMS];
+        typename IO::Extra x[ITEMS];
+        const int64_t base = t0 + (int64_t)tid * ITEMS;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            if (base + i < t1)
+                io.load(lane, base + i, e[i], x[i]);
+            else
+                e[i] = aff_identity<R, M>();
+        }
+        A agg = e[0];
+#pragma unroll
+        for (int i = 1; i < ITEMS; i++) agg = compose(e[i], agg);
+        A inc = agg;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            A o = shfl_up_aff(inc, off);
+            if (lid >= off) inc = compose(inc, o);
+        }
+        A excl = shfl_up_aff(inc, 1);
+        if (lid == 0) excl = aff_identity<R, M>();
+        if (lid == kWave - 1) s_wagg[wid] = inc;
+        __syncthreads();
+        A wpre = aff_identity<R, M>();
+        for (int w = 0; w < wid; w++) wpre = compose(s_wagg[w], wpre);
+        if (wid == 0) {
+            A total = s_wagg[0];
+            for (int w = 1; w < NW; w++) total = compose(s_wagg[w], total);
+            R carry[M];
+#pragma unroll
+            for (int i = 0; i < M; i++) carry[i] = R(0);
+            const int64_t self = (int64_t)lane * n_tiles + ti;
+            if (ti != head_ti) {
+                if (lid == 0) publish_agg<R, M>(desc + (size_t)self * DS::kWords, epoch, total);
+                lookback<R, M>(desc, self, (int64_t)lane * n_tiles + head_ti, epoch, carry, sync);
+            }
+            if (lid == 0) {
+                R outv[M];
+                apply(total, carry, outv);
+                publish_inc<R, M>(desc + (size_t)self * DS::kWords, epoch, outv);
+#pragma unroll
+                for (int i = 0; i < M; i++) s_carry[i] = carry[i];
+            }
+        }
+        __syncthreads();
+        R d[M];
+#pragma unroll
+        for (int i = 0; i < M; i++) d[i] = s_carry[i];
+        apply(wpre, d, d);
+        apply(excl, d, d);
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            if (base + i < t1) {
+                R dp[M];
+#pragma unroll
+                for (int k = 0; k < M; k++) dp[k] = d[k];
+                apply(e[i], dp, d);
+                io.store(lane, base + i, e[i], x[i], dp, d, part);
+            }
+        }
+    }
+
+    if constexpr (HasPartials<IO>::value) {
+#pragma unroll
+        for (int m = 1; m < kWave; m <<= 1) part_merge(part, part_shfl_xor(part, m));
+        if (lid == 0) s_part[wid] = part;
+        __syncthreads();
+        if (tid == 0) {
+            Part p = s_part[0];
+            for (int w = 1; w < NW; w++) part_merge(p, s_part[w]);
+            TilePartial &tp = partials[id];
+            tp.max_ratio = p.ratio;
+            tp.nonfinite = p.nonfinite;
+            tp.first_bad = p.first_bad;
+            tp.resid_sq = p.rsq;
+            tp.resid_inf = p.rinf;
+        }
+    }
+    // the last workgroup resets the counter and advances the epoch
+    if (tid == 0) {
+        const uint32_t done = atomicAdd(&sync->done_ctr, 1u);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(&sync->tile_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync->done_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync->epoch, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <class IO, int BLOCK, int ITEMS>
+pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, TilePartial *partials)
+{
+    using DS = Desc<typename IO::Real, IO::M>;
+    const size_t n_desc = (size_t)n_lanes * n_tiles;
+    if (n_desc == 0) return PMC_OK;
+    if (n_desc > 0x7fffffffULL) {
+        set_error("scan: %zu tiles exceed the launch limit", n_desc);
+        return PMC_ERR_UNSUPPORTED;
+    }
+    PMC_TRY(ensure_lb_desc(ctx, n_desc * DS::kWords * sizeof(uint64_t)));
+    hipLaunchKernelGGL((k_scan<IO, BLOCK, ITEMS>), dim3((unsigned)n_desc), dim3(BLOCK), 0,
+                       ctx->stream, io, ctx->sync, (uint64_t *)ctx->lb_desc, n_tiles, partials);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+// ------------------------------------------------------- chain status fold
+// One thread per chain folds its tiles' partials (all lanes, fixed order, so
+// the FP64 sums are deterministic), updates the chain's Newton state, then the
+// block folds chains into the global status in fixed order.
+__global__ void __launch_bounds__(1024) k_status(StatusArgs a)
+{
+    __shared__ double s_rsq[1024];
+    __shared__ double s_rinf[1024];
+    __shared__ float s_ratio[1024];
+    __shared__ int s_active[1024], s_conv[1024], s_sweeps[1024], s_floor[1024];
+    __shared__ uint32_t s_nf[1024];
+    __shared__ long long s_acc[1024];
+    const int tid = threadIdx.x;
+    double rsq = 0, rinf = 0;
+    float ratio = 0;
+    int nact = 0, nconv = 0, sweeps = 0, nfloor = 0;
+    uint32_t nf = 0;
+    long long nacc = 0;
+    for (int c = tid; c < a.n_chains; c += blockDim.x) {
+        ChainStatus &cs = a.chains[c];
+        if (cs.active) {
+            float r = 0;
+            int64_t fb = INT64_MAX;
+            double q = 0, qi = 0;
+            uint32_t f = 0;
+            for (int l = 0; l < a.n_lanes; l++) {
+                for (int k = a.chain_tile_begin[c]; k < a.chain_tile_begin[c + 1]; k++) {
+                    const TilePartial &p = a.partials[(size_t)l * a.n_tiles + k];
+                    r = fmaxf(r, p.max_ratio);
+                    fb = min(fb, p.first_bad);
+                    q += p.resid_sq;
+                    qi = fmax(qi, p.resid_inf);
+                    f += p.nonfinite;
+                }
+            }
+            cs.sweeps += 1;
+            cs.max_ratio = r;
+            cs.first_bad = fb;
+            cs.resid_sq = q;
+            cs.resid_inf = qi;
+            cs.nonfinite = f;
+            // Plateau detection: progress is a 2x drop of the best ratio or an
+            // advance of the converged front; rounding noise gives neither.
+            const int64_t front = fb == INT64_MAX ? a.offsets[c + 1] : fb;
+            if (r < 0.5f * cs.best_ratio || front > cs.best_front) {
+                cs.best_ratio = fminf(cs.best_ratio, r);
+                cs.best_front = front > cs.best_front ? front : cs.best_front;
+                cs.stall = 0;
+            } else {
+                cs.stall += 1;
+            }
+            if (r <= 1.f) {
+                cs.converged = 1;
+                cs.active = 0;
+            } else if (cs.sweeps >= a.max_iter) {
+                cs.active = 0;
+            } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 100.f) {
+                // rounding floor: no progress for floor_stall sweeps within 100x of the tolerance
+                cs.at_floor = 1;
+                cs.active = 0;
+            } else if (a.skip_prefix && fb != INT64_MAX) {
+                cs.win_start = fb;
+            }
+        }
+        rsq += cs.resid_sq;
+        rinf = fmax(rinf, cs.resid_inf);
+        ratio = fmaxf(ratio, cs.max_ratio);
+        nact += cs.active;
+        nconv += cs.converged;
+        nfloor += cs.at_floor;
+        sweeps = max(sweeps, cs.sweeps);
+        nf += cs.nonfinite;
+        if (a.accept) {
+            long long s = 0;
+            for (int64_t t = a.offsets[c]; t < a.offsets[c + 1]; t++) s += a.accept[t];
+            nacc += s;
+        }
+    }
+    s_rsq[tid] = rsq;
+    s_rinf[tid] = rinf;
+    s_ratio[tid] = ratio;
+    s_active[tid] = nact;
+    s_conv[tid] = nconv;
+    s_floor[tid] = nfloor;
+    s_sweeps[tid] = sweeps;
+    s_nf[tid] = nf;
+    s_acc[tid] = nacc;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+            s_rsq[tid] += s_rsq[tid + h];
+            s_rinf[tid] = fmax(s_rinf[tid], s_rinf[tid + h]);
+            s_ratio[tid] = fmaxf(s_ratio[tid], s_ratio[tid + h]);
+            s_active[tid] += s_active[tid + h];
+            s_conv[tid] += s_conv[tid + h];
+            s_floor[tid] += s_floor[tid + h];
+            s_sweeps[tid] = max(s_sweeps[tid], s_sweeps[tid + h]);
+            s_nf[tid] += s_nf[tid + h];
+            s_acc[tid] += s_acc[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        GlobalStatus *g = a.global;
+        g->n_active = s_active[0];
+        g->n_converged = s_conv[0];
+        g->n_floor = s_floor[0];
+        g->sweeps = s_sweeps[0];
+        g->resid_sq = s_rsq[0];
+        g->resid_inf = s_rinf[0];
+        g->max_ratio = s_ratio[0];
+        g->nonfinite = s_nf[0];
+        g->n_accept = s_acc[0];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+namespace {
+template <typename R, int BLOCK, int ITEMS>
+pmc_status diag_newton(pmc_context *ctx, const NewtonScanArgs &a)
+{
+    SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
+    DiagNewtonIO<R> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol, a.rtol};
+    return run_scan<DiagNewtonIO<R>, BLOCK, ITEMS>(ctx, io, a.n_lanes, a.n_tiles, a.partials);
+}
+template <typename R, int MM, int BLOCK, int ITEMS>
+pmc_status dense_newton(pmc_context *ctx, const NewtonScanArgs &a)
+{
+    SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
+    DenseNewtonIO<R, MM> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol,
+                            a.rtol};
+    return run_scan<DenseNewtonIO<R, MM>, BLOCK, ITEMS>(ctx, io, 1, a.n_tiles, a.partials);
+}
+}  // namespace
+
+int scan_tile_steps(pmc_dtype dt, int variant_m, int items, int block)
+{
+    if (variant_m > 1) return 256 * (variant_m == 2 ? 4 : 2);
+    if (dt == PMC_F64) return 256 * (items >= 8 ? 8 : 4);
+    if (block == 512) return 512 * (items >= 16 ? 16 : 8);
+    return 256 * (items >= 16 ? 16 : (items >= 8 ? 8 : 4));
+}
+
+pmc_status launch_newton_scan_diag(pmc_context *ctx, pmc_dtype dt, const NewtonScanArgs &a,
+                                   int items, int block)
+{
+    if (dt == PMC_F64) {
+        if (items >= 8) return diag_newton<double, 256, 8>(ctx, a);
+        return diag_newton<double, 256, 4>(ctx, a);
+    }
+    if (block == 512) {
+        if (items >= 16) return diag_newton<float, 512, 16>(ctx, a);
+        return diag_newton<float, 512, 8>(ctx, a);
+    }
+    if (items >= 16) return diag_newton<float, 256, 16>(ctx, a);
+    if (items >= 8) return diag_newton<float, 256, 8>(ctx, a);
+    return diag_newton<float, 256, 4>(ctx, a);
+}
+
+pmc_status launch_newton_scan_dense_small(pmc_context *ctx, pmc_dtype dt, int D,
+                                          const NewtonScanArgs &a)
+{
+    if (dt == PMC_F64) {
+        switch (D) {
+        case 2: return dense_newton<double, 2, 256, 4>(ctx, a);
+        case 3: return dense_newton<double, 3, 256, 2>(ctx, a);
+        case 4: return dense_newton<double, 4, 256, 2>(ctx, a);
+        }
+    } else {
+        switch (D) {
+        case 2: return dense_newton<float, 2, 256, 4>(ctx, a);
+        case 3: return dense_newton<float, 3, 256, 2>(ctx, a);
+        case 4: return dense_newton<float, 4, 256, 2>(ctx, a);
+        }
+    }
+    set_error("dense VALU scan supports D <= 4 (got %d)", D);
+    return PMC_ERR_UNSUPPORTED;
+}
+
+pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64_t T, const void *a,
+                              const void *b, void *out)
+{
+    if (dt == PMC_F64) {
+        constexpr int C = 256 * 8;
+        int nt = (int)((T + C - 1) / C);
+        DiagLinIO<double> io{LinGeom{T, nt}, (const double *)a, (const double *)b, (double *)out};
+        return run_scan<DiagLinIO<double>, 256, 8>(ctx, io, n_lanes, nt, nullptr);
+    }
+    constexpr int C = 256 * 16;
+    int nt = (int)((T + C - 1) / C);
+    DiagLinIO<float> io{LinGeom{T, nt}, (const float *)a, (const float *)b, (float *)out};
+    return run_scan<DiagLinIO<float>, 256, 16>(ctx, io, n_lanes, nt, nullptr);
+}
+
+pmc_status launch_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
+                                const void *rhs, void *out)
+{
+    constexpr int C = 256 * 4;
+    int nt = (int)((T + C - 1) / C);
+    Block2LinIO io{LinGeom{T, nt}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};
+    return run_scan<Block2LinIO, 256, 4>(ctx, io, n_lanes, nt, nullptr);
+}
+
+pmc_status launch_linrec_dense_small(pmc_context *ctx, int D, int64_t T, const double *A,
+                                     const double *b, double *out)
+{
+    constexpr int C2 = 256 * 4, C4 = 256 * 2;
+    switch (D) {
+    case 1: return launch_linrec_diag(ctx, PMC_F64, 1, T, A, b, out);
+    case 2: {
+        int nt = (int)((T + C2 - 1) / C2);
+        DenseLinIO<double, 2> io{LinGeom{T, nt}, A, b, out};
+        return run_scan<DenseLinIO<double, 2>, 256, 4>(ctx, io, 1, nt, nullptr);
+    }
+    case 3: {
+        int nt = (int)((T + C4 - 1) / C4);
+        DenseLinIO<double, 3> io{LinGeom{T, nt}, A, b, out};
+        return run_scan<DenseLinIO<double, 3>, 256, 2>(ctx, io, 1, nt, nullptr);
+    }
+    case 4: {
+        int nt = (int)((T + C4 - 1) / C4);
+        DenseLinIO<double, 4> io{LinGeom{T, nt}, A, b, out};
+        return run_scan<DenseLinIO<double, 4>, 256, 2>(ctx, io, 1, nt, nullptr);
+    }
+    }
+    set_error("dense FP64 scan supports D <= 4 (got %d)", D);
+    return PMC_ERR_UNSUPPORTED;
+}
+
+pmc_status check_scan_health(pmc_context *ctx)
+{
+    ScanSync h;
+    PMC_TRY_HIP(hipMemcpyAsync(&h, ctx->sync, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (h.pad) {
+        set_error("scan look-back timed out (a predecessor tile never published)");
+        return PMC_ERR_HIP;
+    }
+    return PMC_OK;
+}
+
+pmc_status launch_status(pmc_context *ctx, const StatusArgs &a)
+{
+    hipLaunchKernelGGL(k_status, dim3(1), dim3(1024), 0, ctx->stream, a);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+}  // namespace pmc

@@ -1,0 +1,533 @@
+// Newton driver (Algorithm 1, Appendix A.1) and the sequential baseline entry.
+//
+// Per sweep, for every still-active chain (and, with the sliding window, only
+// from its first unconverged step): eval kernel (F_t, J_t at s^{(i)}), scan
+// kernel (the linearised recursion, Sec. 2 eq. 2-4, updating s in place and
+// emitting convergence partials), status kernel (per-chain Delta test, sweep
+// counts, window starts, global status).  The host either reads the status
+// after each sweep or replays a captured HIP graph of `graph_sweeps` sweeps
+// between reads; kernels of converged chains return immediately, so a replay
+// past convergence changes nothing.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pmc_internal.hpp"
+
+namespace pmc {
+namespace {
+
+struct Plan {
+    const DevTarget *tg;
+    pmc_dtype dt;
+    size_t es;
+    int D;
+    int64_t n;
+    int n_chains;
+    int64_t ld;
+    int64_t Tmax;
+    int variant;
+    int jmode;
+    int n_lanes;
+    int scan_items, scan_block, C_scan, C_eval;
+    std::vector<int64_t> offs;
+    std::vector<SegTile> etiles, stiles;
+    std::vector<int32_t> ctb;
+    size_t o_S, o_F, o_J, o_acc, o_gt, o_etiles, o_stiles, o_ctb, o_offs, o_part, o_chains,
+        o_global, total;
+    int max_iter;
+};
+
+void build_tiles(const std::vector<int64_t> &offs, int C, std::vector<SegTile> &tiles,
+                 std::vector<int32_t> *ctb)
+{
+    tiles.clear();
+    const int nc = (int)offs.size() - 1;
+    if (ctb) ctb->assign(nc + 1, 0);
+    for (int c = 0; c < nc; c++) {
+        if (ctb) (*ctb)[c] = (int32_t)tiles.size();
+        for (int64_t s = offs[c]; s < offs[c + 1]; s += C)
+            tiles.push_back(SegTile{s, (int32_t)std::min<int64_t>(C, offs[c + 1] - s), c});
+    }
+    if (ctb) (*ctb)[nc] = (int32_t)tiles.size();
+}
+
+pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *o, Plan &pl)
+{
+    PMC_REQUIRE(ctx && p && o, "pmc_solve: NULL argument");
+    PMC_REQUIRE(p->target, "pmc_solve: problem has no target");
+    const DevTarget &t = p->target->t;
+    pl.tg = &t;
+    pl.dt = t.dtype;
+    pl.es = t.dtype == PMC_F64 ? 8 : 4;
+    pl.D = t.dim;
+    PMC_REQUIRE(p->sampler == PMC_SAMPLER_MALA || p->sampler == PMC_SAMPLER_ULA,
+                "pmc_solve: sampler must be MALA or ULA");
+    PMC_REQUIRE(p->n_chains >= 1, "pmc_solve: n_chains >= 1 (got %d)", p->n_chains);
+    PMC_REQUIRE(p->step_size > 0 && isfinite(p->step_size), "pmc_solve: step_size > 0");
+    PMC_REQUIRE(o->atol >= 0 && o->rtol >= 0 && (o->atol > 0 || o->rtol > 0),
+                "pmc_solve: tolerances must be >= 0 and not both 0");
+    pl.n_chains = p->n_chains;
+    pl.offs.assign(p->n_chains + 1, 0);
+    if (p->offsets) {
+        PMC_REQUIRE(p->offsets[0] == 0, "pmc_solve: offsets[0] must be 0");
+        for (int c = 0; c < p->n_chains; c++) {
+            PMC_REQUIRE(p->offsets[c + 1] >= p->offsets[c], "pmc_solve: offsets must be non-decreasing");
+            pl.offs[c + 1] = p->offsets[c + 1];
+        }
+        PMC_REQUIRE(p->offsets[p->n_chains] == p->n_steps,
+                    "pmc_solve: offsets[n_chains] (%lld) != n_steps (%lld)",
+                    (long long)p->offsets[p->n_chains], (long long)p->n_steps);
+    } else {
+        PMC_REQUIRE(p->n_chains == 1, "pmc_solve: offsets required for n_chains > 1");
+        pl.offs[1] = p->n_steps;
+    }
+    PMC_REQUIRE(p->n_steps >= 0, "pmc_solve: n_steps >= 0");
+    pl.n = p->n_steps;
+    pl.Tmax = 0;
+    for (int c = 0; c < p->n_chains; c++) pl.Tmax = std::max(pl.Tmax, pl.offs[c + 1] - pl.offs[c]);
+    if (pl.n > 0) {
+        PMC_REQUIRE(is_device_ptr(p->s0), "pmc_solve: s0 must be a device pointer");
+        PMC_REQUIRE(is_device_ptr(p->noise), "pmc_solve: noise must be a device pointer");
+        PMC_REQUIRE(is_device_ptr(p->out_states), "pmc_solve: out_states must be a device pointer");
+        if (p->sampler == PMC_SAMPLER_MALA)
+            PMC_REQUIRE(is_device_ptr(p->uniforms), "pmc_solve: MALA needs device uniforms");
+        if (p->init_guess)
+            PMC_REQUIRE(is_device_ptr(p->init_guess), "pmc_solve: init_guess must be a device pointer");
+    }
+    pl.variant = o->variant;
+    pl.n_lanes = pl.D;
+    switch (o->variant) {
+    case PMC_QDEER_DIAG: pl.jmode = JM_DIAG; break;
+    case PMC_PICARD: pl.jmode = JM_NONE; break;
+    case PMC_DEER_DENSE:
+        if (pl.D > 4) {
+            set_error("pmc_solve: dense DEER with D = %d needs the matrix-core scan (D <= 4 here)", pl.D);
+            return PMC_ERR_UNSUPPORTED;
+        }
+        if (t.kind == PMC_TARGET_LOGREG) {
+            set_error("pmc_solve: dense DEER on logistic regression is not built");
+            return PMC_ERR_UNSUPPORTED;
+        }
+        pl.jmode = JM_DENSE_ROW;
+        pl.n_lanes = 1;
+        break;
+    case PMC_QDEER_BLOCK2:
+        set_error("pmc_solve: block quasi-DEER applies to leapfrog integration (pmc_hmc_sample)");
+        return PMC_ERR_UNSUPPORTED;
+    default:
+        set_error("pmc_solve: unknown variant %d", (int)o->variant);
+        return PMC_ERR_INVALID;
+    }
+    PMC_REQUIRE(o->gate == PMC_GATE_FROZEN || o->gate == PMC_GATE_SURROGATE, "pmc_solve: bad gate");
+    PMC_REQUIRE(o->damping > 0 && isfinite(o->damping), "pmc_solve: damping must be > 0");
+    if (t.kind == PMC_TARGET_LOGREG && o->gate == PMC_GATE_SURROGATE && p->sampler == PMC_SAMPLER_MALA) {
+        set_error("pmc_solve: logistic regression supports the frozen gate only");
+        return PMC_ERR_UNSUPPORTED;
+    }
+    PMC_REQUIRE(!(o->graph_sweeps > 0 && o->trace_out), "pmc_solve: trace_out needs graph_sweeps = 0");
+
+    if (pl.jmode == JM_DENSE_ROW) {
+        pl.scan_items = pl.D == 2 ? 4 : 2;
+        pl.scan_block = 256;
+        pl.C_scan = 256 * pl.scan_items;
+    } else {
+        pl.scan_items = ctx->diag_items ? ctx->diag_items : (pl.dt == PMC_F64 ? 8 : 16);
+        pl.scan_block = ctx->diag_block ? ctx->diag_block : 256;
+        pl.C_scan = scan_tile_steps(pl.dt, 1, pl.scan_items, pl.scan_block);
+    }
+    pl.C_eval = eval_tile_steps(t);
+    build_tiles(pl.offs, pl.C_scan, pl.stiles, &pl.ctb);
+    build_tiles(pl.offs, pl.C_eval, pl.etiles, nullptr);
+
+    pl.max_iter = o->max_iter;
+    if (pl.max_iter <= 0)
+        pl.max_iter = (int)std::min<int64_t>(pl.Tmax + 1, 50 + (int64_t)(5e-4 * (double)pl.Tmax));
+    if (o->trace_out) {
+        const size_t need = (size_t)pl.max_iter * pl.n * pl.D * pl.es;
+        PMC_REQUIRE(o->trace_bytes >= need, "pmc_solve: trace_out needs %zu bytes", need);
+    }
+
+    pl.ld = (int64_t)align_up((size_t)std::max<int64_t>(pl.n, 1), 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o2 = off;
+        off = align_up(off + bytes, 256);
+        return o2;
+    };
+    const size_t plane = (size_t)pl.ld * pl.es;
+    pl.o_S = take(plane * pl.D);
+    pl.o_F = take(plane * pl.D);
+    size_t jb = 0;
+    switch (pl.jmode) {
+    case JM_DIAG:
+    case JM_NONE: jb = plane * pl.D; break;
+    case JM_DENSE_ROW: jb = (size_t)pl.n * pl.D * pl.D * pl.es; break;
+    default: jb = 0;
+    }
+    pl.o_J = take(std::max<size_t>(jb, 256));
+    pl.o_acc = take(std::max<int64_t>(pl.n, 1));
+    pl.o_gt = take(4 * std::max<int64_t>(pl.n, 1));
+    pl.o_etiles = take(sizeof(SegTile) * std::max<size_t>(pl.etiles.size(), 1));
+    pl.o_stiles = take(sizeof(SegTile) * std::max<size_t>(pl.stiles.size(), 1));
+    pl.o_ctb = take(sizeof(int32_t) * pl.ctb.size());
+    pl.o_offs = take(sizeof(int64_t) * pl.offs.size());
+    pl.o_part = take(sizeof(TilePartial) * std::max<size_t>((size_t)pl.n_lanes * pl.stiles.size(), 1));
+    pl.o_chains = take(sizeof(ChainStatus) * pl.n_chains);
+    pl.o_global = take(sizeof(GlobalStatus));
+    pl.total = off;
+    return PMC_OK;
+}
+
+struct Sweep {
+    EvalArgs ea;
+    NewtonScanArgs sa;
+    StatusArgs st;
+};
+
+pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, bool prof = false)
+{
+    if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[0], ctx->stream));
+    PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
+    if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[1], ctx->stream));
+    if (pl.jmode == JM_DENSE_ROW)
+        PMC_TRY(launch_newton_scan_dense_small(ctx, pl.dt, pl.D, sw.sa));
+    else
+        PMC_TRY(launch_newton_scan_diag(ctx, pl.dt, sw.sa, pl.scan_items, pl.scan_block));
+    if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[2], ctx->stream));
+    PMC_TRY(launch_status(ctx, sw.st));
+    return PMC_OK;
+}
+
+}  // namespace
+}  // namespace pmc
+
+using namespace pmc;
+
+extern "C" {
+
+pmc_status pmc_default_options(pmc_options *o, pmc_dtype dtype)
+{
+    PMC_REQUIRE(o, "pmc_default_options: NULL");
+    memset(o, 0, sizeof(*o));
+    o->variant = PMC_QDEER_DIAG;
+    o->jac_prec = PMC_JAC_F32;
+    o->gate = PMC_GATE_FROZEN;
+    o->atol = o->rtol = dtype == PMC_F64 ? 1e-12 : 1e-6;
+    o->max_iter = 0;
+    o->damping = 1.0;
+    o->clip = 0.0;
+    o->floor_stall = 16;
+    return PMC_OK;
+}
+
+pmc_status pmc_workspace_size(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                              size_t *bytes)
+{
+    PMC_REQUIRE(bytes, "pmc_workspace_size: bytes is NULL");
+    Plan pl;
+    PMC_TRY(make_plan(ctx, prob, opts, pl));
+    *bytes = pl.total;
+    return PMC_OK;
+}
+
+pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                     void *workspace, size_t ws_bytes, pmc_result *res)
+{
+    Plan pl;
+    PMC_TRY(make_plan(ctx, prob, opts, pl));
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    if (res) {
+        int32_t *spc = res->sweeps_per_chain;
+        memset(res, 0, sizeof(*res));
+        res->sweeps_per_chain = spc;
+    }
+    if (pl.n == 0) {
+        if (res) {
+            res->n_converged = pl.n_chains;
+            if (res->sweeps_per_chain) memset(res->sweeps_per_chain, 0, 4 * pl.n_chains);
+        }
+        return PMC_OK;
+    }
+    char *ws;
+    if (workspace) {
+        PMC_REQUIRE(ws_bytes >= pl.total, "pmc_solve: workspace of %zu bytes < %zu needed", ws_bytes,
+                    pl.total);
+        PMC_REQUIRE(is_device_ptr(workspace), "pmc_solve: workspace must be a device pointer");
+        ws = (char *)workspace;
+    } else {
+        PMC_TRY(ensure_pool(ctx, pl.total));
+        ws = (char *)ctx->pool;
+    }
+    hipStream_t st = ctx->stream;
+    void *S = ws + pl.o_S, *F = ws + pl.o_F, *J = ws + pl.o_J;
+    uint8_t *acc = prob->out_accept ? prob->out_accept : (uint8_t *)(ws + pl.o_acc);
+    float *gt = prob->out_gtilde ? prob->out_gtilde : (float *)(ws + pl.o_gt);
+    SegTile *d_et = (SegTile *)(ws + pl.o_etiles), *d_st = (SegTile *)(ws + pl.o_stiles);
+    int32_t *d_ctb = (int32_t *)(ws + pl.o_ctb);
+    int64_t *d_offs = (int64_t *)(ws + pl.o_offs);
+    TilePartial *d_part = (TilePartial *)(ws + pl.o_part);
+    ChainStatus *d_chains = (ChainStatus *)(ws + pl.o_chains);
+    GlobalStatus *d_glob = (GlobalStatus *)(ws + pl.o_global);
+
+    std::vector<ChainStatus> hc(pl.n_chains);
+    for (int c = 0; c < pl.n_chains; c++) {
+        ChainStatus &cs = hc[c];
+        memset(&cs, 0, sizeof(cs));
+        cs.win_start = pl.offs[c];
+        cs.first_bad = INT64_MAX;
+        const bool nonempty = pl.offs[c + 1] > pl.offs[c];
+        cs.active = nonempty;
+        cs.converged = !nonempty;
+        cs.best_ratio = INFINITY;
+        cs.best_front = pl.offs[c];
+    }
+    PMC_TRY_HIP(hipMemcpyAsync(d_et, pl.etiles.data(), sizeof(SegTile) * pl.etiles.size(),
+                               hipMemcpyHostToDevice, st));
+    PMC_TRY_HIP(hipMemcpyAsync(d_st, pl.stiles.data(), sizeof(SegTile) * pl.stiles.size(),
+                               hipMemcpyHostToDevice, st));
+    PMC_TRY_HIP(hipMemcpyAsync(d_ctb, pl.ctb.data(), sizeof(int32_t) * pl.ctb.size(),
+                               hipMemcpyHostToDevice, st));
+    PMC_TRY_HIP(hipMemcpyAsync(d_offs, pl.offs.data(), sizeof(int64_t) * pl.offs.size(),
+                               hipMemcpyHostToDevice, st));
+    PMC_TRY_HIP(hipMemcpyAsync(d_chains, hc.data(), sizeof(ChainStatus) * hc.size(),
+                               hipMemcpyHostToDevice, st));
+    if (pl.jmode == JM_NONE)  // Picard: J = 0 through the diagonal scan
+        PMC_TRY_HIP(hipMemsetAsync(J, 0, (size_t)pl.ld * pl.es * pl.D, st));
+
+    PMC_TRY_HIP(hipEventRecord(ctx->ev0, st));
+    if (prob->init_guess)
+        PMC_TRY(rows_to_planes(ctx, pl.dt, prob->init_guess, S, pl.n, pl.D, pl.ld));
+    else
+        PMC_TRY(broadcast_s0(ctx, pl.dt, prob->s0, d_offs, pl.n_chains, S, pl.n, pl.D, pl.ld));
+
+    Sweep sw;
+    EvalArgs &ea = sw.ea;
+    ea.tiles = d_et;
+    ea.n_tiles = (int)pl.etiles.size();
+    ea.offsets = d_offs;
+    ea.chains = d_chains;
+    ea.D = pl.D;
+    ea.ld = pl.ld;
+    ea.s0 = prob->s0;
+    ea.S = S;
+    ea.noise = prob->noise;
+    ea.unif = prob->uniforms;
+    ea.F = F;
+    ea.J = J;
+    ea.accept = acc;
+    ea.gtilde = gt;
+    ea.eps = prob->step_size;
+    ea.ula = prob->sampler == PMC_SAMPLER_ULA;
+    ea.gate = opts->gate;
+    ea.damping = opts->damping;
+    ea.clip = opts->clip;
+    ea.clip_inf = opts->clip_inf_norm;
+    ea.jmode = pl.jmode == JM_NONE ? JM_NONE : pl.jmode;
+    ea.tg = pl.tg;
+    NewtonScanArgs &sa = sw.sa;
+    sa.n_lanes = pl.n_lanes;
+    sa.ld = pl.ld;
+    sa.tiles = d_st;
+    sa.n_tiles = (int)pl.stiles.size();
+    sa.offsets = d_offs;
+    sa.chains = d_chains;
+    sa.chain_tile_begin = d_ctb;
+    sa.J = J;
+    sa.F = F;
+    sa.S = S;
+    sa.partials = d_part;
+    sa.atol = opts->atol;
+    sa.rtol = opts->rtol;
+    sa.eps = prob->step_size;
+    sa.trace = nullptr;
+    StatusArgs &sta = sw.st;
+    sta.n_chains = pl.n_chains;
+    sta.n_lanes = pl.n_lanes;
+    sta.tiles = d_st;
+    sta.n_tiles = (int)pl.stiles.size();
+    sta.chain_tile_begin = d_ctb;
+    sta.partials = d_part;
+    sta.chains = d_chains;
+    sta.global = d_glob;
+    sta.accept = nullptr;
+    sta.offsets = d_offs;
+    sta.max_iter = pl.max_iter;
+    sta.skip_prefix = opts->skip_converged_prefix;
+    sta.floor_stall = opts->floor_stall;
+    sta.n_steps = pl.n;
+
+    GlobalStatus *hs = ctx->h_status;
+    int sweeps_done = 0;
+    float prof_eval_ms = 0, prof_scan_ms = 0;
+    int64_t prof_steps = 0;
+    PMC_REQUIRE(!(opts->profile_kernels && opts->graph_sweeps > 0),
+                "pmc_solve: profile_kernels needs graph_sweeps = 0");
+    if (opts->graph_sweeps > 0) {
+        const int m = opts->graph_sweeps;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        PMC_TRY_HIP(hipStreamSynchronize(st));
+        hipStream_t cap = st;
+        bool own_stream = false;
+        if (!cap) {  // the legacy default stream cannot be captured
+            PMC_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        // descriptors and pool must not grow inside the capture
+        PMC_TRY(ensure_lb_desc(ctx, (size_t)48 * 8 * pl.n_lanes * pl.stiles.size()));
+        hipStream_t saved = ctx->stream;
+        ctx->stream = cap;
+        pmc_status rc = PMC_OK;
+        hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (he == hipSuccess) {
+            for (int i = 0; i < m && rc == PMC_OK; i++) rc = one_sweep(ctx, pl, sw);
+            if (rc == PMC_OK)
+                he = hipMemcpyAsync(hs, d_glob, sizeof(GlobalStatus), hipMemcpyDeviceToHost, cap);
+            hipError_t he2 = hipStreamEndCapture(cap, &graph);
+            if (he == hipSuccess) he = he2;
+        }
+        if (rc == PMC_OK && he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        for (; rc == PMC_OK && he == hipSuccess && sweeps_done < pl.max_iter;) {
+            he = hipGraphLaunch(exec, cap);
+            if (he == hipSuccess) he = hipStreamSynchronize(cap);
+            sweeps_done = hs->sweeps;
+            if (hs->n_active == 0) break;
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->stream = saved;
+        if (own_stream) (void)hipStreamDestroy(cap);
+        if (rc != PMC_OK) return rc;
+        PMC_TRY_HIP(he);
+    } else {
+        const bool prof = opts->profile_kernels != 0;
+        for (int it = 0; it < pl.max_iter; it++) {
+            // steps this sweep evaluates (active chains, from their windows)
+            int64_t act_steps = 0;
+            if (prof) {
+                PMC_TRY_HIP(hipMemcpyAsync(hc.data(), d_chains, sizeof(ChainStatus) * hc.size(),
+                                           hipMemcpyDeviceToHost, st));
+                PMC_TRY_HIP(hipStreamSynchronize(st));
+                for (int c = 0; c < pl.n_chains; c++)
+                    if (hc[c].active)
+                        act_steps += pl.offs[c + 1] - std::max(hc[c].win_start, pl.offs[c]);
+            }
+            PMC_TRY(one_sweep(ctx, pl, sw, prof));
+            if (opts->trace_out)
+                PMC_TRY(planes_to_rows(ctx, pl.dt, S,
+                                       (char *)opts->trace_out + (size_t)it * pl.n * pl.D * pl.es,
+                                       pl.n, pl.D, pl.ld));
+            PMC_TRY_HIP(hipMemcpyAsync(hs, d_glob, sizeof(GlobalStatus), hipMemcpyDeviceToHost, st));
+            PMC_TRY_HIP(hipStreamSynchronize(st));
+            if (prof) {
+                float me = 0, msc = 0;
+                PMC_TRY_HIP(hipEventElapsedTime(&me, ctx->kev[0], ctx->kev[1]));
+                PMC_TRY_HIP(hipEventElapsedTime(&msc, ctx->kev[1], ctx->kev[2]));
+                prof_eval_ms += me;
+                prof_scan_ms += msc;
+                prof_steps += act_steps;
+            }
+            sweeps_done = hs->sweeps;
+            if (hs->n_active == 0) break;
+        }
+    }
+    PMC_TRY(planes_to_rows(ctx, pl.dt, S, prob->out_states, pl.n, pl.D, pl.ld));
+    PMC_TRY_HIP(hipEventRecord(ctx->ev1, st));
+    // final accept count
+    sta.accept = acc;
+    PMC_TRY(launch_status(ctx, sta));  // no active chain left or max_iter: only re-folds totals
+    PMC_TRY_HIP(hipMemcpyAsync(hs, d_glob, sizeof(GlobalStatus), hipMemcpyDeviceToHost, st));
+    PMC_TRY_HIP(hipMemcpyAsync(hc.data(), d_chains, sizeof(ChainStatus) * hc.size(),
+                               hipMemcpyDeviceToHost, st));
+    PMC_TRY_HIP(hipStreamSynchronize(st));
+    PMC_TRY(check_scan_health(ctx));
+    float ms = 0;
+    PMC_TRY_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (res) {
+        res->n_converged = hs->n_converged;
+        res->sweeps_total = hs->sweeps;
+        res->n_accept = prob->sampler == PMC_SAMPLER_ULA ? pl.n : hs->n_accept;
+        res->resid_inf = hs->resid_inf;
+        res->resid_l2 = sqrt(hs->resid_sq);
+        res->max_ratio = hs->max_ratio;
+        res->nonfinite = hs->nonfinite;
+        res->elapsed_ms = ms;
+        res->eval_ms = prof_eval_ms;
+        res->scan_ms = prof_scan_ms;
+        res->eval_steps = prof_steps;
+        if (res->sweeps_per_chain)
+            for (int c = 0; c < pl.n_chains; c++) res->sweeps_per_chain[c] = hc[c].sweeps;
+    }
+    if (res) res->n_floor = hs->n_floor;
+    if (hs->n_converged + hs->n_floor < pl.n_chains) {
+        set_error("pmc_solve: %d of %d chains not converged after %d sweeps (max ratio %g)",
+                  pl.n_chains - hs->n_converged, pl.n_chains, hs->sweeps, (double)hs->max_ratio);
+        return PMC_NOT_CONVERGED;
+    }
+    return PMC_OK;
+}
+
+pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_result *res)
+{
+    PMC_REQUIRE(ctx && p && p->target, "pmc_sample_sequential: NULL argument");
+    const DevTarget &t = p->target->t;
+    PMC_REQUIRE(p->sampler == PMC_SAMPLER_MALA || p->sampler == PMC_SAMPLER_ULA,
+                "pmc_sample_sequential: sampler must be MALA or ULA");
+    PMC_REQUIRE(p->n_chains >= 1, "pmc_sample_sequential: n_chains >= 1");
+    std::vector<int64_t> offs(p->n_chains + 1, 0);
+    if (p->offsets) {
+        PMC_REQUIRE(p->offsets[0] == 0, "pmc_sample_sequential: offsets[0] must be 0");
+        for (int c = 0; c < p->n_chains; c++) {
+            PMC_REQUIRE(p->offsets[c + 1] >= p->offsets[c], "offsets must be non-decreasing");
+            offs[c + 1] = p->offsets[c + 1];
+        }
+        PMC_REQUIRE(offs[p->n_chains] == p->n_steps, "offsets[n_chains] != n_steps");
+    } else {
+        PMC_REQUIRE(p->n_chains == 1, "pmc_sample_sequential: offsets required for n_chains > 1");
+        offs[1] = p->n_steps;
+    }
+    if (res) {
+        int32_t *spc = res->sweeps_per_chain;
+        memset(res, 0, sizeof(*res));
+        res->sweeps_per_chain = spc;
+    }
+    if (p->n_steps == 0) return PMC_OK;
+    PMC_REQUIRE(is_device_ptr(p->s0) && is_device_ptr(p->noise) && is_device_ptr(p->out_states),
+                "pmc_sample_sequential: s0, noise and out_states must be device pointers");
+    if (p->sampler == PMC_SAMPLER_MALA)
+        PMC_REQUIRE(is_device_ptr(p->uniforms), "pmc_sample_sequential: MALA needs device uniforms");
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    PMC_TRY(ensure_pool(ctx, sizeof(int64_t) * offs.size()));
+    int64_t *d_offs = (int64_t *)ctx->pool;
+    hipStream_t st = ctx->stream;
+    PMC_TRY_HIP(hipMemcpyAsync(d_offs, offs.data(), sizeof(int64_t) * offs.size(),
+                               hipMemcpyHostToDevice, st));
+    SeqArgs a;
+    a.n_chains = p->n_chains;
+    a.offsets = d_offs;
+    a.D = t.dim;
+    a.s0 = p->s0;
+    a.noise = p->noise;
+    a.unif = p->sampler == PMC_SAMPLER_MALA ? p->uniforms : nullptr;
+    a.out = p->out_states;
+    a.accept = p->out_accept;
+    a.gtilde = p->out_gtilde;
+    a.eps = p->step_size;
+    a.ula = p->sampler == PMC_SAMPLER_ULA;
+    PMC_TRY_HIP(hipEventRecord(ctx->ev0, st));
+    PMC_TRY(launch_sequential(ctx, t, a));
+    PMC_TRY_HIP(hipEventRecord(ctx->ev1, st));
+    PMC_TRY_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    PMC_TRY_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (res) {
+        res->elapsed_ms = ms;
+        res->n_converged = p->n_chains;
+    }
+    return PMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+"""GPU parity of HMC with parallel leapfrog (Appendix A.2 algorithm) against the
+FP64 oracle's sequential HMC on the same momenta and uniforms.
+
+The Metropolis test compares log U with H0 - HL, a difference of two FP32
+energies of size ~D; decisions whose oracle margin is below 1e-4 are treated
+as near-ties (reported and resynchronised)."""
+import numpy as np
+import pytest
+
+from conftest import oracle_target
+from parity import compare_with_resync, state_error
+from paper_2508_18413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV)
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_2508_18413_amd as pm
+    return pm
+
+
+@pytest.fixture(scope="module")
+def ctx(pm):
+    c = pm.Context(0)
+    yield c
+    c.close()
+
+
+def _run(pm, ctx, orc, prob, n_prop, parallel, **kw):
+    tg = oracle_target(prob.target)
+    g = pm.Target(ctx, prob.target)
+    mom, U = prob.momenta[:n_prop], prob.U[:n_prop]
+    r = pm.hmc_sample(ctx, g, prob.eps, prob.L, _t(prob.x0), _t(mom), _t(U),
+                      parallel_leapfrog=parallel, **kw)
+    acc = r["accept"].cpu().numpy()
+
+    def run_oracle(force):
+        o = orc.hmc_chain(tg, prob.eps, prob.L, prob.x0.astype(np.float64), mom, U, force=force)
+        return o["chain"][1:], o["accept"], o["logr"]
+
+    st, oacc, rep = compare_with_resync(run_oracle, acc, tie_band=1e-4)
+    err = state_error(r["chain"].cpu().numpy()[1:], st)
+    print(f"  parallel={parallel} {kw} err={err:.3e} acc={acc.mean():.3f} "
+          f"sweeps(median,max)=({np.median(r['sweeps']):.0f},{max(r['sweeps'])}) rep={rep}",
+          flush=True)
+    assert not [x for x in rep if x[2] == "failure"], rep
+    return r, err
+
+
+@pytest.mark.parametrize("variant", ["block2", "diag", "picard"])
+def test_hmc_parallel_leapfrog(pm, ctx, orc, variant):
+    print(f"hmc parallel leapfrog {variant}", flush=True)
+    prob = W.hmc_gaussian(seed=0, dim=100, L=64, eps=0.05, n_prop=2000)
+    r, err = _run(pm, ctx, orc, prob, 100, True, variant=variant, atol=1e-6, rtol=1e-6)
+    assert err <= 1e-5
+    assert all(1 <= s <= prob.L + 1 for s in r["sweeps"])
+
+
+def test_hmc_sequential_leapfrog(pm, ctx, orc):
+    print("hmc sequential leapfrog", flush=True)
+    prob = W.hmc_gaussian(seed=1, dim=100, L=64, eps=0.05, n_prop=2000)
+    r, err = _run(pm, ctx, orc, prob, 200, False)
+    assert err <= 1e-5
+
+
+def test_hmc_full_length_block2(pm, ctx, orc):
+    """All 2000 proposals of the D = 100, L = 64 workload."""
+    print("hmc full length block2", flush=True)
+    prob = W.hmc_gaussian(seed=0, dim=100, L=64, eps=0.05, n_prop=2000)
+    r, err = _run(pm, ctx, orc, prob, 2000, True, variant="block2", atol=1e-6, rtol=1e-6)
+    assert err <= 1e-5
+
+
+def test_hmc_unsupported_target(pm, ctx):
+    from paper_2508_18413_amd import _binding as B
+    ch = W.funnel_chain(T=10, dim=4)
+    g = pm.Target(ctx, ch.target)
+    with pytest.raises(B.PMCError) as e:
+        pm.hmc_sample(ctx, g, 0.1, 4, _t(np.zeros(4, np.float32)), _t(np.zeros((3, 4), np.float32)),
+                      _t(np.full(3, 0.5, np.float32)))
+    assert e.value.status == B.PMC_ERR_UNSUPPORTED

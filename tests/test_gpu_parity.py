@@ -1,0 +1,323 @@
+"""GPU parity of the parallel Newton path (through the C ABI) against the FP64
+oracle, on seeded synthetic inputs.
+
+Bars: FP64 state error <= 1e-10; FP32 state error <= 1e-5 (mixed
+absolute/relative per step); accept patterns identical except near-ties
+(|g~*| < 1e-6), which are reported and resynchronised.  Scans: relative
+error <= 1e-12 (FP64) / 2e-5 (FP32) against the sequential recursion.
+"""
+import numpy as np
+import pytest
+
+from conftest import oracle_burnin, oracle_target
+from parity import compare_with_resync, state_error
+from paper_2508_18413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _t(x, dtype=None):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_2508_18413_amd as pm
+    return pm
+
+
+@pytest.fixture(scope="module")
+def ctx(pm):
+    c = pm.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------- scans
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("T", [1, 63, 64, 65, 2047, 4096, 4097, 100003])
+def test_linrec_diag(ctx, pm, orc, dtype, T):
+    _say(f"linrec_diag dtype={dtype} T={T}")
+    rng = np.random.default_rng(T)
+    lanes = 3
+    a = rng.uniform(-0.98, 0.98, size=(lanes, T))
+    b = rng.normal(size=(lanes, T))
+    td = torch.float32 if dtype == "f32" else torch.float64
+    ga, gb = _t(a, td), _t(b, td)
+    out = pm.linrec_diag(ctx, ga, gb).cpu().numpy().astype(np.float64)
+    ref = orc.linrec_diag(ga.cpu().numpy().T, gb.cpu().numpy().T).T
+    tol = 2e-5 if dtype == "f32" else 1e-12
+    assert np.max(np.abs(out - ref)) <= tol * max(1.0, np.max(np.abs(ref)))
+
+
+def test_linrec_diag_exact_carries(ctx, pm):
+    """a = 1, b = 1: delta_t = t + 1, exact in FP32 below 2^24 -- every carry
+    across ~260 tiles must be exact; a = 0 returns b."""
+    _say("linrec_diag exact carries T=2^20+17")
+    T = (1 << 20) + 17
+    ones = torch.ones((2, T), device=DEV)
+    out = pm.linrec_diag(ctx, ones, ones)
+    ref = torch.arange(1, T + 1, device=DEV, dtype=torch.float32)
+    assert torch.equal(out[0], ref) and torch.equal(out[1], ref)
+    b = torch.randn((4, 5000), device=DEV)
+    assert torch.equal(pm.linrec_diag(ctx, torch.zeros_like(b), b), b)
+
+
+def test_linrec_diag_large(ctx, pm, orc):
+    _say("linrec_diag large T=2^20+17")
+    T = (1 << 20) + 17
+    rng = np.random.default_rng(5)
+    a = rng.uniform(-0.99, 0.99, size=(2, T)).astype(np.float32)
+    b = rng.normal(size=(2, T)).astype(np.float32)
+    out = pm.linrec_diag(ctx, _t(a), _t(b)).cpu().numpy().astype(np.float64)
+    ref = orc.linrec_diag(a.T, b.T).T
+    assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("T", [1, 1000, 5001])
+def test_linrec_block2(ctx, pm, orc, T):
+    _say(f"linrec_block2 T={T}")
+    rng = np.random.default_rng(T + 7)
+    lanes = 5
+    coef = rng.uniform(-0.6, 0.6, size=(4, lanes, T)).astype(np.float32)
+    rhs = rng.normal(size=(2, lanes, T)).astype(np.float32)
+    out = pm.linrec_block2(ctx, _t(coef), _t(rhs)).cpu().numpy().astype(np.float64)
+    c = coef.astype(np.float64)
+    r = rhs.astype(np.float64)
+    p, q = orc.linrec_block2(c[0].T, c[1].T, c[2].T, c[3].T, r[0].T, r[1].T)
+    ref = np.stack([p.T, q.T])
+    assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+@pytest.mark.parametrize("T", [1, 1000, 3001])
+def test_linrec_dense_f64(ctx, pm, orc, D, T):
+    _say(f"linrec_dense f64 D={D} T={T}")
+    rng = np.random.default_rng(D * 1000 + T)
+    A = rng.normal(size=(T, D, D)) / (1.2 * D)
+    b = rng.normal(size=(T, D))
+    out = pm.linrec_dense(ctx, _t(A), _t(b)).cpu().numpy()
+    ref = orc.linrec_dense(A, b)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+# -------------------------------------------------------- Newton solves
+
+def _banana(orc, T=1024, seed=0):
+    ch = W.banana_chain(T=T, seed=seed)
+    tg = oracle_target(ch.target)
+    return ch, tg
+
+
+@pytest.mark.parametrize("variant,kw", [("diag", {}), ("picard", {}),
+                                        ("dense", dict(clip=1.0, clip_inf_norm=True)),
+                                        ("dense", {})])
+def test_banana_fp64(ctx, pm, orc, variant, kw):
+    _say(f"banana fp64 variant={variant} {kw}")
+    ch, tg = _banana(orc)
+    g = pm.Target(ctx, ch.target, dtype=torch.float64)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant=variant,
+                 max_iter=ch.T + 1, **kw)
+    _say(f"  sweeps={r.sweeps} status={r.status} ratio={r.max_ratio:.3g}")
+    assert r.status == 0
+    gacc = r.accept.cpu().numpy()
+    st, acc, rep = compare_with_resync(
+        lambda f: orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, ch.u, force=f), gacc)
+    assert not [x for x in rep if x[2] == "failure"], rep
+    assert state_error(r.states.cpu().numpy(), st) <= 1e-10
+    assert r.n_accept == int(acc.sum())
+
+
+def test_banana_golden_fixture(ctx, pm):
+    """The first 32 steps against the stored oracle fixture (tests/golden)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "banana_mala_t32.json")) as f:
+        gd = json.load(f)
+    g = pm.Target(ctx, W.banana_target(), dtype=torch.float64)
+    r = pm.solve(ctx, g, gd["eps"], _t(gd["x0"], torch.float64), _t(gd["xi"], torch.float64),
+                 _t(gd["u"], torch.float64), variant="diag", max_iter=40)
+    assert state_error(r.states.cpu().numpy(), np.array(gd["states"])) <= 1e-10
+    assert np.array_equal(r.accept.cpu().numpy(), np.array(gd["accept"]))
+
+
+def test_causal_exactness_trace(ctx, pm, orc):
+    """After sweep i the first i states equal the sequential trace (FP64)."""
+    _say("causal exactness trace")
+    ch, tg = _banana(orc, T=48, seed=4)
+    g = pm.Target(ctx, ch.target, dtype=torch.float64)
+    for variant in ("diag", "picard"):
+        r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant=variant, max_iter=49,
+                     want_trace=True)
+        ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, ch.u)
+        tr = r.trace.cpu().numpy()
+        for i in range(r.sweeps):
+            k = i + 1
+            assert np.max(np.abs(tr[i, :k] - ref[:k])) <= 1e-13, (variant, i)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ula_gaussian_one_solve(ctx, pm, orc, dtype):
+    """ULA on a Gaussian is affine: the first dense Newton solve is already the
+    chain; Algorithm 1 stops after the confirming sweep."""
+    _say(f"ula gaussian one solve {dtype}")
+    td = torch.float64 if dtype == "f64" else torch.float32
+    npd = np.float64 if dtype == "f64" else np.float32
+    ch = W.gaussian_chain(3000, seed=2, eps=0.2, dim=4, dtype=npd, lam_lo=0.3)
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target, dtype=td)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0, td), _t(ch.xi, td), None, sampler="ula",
+                 variant="dense", max_iter=5, want_trace=True)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, None, ula=True)
+    first = r.trace[0].cpu().numpy()
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert state_error(first, ref) <= tol
+    assert r.sweeps == 2 and r.status == 0
+
+
+def _logreg_case(orc, T, eps, seed=0):
+    ch = W.logreg_chain(T=T, seed=seed, eps=eps)
+    tg = oracle_target(ch.target)
+    s0 = oracle_burnin(tg, ch).astype(np.float32)
+    return ch, tg, s0
+
+
+def _check_mala(orc, tg, ch, s0, got_states, got_acc, tol=1e-5):
+    x0 = s0.astype(np.float64)
+    st, acc, rep = compare_with_resync(
+        lambda f: orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u, force=f), got_acc)
+    err = state_error(got_states, st)
+    _say(f"  state_error={err:.3e} mismatches={rep}")
+    assert not [x for x in rep if x[2] == "failure"], rep
+    assert err <= tol
+    return err, rep
+
+
+@pytest.mark.parametrize("T", [4096, 5000])
+def test_logreg_diag_fp32(ctx, pm, orc, T):
+    _say(f"logreg diag fp32 T={T}")
+    ch, tg, s0 = _logreg_case(orc, T, 0.0015)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=T + 1)
+    _say(f"  sweeps={r.sweeps} status={r.status} ratio={r.max_ratio:.3g}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+def test_logreg_sequential_fp32(ctx, pm, orc):
+    _say("logreg sequential fp32")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015)
+    g = pm.Target(ctx, ch.target)
+    r = pm.sample_sequential(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u))
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+@pytest.mark.parametrize("variant", ["diag", "picard"])
+def test_funnel_fp32(ctx, pm, orc, variant):
+    _say(f"funnel fp32 {variant}")
+    ch = W.funnel_chain(T=2048, seed=1)
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant=variant,
+                 max_iter=ch.T + 1)
+    _say(f"  sweeps={r.sweeps} status={r.status}")
+    _check_mala(orc, tg, ch, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+@pytest.mark.parametrize("kind", ["banana", "funnel"])
+def test_surrogate_gate(ctx, pm, orc, kind):
+    """The stop-gradient Jacobian changes sweep counts, never the fixed point."""
+    _say(f"surrogate gate {kind}")
+    if kind == "banana":
+        ch = W.banana_chain(1024, seed=2)
+        td, x0 = torch.float64, ch.x0
+        tol = 1e-10
+    else:
+        ch = W.funnel_chain(T=1024, seed=3)
+        td, x0 = torch.float32, ch.x0
+        tol = 1e-5
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target, dtype=td)
+    r = pm.solve(ctx, g, ch.eps, _t(x0, td), _t(ch.xi, td), _t(ch.u, td), variant="diag",
+                 gate="surrogate", max_iter=ch.T + 1)
+    _say(f"  sweeps={r.sweeps}")
+    _check_mala(orc, tg, ch, np.asarray(x0), r.states.cpu().numpy(), r.accept.cpu().numpy(), tol)
+
+
+def test_batched_uneven_chains(ctx, pm, orc):
+    _say("batched uneven chains")
+    b = W.logreg_batch(seed=3, n_chains=6, lo=1, hi=9000, eps=0.0015)
+    lens = np.diff(b.offsets)
+    tg = oracle_target(b.target)
+    s0 = np.stack([oracle_burnin(tg, _as_chain(b, c)) for c in range(b.n_chains)]).astype(np.float32)
+    g = pm.Target(ctx, b.target)
+    r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets),
+                 variant="diag", max_iter=int(lens.max()) + 1)
+    _say(f"  lens={lens.tolist()} sweeps/chain={r.sweeps_per_chain}")
+    assert r.status == 0 and r.n_converged == b.n_chains
+    st = r.states.cpu().numpy()
+    acc = r.accept.cpu().numpy()
+    for c in range(b.n_chains):
+        o0, o1 = b.offsets[c], b.offsets[c + 1]
+        ch = _as_chain(b, c)
+        _check_mala(orc, tg, ch, s0[c], st[o0:o1], acc[o0:o1])
+
+
+def _as_chain(b, c):
+    o0, o1 = b.offsets[c], b.offsets[c + 1]
+    return W.Chain(target=b.target, eps=b.eps, x0=b.x0[c], xi=b.xi[o0:o1], u=b.u[o0:o1],
+                   burn_xi=b.burn_xi[c], burn_u=b.burn_u[c])
+
+
+def test_graph_mode_matches_eager(ctx, pm):
+    _say("graph mode vs eager")
+    ch = W.funnel_chain(T=3000, seed=5)
+    g = pm.Target(ctx, ch.target)
+    args = (ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u))
+    r0 = pm.solve(*args, variant="diag", max_iter=3001)
+    for m in (1, 3, 8):
+        r1 = pm.solve(*args, variant="diag", max_iter=3001, graph_sweeps=m)
+        assert torch.equal(r0.states, r1.states), m
+        assert torch.equal(r0.accept, r1.accept), m
+        assert r1.sweeps == r0.sweeps
+
+
+def test_sliding_window_prefix_skip(ctx, pm, orc):
+    _say("sliding window")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015, seed=1)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=4097,
+                 skip_converged_prefix=True)
+    _say(f"  sweeps={r.sweeps} status={r.status}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+def test_invalid_arguments(ctx, pm):
+    from paper_2508_18413_amd import _binding as B
+    ch = W.funnel_chain(T=100, seed=1, dim=8)
+    g = pm.Target(ctx, ch.target)
+    with pytest.raises(B.PMCError) as e:
+        pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), offsets=[0, 50])
+    assert e.value.status == B.PMC_ERR_INVALID
+    with pytest.raises(B.PMCError) as e:
+        pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="block2")
+    assert e.value.status == B.PMC_ERR_UNSUPPORTED
+
+
+def test_empty_and_length_one(ctx, pm, orc):
+    ch = W.banana_chain(1, seed=9)
+    g = pm.Target(ctx, ch.target, dtype=torch.float64)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag")
+    ref, _, _ = orc.mala_chain(orc.Target(orc.BANANA, 2), ch.eps, ch.x0, ch.xi, ch.u)
+    assert state_error(r.states.cpu().numpy(), ref) <= 1e-12 and r.sweeps == 2
+    e = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi[:0].reshape(0, 2)), _t(ch.u[:0]))
+    assert e.states.shape == (0, 2) and e.status == 0
