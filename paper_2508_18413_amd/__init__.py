@@ -14,7 +14,7 @@ from dataclasses import dataclass
 from . import _binding as B
 
 __all__ = ["Context", "Target", "solve", "sample_sequential", "linrec_diag", "linrec_block2",
-           "linrec_dense", "hmc_sample", "adjoint", "autotune", "B"]
+           "linrec_dense", "hmc_sample", "adjoint", "autotune", "ParallelMALA", "B"]
 
 VARIANTS = {"dense": B.PMC_DEER_DENSE, "diag": B.PMC_QDEER_DIAG, "block2": B.PMC_QDEER_BLOCK2,
             "picard": B.PMC_PICARD}
@@ -300,3 +300,40 @@ def autotune(ctx: Context, target: Target, eps, s0, noise, uniforms, cache_path=
     B.check(B.lib().pmc_autotune(ctx.h, C.byref(p), C.byref(o),
                                  cache_path.encode() if cache_path else None))
     del keep
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class ParallelMALA(torch.autograd.Function):
+        """states = ParallelMALA.apply(theta, eps, ctx, spec, s0, noise, uniforms, solve_kw).
+
+        Forward: pmc_solve of the MALA chain on the target `spec` with its
+        parameter theta (the funnel's log-scale) and step size eps.  Backward:
+        pmc_adjoint, the reverse scan over transposed step Jacobians at the
+        converged trajectory (frozen accept gate), returning dL/dtheta and
+        dL/deps for the incoming dL/dstates."""
+
+        @staticmethod
+        def forward(fctx, theta, eps, ctx, spec, s0, noise, uniforms, solve_kw):
+            tg = Target(ctx, dict(spec, theta=float(theta)))
+            r = solve(ctx, tg, float(eps), s0, noise, uniforms, **(solve_kw or {}))
+            fctx.save_for_backward(r.states, r.accept)
+            fctx.keep = (ctx, tg, float(eps), s0, noise, uniforms, theta.dtype, theta.device)
+            return r.states
+
+        @staticmethod
+        def backward(fctx, g):
+            states, accept = fctx.saved_tensors
+            ctx, tg, eps, s0, noise, uniforms, dt, dev = fctx.keep
+            dth, deps = adjoint(ctx, tg, eps, s0, noise, uniforms, states, accept, g.contiguous())
+            return (torch.tensor(dth, dtype=dt, device=dev), torch.tensor(deps, dtype=dt, device=dev),
+                    None, None, None, None, None, None)
+
+    return ParallelMALA
+
+
+def __getattr__(name):
+    if name == "ParallelMALA":
+        return _autograd_function()
+    raise AttributeError(name)

@@ -47,20 +47,19 @@ pmc_status pmc_linrec_dense(pmc_context *ctx, pmc_dtype dtype, pmc_jac_prec jac_
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     if (dtype == PMC_F64) {
         PMC_TRY(launch_linrec_dense_small(ctx, D, T, (const double *)A, (const double *)b, (double *)out));
+    } else if (dtype == PMC_F32) {
+        if (D > 32) {
+            set_error("pmc_linrec_dense: F32 matrix-core path supports D <= 32 (got %d)", D);
+            return PMC_ERR_UNSUPPORTED;
+        }
+        PMC_TRY(launch_linrec_dense_mfma(ctx, jac_prec == PMC_JAC_BF16, D, T, (const float *)A,
+                                         (const float *)b, (float *)out));
     } else {
-        (void)jac_prec;
-        set_error("pmc_linrec_dense: F32 matrix-core path not built");
-        return PMC_ERR_UNSUPPORTED;
+        set_error("pmc_linrec_dense: bad dtype");
+        return PMC_ERR_INVALID;
     }
     PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
     return check_scan_health(ctx);
-}
-
-pmc_status pmc_adjoint(pmc_context *ctx, const pmc_problem *prob, const void *states,
-                       const uint8_t *accept, const void *dF_ds, double *dF_dtheta, double *dF_dstep)
-{
-    set_error("pmc_adjoint: not built");
-    return PMC_ERR_UNSUPPORTED;
 }
 
 pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,

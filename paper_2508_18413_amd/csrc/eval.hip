@@ -34,25 +34,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 }
 
 template <typename R>
-__device__ __forceinline__ R sigmoid(R z)
-{
-    if (z >= R(0)) return R(1) / (R(1) + exp(-z));
-    const R e = exp(z);
-    return e / (R(1) + e);
-}
-
-// softplus(z + dz) - softplus(z) given s = sigmoid(z):  log1p(s * expm1(dz))
-template <typename R>
-__device__ __forceinline__ R softplus_diff(R z, R dz, R s)
-{
-    if (dz < R(30)) return log1p(s * expm1(dz));
-    const R zt = z + dz;
-    const R spt = zt > R(0) ? zt + log1p(exp(-zt)) : log1p(exp(zt));
-    const R sp = z > R(0) ? z + log1p(exp(-z)) : log1p(exp(z));
-    return spt - sp;
-}
-
-template <typename R>
 __device__ __forceinline__ R clampj(R v, double damping, double clip, int clip_inf)
 {
     v = (R)damping * v;
@@ -214,143 +195,6 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
     }
 }
 
-// ------------------------------------------- logistic regression eval
-// One workgroup = 64 consecutive steps (one per lane) x NW waves; wave w
-// handles data rows [w N/NW, (w+1) N/NW) with the row address uniform across
-// the wave (scalar loads of X), and partial sums meet in LDS.
-template <int DM, int NW>
-__global__ void __launch_bounds__(64 * NW)
-k_eval_logreg(EvalArgs a, const float *__restrict__ X, const float *__restrict__ y, int N,
-              float prior_prec)
-{
-    __shared__ float s_red[NW][2 * DM + 1][64];
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const SegTile tl = a.tiles[blockIdx.x];
-    const ChainStatus &cs = a.chains[tl.chain];
-    if (!cs.active || tl.start + tl.len <= cs.win_start) return;
-    const int64_t t = tl.start + lane;
-    const bool valid = lane < tl.len && t >= cs.win_start;
-    const int64_t tt = valid ? t : tl.start;
-    const int D = a.D;
-    const int64_t ld = a.ld;
-    const bool head = (tt == a.offsets[tl.chain]);
-    const float *S = (const float *)a.S;
-
-    float x[DM], xi[DM];
-#pragma unroll
-    for (int d = 0; d < DM; d++) {
-        if (d < D) {
-            x[d] = head ? ((const float *)a.s0)[(size_t)tl.chain * D + d] : S[(size_t)d * ld + tt - 1];
-            xi[d] = ((const float *)a.noise)[(size_t)tt * D + d];
-        } else {
-            x[d] = 0.f;
-            xi[d] = 0.f;
-        }
-    }
-    const int per = (N + NW - 1) / NW;
-    const int n0 = w * per, n1 = min(N, n0 + per);
-
-    // pass 1: gradient of the log-likelihood at x
-    float gp[DM];
-#pragma unroll
-    for (int d = 0; d < DM; d++) gp[d] = 0.f;
-    for (int n = n0; n < n1; n++) {
-        const float *xn = X + (size_t)n * DM;
-        float z = 0.f;
-#pragma unroll
-        for (int d = 0; d < DM; d++) z = fmaf(xn[d], x[d], z);
-        const float r = y[n] - sigmoid(z);
-#pragma unroll
-        for (int d = 0; d < DM; d++) gp[d] = fmaf(r, xn[d], gp[d]);
-    }
-#pragma unroll
-    for (int d = 0; d < DM; d++) s_red[w][d][lane] = gp[d];
-    __syncthreads();
-    const float eps = (float)a.eps;
-    const float c = sqrtf(2.f * eps);
-    float g[DM], dl[DM];
-#pragma unroll
-    for (int d = 0; d < DM; d++) {
-        float s = 0.f;
-#pragma unroll
-        for (int v = 0; v < NW; v++) s += s_red[v][d][lane];
-        g[d] = s - prior_prec * x[d];
-        dl[d] = d < D ? fmaf(eps, g[d], c * xi[d]) : 0.f;
-    }
-    __syncthreads();
-
-    // pass 2: gradient at x~, Hessian diagonal at x, log-likelihood difference
-    float gtp[DM], hp[DM], dll = 0.f;
-#pragma unroll
-    for (int d = 0; d < DM; d++) gtp[d] = hp[d] = 0.f;
-    for (int n = n0; n < n1; n++) {
-        const float *xn = X + (size_t)n * DM;
-        float z = 0.f, dz = 0.f;
-#pragma unroll
-        for (int d = 0; d < DM; d++) {
-            z = fmaf(xn[d], x[d], z);
-            dz = fmaf(xn[d], dl[d], dz);
-        }
-        const float s = sigmoid(z), st = sigmoid(z + dz);
-        const float yn = y[n];
-        const float r = yn - st, wv = s * (1.f - s);
-        dll += yn * dz - softplus_diff(z, dz, s);
-#pragma unroll
-        for (int d = 0; d < DM; d++) {
-            gtp[d] = fmaf(r, xn[d], gtp[d]);
-            hp[d] = fmaf(wv * xn[d], xn[d], hp[d]);
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < DM; d++) {
-        s_red[w][d][lane] = gtp[d];
-        s_red[w][DM + d][lane] = hp[d];
-    }
-    s_red[w][2 * DM][lane] = dll;
-    __syncthreads();
-    if (w != 0 || !valid) return;
-
-    float sn = 0.f, sx = 0.f, dpr = 0.f, dsum = 0.f;
-    float hd[DM], xt[DM];
-#pragma unroll
-    for (int d = 0; d < DM; d++) {
-        float a1 = 0.f, a2 = 0.f;
-#pragma unroll
-        for (int v = 0; v < NW; v++) {
-            a1 += s_red[v][d][lane];
-            a2 += s_red[v][DM + d][lane];
-        }
-        xt[d] = x[d] + dl[d];
-        const float gtd = a1 - prior_prec * xt[d];
-        hd[d] = -a2 - prior_prec;
-        const float s = g[d] + gtd;
-        sn = fmaf(s, s, sn);
-        sx = fmaf(xi[d], s, sx);
-        dpr = fmaf(dl[d], xt[d] + x[d], dpr);
-    }
-#pragma unroll
-    for (int v = 0; v < NW; v++) dsum += s_red[v][2 * DM][lane];
-    const float ell = dsum - 0.5f * prior_prec * dpr - 0.25f * eps * sn - sqrtf(0.5f * eps) * sx;
-    const float la = ell < 0.f ? ell : 0.f;
-    const float gate = la - logf(((const float *)a.unif)[t]);
-    int acc = gate > 0.f;
-    if (!(ell == ell)) acc = 0;
-    float *F = (float *)a.F;
-#pragma unroll
-    for (int d = 0; d < DM; d++)
-        if (d < D) F[(size_t)d * ld + t] = acc ? xt[d] : x[d];
-    if (a.accept) a.accept[t] = (uint8_t)acc;
-    if (a.gtilde) a.gtilde[t] = gate;
-    if (a.jmode == JM_DIAG) {
-        float *J = (float *)a.J;
-        const float ea = acc ? eps : 0.f;
-#pragma unroll
-        for (int d = 0; d < DM; d++)
-            if (d < D) J[(size_t)d * ld + t] = clampj(fmaf(ea, hd[d], 1.f), a.damping, a.clip, 0);
-    }
-}
-
 template <class Tg, typename R>
 pmc_status eval_small(pmc_context *ctx, const EvalArgs &a, const Tg &tg)
 {
@@ -377,27 +221,9 @@ pmc_status eval_dm(pmc_context *ctx, const EvalArgs &a, int D, Extra... ex)
     return PMC_ERR_UNSUPPORTED;
 }
 
-template <int NW>
-pmc_status eval_logreg_nw(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
-{
-    const float pp = (float)(1.0 / t.prior_var);
-    dim3 grid(a.n_tiles), block(64 * NW);
-    const float *X = (const float *)t.X, *y = (const float *)t.y;
-    switch (t.ldx) {
-    case 4: hipLaunchKernelGGL((k_eval_logreg<4, NW>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-    case 8: hipLaunchKernelGGL((k_eval_logreg<8, NW>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-    case 16: hipLaunchKernelGGL((k_eval_logreg<16, NW>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-    case 25: hipLaunchKernelGGL((k_eval_logreg<25, NW>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-    case 32: hipLaunchKernelGGL((k_eval_logreg<32, NW>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-    default: set_error("logreg: unsupported padded dimension %d", t.ldx); return PMC_ERR_UNSUPPORTED;
-    }
-    PMC_TRY_HIP(hipGetLastError());
-    return PMC_OK;
-}
-
 }  // namespace
 
-int eval_tile_steps(const DevTarget &tg) { return tg.kind == PMC_TARGET_LOGREG ? 64 : 256; }
+int eval_tile_steps(const DevTarget &tg) { return tg.kind == PMC_TARGET_LOGREG ? 32 : 256; }
 
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
 {
@@ -427,7 +253,7 @@ pmc_status launch_eval(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
             set_error("logistic regression eval supports the frozen gate only");
             return PMC_ERR_UNSUPPORTED;
         }
-        return eval_logreg_nw<4>(ctx, t, a);
+        return launch_eval_logreg(ctx, t, a);
     }
     set_error("unknown target kind %d", (int)t.kind);
     return PMC_ERR_INVALID;

@@ -111,6 +111,9 @@ struct DevTarget {
     void *prec = nullptr;  // [D*D]
     void *X = nullptr;     // [n_data * ldx], zero padded
     void *y = nullptr;     // [n_data]
+    // logreg matrix-core fragments (per 32-row tile)
+    int nr = 0, mk = 0;
+    void *xa = nullptr, *xta = nullptr, *x2ta = nullptr, *ypad = nullptr;
 };
 
 }  // namespace pmc
@@ -230,6 +233,8 @@ struct EvalArgs {
     const pmc::DevTarget *tg; // host copy of the target description (fields passed by value)
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
+pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
+pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
 // Tile length the eval kernel for this target expects.
 int eval_tile_steps(const DevTarget &tg);
 
@@ -247,6 +252,19 @@ struct SeqArgs {
     int ula;
 };
 pmc_status launch_sequential(pmc_context *ctx, const DevTarget &tg, const SeqArgs &a);
+
+// Dense DEER scan on matrix cores (D <= 32, F32 states; J in the BF16 or F32
+// fragment layout written by the eval kernels).  Single sequence of n steps.
+size_t dense_mfma_ws_bytes(int64_t n);
+int dense_mfma_unit();
+pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
+                                    float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
+                                    double atol, double rtol, float *trace, void *ws);
+pmc_status launch_linrec_dense_mfma(pmc_context *ctx, int bf16, int D, int64_t T, const float *A,
+                                    const float *b, float *out);
+// Same on J already in the fragment layout; ws: dense_mfma_ws_bytes(T) bytes.
+pmc_status launch_linrec_dense_mfma_packed(pmc_context *ctx, int bf16, int D, int64_t T,
+                                           const void *Jf, const float *b, float *out, void *ws);
 
 // Chain status fold (one launch per sweep).
 struct StatusArgs {

@@ -256,7 +256,7 @@ pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *d, pmc_tar
         PMC_REQUIRE(d->dim >= 2 && d->dim <= 32, "funnel target: 2 <= dim <= 32 (got %d)", d->dim);
         break;
     case PMC_TARGET_GAUSSIAN: {
-        PMC_REQUIRE(d->dim <= 32, "gaussian target: dim <= 32 (got %d)", d->dim);
+        PMC_REQUIRE(d->dim <= 1024, "gaussian target: dim <= 1024 (got %d)", d->dim);
         PMC_REQUIRE(is_device_ptr(d->mean) && is_device_ptr(d->prec),
                     "gaussian target: mean and prec must be device pointers");
         PMC_TRY_HIP(hipMalloc(&t.mean, es * d->dim));
@@ -291,6 +291,7 @@ pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *d, pmc_tar
                                      hipMemcpyDeviceToDevice, ctx->stream));
         PMC_TRY_HIP(hipMemcpyAsync(t.y, d->y, 4 * (size_t)d->n_data, hipMemcpyDeviceToDevice,
                                    ctx->stream));
+        PMC_TRY(logreg_build_frags(ctx, t));
         break;
     }
     default:
@@ -313,6 +314,8 @@ pmc_status pmc_target_destroy(pmc_target *tgt)
     if (tgt->t.prec) (void)hipFree(tgt->t.prec);
     if (tgt->t.X) (void)hipFree(tgt->t.X);
     if (tgt->t.y) (void)hipFree(tgt->t.y);
+    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad})
+        if (q) (void)hipFree(q);
     delete tgt;
     return PMC_OK;
 }

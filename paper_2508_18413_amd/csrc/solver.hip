@@ -35,7 +35,7 @@ struct Plan {
     std::vector<int64_t> offs;
     std::vector<SegTile> etiles, stiles;
     std::vector<int32_t> ctb;
-    size_t o_S, o_F, o_J, o_acc, o_gt, o_etiles, o_stiles, o_ctb, o_offs, o_part, o_chains,
+    size_t o_S, o_F, o_J, o_hier, o_acc, o_gt, o_etiles, o_stiles, o_ctb, o_offs, o_part, o_chains,
         o_global, total;
     int max_iter;
 };
@@ -97,22 +97,38 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         if (p->init_guess)
             PMC_REQUIRE(is_device_ptr(p->init_guess), "pmc_solve: init_guess must be a device pointer");
     }
+    if (t.kind == PMC_TARGET_GAUSSIAN && pl.D > 32) {
+        set_error("pmc_solve: per-step Gaussian evaluation supports D <= 32 (got %d)", pl.D);
+        return PMC_ERR_UNSUPPORTED;
+    }
     pl.variant = o->variant;
     pl.n_lanes = pl.D;
     switch (o->variant) {
     case PMC_QDEER_DIAG: pl.jmode = JM_DIAG; break;
     case PMC_PICARD: pl.jmode = JM_NONE; break;
     case PMC_DEER_DENSE:
-        if (pl.D > 4) {
-            set_error("pmc_solve: dense DEER with D = %d needs the matrix-core scan (D <= 4 here)", pl.D);
-            return PMC_ERR_UNSUPPORTED;
-        }
         if (t.kind == PMC_TARGET_LOGREG) {
             set_error("pmc_solve: dense DEER on logistic regression is not built");
             return PMC_ERR_UNSUPPORTED;
         }
-        pl.jmode = JM_DENSE_ROW;
         pl.n_lanes = 1;
+        if (pl.dt == PMC_F64 || (pl.D <= 4 && o->jac_prec == PMC_JAC_F32)) {
+            if (pl.D > 4) {
+                set_error("pmc_solve: FP64 dense DEER supports D <= 4 (got %d)", pl.D);
+                return PMC_ERR_UNSUPPORTED;
+            }
+            pl.jmode = JM_DENSE_ROW;
+        } else {
+            if (pl.D > 32) {
+                set_error("pmc_solve: matrix-core dense DEER supports D <= 32 (got %d)", pl.D);
+                return PMC_ERR_UNSUPPORTED;
+            }
+            if (p->n_chains != 1) {
+                set_error("pmc_solve: matrix-core dense DEER solves one chain per call");
+                return PMC_ERR_UNSUPPORTED;
+            }
+            pl.jmode = o->jac_prec == PMC_JAC_BF16 ? JM_DENSE_BF16 : JM_DENSE_F32;
+        }
         break;
     case PMC_QDEER_BLOCK2:
         set_error("pmc_solve: block quasi-DEER applies to leapfrog integration (pmc_hmc_sample)");
@@ -129,7 +145,11 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     }
     PMC_REQUIRE(!(o->graph_sweeps > 0 && o->trace_out), "pmc_solve: trace_out needs graph_sweeps = 0");
 
-    if (pl.jmode == JM_DENSE_ROW) {
+    if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) {
+        pl.scan_items = 1;
+        pl.scan_block = 256;
+        pl.C_scan = dense_mfma_unit();
+    } else if (pl.jmode == JM_DENSE_ROW) {
         pl.scan_items = pl.D == 2 ? 4 : 2;
         pl.scan_block = 256;
         pl.C_scan = 256 * pl.scan_items;
@@ -165,9 +185,13 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     case JM_DIAG:
     case JM_NONE: jb = plane * pl.D; break;
     case JM_DENSE_ROW: jb = (size_t)pl.n * pl.D * pl.D * pl.es; break;
+    case JM_DENSE_BF16: jb = (size_t)pl.n * 2048; break;
+    case JM_DENSE_F32: jb = (size_t)pl.n * 4096; break;
     default: jb = 0;
     }
     pl.o_J = take(std::max<size_t>(jb, 256));
+    pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? dense_mfma_ws_bytes(pl.n)
+                                                                         : 256);
     pl.o_acc = take(std::max<int64_t>(pl.n, 1));
     pl.o_gt = take(4 * std::max<int64_t>(pl.n, 1));
     pl.o_etiles = take(sizeof(SegTile) * std::max<size_t>(pl.etiles.size(), 1));
@@ -185,6 +209,7 @@ struct Sweep {
     EvalArgs ea;
     NewtonScanArgs sa;
     StatusArgs st;
+    void *hier;  // matrix-core scan hierarchy workspace
 };
 
 pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, bool prof = false)
@@ -192,7 +217,11 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, bool pro
     if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[0], ctx->stream));
     PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
     if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[1], ctx->stream));
-    if (pl.jmode == JM_DENSE_ROW)
+    if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
+        PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
+                                         (float *)sw.sa.S, sw.sa.ld, pl.D, pl.n, sw.sa.partials,
+                                         sw.sa.atol, sw.sa.rtol, nullptr, sw.hier));
+    else if (pl.jmode == JM_DENSE_ROW)
         PMC_TRY(launch_newton_scan_dense_small(ctx, pl.dt, pl.D, sw.sa));
     else
         PMC_TRY(launch_newton_scan_diag(ctx, pl.dt, sw.sa, pl.scan_items, pl.scan_block));
@@ -304,6 +333,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
         PMC_TRY(broadcast_s0(ctx, pl.dt, prob->s0, d_offs, pl.n_chains, S, pl.n, pl.D, pl.ld));
 
     Sweep sw;
+    sw.hier = ws + pl.o_hier;
     EvalArgs &ea = sw.ea;
     ea.tiles = d_et;
     ea.n_tiles = (int)pl.etiles.size();

@@ -37,6 +37,7 @@ struct Banana {
         h[0] = hess(x, 0, 0);
         h[1] = R(-1);
     }
+    __device__ void dgrad_dtheta(const R *, R *o) const { o[0] = o[1] = R(0); }
     __device__ void hvp(const R *x, const R *v, R *o) const
     {
         const R h00 = hess(x, 0, 0), h01 = R(2) * x[0];
@@ -77,6 +78,11 @@ struct Gaussian {
         }
     }
     __device__ R hess(const R *, int i, int j) const { return -prec[i * D + j]; }
+    __device__ void dgrad_dtheta(const R *, R *o) const
+    {
+#pragma unroll
+        for (int i = 0; i < DM; i++) o[i] = R(0);
+    }
     __device__ void hess_diag(const R *, R *h) const
     {
 #pragma unroll
@@ -132,6 +138,13 @@ struct Funnel {
         if (i == 0) return e * x[j];
         if (j == 0) return e * x[i];
         return i == j ? -e : R(0);
+    }
+    // d/dtheta of grad log p: only the first coordinate depends on theta
+    __device__ void dgrad_dtheta(const R *x, R *o) const
+    {
+        o[0] = R(2) * x[0] * dexp<R>(R(-2) * theta);
+#pragma unroll
+        for (int d = 1; d < DM; d++) o[d] = R(0);
     }
     __device__ void hess_diag(const R *x, R *h) const
     {

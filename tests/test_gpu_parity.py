@@ -321,3 +321,48 @@ def test_empty_and_length_one(ctx, pm, orc):
     assert state_error(r.states.cpu().numpy(), ref) <= 1e-12 and r.sweeps == 2
     e = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi[:0].reshape(0, 2)), _t(ch.u[:0]))
     assert e.states.shape == (0, 2) and e.status == 0
+
+
+# ------------------------------------------------ matrix-core dense DEER
+
+@pytest.mark.parametrize("jac", ["f32", "bf16"])
+@pytest.mark.parametrize("D,T", [(32, 1), (32, 31), (32, 33), (25, 1000), (7, 4097), (32, 40000)])
+def test_linrec_dense_mfma(ctx, pm, orc, jac, D, T):
+    """F32 compositions match the sequential recursion to FP32 accuracy; BF16
+    compositions (one solve, no refinement) to the BF16 product bound."""
+    _say(f"linrec_dense mfma {jac} D={D} T={T}")
+    rng = np.random.default_rng(D * 7 + T)
+    A = (rng.normal(size=(T, D, D)) / (1.6 * np.sqrt(D))).astype(np.float32)
+    b = rng.normal(size=(T, D)).astype(np.float32)
+    out = pm.linrec_dense(ctx, _t(A), _t(b), jac_prec=jac).cpu().numpy().astype(np.float64)
+    ref = orc.linrec_dense(A.astype(np.float64), b.astype(np.float64))
+    rel = np.max(np.abs(out - ref)) / max(1.0, np.max(np.abs(ref)))
+    _say(f"  rel={rel:.3e}")
+    assert rel <= (2e-5 if jac == "f32" else 4e-2)
+
+
+@pytest.mark.parametrize("jac", ["f32", "bf16"])
+def test_funnel_dense_deer(ctx, pm, orc, jac):
+    _say(f"funnel dense DEER {jac}")
+    ch = W.funnel_chain(T=4096, seed=1)
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="dense", jac_prec=jac,
+                 max_iter=ch.T + 1)
+    rd = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=ch.T + 1)
+    _say(f"  dense sweeps={r.sweeps} (diag {rd.sweeps}) status={r.status} floor={r.n_floor}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+def test_ula_gaussian_one_solve_mfma(ctx, pm, orc):
+    """Affine f: the first matrix-core (F32) dense solve already gives the chain."""
+    _say("ula gaussian one solve mfma D=16")
+    ch = W.gaussian_chain(5000, seed=6, eps=0.2, dim=16, dtype=np.float32, lam_lo=0.3)
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), None, sampler="ula", variant="dense",
+                 jac_prec="f32", max_iter=5, want_trace=True)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, None, ula=True)
+    assert state_error(r.trace[0].cpu().numpy(), ref) <= 1e-5
+    assert r.sweeps <= 3
