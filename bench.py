@@ -40,6 +40,10 @@ def main():
     ap.add_argument("--eps", type=float, default=0.0015)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-as-specified", action="store_true")
+    ap.add_argument("--workload", default="logreg",
+                    choices=["logreg", "banana", "hmc", "funnel", "batched"],
+                    help="logreg (default) is the benchmark line; the others print "
+                         "measurements of the remaining configurations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -53,6 +57,9 @@ def main():
     from paper_2508_18413_amd import workloads as W
 
     dev = "cuda:0"
+    if args.workload != "logreg":
+        print(json.dumps(other_workload(args, pm, W, np, torch)), flush=True)
+        return
     T, eps = args.T, args.eps
     ch = W.logreg_chain(T=T, seed=0, eps=eps)
     ctx = pm.Context(0)
@@ -134,6 +141,26 @@ def main():
                                    "avg_launch_ms": scan_avg_ms, "kernel": "k_scan<DiagNewtonIO>"},
     }
 
+    # ---- scan roofline at a large shape: the Newton diagonal scan of a
+    # 16-dimensional ULA chain with T = 2^22 (1.07 GB per scan), live HIP events
+    gch = W.gaussian_chain(1 << 22, seed=1, eps=0.1, dim=16, dtype=np.float32, lam_lo=0.3)
+    gtg = pm.Target(ctx, gch.target)
+    gx0, gxi = torch.tensor(gch.x0, device=dev), torch.tensor(gch.xi, device=dev)
+    del gch
+    pm.solve(ctx, gtg, 0.1, gx0, gxi, None, sampler="ula", variant="diag", max_iter=2,
+             profile_kernels=True)
+    rg = pm.solve(ctx, gtg, 0.1, gx0, gxi, None, sampler="ula", variant="diag", max_iter=4,
+                  profile_kernels=True)
+    scan_ms_big = rg.scan_ms / rg.sweeps
+    bytes_big = 16.0 * 16 * (1 << 22)
+    out["roofline_scan"] = {"bound": "hbm", "achieved": bytes_big / (scan_ms_big * 1e-3) / 1e9,
+                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": bytes_big / (scan_ms_big * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                            "traffic": None, "kernel": "k_scan<DiagNewtonIO>",
+                            "shape": "16 planes x 2^22 steps, FP32", "avg_launch_ms": scan_ms_big}
+    del gx0, gxi, gtg
+    torch.cuda.empty_cache()
+
     # ---- the step size as specified (0.02): run and report
     if not args.no_as_specified:
         ch2 = W.logreg_chain(T=T, seed=0, eps=0.02)
@@ -176,6 +203,99 @@ def main():
                                    "gtilde_at_first_mismatch": float(gt[mism[0]]) if mism.size else None,
                                    "n_accept_mismatch": int(mism.size)}
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    best = None
+    out = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return out, best
+
+
+def other_workload(args, pm, W, np, torch):
+    """Measurements of the configurations other than the benchmark line."""
+    dev = "cuda:0"
+    ctx = pm.Context(0)
+    t = lambda x: torch.tensor(np.ascontiguousarray(x), device=dev)  # noqa: E731
+    reps = max(1, args.steps)
+    res = {"workload": args.workload}
+    if args.workload == "banana":
+        ch = W.banana_chain(T=1024, seed=0)
+        g = pm.Target(ctx, ch.target, dtype=torch.float64)
+        x0, xi, u = t(ch.x0), t(ch.xi), t(ch.u)
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch)
+        res["sequential_ms"] = 1e3 * ts
+        for name, kw in [("diag", dict(variant="diag")), ("dense_clip_inf", dict(variant="dense", clip=1.0,
+                                                                                  clip_inf_norm=True)),
+                         ("dense", dict(variant="dense")), ("picard", dict(variant="picard")),
+                         ("diag_graph8", dict(variant="diag", graph_sweeps=8))]:
+            r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=1025, **kw), reps, torch)
+            res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status,
+                         "chain_steps_per_s": 1024 / tp, "vs_sequential": ts / tp,
+                         "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+    elif args.workload == "hmc":
+        pr = W.hmc_gaussian(seed=0, dim=100, L=64, eps=0.05, n_prop=2000)
+        g = pm.Target(ctx, pr.target)
+        x0, mom, U = t(pr.x0), t(pr.momenta), t(pr.U)
+        rs, ts = _timed(lambda: pm.hmc_sample(ctx, g, pr.eps, pr.L, x0, mom, U, parallel_leapfrog=False),
+                        reps, torch)
+        res["sequential_leapfrog_ms"] = 1e3 * ts
+        res["acceptance"] = rs["n_accept"] / 2000
+        for v in ("block2", "diag", "picard"):
+            r, tp = _timed(lambda: pm.hmc_sample(ctx, g, pr.eps, pr.L, x0, mom, U, variant=v,
+                                                 atol=1e-6, rtol=1e-6), reps, torch)
+            sw = np.array(r["sweeps"])
+            res[v] = {"ms": 1e3 * tp, "vs_sequential": ts / tp, "sweeps_median": float(np.median(sw)),
+                      "sweeps_p90": float(np.percentile(sw, 90)), "sweeps_max": int(sw.max()),
+                      "max_abs_vs_sequential": (r["chain"] - rs["chain"]).abs().max().item()}
+    elif args.workload == "funnel":
+        ch = W.funnel_chain(T=16384, seed=0)
+        g = pm.Target(ctx, ch.target)
+        x0, xi, u = t(ch.x0), t(ch.xi), t(ch.u)
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch)
+        res["sequential_ms"] = 1e3 * ts
+        for name, kw in [("diag", dict(variant="diag")), ("dense_f32", dict(variant="dense", jac_prec="f32")),
+                         ("dense_bf16", dict(variant="dense", jac_prec="bf16"))]:
+            r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=16385, **kw), reps, torch)
+            res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status, "n_floor": r.n_floor,
+                         "vs_sequential": ts / tp,
+                         "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+        r = pm.solve(ctx, g, ch.eps, x0, xi, u, variant="diag", max_iter=16385)
+        dF = ((2.0 / ch.T) * r.states).contiguous()
+        (dth, dep), ta = _timed(lambda: pm.adjoint(ctx, g, ch.eps, x0, xi, u, r.states, r.accept, dF),
+                                reps, torch)
+        res["adjoint"] = {"ms": 1e3 * ta, "dF_dtheta": dth, "dF_deps": dep, "theta": ch.target["theta"]}
+    elif args.workload == "batched":
+        b = W.logreg_batch(seed=0, n_chains=512, lo=4096, hi=131072, eps=args.eps)
+        g = pm.Target(ctx, b.target)
+        bx = pm.sample_sequential(ctx, g, b.eps, t(b.x0), t(b.burn_xi.reshape(-1, b.x0.shape[1])),
+                                  t(b.burn_u.reshape(-1)), offsets=list(range(0, 3 * 512 + 1, 3)))
+        s0 = bx.states.reshape(512, 3, -1)[:, -1].contiguous()
+        xi, u = t(b.xi), t(b.u)
+        off = list(int(v) for v in b.offsets)
+        n = int(b.offsets[-1])
+        res["n_steps"] = n
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, b.eps, s0, xi, u, offsets=off), 1, torch)
+        res["sequential"] = {"ms": 1e3 * ts, "chain_steps_per_s": n / ts}
+        pm.autotune(ctx, g, b.eps, s0, xi, u)
+        for name, kw in [("diag_graph8", dict(variant="diag", graph_sweeps=8)),
+                         ("diag_window", dict(variant="diag", skip_converged_prefix=True))]:
+            r, tp = _timed(lambda: pm.solve(ctx, g, b.eps, s0, xi, u, offsets=off, max_iter=400, **kw), 1,
+                           torch)
+            spc = np.array(r.sweeps_per_chain)
+            res[name] = {"ms": 1e3 * tp, "chain_steps_per_s": n / tp, "vs_sequential": ts / tp,
+                         "status": r.status, "n_converged": r.n_converged, "n_floor": r.n_floor,
+                         "sweeps_median": float(np.median(spc)), "sweeps_p90": float(np.percentile(spc, 90)),
+                         "sweeps_max": int(spc.max()),
+                         "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+    return res
 
 
 if __name__ == "__main__":

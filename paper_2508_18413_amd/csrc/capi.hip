@@ -62,11 +62,4 @@ pmc_status pmc_linrec_dense(pmc_context *ctx, pmc_dtype dtype, pmc_jac_prec jac_
     return check_scan_health(ctx);
 }
 
-pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
-                        const char *cache_path)
-{
-    set_error("pmc_autotune: not built");
-    return PMC_ERR_UNSUPPORTED;
-}
-
 }  // extern "C"

@@ -36,18 +36,28 @@ __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h 
 
 __device__ __forceinline__ float sigm(float z)
 {
-    if (z >= 0.f) return 1.f / (1.f + expf(-z));
-    const float e = expf(z);
-    return e / (1.f + e);
+    const float e = expf(-fabsf(z));
+    const float r = 1.f / (1.f + e);
+    return z >= 0.f ? r : e * r;
 }
 
-__device__ __forceinline__ float sp_diff(float z, float dz, float s)
+// With s = sigma(z) and m = expm1(dz): sigma(z + dz) = s (1 + m) / (1 + s m) and
+// softplus(z + dz) - softplus(z) = log1p(s m); one exponential serves both.
+// Large increments (dz >= 30) take the direct forms.
+__device__ __forceinline__ void shifted(float z, float dz, float s, float &st, float &spd)
 {
-    if (dz < 30.f) return log1pf(s * expm1f(dz));
-    const float zt = z + dz;
-    const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
-    const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
-    return spt - sp;
+    if (dz < 30.f) {
+        const float m = expm1f(dz);
+        const float q = fmaf(s, m, 1.f);
+        st = s * (1.f + m) / q;
+        spd = log1pf(s * m);
+    } else {
+        const float zt = z + dz;
+        st = sigm(zt);
+        const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
+        const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+        spd = spt - sp;
+    }
 }
 
 // accumulator -> B operand (rows of parity hh)
@@ -73,7 +83,7 @@ struct Frags {
 };
 
 template <int MK>
-__global__ void __launch_bounds__(64 * kWaves) k_eval_logreg(EvalArgs a, Frags f)
+__global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frags f)
 {
     __shared__ float s_t[kWaves][3][32 * 33];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 31, hh = lane >> 5;
@@ -106,21 +116,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_eval_logreg(EvalArgs a, Frags f
     for (int rt = 0; rt < f.nr; rt++) {
         const float *xa = f.xa + (size_t)rt * MK * 64 + lane;
         const float *xta = f.xta + (size_t)rt * 16 * 64 + lane;
-        float A1[MK], A2[16];
-#pragma unroll
-        for (int m = 0; m < MK; m++) A1[m] = xa[m * 64];
-#pragma unroll
-        for (int m = 0; m < 16; m++) A2[m] = xta[m * 64];
         f32x16 Z = zero;
 #pragma unroll
-        for (int m = 0; m < MK; m++) Z = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[m], SB[m], Z, 0, 0, 0);
+        for (int m = 0; m < MK; m++) Z = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[m * 64], SB[m], Z, 0, 0, 0);
         f32x16 R;
 #pragma unroll
         for (int r = 0; r < 16; r++) R[r] = f.y[32 * rt + crow(r, hh)] - sigm(Z[r]);
         float RB[16];
         acc_to_b(R, RB, hh);
 #pragma unroll
-        for (int m = 0; m < 16; m++) G = __builtin_amdgcn_mfma_f32_32x32x2f32(A2[m], RB[m], G, 0, 0, 0);
+        for (int m = 0; m < 16; m++) G = __builtin_amdgcn_mfma_f32_32x32x2f32(xta[m * 64], RB[m], G, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 16; r++) sg[crow(r, hh) * 33 + j] = G[r];
@@ -147,19 +152,12 @@ __global__ void __launch_bounds__(64 * kWaves) k_eval_logreg(EvalArgs a, Frags f
         const float *xa = f.xa + (size_t)rt * MK * 64 + lane;
         const float *xta = f.xta + (size_t)rt * 16 * 64 + lane;
         const float *x2ta = f.x2ta + (size_t)rt * 16 * 64 + lane;
-        float A1[MK], A2[16], A3[16];
-#pragma unroll
-        for (int m = 0; m < MK; m++) A1[m] = xa[m * 64];
-#pragma unroll
-        for (int m = 0; m < 16; m++) {
-            A2[m] = xta[m * 64];
-            A3[m] = x2ta[m * 64];
-        }
         f32x16 Z = zero, dZ = zero;
 #pragma unroll
         for (int m = 0; m < MK; m++) {
-            Z = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[m], SB[m], Z, 0, 0, 0);
-            dZ = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[m], DB[m], dZ, 0, 0, 0);
+            const float a1 = xa[m * 64];
+            Z = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, SB[m], Z, 0, 0, 0);
+            dZ = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, DB[m], dZ, 0, 0, 0);
         }
         f32x16 Rt, Wv;
 #pragma unroll
@@ -167,17 +165,25 @@ __global__ void __launch_bounds__(64 * kWaves) k_eval_logreg(EvalArgs a, Frags f
             const float yv = f.y[32 * rt + crow(r, hh)];
             const float z = Z[r], dz = dZ[r];
             const float s = sigm(z);
-            Rt[r] = yv - sigm(z + dz);
+            float st, spd;
+            shifted(z, dz, s, st, spd);
+            Rt[r] = yv - st;
             Wv[r] = s * (1.f - s);
-            dll += yv * dz - sp_diff(z, dz, s);
+            dll += yv * dz - spd;
         }
-        float RB[16], WB[16];
-        acc_to_b(Rt, RB, hh);
-        acc_to_b(Wv, WB, hh);
+        {
+            float RB[16];
+            acc_to_b(Rt, RB, hh);
 #pragma unroll
-        for (int m = 0; m < 16; m++) {
-            Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(A2[m], RB[m], Gt, 0, 0, 0);
-            Hd = __builtin_amdgcn_mfma_f32_32x32x2f32(A3[m], WB[m], Hd, 0, 0, 0);
+            for (int m = 0; m < 16; m++)
+                Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(xta[m * 64], RB[m], Gt, 0, 0, 0);
+        }
+        {
+            float WB[16];
+            acc_to_b(Wv, WB, hh);
+#pragma unroll
+            for (int m = 0; m < 16; m++)
+                Hd = __builtin_amdgcn_mfma_f32_32x32x2f32(x2ta[m * 64], WB[m], Hd, 0, 0, 0);
         }
     }
 #pragma unroll

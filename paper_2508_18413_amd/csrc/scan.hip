@@ -379,7 +379,9 @@ struct SegGeom {
         t1 = st.start + st.len;
         if (ws >= t1) return false;
         t0 = st.start > ws ? st.start : ws;
-        head_ti = chain_tile_begin[st.chain] + (int)((ws - off) / C);
+        // tile boundaries sit at absolute multiples of C (the first tile of a
+        // chain runs from its offset to the next multiple)
+        head_ti = chain_tile_begin[st.chain] + (int)(ws / C - off / C);
         return true;
     }
 };
@@ -414,6 +416,34 @@ struct DiagNewtonIO {
         S[i] = s;
         if (trace) trace[i] = s;
         part_add<R>(p, t, dc[0], s, e.b[0], atol, rtol);
+    }
+    // four consecutive steps from a 16-byte aligned index (FP32 only)
+    static constexpr bool kVec = sizeof(R) == 4;
+    __device__ void load4(int lane, int64_t t, Aff<R, 1> *e, Extra *x) const
+    {
+        const size_t i = (size_t)lane * ld + t;
+        const float4 j4 = *(const float4 *)(J + i), f4 = *(const float4 *)(F + i),
+                     s4 = *(const float4 *)(S + i);
+        const float jj[4] = {j4.x, j4.y, j4.z, j4.w}, ff[4] = {f4.x, f4.y, f4.z, f4.w},
+                    ss[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            e[q].a[0][0] = jj[q];
+            e[q].b[0] = ff[q] - ss[q];
+            x[q].f[0] = ff[q];
+        }
+    }
+    __device__ void store1(int lane, int64_t t, R s) const
+    {
+        const size_t i = (size_t)lane * ld + t;
+        S[i] = s;
+        if (trace) trace[i] = s;
+    }
+    __device__ void store4(int lane, int64_t t, const R *s4) const
+    {
+        const size_t i = (size_t)lane * ld + t;
+        *(float4 *)(S + i) = make_float4(s4[0], s4[1], s4[2], s4[3]);
+        if (trace) *(float4 *)(trace + i) = make_float4(s4[0], s4[1], s4[2], s4[3]);
     }
 };
 
@@ -547,6 +577,15 @@ struct DenseLinIO {
     }
 };
 
+template <class IO, class = void>
+struct HasVec {
+    static constexpr bool value = false;
+};
+template <class IO>
+struct HasVec<IO, decltype(void(IO::kVec))> {
+    static constexpr bool value = IO::kVec;
+};
+
 template <class IO>
 struct HasPartials {
     static constexpr bool value = false;
@@ -595,12 +634,34 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         A e[ITEMS];
         typename IO::Extra x[ITEMS];
         const int64_t base = t0 + (int64_t)tid * ITEMS;
+        bool vec = false;
+        if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) vec = (t0 & 3) == 0;
+        if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) {
+            if (vec) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (base + i < t1)
-                io.load(lane, base + i, e[i], x[i]);
-            else
-                e[i] = aff_identity<R, M>();
+                for (int i = 0; i < ITEMS; i += 4) {
+                    if (base + i + 3 < t1) {
+                        io.load4(lane, base + i, &e[i], &x[i]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            if (base + i + q < t1)
+                                io.load(lane, base + i + q, e[i + q], x[i + q]);
+                            else
+                                e[i + q] = aff_identity<R, M>();
+                        }
+                    }
+                }
+            }
+        }
+        if (!vec) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if (base + i < t1)
+                    io.load(lane, base + i, e[i], x[i]);
+                else
+                    e[i] = aff_identity<R, M>();
+            }
         }
         A agg = e[0];
 #pragma unroll
@@ -642,14 +703,38 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         for (int i = 0; i < M; i++) d[i] = s_carry[i];
         apply(wpre, d, d);
         apply(excl, d, d);
+        if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) {
+            if (vec) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; i++) {
-            if (base + i < t1) {
-                R dp[M];
+                for (int i = 0; i < ITEMS; i += 4) {
+                    R sv[4];
+                    const bool full = base + i + 3 < t1;
 #pragma unroll
-                for (int k = 0; k < M; k++) dp[k] = d[k];
-                apply(e[i], dp, d);
-                io.store(lane, base + i, e[i], x[i], dp, d, part);
+                    for (int q = 0; q < 4; q++) {
+                        if (base + i + q < t1) {
+                            R dp[M];
+#pragma unroll
+                            for (int k = 0; k < M; k++) dp[k] = d[k];
+                            apply(e[i + q], dp, d);
+                            sv[q] = fma(e[i + q].a[0][0], dp[0], x[i + q].f[0]);
+                            part_add<R>(part, base + i + q, d[0], sv[q], e[i + q].b[0], io.atol, io.rtol);
+                            if (!full) io.store1(lane, base + i + q, sv[q]);
+                        }
+                    }
+                    if (full) io.store4(lane, base + i, sv);
+                }
+            }
+        }
+        if (!vec) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if (base + i < t1) {
+                    R dp[M];
+#pragma unroll
+                    for (int k = 0; k < M; k++) dp[k] = d[k];
+                    apply(e[i], dp, d);
+                    io.store(lane, base + i, e[i], x[i], dp, d, part);
+                }
             }
         }
     }
@@ -759,7 +844,10 @@ __global__ void __launch_bounds__(1024) k_status(StatusArgs a)
                 cs.at_floor = 1;
                 cs.active = 0;
             } else if (a.skip_prefix && fb != INT64_MAX) {
-                cs.win_start = fb;
+                // window start rounded down to a multiple of 4 (aligned vector loads)
+                const int64_t off = a.offsets[c];
+                const int64_t w = fb & ~(int64_t)3;
+                cs.win_start = w > off ? w : off;
             }
         }
         rsq += cs.resid_sq;

@@ -25,14 +25,21 @@ __device__ __forceinline__ R sigm(R z)
     const R e = exp(z);
     return e / (R(1) + e);
 }
-template <typename R>
-__device__ __forceinline__ R sp_diff(R z, R dz, R s)
+// sigma(z + dz) and softplus(z + dz) - softplus(z) from s = sigma(z) and one
+// expm1: s (1 + m) / (1 + s m) and log1p(s m), m = expm1(dz).
+__device__ __forceinline__ void shifted(float z, float dz, float s, float &st, float &spd)
 {
-    if (dz < R(30)) return log1p(s * expm1(dz));
-    const R zt = z + dz;
-    const R spt = zt > R(0) ? zt + log1p(exp(-zt)) : log1p(exp(zt));
-    const R sp = z > R(0) ? z + log1p(exp(-z)) : log1p(exp(z));
-    return spt - sp;
+    if (dz < 30.f) {
+        const float m = expm1f(dz);
+        st = s * (1.f + m) / fmaf(s, m, 1.f);
+        spd = log1pf(s * m);
+    } else {
+        const float zt = z + dz;
+        st = sigm(zt);
+        const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
+        const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+        spd = spt - sp;
+    }
 }
 
 template <class Tg, typename R>
@@ -115,7 +122,7 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
     const float *noise = (const float *)a.noise, *unif = (const float *)a.unif;
     float *out = (float *)a.out;
     const bool w0 = tid < 64;
-    const bool own = w0 && lane < D;
+    const bool own = w0 && lane < D;  // lanes 32..63 of wave 0 never own a coordinate (D <= 32)
 
     float xr[RPT][DM], yr[RPT], z[RPT], sz[RPT];
 #pragma unroll
@@ -167,34 +174,38 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
         if (w0 && lane < DM) g = s_sum[lane] - pp * x;
     }
 
-    float xin = (own && t0 < t1) ? noise[(size_t)t0 * D + lane] : 0.f;
-    float uin = (t0 < t1 && unif) ? unif[t0] : 0.5f;
+    // wave 0 publishes the first increment; afterwards each step's epilogue
+    // publishes the decision together with the next step's increment
+    float xi = (own && t0 < t1) ? noise[(size_t)t0 * D + lane] : 0.f;
+    float u = (t0 < t1 && unif) ? unif[t0] : 0.5f;
+    float dl = 0.f;
+    if (w0) {
+        dl = own ? fmaf(eps, g, cc * xi) : 0.f;
+        if (lane < DM) s_dl[lane] = dl;
+        if (lane == 0) s_acc = 0;
+    }
+    __syncthreads();
+    float zt[RPT], szt[RPT];
     for (int64_t t = t0; t < t1; t++) {
-        const float xi = xin, u = uin;
-        if (t + 1 < t1) {  // prefetch
-            if (own) xin = noise[(size_t)(t + 1) * D + lane];
-            if (unif) uin = unif[t + 1];
-        }
-        float dl = 0.f;
-        if (w0) {
-            dl = own ? fmaf(eps, g, cc * xi) : 0.f;
-            if (lane < DM) s_dl[lane] = dl;
-        }
-        __syncthreads();
-        float v[V], zt[RPT], szt[RPT];
+        // rows: predictors at the proposal, gradient and log-likelihood partials
+        float v[V];
 #pragma unroll
         for (int i = 0; i < V; i++) v[i] = 0.f;
+        float dlv[DM];
+#pragma unroll
+        for (int d = 0; d < DM; d++) dlv[d] = s_dl[d];
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
             float dz = 0.f;
 #pragma unroll
-            for (int d = 0; d < DM; d++) dz = fmaf(xr[k][d], s_dl[d], dz);
+            for (int d = 0; d < DM; d++) dz = fmaf(xr[k][d], dlv[d], dz);
             zt[k] = z[k] + dz;
-            szt[k] = sigm(zt[k]);
+            float spd;
+            shifted(z[k], dz, sz[k], szt[k], spd);
             const float r = yr[k] - szt[k];
 #pragma unroll
             for (int d = 0; d < DM; d++) v[d] = fmaf(r, xr[k][d], v[d]);
-            v[DM] += yr[k] * dz - sp_diff(z[k], dz, sz[k]);
+            v[DM] += yr[k] * dz - spd;
         }
         column_sum(v);
         if (w0) {
@@ -203,10 +214,10 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
             const float sg = g + gt;
             float sn = own ? sg * sg : 0.f, sx = own ? xi * sg : 0.f, dpr = own ? dl * (xt + x) : 0.f;
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-                sn += __shfl_xor(sn, m, 64);
-                sx += __shfl_xor(sx, m, 64);
-                dpr += __shfl_xor(dpr, m, 64);
+            for (int m = 16; m >= 1; m >>= 1) {  // D <= 32: lanes 0..31 hold the components
+                sn += __shfl_xor(sn, m, 32);
+                sx += __shfl_xor(sx, m, 32);
+                dpr += __shfl_xor(dpr, m, 32);
             }
             int acc = 1;
             float gate = INFINITY;
@@ -223,10 +234,17 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
             }
             if (own) out[(size_t)t * D + lane] = x;
             if (lane == 0) {
-                s_acc = acc;
                 if (a.accept) a.accept[t] = (uint8_t)acc;
                 if (a.gtilde) a.gtilde[t] = gate;
             }
+            // next step's increment
+            if (t + 1 < t1) {
+                xi = own ? noise[(size_t)(t + 1) * D + lane] : 0.f;
+                if (unif) u = unif[t + 1];
+                dl = own ? fmaf(eps, g, cc * xi) : 0.f;
+                if (lane < DM) s_dl[lane] = dl;
+            }
+            if (lane == 0) s_acc = acc;
         }
         __syncthreads();
         if (s_acc) {

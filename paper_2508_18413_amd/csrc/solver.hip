@@ -11,7 +11,12 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+
 #include <algorithm>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "pmc_internal.hpp"
@@ -46,10 +51,15 @@ void build_tiles(const std::vector<int64_t> &offs, int C, std::vector<SegTile> &
     tiles.clear();
     const int nc = (int)offs.size() - 1;
     if (ctb) ctb->assign(nc + 1, 0);
+    // tile boundaries at absolute multiples of C: interior tiles start
+    // aligned; a chain's first tile runs from its offset to the next multiple
     for (int c = 0; c < nc; c++) {
         if (ctb) (*ctb)[c] = (int32_t)tiles.size();
-        for (int64_t s = offs[c]; s < offs[c + 1]; s += C)
-            tiles.push_back(SegTile{s, (int32_t)std::min<int64_t>(C, offs[c + 1] - s), c});
+        for (int64_t s = offs[c]; s < offs[c + 1];) {
+            const int64_t e = std::min<int64_t>(offs[c + 1], (s / C + 1) * C);
+            tiles.push_back(SegTile{s, (int32_t)(e - s), c});
+            s = e;
+        }
     }
     if (ctb) (*ctb)[nc] = (int32_t)tiles.size();
 }
@@ -561,3 +571,157 @@ pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_res
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+// Times the diagonal-scan tile configurations (items per thread x block) on
+// this problem's shape and keeps the fastest in the context.  Cache file:
+// one JSON object, one entry per line, keyed "<gcnArchName>|<shape key>".
+namespace {
+struct Cand {
+    int items, block;
+};
+
+std::string tune_key(pmc_context *ctx, const Plan &pl)
+{
+    int ln = 0, lc = 0;
+    while ((int64_t(1) << (ln + 1)) <= pl.n) ln++;
+    while ((1 << (lc + 1)) <= pl.n_chains) lc++;
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|diag-%s-d%d-n2^%d-c2^%d", ctx->arch.c_str(),
+             pl.dt == PMC_F64 ? "f64" : "f32", pl.D, ln, lc);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, Cand &c)
+{
+    std::ifstream f(path);
+    std::string line;
+    const std::string q = "\"" + key + "\"";
+    while (std::getline(f, line)) {
+        const size_t p = line.find(q);
+        if (p == std::string::npos) continue;
+        int it = 0, bl = 0;
+        const size_t a = line.find("\"items\":", p), b = line.find("\"block\":", p);
+        if (a == std::string::npos || b == std::string::npos) continue;
+        if (sscanf(line.c_str() + a + 8, "%d", &it) == 1 && sscanf(line.c_str() + b + 8, "%d", &bl) == 1) {
+            c = Cand{it, bl};
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char *path, const std::string &key, const Cand &c, float ms)
+{
+    std::vector<std::string> lines;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line))
+            if (line.find("\"items\"") != std::string::npos && line.find("\"" + key + "\"") == std::string::npos)
+                lines.push_back(line);
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf), "  \"%s\": {\"items\": %d, \"block\": %d, \"ms\": %.5f}", key.c_str(),
+             c.items, c.block, ms);
+    lines.push_back(buf);
+    std::ofstream o(path);
+    o << "{\n";
+    for (size_t i = 0; i < lines.size(); i++) {
+        std::string l = lines[i];
+        while (!l.empty() && (l.back() == ',' || l.back() == ' ')) l.pop_back();
+        o << l << (i + 1 < lines.size() ? ",\n" : "\n");
+    }
+    o << "}\n";
+}
+}  // namespace
+
+extern "C" pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                                   const char *cache_path)
+{
+    Plan base;
+    PMC_TRY(make_plan(ctx, prob, opts, base));
+    if (base.jmode != JM_DIAG && base.jmode != JM_NONE) return PMC_OK;  // only the diagonal scan is tuned
+    if (base.n == 0) return PMC_OK;
+    const std::string key = tune_key(ctx, base);
+    Cand best{0, 0};
+    if (cache_path && cache_lookup(cache_path, key, best)) {
+        ctx->diag_items = best.items;
+        ctx->diag_block = best.block;
+        return PMC_OK;
+    }
+    std::vector<Cand> cands;
+    if (base.dt == PMC_F64)
+        cands = {{4, 256}, {8, 256}};
+    else
+        cands = {{4, 256}, {8, 256}, {16, 256}, {8, 512}, {16, 512}};
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    // workspace: planes J, F, S (zero), per-tile partials for the smallest tile, tiles, chains
+    const size_t plane = (size_t)base.ld * base.es * base.D;
+    int minC = 1 << 30;
+    for (auto &c : cands) minC = std::min(minC, scan_tile_steps(base.dt, 1, c.items, c.block));
+    std::vector<SegTile> tiles;
+    std::vector<int32_t> ctb;
+    build_tiles(base.offs, minC, tiles, &ctb);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align_up(off + b, 256);
+        return o;
+    };
+    const size_t oJ = take(plane), oF = take(plane), oS = take(plane),
+                 oP = take(sizeof(TilePartial) * base.D * tiles.size()), oT = take(sizeof(SegTile) * tiles.size()),
+                 oC = take(sizeof(int32_t) * ctb.size()), oO = take(sizeof(int64_t) * base.offs.size()),
+                 oCh = take(sizeof(ChainStatus) * base.n_chains);
+    PMC_TRY(ensure_pool(ctx, off));
+    char *ws = (char *)ctx->pool;
+    hipStream_t st = ctx->stream;
+    PMC_TRY_HIP(hipMemsetAsync(ws, 0, 3 * plane, st));
+    std::vector<ChainStatus> hc(base.n_chains);
+    for (int c = 0; c < base.n_chains; c++) {
+        memset(&hc[c], 0, sizeof(ChainStatus));
+        hc[c].win_start = base.offs[c];
+        hc[c].active = base.offs[c + 1] > base.offs[c];
+    }
+    PMC_TRY_HIP(hipMemcpyAsync(ws + oCh, hc.data(), sizeof(ChainStatus) * hc.size(), hipMemcpyHostToDevice, st));
+    PMC_TRY_HIP(hipMemcpyAsync(ws + oO, base.offs.data(), sizeof(int64_t) * base.offs.size(),
+                               hipMemcpyHostToDevice, st));
+    float best_ms = 1e30f;
+    for (auto &c : cands) {
+        const int C = scan_tile_steps(base.dt, 1, c.items, c.block);
+        build_tiles(base.offs, C, tiles, &ctb);
+        PMC_TRY_HIP(hipMemcpyAsync(ws + oT, tiles.data(), sizeof(SegTile) * tiles.size(), hipMemcpyHostToDevice, st));
+        PMC_TRY_HIP(hipMemcpyAsync(ws + oC, ctb.data(), sizeof(int32_t) * ctb.size(), hipMemcpyHostToDevice, st));
+        NewtonScanArgs sa;
+        memset(&sa, 0, sizeof(sa));
+        sa.n_lanes = base.D;
+        sa.ld = base.ld;
+        sa.tiles = (const SegTile *)(ws + oT);
+        sa.n_tiles = (int)tiles.size();
+        sa.offsets = (const int64_t *)(ws + oO);
+        sa.chains = (const ChainStatus *)(ws + oCh);
+        sa.chain_tile_begin = (const int32_t *)(ws + oC);
+        sa.J = ws + oJ;
+        sa.F = ws + oF;
+        sa.S = ws + oS;
+        sa.partials = (TilePartial *)(ws + oP);
+        sa.atol = sa.rtol = 1e-6;
+        PMC_TRY(launch_newton_scan_diag(ctx, base.dt, sa, c.items, c.block));  // warm-up
+        PMC_TRY_HIP(hipEventRecord(ctx->ev0, st));
+        for (int r = 0; r < 5; r++) PMC_TRY(launch_newton_scan_diag(ctx, base.dt, sa, c.items, c.block));
+        PMC_TRY_HIP(hipEventRecord(ctx->ev1, st));
+        PMC_TRY_HIP(hipEventSynchronize(ctx->ev1));
+        float ms = 0;
+        PMC_TRY_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ms /= 5;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    PMC_TRY(check_scan_health(ctx));
+    ctx->diag_items = best.items;
+    ctx->diag_block = best.block;
+    if (cache_path) cache_store(cache_path, key, best, best_ms);
+    return PMC_OK;
+}

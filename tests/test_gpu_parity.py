@@ -366,3 +366,19 @@ def test_ula_gaussian_one_solve_mfma(ctx, pm, orc):
     ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, None, ula=True)
     assert state_error(r.trace[0].cpu().numpy(), ref) <= 1e-5
     assert r.sweeps <= 3
+
+
+def test_autotune_and_cache(ctx, pm, orc, tmp_path):
+    """The tuner picks a tile configuration, caches it by architecture and
+    shape, and the solve with the tuned tiles still matches the oracle."""
+    _say("autotune")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015, seed=2)
+    g = pm.Target(ctx, ch.target)
+    cache = tmp_path / "tune.json"
+    pm.autotune(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), cache_path=str(cache))
+    txt = cache.read_text()
+    assert "gfx950" in txt and '"items"' in txt
+    pm.autotune(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), cache_path=str(cache))  # cached
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=4097)
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
