@@ -85,6 +85,8 @@ struct GlobalStatus {
     float max_ratio;
     uint32_t nonfinite;
     int64_t n_accept;
+    uint32_t fold_ctr;   // status-fold completion counter; zero between launches
+    uint32_t pad;
 };
 
 // Synchronisation words of the single-pass scans.  The last workgroup of a

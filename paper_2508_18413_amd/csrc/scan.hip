@@ -784,46 +784,81 @@ pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, Ti
 }
 
 // ------------------------------------------------------- chain status fold
-// One thread per chain folds its tiles' partials (all lanes, fixed order, so
-// the FP64 sums are deterministic), updates the chain's Newton state, then the
-// block folds chains into the global status in fixed order.
-__global__ void __launch_bounds__(1024) k_status(StatusArgs a)
+namespace {
+
+constexpr int kStatusThreads = 256;
+
+struct Fold {
+    double q, qi;
+    float r;
+    uint32_t f;
+    int64_t fb;
+};
+
+// Block-wide fold of per-thread values; the result is valid in thread 0.
+// Fixed tree order, so the FP64 sums are deterministic.
+__device__ Fold block_fold(Fold v)
 {
-    __shared__ double s_rsq[1024];
-    __shared__ double s_rinf[1024];
-    __shared__ float s_ratio[1024];
-    __shared__ int s_active[1024], s_conv[1024], s_sweeps[1024], s_floor[1024];
-    __shared__ uint32_t s_nf[1024];
-    __shared__ long long s_acc[1024];
-    const int tid = threadIdx.x;
-    double rsq = 0, rinf = 0;
-    float ratio = 0;
-    int nact = 0, nconv = 0, sweeps = 0, nfloor = 0;
-    uint32_t nf = 0;
-    long long nacc = 0;
-    for (int c = tid; c < a.n_chains; c += blockDim.x) {
-        ChainStatus &cs = a.chains[c];
-        if (cs.active) {
-            float r = 0;
-            int64_t fb = INT64_MAX;
-            double q = 0, qi = 0;
-            uint32_t f = 0;
-            for (int l = 0; l < a.n_lanes; l++) {
-                for (int k = a.chain_tile_begin[c]; k < a.chain_tile_begin[c + 1]; k++) {
-                    const TilePartial &p = a.partials[(size_t)l * a.n_tiles + k];
-                    r = fmaxf(r, p.max_ratio);
-                    fb = min(fb, p.first_bad);
-                    q += p.resid_sq;
-                    qi = fmax(qi, p.resid_inf);
-                    f += p.nonfinite;
-                }
-            }
+    __shared__ Fold s_w[kStatusThreads / 64];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        v.q += __shfl_xor(v.q, m);
+        v.qi = fmax(v.qi, __shfl_xor(v.qi, m));
+        v.r = fmaxf(v.r, __shfl_xor(v.r, m));
+        v.f += __shfl_xor(v.f, m);
+        const int64_t o = __shfl_xor(v.fb, m);
+        v.fb = o < v.fb ? o : v.fb;
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_w[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kStatusThreads / 64; i++) {
+            const Fold &o = s_w[i];
+            v.q += o.q;
+            v.qi = fmax(v.qi, o.qi);
+            v.r = fmaxf(v.r, o.r);
+            v.f += o.f;
+            v.fb = o.fb < v.fb ? o.fb : v.fb;
+        }
+    }
+    __syncthreads();
+    return v;
+}
+
+}  // namespace
+
+// One workgroup per chain folds that chain's tile partials (all lanes) and
+// updates its Newton state; the last workgroup to finish folds every chain
+// into the global status and re-arms the completion counter, so the kernel
+// can be replayed inside a captured graph.
+__global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
+{
+    const int c = blockIdx.x, tid = threadIdx.x;
+    ChainStatus &cs = a.chains[c];
+    if (cs.active) {  // uniform per block
+        const int k0 = a.chain_tile_begin[c], ntc = a.chain_tile_begin[c + 1] - k0;
+        const int64_t cnt = (int64_t)a.n_lanes * ntc;
+        Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
+        for (int64_t i = tid; i < cnt; i += kStatusThreads) {
+            const int l = (int)(i / ntc), k = k0 + (int)(i - (int64_t)l * ntc);
+            const TilePartial &p = a.partials[(size_t)l * a.n_tiles + k];
+            v.r = fmaxf(v.r, p.max_ratio);
+            v.fb = p.first_bad < v.fb ? p.first_bad : v.fb;
+            v.q += p.resid_sq;
+            v.qi = fmax(v.qi, p.resid_inf);
+            v.f += p.nonfinite;
+        }
+        v = block_fold(v);
+        if (tid == 0) {
+            const float r = v.r;
+            const int64_t fb = v.fb;
             cs.sweeps += 1;
             cs.max_ratio = r;
             cs.first_bad = fb;
-            cs.resid_sq = q;
-            cs.resid_inf = qi;
-            cs.nonfinite = f;
+            cs.resid_sq = v.q;
+            cs.resid_inf = v.qi;
+            cs.nonfinite = v.f;
             // Plateau detection: progress is a 2x drop of the best ratio or an
             // advance of the converged front; rounding noise gives neither.
             const int64_t front = fb == INT64_MAX ? a.offsets[c + 1] : fb;
@@ -850,56 +885,81 @@ __global__ void __launch_bounds__(1024) k_status(StatusArgs a)
                 cs.win_start = w > off ? w : off;
             }
         }
-        rsq += cs.resid_sq;
-        rinf = fmax(rinf, cs.resid_inf);
-        ratio = fmaxf(ratio, cs.max_ratio);
-        nact += cs.active;
-        nconv += cs.converged;
-        nfloor += cs.at_floor;
-        sweeps = max(sweeps, cs.sweeps);
-        nf += cs.nonfinite;
-        if (a.accept) {
-            long long s = 0;
-            for (int64_t t = a.offsets[c]; t < a.offsets[c + 1]; t++) s += a.accept[t];
-            nacc += s;
-        }
     }
-    s_rsq[tid] = rsq;
-    s_rinf[tid] = rinf;
-    s_ratio[tid] = ratio;
-    s_active[tid] = nact;
-    s_conv[tid] = nconv;
-    s_floor[tid] = nfloor;
-    s_sweeps[tid] = sweeps;
-    s_nf[tid] = nf;
-    s_acc[tid] = nacc;
+    // completion count: the last workgroup sees every chain's update
+    __shared__ int s_last;
+    __threadfence();
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (tid < h) {
-            s_rsq[tid] += s_rsq[tid + h];
-            s_rinf[tid] = fmax(s_rinf[tid], s_rinf[tid + h]);
-            s_ratio[tid] = fmaxf(s_ratio[tid], s_ratio[tid + h]);
-            s_active[tid] += s_active[tid + h];
-            s_conv[tid] += s_conv[tid + h];
-            s_floor[tid] += s_floor[tid + h];
-            s_sweeps[tid] = max(s_sweeps[tid], s_sweeps[tid + h]);
-            s_nf[tid] += s_nf[tid + h];
-            s_acc[tid] += s_acc[tid + h];
-        }
-        __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&a.global->fold_ctr, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    __shared__ int s_cnt[kStatusThreads / 64][4];
+    Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
+    int nact = 0, nconv = 0, nfloor = 0, sweeps = 0;
+    for (int i = tid; i < a.n_chains; i += kStatusThreads) {
+        const ChainStatus &o = a.chains[i];
+        v.q += o.resid_sq;
+        v.qi = fmax(v.qi, o.resid_inf);
+        v.r = fmaxf(v.r, o.max_ratio);
+        v.f += o.nonfinite;
+        nact += o.active;
+        nconv += o.converged;
+        nfloor += o.at_floor;
+        sweeps = max(sweeps, o.sweeps);
     }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        nact += __shfl_xor(nact, m);
+        nconv += __shfl_xor(nconv, m);
+        nfloor += __shfl_xor(nfloor, m);
+        sweeps = max(sweeps, __shfl_xor(sweeps, m));
+    }
+    if ((tid & 63) == 0) {
+        s_cnt[tid >> 6][0] = nact;
+        s_cnt[tid >> 6][1] = nconv;
+        s_cnt[tid >> 6][2] = nfloor;
+        s_cnt[tid >> 6][3] = sweeps;
+    }
+    v = block_fold(v);
     if (tid == 0) {
+        for (int w = 1; w < kStatusThreads / 64; w++) {
+            nact += s_cnt[w][0];
+            nconv += s_cnt[w][1];
+            nfloor += s_cnt[w][2];
+            sweeps = max(sweeps, s_cnt[w][3]);
+        }
         GlobalStatus *g = a.global;
-        g->n_active = s_active[0];
-        g->n_converged = s_conv[0];
-        g->n_floor = s_floor[0];
-        g->sweeps = s_sweeps[0];
-        g->resid_sq = s_rsq[0];
-        g->resid_inf = s_rinf[0];
-        g->max_ratio = s_ratio[0];
-        g->nonfinite = s_nf[0];
-        g->n_accept = s_acc[0];
+        g->n_active = nact;
+        g->n_converged = nconv;
+        g->n_floor = nfloor;
+        g->sweeps = sweeps;
+        g->resid_sq = v.q;
+        g->resid_inf = v.qi;
+        g->max_ratio = v.r;
+        g->nonfinite = v.f;
+        g->n_accept = 0;
+        __hip_atomic_store(&g->fold_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// Number of accepted proposals: a grid-stride byte count added into the
+// global status (which the preceding status fold has set to zero).
+__global__ void __launch_bounds__(256) k_count_accept(const uint8_t *__restrict__ acc, int64_t n,
+                                                      GlobalStatus *g)
+{
+    uint32_t s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s += acc[i];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    __shared__ uint32_t s_w[4];
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd((unsigned long long *)&g->n_accept,
+                  (unsigned long long)(s_w[0] + s_w[1] + s_w[2] + s_w[3]));
 }
 
 }  // namespace
@@ -1031,8 +1091,16 @@ pmc_status check_scan_health(pmc_context *ctx)
 
 pmc_status launch_status(pmc_context *ctx, const StatusArgs &a)
 {
-    hipLaunchKernelGGL(k_status, dim3(1), dim3(1024), 0, ctx->stream, a);
+    if (a.n_chains <= 0) return PMC_OK;
+    hipLaunchKernelGGL(k_status, dim3(a.n_chains), dim3(kStatusThreads), 0, ctx->stream, a);
     PMC_TRY_HIP(hipGetLastError());
+    if (a.accept && a.n_steps > 0) {
+        const int64_t per = 256 * 16;
+        const int blocks = (int)std::min<int64_t>(1024, (a.n_steps + per - 1) / per);
+        hipLaunchKernelGGL(k_count_accept, dim3(blocks), dim3(256), 0, ctx->stream, a.accept,
+                           a.n_steps, a.global);
+        PMC_TRY_HIP(hipGetLastError());
+    }
     return PMC_OK;
 }
 

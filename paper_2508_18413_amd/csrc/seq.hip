@@ -25,21 +25,15 @@ __device__ __forceinline__ R sigm(R z)
     const R e = exp(z);
     return e / (R(1) + e);
 }
-// sigma(z + dz) and softplus(z + dz) - softplus(z) from s = sigma(z) and one
-// expm1: s (1 + m) / (1 + s m) and log1p(s m), m = expm1(dz).
-__device__ __forceinline__ void shifted(float z, float dz, float s, float &st, float &spd)
+// softplus(z + dz) - softplus(z) from s = sigma(z) and one expm1:
+// log1p(s m), m = expm1(dz); written out directly for large dz.
+__device__ __forceinline__ float softplus_diff(float z, float dz, float s)
 {
-    if (dz < 30.f) {
-        const float m = expm1f(dz);
-        st = s * (1.f + m) / fmaf(s, m, 1.f);
-        spd = log1pf(s * m);
-    } else {
-        const float zt = z + dz;
-        st = sigm(zt);
-        const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
-        const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
-        spd = spt - sp;
-    }
+    if (dz < 30.f) return log1pf(s * expm1f(dz));
+    const float zt = z + dz;
+    const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
+    const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+    return spt - sp;
 }
 
 template <class Tg, typename R>
@@ -100,7 +94,9 @@ __global__ void __launch_bounds__(64) k_seq_small(SeqArgs a, Tg tg)
 // Workgroup-per-chain logistic regression sampler (F32).  The state and its
 // gradient live in wave 0 (lane d holds coordinate d); every thread owns RPT
 // data rows with their linear predictors.  Per step: wave 0 publishes the
-// increment delta through LDS, every thread updates its rows' predictors and
+// increment delta and the proposal through LDS, every thread recomputes its
+// rows' predictors at the proposal from scratch (never by accumulating
+// increments, so rounding does not build up over accepted steps) and its
 // partial sums, the partials are summed through LDS in 8-way column groups,
 // and wave 0 takes the accept decision.
 template <int DM, int NT, int RPT>
@@ -113,7 +109,7 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
     static_assert(V * GRP <= NT, "reduction groups exceed the block");
     __shared__ float s_part[NT * VS];
     __shared__ float s_sum[V];
-    __shared__ float s_dl[DM];
+    __shared__ float s_dl[DM], s_xt[DM];
     __shared__ int s_acc;
     const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int D = a.D;
@@ -181,7 +177,10 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
     float dl = 0.f;
     if (w0) {
         dl = own ? fmaf(eps, g, cc * xi) : 0.f;
-        if (lane < DM) s_dl[lane] = dl;
+        if (lane < DM) {
+            s_dl[lane] = dl;
+            s_xt[lane] = x + dl;
+        }
         if (lane == 0) s_acc = 0;
     }
     __syncthreads();
@@ -191,17 +190,17 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
         float v[V];
 #pragma unroll
         for (int i = 0; i < V; i++) v[i] = 0.f;
-        float dlv[DM];
-#pragma unroll
-        for (int d = 0; d < DM; d++) dlv[d] = s_dl[d];
 #pragma unroll
         for (int k = 0; k < RPT; k++) {
-            float dz = 0.f;
+            float dz = 0.f, zz = 0.f;
 #pragma unroll
-            for (int d = 0; d < DM; d++) dz = fmaf(xr[k][d], dlv[d], dz);
-            zt[k] = z[k] + dz;
-            float spd;
-            shifted(z[k], dz, sz[k], szt[k], spd);
+            for (int d = 0; d < DM; d++) {
+                dz = fmaf(xr[k][d], s_dl[d], dz);
+                zz = fmaf(xr[k][d], s_xt[d], zz);
+            }
+            zt[k] = zz;
+            szt[k] = sigm(zz);
+            const float spd = softplus_diff(z[k], dz, sz[k]);
             const float r = yr[k] - szt[k];
 #pragma unroll
             for (int d = 0; d < DM; d++) v[d] = fmaf(r, xr[k][d], v[d]);
@@ -242,7 +241,10 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
                 xi = own ? noise[(size_t)(t + 1) * D + lane] : 0.f;
                 if (unif) u = unif[t + 1];
                 dl = own ? fmaf(eps, g, cc * xi) : 0.f;
-                if (lane < DM) s_dl[lane] = dl;
+                if (lane < DM) {
+                    s_dl[lane] = dl;
+                    s_xt[lane] = x + dl;
+                }
             }
             if (lane == 0) s_acc = acc;
         }

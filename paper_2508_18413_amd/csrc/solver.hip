@@ -333,6 +333,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
                                hipMemcpyHostToDevice, st));
     PMC_TRY_HIP(hipMemcpyAsync(d_chains, hc.data(), sizeof(ChainStatus) * hc.size(),
                                hipMemcpyHostToDevice, st));
+    PMC_TRY_HIP(hipMemsetAsync(d_glob, 0, sizeof(GlobalStatus), st));
     if (pl.jmode == JM_NONE)  // Picard: J = 0 through the diagonal scan
         PMC_TRY_HIP(hipMemsetAsync(J, 0, (size_t)pl.ld * pl.es * pl.D, st));
 

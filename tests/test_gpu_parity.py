@@ -382,3 +382,35 @@ def test_autotune_and_cache(ctx, pm, orc, tmp_path):
     r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=4097)
     assert r.status == 0
     _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+def test_batched_full_size_sampled(ctx, pm, orc):
+    """512 burned-in chains, lengths log-uniform in [4096, 131072] (sum ~ 1.9e7
+    steps) in one graph-replayed solve: every chain must converge (or reach its
+    rounding floor), and the three shortest chains -- the ones the oracle runs
+    in seconds -- are compared step by step."""
+    _say("batched full size (512 chains)")
+    b = W.logreg_batch(seed=0, n_chains=512, lo=4096, hi=131072, eps=0.0015)
+    lens = np.diff(b.offsets)
+    tg = oracle_target(b.target)
+    g = pm.Target(ctx, b.target)
+    pick = np.argsort(lens)[:3]
+    # 3 burn-in steps per chain (Appendix B.1) by the GPU sequential sampler;
+    # the compared chains start from the oracle's own burn-in instead
+    D = b.x0.shape[1]
+    bx = pm.sample_sequential(ctx, g, b.eps, _t(b.x0), _t(b.burn_xi.reshape(-1, D)),
+                              _t(b.burn_u.reshape(-1)), offsets=list(range(0, 3 * b.n_chains + 1, 3)))
+    s0 = bx.states.reshape(b.n_chains, 3, D)[:, -1].cpu().numpy().copy()
+    for c in pick:
+        s0[c] = oracle_burnin(tg, _as_chain(b, c)).astype(np.float32)
+    r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), variant="diag",
+                 max_iter=400, graph_sweeps=8)
+    spc = np.array(r.sweeps_per_chain)
+    _say(f"  n={int(b.offsets[-1])} status={r.status} converged={r.n_converged} floor={r.n_floor} "
+         f"sweeps median={np.median(spc)} max={spc.max()} ms={r.elapsed_ms:.1f}")
+    assert r.status == 0 and r.n_converged + r.n_floor == b.n_chains
+    st = r.states
+    acc = r.accept
+    for c in pick:
+        o0, o1 = int(b.offsets[c]), int(b.offsets[c + 1])
+        _check_mala(orc, tg, _as_chain(b, c), s0[c], st[o0:o1].cpu().numpy(), acc[o0:o1].cpu().numpy())
