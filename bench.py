@@ -40,6 +40,9 @@ def main():
     ap.add_argument("--eps", type=float, default=0.0015)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-as-specified", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="end with a plain device copy of MIB MiB (FP32), the reference "
+                         "kernel for scaling hardware byte counters")
     ap.add_argument("--workload", default="logreg",
                     choices=["logreg", "banana", "hmc", "funnel", "batched"],
                     help="logreg (default) is the benchmark line; the others print "
@@ -202,10 +205,21 @@ def main():
                                    int(mism[0]) if mism.size else None,
                                    "gtilde_at_first_mismatch": float(gt[mism[0]]) if mism.size else None,
                                    "n_accept_mismatch": int(mism.size)}
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 4 * n, "written": 4 * n}
+        del src, dst
     print(json.dumps(out), flush=True)
 
 
-def _timed(fn, reps, torch):
+def _timed(fn, reps, torch, label=""):
+    """Best of `reps` timed calls after one untimed call; a progress line per call
+    goes to stderr."""
     fn()
     torch.cuda.synchronize()
     best = None
@@ -216,6 +230,7 @@ def _timed(fn, reps, torch):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
+        print(f"[bench] {label} {1e3 * dt:.2f} ms", file=sys.stderr, flush=True)
     return out, best
 
 
@@ -230,13 +245,13 @@ def other_workload(args, pm, W, np, torch):
         ch = W.banana_chain(T=1024, seed=0)
         g = pm.Target(ctx, ch.target, dtype=torch.float64)
         x0, xi, u = t(ch.x0), t(ch.xi), t(ch.u)
-        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch)
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch, "sequential")
         res["sequential_ms"] = 1e3 * ts
         for name, kw in [("diag", dict(variant="diag")), ("dense_clip_inf", dict(variant="dense", clip=1.0,
                                                                                   clip_inf_norm=True)),
                          ("dense", dict(variant="dense")), ("picard", dict(variant="picard")),
                          ("diag_graph8", dict(variant="diag", graph_sweeps=8))]:
-            r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=1025, **kw), reps, torch)
+            r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=1025, **kw), reps, torch, name)
             res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status,
                          "chain_steps_per_s": 1024 / tp, "vs_sequential": ts / tp,
                          "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
@@ -245,12 +260,12 @@ def other_workload(args, pm, W, np, torch):
         g = pm.Target(ctx, pr.target)
         x0, mom, U = t(pr.x0), t(pr.momenta), t(pr.U)
         rs, ts = _timed(lambda: pm.hmc_sample(ctx, g, pr.eps, pr.L, x0, mom, U, parallel_leapfrog=False),
-                        reps, torch)
+                        reps, torch, "sequential leapfrog")
         res["sequential_leapfrog_ms"] = 1e3 * ts
         res["acceptance"] = rs["n_accept"] / 2000
         for v in ("block2", "diag", "picard"):
             r, tp = _timed(lambda: pm.hmc_sample(ctx, g, pr.eps, pr.L, x0, mom, U, variant=v,
-                                                 atol=1e-6, rtol=1e-6), reps, torch)
+                                                 atol=1e-6, rtol=1e-6), reps, torch, v)
             sw = np.array(r["sweeps"])
             res[v] = {"ms": 1e3 * tp, "vs_sequential": ts / tp, "sweeps_median": float(np.median(sw)),
                       "sweeps_p90": float(np.percentile(sw, 90)), "sweeps_max": int(sw.max()),
@@ -259,18 +274,19 @@ def other_workload(args, pm, W, np, torch):
         ch = W.funnel_chain(T=16384, seed=0)
         g = pm.Target(ctx, ch.target)
         x0, xi, u = t(ch.x0), t(ch.xi), t(ch.u)
-        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch)
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch, "sequential")
         res["sequential_ms"] = 1e3 * ts
         for name, kw in [("diag", dict(variant="diag")), ("dense_f32", dict(variant="dense", jac_prec="f32")),
                          ("dense_bf16", dict(variant="dense", jac_prec="bf16"))]:
-            r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=16385, **kw), reps, torch)
+            r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=16385, **kw), reps, torch,
+                           name)
             res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status, "n_floor": r.n_floor,
                          "vs_sequential": ts / tp,
                          "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
         r = pm.solve(ctx, g, ch.eps, x0, xi, u, variant="diag", max_iter=16385)
         dF = ((2.0 / ch.T) * r.states).contiguous()
         (dth, dep), ta = _timed(lambda: pm.adjoint(ctx, g, ch.eps, x0, xi, u, r.states, r.accept, dF),
-                                reps, torch)
+                                reps, torch, "adjoint")
         res["adjoint"] = {"ms": 1e3 * ta, "dF_dtheta": dth, "dF_deps": dep, "theta": ch.target["theta"]}
     elif args.workload == "batched":
         b = W.logreg_batch(seed=0, n_chains=512, lo=4096, hi=131072, eps=args.eps)
@@ -282,13 +298,15 @@ def other_workload(args, pm, W, np, torch):
         off = list(int(v) for v in b.offsets)
         n = int(b.offsets[-1])
         res["n_steps"] = n
-        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, b.eps, s0, xi, u, offsets=off), 1, torch)
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, b.eps, s0, xi, u, offsets=off), 1, torch,
+                        "sequential")
         res["sequential"] = {"ms": 1e3 * ts, "chain_steps_per_s": n / ts}
         pm.autotune(ctx, g, b.eps, s0, xi, u)
-        for name, kw in [("diag_graph8", dict(variant="diag", graph_sweeps=8)),
-                         ("diag_window", dict(variant="diag", skip_converged_prefix=True))]:
+        for name, kw in [("diag_window_graph8", dict(variant="diag", graph_sweeps=8)),
+                         ("diag_window", dict(variant="diag")),
+                         ("diag_no_window", dict(variant="diag", skip_converged_prefix=False))]:
             r, tp = _timed(lambda: pm.solve(ctx, g, b.eps, s0, xi, u, offsets=off, max_iter=400, **kw), 1,
-                           torch)
+                           torch, name)
             spc = np.array(r.sweeps_per_chain)
             res[name] = {"ms": 1e3 * tp, "chain_steps_per_s": n / tp, "vs_sequential": ts / tp,
                          "status": r.status, "n_converged": r.n_converged, "n_floor": r.n_floor,

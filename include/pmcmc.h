@@ -121,8 +121,10 @@ typedef struct {
     double clip;              /* > 0: clip entries of J to [-clip, clip] (clip_inf_norm = 0), or
                                  rescale J so that |J|_inf <= clip (clip_inf_norm = 1)        */
     int clip_inf_norm;
-    int skip_converged_prefix;/* sliding window: each sweep starts at the chain's first
-                                 unconverged step                                            */
+    int skip_converged_prefix;/* sliding window (default 1): each sweep starts at the chain's
+                                 first unconverged step, so the converged prefix is frozen;
+                                 without it, rounding-level changes of that prefix can keep
+                                 flipping a near-tie accept decision further on              */
     int graph_sweeps;         /* > 0: replay a captured HIP graph of this many sweeps between
                                  host convergence checks; 0: one host check per sweep       */
     void *trace_out;          /* DEVICE or NULL: iterate after every sweep, [max_iter, n_steps, D] */

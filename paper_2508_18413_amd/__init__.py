@@ -162,7 +162,7 @@ def _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out
 
 
 def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rtol=None,
-             max_iter=0, damping=1.0, clip=0.0, clip_inf_norm=False, skip_converged_prefix=False,
+             max_iter=0, damping=1.0, clip=0.0, clip_inf_norm=False, skip_converged_prefix=True,
              graph_sweeps=0, trace=None, floor_stall=None, profile_kernels=False):
     o = B.pmc_options()
     B.check(B.lib().pmc_default_options(C.byref(o), _dtype_code(dtype)))

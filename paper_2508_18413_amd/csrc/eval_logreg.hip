@@ -24,6 +24,9 @@
 //   registers between lanes l and l ^ 32.
 #include <math.h>
 
+#include <algorithm>
+
+#include "logistic.hpp"
 #include "pmc_internal.hpp"
 
 namespace pmc {
@@ -34,29 +37,20 @@ constexpr int kWaves = 4;
 
 __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-__device__ __forceinline__ float sigm(float z)
-{
-    const float e = expf(-fabsf(z));
-    const float r = 1.f / (1.f + e);
-    return z >= 0.f ? r : e * r;
-}
-
-// With s = sigma(z) and m = expm1(dz): sigma(z + dz) = s (1 + m) / (1 + s m) and
-// softplus(z + dz) - softplus(z) = log1p(s m); one exponential serves both.
-// Large increments (dz >= 30) take the direct forms.
+// With s = sigma(z), m = expm1(dz) and w = s m:
+//   sigma(z + dz) = s (1 + m) / (1 + w),  softplus(z + dz) - softplus(z) = log1p(w);
+// one exponential serves both.  Large increments (dz >= 30) take the direct forms.
 __device__ __forceinline__ void shifted(float z, float dz, float s, float &st, float &spd)
 {
     if (dz < 30.f) {
-        const float m = expm1f(dz);
-        const float q = fmaf(s, m, 1.f);
-        st = s * (1.f + m) / q;
-        spd = log1pf(s * m);
+        const float m = expm1_s(dz);
+        const float w = s * m;
+        st = s * (1.f + m) * frcp(1.f + w);
+        spd = log1p_s(w);
     } else {
         const float zt = z + dz;
         st = sigm(zt);
-        const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
-        const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
-        spd = spt - sp;
+        spd = softplus(zt) - softplus(z);
     }
 }
 
@@ -73,6 +67,318 @@ __device__ __forceinline__ void acc_to_b(const f32x16 &c, float (&b)[16], int h)
             b[m] = w < 2 ? c[4 * g + 2 * w] : rc[2 * g + (w - 2)];
         else
             b[m] = w < 2 ? rc[2 * g + w] : c[4 * g + 2 * (w - 2) + 1];
+    }
+}
+
+// Same exchange with the gfx950 lane-half swap: the instruction exchanges
+// the upper 32 lanes of its first operand with the lower 32 lanes of its
+// second, which turns the pair (c[4g], c[4g+1]) into (b[4g], b[4g+2]) and
+// (c[4g+2], c[4g+3]) into (b[4g+1], b[4g+3]).
+__device__ __forceinline__ void acc_to_b_swap(const f32x16 &c, float (&b)[16])
+{
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[4 * g]),
+                                                        __float_as_uint(c[4 * g + 1]), false, false);
+        b[4 * g] = __uint_as_float(p[0]);
+        b[4 * g + 2] = __uint_as_float(p[1]);
+        const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[4 * g + 2]),
+                                                        __float_as_uint(c[4 * g + 3]), false, false);
+        b[4 * g + 1] = __uint_as_float(q[0]);
+        b[4 * g + 3] = __uint_as_float(q[1]);
+    }
+}
+
+// v(lane) + v(lane ^ 32), added in the same order in both halves.
+__device__ __forceinline__ float half_sum(float v)
+{
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------ LDS-resident evaluation
+// The data matrix (rows padded to 32, row stride kXS words, zero columns up
+// to kXS) and y live in LDS, loaded once per workgroup; the workgroup's waves
+// then take 32-step tiles round-robin until none is left.  A fragments are
+// read from LDS in both layouts, so nothing but the iterate, the noise and
+// the outputs touch global memory inside the loop.  The per-step epilogue
+// works in the B layout (lane (i, hh) holds coordinates 2 m + hh of step i)
+// and combines the two halves with lane swaps.  The Hessian diagonal, which
+// only shapes the Jacobian approximation, is accumulated with BF16 matrix
+// instructions whose contraction slots are assigned to the rows already held
+// in the FP32 fragments (slot j of instruction kk, half hh <-> row
+// 2 (8 kk + j) + hh).
+constexpr int kXS = 33;
+constexpr int kLdsWaves = 8;
+constexpr int kLdsMaxRowTiles = 36;  // 36 * 32 * 34 * 4 bytes = 153 KiB
+
+struct LdsArgs {
+    const float *xl;  // [nr * 32 * kXS] padded X followed by [nr * 32] padded y
+    int nr;
+    float pp;
+};
+
+// Per-element work of pass 2 for the usual range of increments (-8 < dz < 30),
+// free of branches so that the compiler can overlap it with matrix
+// instructions: s = sigma(z), m = expm1(dz), w = s m,
+//   sigma(z + dz) = (s + w) / (1 + w),  softplus(z + dz) - softplus(z) = log1p(w),
+// with one reciprocal of (2 + w)(1 + w) serving both divisions.
+__device__ __forceinline__ void pass2_elem(float z, float dz, float &st, float &spd)
+{
+    const float s = sigm(z);
+    float q = fmaf(dz, 1.f / 40320.f, 1.f / 5040.f);
+    q = fmaf(dz, q, 1.f / 720.f);
+    q = fmaf(dz, q, 1.f / 120.f);
+    q = fmaf(dz, q, 1.f / 24.f);
+    q = fmaf(dz, q, 1.f / 6.f);
+    q = fmaf(dz, q, 0.5f);
+    q = fmaf(dz, q, 1.f);
+    const float m = fabsf(dz) < 0.5f ? dz * q : fexp(dz) - 1.f;
+    const float w = s * m;
+    const float a1 = 1.f + w, a2 = 2.f + w;
+    const float R = frcp(a1 * a2);
+    const float r = w * a1 * R;  // w / (2 + w)
+    const float r2 = r * r;
+    float p = fmaf(r2, 2.f / 7.f, 2.f / 5.f);
+    p = fmaf(r2, p, 2.f / 3.f);
+    p = fmaf(r2, p, 2.f);
+    spd = fabsf(w) < 0.25f ? r * p : flog(a1);
+    st = (s + w) * a2 * R;
+}
+
+// The same quantities for any increment, written directly.
+__device__ __forceinline__ void pass2_elem_wide(float z, float dz, float &st, float &spd)
+{
+    const float zt = z + dz;
+    st = sigm(zt);
+    spd = softplus(zt) - softplus(z);
+}
+
+template <int MK>
+__device__ __forceinline__ f32x16 z_chain(const float *xr, int i, int hh, const float (&v)[MK])
+{
+    f32x16 Z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < MK; m++) Z = __builtin_amdgcn_mfma_f32_32x32x2f32(xr[i * kXS + 2 * m + hh], v[m], Z, 0, 0, 0);
+    return Z;
+}
+
+template <int MK>
+__global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs a, LdsArgs f)
+{
+    extern __shared__ float s_x[];
+    const int nrow = f.nr * 32;
+    {
+        const int nw = nrow * (kXS + 1);
+        const float4 *src = (const float4 *)f.xl;
+        float4 *dst = (float4 *)s_x;
+        for (int k = threadIdx.x; k < nw / 4; k += blockDim.x) dst[k] = src[k];
+    }
+    __syncthreads();
+    const float *s_y = s_x + nrow * kXS;
+    const int lane = threadIdx.x & 63, i = lane & 31, hh = lane >> 5;
+    const int D = a.D, nr = f.nr;
+    const int64_t ld = a.ld;
+    const float *S = (const float *)a.S, *noise = (const float *)a.noise;
+    float *F = (float *)a.F, *J = (float *)a.J;
+    const float eps = (float)a.eps, c = sqrtf(2.f * eps), hq = sqrtf(0.5f * eps), pp = f.pp;
+    const float damp = (float)a.damping, clip = (float)a.clip;
+    const bool want_j = a.jmode == JM_DIAG;
+    const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    // tiles are dealt to waves round-robin (tile costs are uniform; the idle
+    // prefix of a sliding window spreads over all waves)
+    const int n_waves = gridDim.x * kLdsWaves;
+    for (int tix = blockIdx.x * kLdsWaves + (threadIdx.x >> 6); tix < a.n_tiles; tix += n_waves) {
+        const SegTile tl = a.tiles[tix];
+        const ChainStatus &cs = a.chains[tl.chain];
+        if (!cs.active || tl.start + tl.len <= cs.win_start) continue;
+        const int64_t t = tl.start + i;
+        const bool valid = i < tl.len && t >= cs.win_start;
+        const int64_t tt = i < tl.len ? t : tl.start;
+        const bool head = (tt == a.offsets[tl.chain]);
+        const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
+
+        float SB[MK];
+#pragma unroll
+        for (int m = 0; m < MK; m++) {
+            const int d = 2 * m + hh;
+            SB[m] = d < D ? (head ? s0[d] : S[(size_t)d * ld + tt - 1]) : 0.f;
+        }
+
+        // ---- pass 1: gradient and Hessian diagonal of the log-likelihood at
+        // s_{t-1}; the next row tile's predictors are issued before this
+        // tile's element work so the two overlap
+        f32x16 G = zero, Hd = zero;
+        f32x16 Zc = z_chain<MK>(s_x, i, hh, SB);
+        for (int rt = 0; rt < nr; rt++) {
+            const float *xr = s_x + (32 * rt) * kXS;
+            const int rn = rt + 1 < nr ? rt + 1 : rt;
+            const f32x16 Zn = z_chain<MK>(s_x + (32 * rn) * kXS, i, hh, SB);
+            const float4 *y4 = (const float4 *)(s_y + 32 * rt + 4 * hh);
+            f32x16 R, Wv;
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const float4 y4v = y4[2 * g];
+                const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const float sv = sigm(Zc[4 * g + q]);
+                    R[4 * g + q] = yv[q] - sv;
+                    Wv[4 * g + q] = fmaf(-sv, sv, sv);
+                }
+            }
+            float XT[16], RB[16], WB[16];
+#pragma unroll
+            for (int m = 0; m < 16; m++) XT[m] = xr[(2 * m + hh) * kXS + i];
+            acc_to_b_swap(R, RB);
+#pragma unroll
+            for (int m = 0; m < 16; m++) G = __builtin_amdgcn_mfma_f32_32x32x2f32(XT[m], RB[m], G, 0, 0, 0);
+            acc_to_b_swap(Wv, WB);
+#pragma unroll
+            for (int kk = 0; kk < 2; kk++) {
+                bf16x8 A, B;
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const float xv = XT[8 * kk + j];
+                    A[j] = (__bf16)(xv * xv);
+                    B[j] = (__bf16)WB[8 * kk + j];
+                }
+                Hd = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, Hd, 0, 0, 0);
+            }
+            Zc = Zn;
+        }
+        // gradient at s_{t-1}, the proposal increment, and the Jacobian
+        // diagonal for an accepted step (rejected steps rewrite it below)
+        float gB[MK], DB[MK];
+        {
+            float GB[16], HB[16];
+            acc_to_b_swap(G, GB);
+            acc_to_b_swap(Hd, HB);
+#pragma unroll
+            for (int m = 0; m < MK; m++) {
+                const int d = 2 * m + hh;
+                gB[m] = GB[m] - pp * SB[m];
+                DB[m] = d < D ? fmaf(eps, gB[m], c * noise[(size_t)tt * D + d]) : 0.f;
+                if (want_j && valid && d < D) {
+                    float jv = damp * fmaf(eps, -HB[m] - pp, 1.f);
+                    if (clip > 0) jv = fminf(fmaxf(jv, -clip), clip);
+                    J[(size_t)d * ld + t] = jv;
+                }
+            }
+        }
+
+        // ---- pass 2: gradient at the proposal and log-likelihood difference
+        f32x16 Gt = zero;
+        float dll_y = 0.f, dll_s = 0.f;
+        Zc = z_chain<MK>(s_x, i, hh, SB);
+        f32x16 dZc = z_chain<MK>(s_x, i, hh, DB);
+        for (int rt = 0; rt < nr; rt++) {
+            const float *xr = s_x + (32 * rt) * kXS;
+            const int rn = rt + 1 < nr ? rt + 1 : rt;
+            f32x16 Zn = zero, dZn = zero;
+            {
+                const float *xn = s_x + (32 * rn) * kXS;
+#pragma unroll
+                for (int m = 0; m < MK; m++) {
+                    const float a1 = xn[i * kXS + 2 * m + hh];
+                    Zn = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, SB[m], Zn, 0, 0, 0);
+                    dZn = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, DB[m], dZn, 0, 0, 0);
+                }
+            }
+            const float4 *y4 = (const float4 *)(s_y + 32 * rt + 4 * hh);
+            f32x16 Rt, Sp;
+            bool wide = false;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const float dz = dZc[r];
+                float st, spd;
+                pass2_elem(Zc[r], dz, st, spd);
+                Rt[r] = st;
+                Sp[r] = spd;
+                wide |= !(dz > -8.f && dz < 30.f);
+            }
+            if (__builtin_amdgcn_ballot_w64(wide)) {  // rare: recompute out-of-range elements
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    const float dz = dZc[r];
+                    if (!(dz > -8.f && dz < 30.f)) {
+                        float st, spd;
+                        pass2_elem_wide(Zc[r], dz, st, spd);
+                        Rt[r] = st;
+                        Sp[r] = spd;
+                    }
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const float4 y4v = y4[2 * g];
+                const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int r = 4 * g + q;
+                    Rt[r] = yv[q] - Rt[r];
+                    dll_y = fmaf(yv[q], dZc[r], dll_y);
+                    dll_s += Sp[r];
+                }
+            }
+            float XT[16], RB[16];
+#pragma unroll
+            for (int m = 0; m < 16; m++) XT[m] = xr[(2 * m + hh) * kXS + i];
+            acc_to_b_swap(Rt, RB);
+#pragma unroll
+            for (int m = 0; m < 16; m++) Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(XT[m], RB[m], Gt, 0, 0, 0);
+            Zc = Zn;
+            dZc = dZn;
+        }
+        const float dll = half_sum(dll_y - dll_s);
+
+        // ---- per step (both halves): log ratio, decision, f_t
+        float GtB[16];
+        acc_to_b_swap(Gt, GtB);
+        float sn = 0.f, sx = 0.f, dpr = 0.f;
+#pragma unroll
+        for (int m = 0; m < MK; m++) {
+            const int d = 2 * m + hh;
+            if (d < D) {
+                const float x = SB[m], dl = DB[m], xt = x + dl;
+                const float gt = GtB[m] - pp * xt;
+                const float sg = gB[m] + gt;
+                sn = fmaf(sg, sg, sn);
+                sx = fmaf(noise[(size_t)tt * D + d], sg, sx);
+                dpr = fmaf(dl, xt + x, dpr);
+            }
+        }
+        sn = half_sum(sn);
+        sx = half_sum(sx);
+        dpr = half_sum(dpr);
+        if (valid) {
+            int acc = 1;
+            float gate = INFINITY;
+            if (!a.ula) {
+                const float ell = dll - 0.5f * pp * dpr - 0.25f * eps * sn - hq * sx;
+                const float la = ell < 0.f ? ell : 0.f;
+                gate = la - logf(((const float *)a.unif)[t]);
+                acc = gate > 0.f;
+                if (!(ell == ell)) acc = 0;
+            }
+            float jrej = damp;
+            if (clip > 0) jrej = fminf(fmaxf(jrej, -clip), clip);
+#pragma unroll
+            for (int m = 0; m < MK; m++) {
+                const int d = 2 * m + hh;
+                if (d < D) {
+                    F[(size_t)d * ld + t] = acc ? SB[m] + DB[m] : SB[m];
+                    if (want_j && !acc) J[(size_t)d * ld + t] = jrej;
+                }
+            }
+            if (hh == 0) {
+                if (a.accept) a.accept[t] = (uint8_t)acc;
+                if (a.gtilde) a.gtilde[t] = gate;
+            }
+        }
     }
 }
 
@@ -258,6 +564,34 @@ __global__ void k_logreg_frags(const float *X, int ldx, const float *y, int N, i
     if (lane < 32) ypad[32 * rt + lane] = (32 * rt + lane < N) ? y[32 * rt + lane] : 0.f;
 }
 
+
+// LDS image: X rows padded to nr * 32, row stride kXS, zero columns beyond D,
+// followed by y padded with zeros.
+__global__ void k_logreg_lds_image(const float *X, int ldx, const float *y, int N, int D, int nr, float *xl)
+{
+    const int nrow = nr * 32;
+    const int64_t total = (int64_t)nrow * (kXS + 1);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        if (k < (int64_t)nrow * kXS) {
+            const int n = (int)(k / kXS), d = (int)(k % kXS);
+            if (n < N && d < D) v = X[(size_t)n * ldx + d];
+        } else {
+            const int n = (int)(k - (int64_t)nrow * kXS);
+            if (n < N) v = y[n];
+        }
+        xl[k] = v;
+    }
+}
+
+template <int MK>
+hipError_t allow_lds()
+{
+    return hipFuncSetAttribute((const void *)k_eval_logreg_lds<MK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kLdsMaxRowTiles * 32 * (kXS + 1) * (int)sizeof(float));
+}
+
 }  // namespace
 
 pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
@@ -265,6 +599,20 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
     const int nr = (t.n_data + 31) / 32, mk = (t.dim + 1) / 2;
     t.nr = nr;
     t.mk = mk <= 2 ? 2 : mk <= 4 ? 4 : mk <= 8 ? 8 : mk <= 13 ? 13 : 16;
+    if (nr <= kLdsMaxRowTiles) {
+        // LDS-resident path: one padded image of X and y
+        const size_t bl = sizeof(float) * (size_t)nr * 32 * (kXS + 1);
+        PMC_TRY_HIP(hipMalloc(&t.xl, bl));
+        hipLaunchKernelGGL(k_logreg_lds_image, dim3(64), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
+                           (const float *)t.y, t.n_data, t.dim, nr, (float *)t.xl);
+        PMC_TRY_HIP(hipGetLastError());
+        PMC_TRY_HIP(allow_lds<2>());
+        PMC_TRY_HIP(allow_lds<4>());
+        PMC_TRY_HIP(allow_lds<8>());
+        PMC_TRY_HIP(allow_lds<13>());
+        PMC_TRY_HIP(allow_lds<16>());
+        return PMC_OK;
+    }
     const size_t bxa = sizeof(float) * nr * t.mk * 64, bxt = sizeof(float) * nr * 16 * 64;
     PMC_TRY_HIP(hipMalloc(&t.xa, bxa));
     PMC_TRY_HIP(hipMalloc(&t.xta, bxt));
@@ -279,6 +627,23 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
 
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
 {
+    if (a.n_tiles <= 0) return PMC_OK;
+    if (t.xl) {
+        LdsArgs f{(const float *)t.xl, t.nr, (float)(1.0 / t.prior_var)};
+        const size_t lds = sizeof(float) * (size_t)t.nr * 32 * (kXS + 1);
+        const int want = (a.n_tiles + kLdsWaves - 1) / kLdsWaves;
+        dim3 grid(std::max(1, std::min(want, ctx->n_cu > 0 ? ctx->n_cu : 256))), block(64 * kLdsWaves);
+        switch (t.mk) {
+        case 2: hipLaunchKernelGGL(k_eval_logreg_lds<2>, grid, block, lds, ctx->stream, a, f); break;
+        case 4: hipLaunchKernelGGL(k_eval_logreg_lds<4>, grid, block, lds, ctx->stream, a, f); break;
+        case 8: hipLaunchKernelGGL(k_eval_logreg_lds<8>, grid, block, lds, ctx->stream, a, f); break;
+        case 13: hipLaunchKernelGGL(k_eval_logreg_lds<13>, grid, block, lds, ctx->stream, a, f); break;
+        case 16: hipLaunchKernelGGL(k_eval_logreg_lds<16>, grid, block, lds, ctx->stream, a, f); break;
+        default: set_error("logreg eval: unsupported dimension"); return PMC_ERR_UNSUPPORTED;
+        }
+        PMC_TRY_HIP(hipGetLastError());
+        return PMC_OK;
+    }
     Frags f{(const float *)t.xa, (const float *)t.xta, (const float *)t.x2ta, (const float *)t.ypad,
             t.nr, (float)(1.0 / t.prior_var)};
     dim3 grid((a.n_tiles + kWaves - 1) / kWaves), block(64 * kWaves);

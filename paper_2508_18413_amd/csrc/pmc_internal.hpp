@@ -85,20 +85,25 @@ struct GlobalStatus {
     float max_ratio;
     uint32_t nonfinite;
     int64_t n_accept;
+    int64_t next_steps;  // steps the next sweep evaluates (active chains, from their windows)
     uint32_t fold_ctr;   // status-fold completion counter; zero between launches
     uint32_t pad;
 };
 
-// Synchronisation words of the single-pass scans.  The last workgroup of a
-// launch resets the tile counter and advances the epoch that tags every
-// look-back descriptor, so descriptors never need clearing and captured
-// graphs can replay the scan.
+// Synchronisation words of the single-pass scans.  A one-thread kernel after
+// each scan advances the epoch that tags every look-back descriptor, so
+// descriptors never need clearing and captured graphs can replay the scan.
+// pad is raised when a look-back gives up.
 struct ScanSync {
-    uint32_t tile_ctr;
-    uint32_t done_ctr;
+    uint32_t spare0;
+    uint32_t spare1;
     uint32_t epoch;
     uint32_t pad;
 };
+// Slots of pmc_context::sync: 0 = single-pass scans (the others are spare).
+constexpr int kScanSyncSlot = 0;
+constexpr int kMaxSyncSlots = 4;
+
 
 // ------------------------------------------------------------ targets
 struct DevTarget {
@@ -116,6 +121,7 @@ struct DevTarget {
     // logreg matrix-core fragments (per 32-row tile)
     int nr = 0, mk = 0;
     void *xa = nullptr, *xta = nullptr, *x2ta = nullptr, *ypad = nullptr;
+    void *xl = nullptr;    // LDS image of X and y (small data sets)
 };
 
 }  // namespace pmc

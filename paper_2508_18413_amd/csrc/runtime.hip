@@ -191,8 +191,8 @@ pmc_status pmc_create(pmc_context **out, int device, void *hip_stream)
     ctx->stream = (hipStream_t)hip_stream;
     ctx->arch = prop.gcnArchName;
     ctx->n_cu = prop.multiProcessorCount;
-    if (hipMalloc((void **)&ctx->sync, sizeof(ScanSync) * 4) != hipSuccess ||
-        hipMemset(ctx->sync, 0, sizeof(ScanSync) * 4) != hipSuccess ||
+    if (hipMalloc((void **)&ctx->sync, sizeof(ScanSync) * kMaxSyncSlots) != hipSuccess ||
+        hipMemset(ctx->sync, 0, sizeof(ScanSync) * kMaxSyncSlots) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_status, sizeof(GlobalStatus)) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
         hipEventCreate(&ctx->kev[0]) != hipSuccess || hipEventCreate(&ctx->kev[1]) != hipSuccess ||
@@ -314,7 +314,7 @@ pmc_status pmc_target_destroy(pmc_target *tgt)
     if (tgt->t.prec) (void)hipFree(tgt->t.prec);
     if (tgt->t.X) (void)hipFree(tgt->t.X);
     if (tgt->t.y) (void)hipFree(tgt->t.y);
-    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad})
+    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl})
         if (q) (void)hipFree(q);
     delete tgt;
     return PMC_OK;

@@ -18,9 +18,11 @@
 // Descriptor words are 64-bit (tag << 32 | 32-bit payload piece) written and
 // read with agent-scope atomics, so every word validates itself and no memory
 // fence is needed between payload and flag.  Tags carry a per-launch epoch
-// that the last workgroup of each launch advances (descriptors never need
-// clearing; captured graphs can replay the scan).  Tile ids come from an
-// atomic counter so a tile's predecessors were scheduled before it.
+// that a one-thread kernel advances after each scan (descriptors never need
+// clearing; captured graphs can replay the scan).  A tile's id is its
+// workgroup index: workgroups are dispatched in index order on each XCD, so a
+// tile's predecessors were scheduled before it, and no per-tile counter (a
+// same-address atomic that serialises across XCDs) is needed.
 #include <float.h>
 #include <math.h>
 
@@ -343,10 +345,23 @@ __device__ __forceinline__ Part part_shfl_xor(const Part &p, int m)
 }
 
 template <typename R>
+__device__ __forceinline__ float delta_ratio(R delta, R snew, double atol, double rtol)
+{
+    return (float)(fabs((double)delta) / (atol + rtol * fabs((double)snew)));
+}
+// FP32 states: the ratio in FP32 with the hardware reciprocal (one ulp); it
+// only feeds the comparison with 1 and the reported maximum.
+template <>
+__device__ __forceinline__ float delta_ratio<float>(float delta, float snew, double atol, double rtol)
+{
+    return fabsf(delta) * __builtin_amdgcn_rcpf(fmaf((float)rtol, fabsf(snew), (float)atol));
+}
+
+template <typename R>
 __device__ __forceinline__ void part_add(Part &p, int64_t t, R delta, R snew, R b, double atol,
                                          double rtol)
 {
-    float r = (float)(fabs((double)delta) / (atol + rtol * fabs((double)snew)));
+    float r = delta_ratio<R>(delta, snew, atol, rtol);
     if (!(r == r)) r = INFINITY;
     if (!isfinite(snew)) p.nonfinite++;
     if (r > 1.f && t < p.first_bad) p.first_bad = t;
@@ -611,18 +626,15 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
     using A = Aff<R, M>;
     using DS = Desc<R, M>;
 
-    __shared__ uint32_t s_id, s_epoch;
+    __shared__ uint32_t s_epoch;
     __shared__ A s_wagg[NW];
     __shared__ R s_carry[M];
     __shared__ Part s_part[NW];
 
     const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
-    if (tid == 0) {
-        s_id = atomicAdd(&sync->tile_ctr, 1u);
-        s_epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (tid == 0) s_epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const uint32_t id = s_id, epoch = s_epoch;
+    const uint32_t id = blockIdx.x, epoch = s_epoch;
     const int lane = (int)(id / (uint32_t)n_tiles), ti = (int)(id % (uint32_t)n_tiles);
 
     int64_t t0 = 0, t1 = 0;
@@ -755,15 +767,14 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
             tp.resid_inf = p.rinf;
         }
     }
-    // the last workgroup resets the counter and advances the epoch
-    if (tid == 0) {
-        const uint32_t done = atomicAdd(&sync->done_ctr, 1u);
-        if (done == gridDim.x - 1) {
-            __hip_atomic_store(&sync->tile_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync->done_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync->epoch, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+}
+
+// Advances the descriptor epoch after a scan, so the next launch (or graph
+// replay) ignores every descriptor this one wrote.
+__global__ void k_bump_epoch(ScanSync *sync)
+{
+    const uint32_t e = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&sync->epoch, (e + 1) & 0x3fffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class IO, int BLOCK, int ITEMS>
@@ -779,6 +790,8 @@ pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, Ti
     PMC_TRY(ensure_lb_desc(ctx, n_desc * DS::kWords * sizeof(uint64_t)));
     hipLaunchKernelGGL((k_scan<IO, BLOCK, ITEMS>), dim3((unsigned)n_desc), dim3(BLOCK), 0,
                        ctx->stream, io, ctx->sync, (uint64_t *)ctx->lb_desc, n_tiles, partials);
+    PMC_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;
 }
@@ -897,8 +910,13 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
     __shared__ int s_cnt[kStatusThreads / 64][4];
     Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
     int nact = 0, nconv = 0, nfloor = 0, sweeps = 0;
+    int64_t nsteps = 0;
     for (int i = tid; i < a.n_chains; i += kStatusThreads) {
         const ChainStatus &o = a.chains[i];
+        if (o.active) {
+            const int64_t off = a.offsets[i];
+            nsteps += a.offsets[i + 1] - (o.win_start > off ? o.win_start : off);
+        }
         v.q += o.resid_sq;
         v.qi = fmax(v.qi, o.resid_inf);
         v.r = fmaxf(v.r, o.max_ratio);
@@ -914,12 +932,15 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         nconv += __shfl_xor(nconv, m);
         nfloor += __shfl_xor(nfloor, m);
         sweeps = max(sweeps, __shfl_xor(sweeps, m));
+        nsteps += __shfl_xor(nsteps, m);
     }
+    __shared__ int64_t s_steps[kStatusThreads / 64];
     if ((tid & 63) == 0) {
         s_cnt[tid >> 6][0] = nact;
         s_cnt[tid >> 6][1] = nconv;
         s_cnt[tid >> 6][2] = nfloor;
         s_cnt[tid >> 6][3] = sweeps;
+        s_steps[tid >> 6] = nsteps;
     }
     v = block_fold(v);
     if (tid == 0) {
@@ -928,6 +949,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
             nconv += s_cnt[w][1];
             nfloor += s_cnt[w][2];
             sweeps = max(sweeps, s_cnt[w][3]);
+            nsteps += s_steps[w];
         }
         GlobalStatus *g = a.global;
         g->n_active = nact;
@@ -939,6 +961,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         g->max_ratio = v.r;
         g->nonfinite = v.f;
         g->n_accept = 0;
+        g->next_steps = nsteps;
         __hip_atomic_store(&g->fold_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }

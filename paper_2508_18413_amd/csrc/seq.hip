@@ -12,28 +12,28 @@
 // per-step gradient is a workgroup reduction.
 #include <math.h>
 
+#include "logistic.hpp"
 #include "pmc_internal.hpp"
 #include "targets.hpp"
 
 namespace pmc {
 namespace {
 
-template <typename R>
-__device__ __forceinline__ R sigm(R z)
-{
-    if (z >= R(0)) return R(1) / (R(1) + exp(-z));
-    const R e = exp(z);
-    return e / (R(1) + e);
-}
-// softplus(z + dz) - softplus(z) from s = sigma(z) and one expm1:
-// log1p(s m), m = expm1(dz); written out directly for large dz.
+// softplus(z + dz) - softplus(z) from s = sigma(z): log1p(s expm1(dz)), written
+// out directly for large or very negative increments.
 __device__ __forceinline__ float softplus_diff(float z, float dz, float s)
 {
-    if (dz < 30.f) return log1pf(s * expm1f(dz));
-    const float zt = z + dz;
-    const float spt = zt > 0.f ? zt + log1pf(expf(-zt)) : log1pf(expf(zt));
-    const float sp = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
-    return spt - sp;
+    if (dz > -8.f && dz < 30.f) return log1p_s(s * expm1_s(dz));
+    return softplus(z + dz) - softplus(z);
+}
+
+// Workgroup barrier that orders LDS only: global loads issued before it stay
+// in flight (the sampler prefetches the next step's noise across it).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <class Tg, typename R>
@@ -136,7 +136,7 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
     auto column_sum = [&](float (&v)[V]) {
 #pragma unroll
         for (int i = 0; i < V; i++) s_part[tid * VS + i] = v[i];
-        __syncthreads();
+        lds_barrier();
         if (tid < V * GRP) {
             const int i = tid / GRP, p = tid % GRP;
             float s = 0.f;
@@ -145,7 +145,7 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
             for (int m = 1; m < GRP; m <<= 1) s += __shfl_xor(s, m, 64);
             if (p == 0) s_sum[i] = s;
         }
-        __syncthreads();
+        lds_barrier();
     };
 
     // initial gradient: publish x through s_dl, rows compute predictors
@@ -186,6 +186,13 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
     __syncthreads();
     float zt[RPT], szt[RPT];
     for (int64_t t = t0; t < t1; t++) {
+        // the next step's noise and uniform, loaded now and used at the end
+        // of this step (LDS-only barriers keep the loads in flight)
+        float xin = 0.f, un = 0.5f;
+        if (w0 && t + 1 < t1) {
+            xin = own ? noise[(size_t)(t + 1) * D + lane] : 0.f;
+            if (unif) un = unif[t + 1];
+        }
         // rows: predictors at the proposal, gradient and log-likelihood partials
         float v[V];
 #pragma unroll
@@ -238,8 +245,8 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
             }
             // next step's increment
             if (t + 1 < t1) {
-                xi = own ? noise[(size_t)(t + 1) * D + lane] : 0.f;
-                if (unif) u = unif[t + 1];
+                xi = xin;
+                u = un;
                 dl = own ? fmaf(eps, g, cc * xi) : 0.f;
                 if (lane < DM) {
                     s_dl[lane] = dl;
@@ -248,7 +255,7 @@ k_seq_logreg(SeqArgs a, const float *__restrict__ X, const float *__restrict__ y
             }
             if (lane == 0) s_acc = acc;
         }
-        __syncthreads();
+        lds_barrier();
         if (s_acc) {
 #pragma unroll
             for (int k = 0; k < RPT; k++) {

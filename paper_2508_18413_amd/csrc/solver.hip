@@ -258,6 +258,7 @@ pmc_status pmc_default_options(pmc_options *o, pmc_dtype dtype)
     o->max_iter = 0;
     o->damping = 1.0;
     o->clip = 0.0;
+    o->skip_converged_prefix = 1;
     o->floor_stall = 16;
     return PMC_OK;
 }
@@ -445,17 +446,9 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
         PMC_TRY_HIP(he);
     } else {
         const bool prof = opts->profile_kernels != 0;
+        // steps the first sweep evaluates: every step of every non-empty chain
+        int64_t act_steps = pl.n;
         for (int it = 0; it < pl.max_iter; it++) {
-            // steps this sweep evaluates (active chains, from their windows)
-            int64_t act_steps = 0;
-            if (prof) {
-                PMC_TRY_HIP(hipMemcpyAsync(hc.data(), d_chains, sizeof(ChainStatus) * hc.size(),
-                                           hipMemcpyDeviceToHost, st));
-                PMC_TRY_HIP(hipStreamSynchronize(st));
-                for (int c = 0; c < pl.n_chains; c++)
-                    if (hc[c].active)
-                        act_steps += pl.offs[c + 1] - std::max(hc[c].win_start, pl.offs[c]);
-            }
             PMC_TRY(one_sweep(ctx, pl, sw, prof));
             if (opts->trace_out)
                 PMC_TRY(planes_to_rows(ctx, pl.dt, S,
@@ -470,6 +463,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
                 prof_eval_ms += me;
                 prof_scan_ms += msc;
                 prof_steps += act_steps;
+                act_steps = hs->next_steps;  // from the status fold of this sweep
             }
             sweeps_done = hs->sweeps;
             if (hs->n_active == 0) break;

@@ -156,7 +156,7 @@ def test_causal_exactness_trace(ctx, pm, orc):
     g = pm.Target(ctx, ch.target, dtype=torch.float64)
     for variant in ("diag", "picard"):
         r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant=variant, max_iter=49,
-                     want_trace=True)
+                     want_trace=True, skip_converged_prefix=False)
         ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, ch.u)
         tr = r.trace.cpu().numpy()
         for i in range(r.sweeps):
@@ -404,7 +404,7 @@ def test_batched_full_size_sampled(ctx, pm, orc):
     for c in pick:
         s0[c] = oracle_burnin(tg, _as_chain(b, c)).astype(np.float32)
     r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), variant="diag",
-                 max_iter=400, graph_sweeps=8)
+                 max_iter=400, graph_sweeps=8, skip_converged_prefix=True)
     spc = np.array(r.sweeps_per_chain)
     _say(f"  n={int(b.offsets[-1])} status={r.status} converged={r.n_converged} floor={r.n_floor} "
          f"sweeps median={np.median(spc)} max={spc.max()} ms={r.elapsed_ms:.1f}")
