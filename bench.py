@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+TOL = 5e-7  # Newton stopping tolerance (atol = rtol), the library's FP32 default
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
@@ -74,7 +75,7 @@ def main():
     xi = torch.tensor(ch.xi, device=dev)
     u = torch.tensor(ch.u, device=dev)
     torch.cuda.synchronize()
-    solve_kw = dict(variant="diag", max_iter=T + 1, profile_kernels=True)
+    solve_kw = dict(variant="diag", max_iter=T + 1, profile_kernels=True, atol=TOL, rtol=TOL)
 
     for _ in range(args.warmup):
         pm.solve(ctx, tg, eps, s0, xi, u, **solve_kw)
@@ -124,7 +125,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"mala-logreg-d{D}-n{N}-T{T}-eps{eps}-quasi-deer",
                    "T": T, "D": D, "n_data": N, "eps": eps, "variant": "diag",
-                   "atol": 1e-6, "rtol": 1e-6, "chains": 1},
+                   "atol": TOL, "rtol": TOL, "chains": 1},
         "newton_iters": r.sweeps,
         "n_converged": r.n_converged,
         "n_floor": r.n_floor,
@@ -265,7 +266,7 @@ def other_workload(args, pm, W, np, torch):
         res["acceptance"] = rs["n_accept"] / 2000
         for v in ("block2", "diag", "picard"):
             r, tp = _timed(lambda: pm.hmc_sample(ctx, g, pr.eps, pr.L, x0, mom, U, variant=v,
-                                                 atol=1e-6, rtol=1e-6), reps, torch, v)
+                                                 atol=TOL, rtol=TOL), reps, torch, v)
             sw = np.array(r["sweeps"])
             res[v] = {"ms": 1e3 * tp, "vs_sequential": ts / tp, "sweeps_median": float(np.median(sw)),
                       "sweeps_p90": float(np.percentile(sw, 90)), "sweeps_max": int(sw.max()),
@@ -301,7 +302,7 @@ def other_workload(args, pm, W, np, torch):
         rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, b.eps, s0, xi, u, offsets=off), 1, torch,
                         "sequential")
         res["sequential"] = {"ms": 1e3 * ts, "chain_steps_per_s": n / ts}
-        pm.autotune(ctx, g, b.eps, s0, xi, u)
+        pm.autotune(ctx, g, b.eps, s0, xi, u, offsets=off)
         for name, kw in [("diag_window_graph8", dict(variant="diag", graph_sweeps=8)),
                          ("diag_window", dict(variant="diag")),
                          ("diag_no_window", dict(variant="diag", skip_converged_prefix=False))]:

@@ -170,7 +170,7 @@ pmc_status pmc_target_destroy(pmc_target *tgt);
 pmc_status pmc_workspace_size(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
                               size_t *bytes);
 /* Fills *opts with the defaults: quasi-DEER diagonal, frozen gate,
- * atol = rtol = 1e-6 (1e-12 for F64), max_iter auto, no damping or clipping,
+ * atol = rtol = 5e-7 (1e-12 for F64), max_iter auto, no damping or clipping,
  * floor_stall 16. */
 pmc_status pmc_default_options(pmc_options *opts, pmc_dtype dtype);
 /* Solves every chain of `prob` by parallel Newton iterations.  `workspace`

@@ -292,10 +292,11 @@ def adjoint(ctx: Context, target: Target, eps, s0, noise, uniforms, states, acce
     return th.value, ep.value
 
 
-def autotune(ctx: Context, target: Target, eps, s0, noise, uniforms, cache_path=None, **opts):
+def autotune(ctx: Context, target: Target, eps, s0, noise, uniforms, cache_path=None, offsets=None,
+             **opts):
     """pmc_autotune: pick the scan tile configuration for this shape."""
     p, keep = _problem(target, "mala", eps, s0.reshape(-1, target.dim).contiguous(), noise, uniforms,
-                       None, None, noise, None, None)
+                       offsets, None, noise, None, None)
     o = _options(noise.dtype, **opts)
     B.check(B.lib().pmc_autotune(ctx.h, C.byref(p), C.byref(o),
                                  cache_path.encode() if cache_path else None))

@@ -350,7 +350,7 @@ k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int6
             float r = (float)(fabs((double)y) / (atol + rtol * fabs((double)sn)));
             if (!(r == r)) r = INFINITY;
             if (!isfinite(sn)) p.nonfinite++;
-            if (r > 1.f && t < p.first_bad) p.first_bad = t;
+            if (r > kFreezeRatio && t < p.first_bad) p.first_bad = t;
             p.ratio = fmaxf(p.ratio, r);
             p.rsq += (double)b * b;
             double ab = fabs((double)b);

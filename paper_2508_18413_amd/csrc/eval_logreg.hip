@@ -209,14 +209,35 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
         }
 
         // ---- pass 1: gradient and Hessian diagonal of the log-likelihood at
-        // s_{t-1}; the next row tile's predictors are issued before this
-        // tile's element work so the two overlap
+        // s_{t-1}.  Software-pipelined over row tiles: iteration rt issues the
+        // predictors of tile rt + 1 and the gradient / Hessian products of
+        // tile rt - 1 on the matrix cores while the vector units work on the
+        // sigmoids of tile rt (the group barriers ask the scheduler to
+        // interleave the two instruction streams).
         f32x16 G = zero, Hd = zero;
         f32x16 Zc = z_chain<MK>(s_x, i, hh, SB);
+        float RBp[16], XTp[16];
+        bf16x8 Wp[2];
+#pragma unroll
+        for (int m = 0; m < 16; m++) {
+            RBp[m] = 0.f;
+            XTp[m] = 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) Wp[0][j] = Wp[1][j] = (__bf16)0.f;
         for (int rt = 0; rt < nr; rt++) {
-            const float *xr = s_x + (32 * rt) * kXS;
             const int rn = rt + 1 < nr ? rt + 1 : rt;
             const f32x16 Zn = z_chain<MK>(s_x + (32 * rn) * kXS, i, hh, SB);
+#pragma unroll
+            for (int m = 0; m < 16; m++) G = __builtin_amdgcn_mfma_f32_32x32x2f32(XTp[m], RBp[m], G, 0, 0, 0);
+#pragma unroll
+            for (int kk = 0; kk < 2; kk++) {
+                bf16x8 A;
+#pragma unroll
+                for (int j = 0; j < 8; j++) A[j] = (__bf16)(XTp[8 * kk + j] * XTp[8 * kk + j]);
+                Hd = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Wp[kk], Hd, 0, 0, 0);
+            }
+            const float *xr = s_x + (32 * rt) * kXS;
             const float4 *y4 = (const float4 *)(s_y + 32 * rt + 4 * hh);
             f32x16 R, Wv;
 #pragma unroll
@@ -230,25 +251,32 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
                     Wv[4 * g + q] = fmaf(-sv, sv, sv);
                 }
             }
-            float XT[16], RB[16], WB[16];
 #pragma unroll
-            for (int m = 0; m < 16; m++) XT[m] = xr[(2 * m + hh) * kXS + i];
-            acc_to_b_swap(R, RB);
+            for (int m = 0; m < 16; m++) XTp[m] = xr[(2 * m + hh) * kXS + i];
+            acc_to_b_swap(R, RBp);
+            {
+                float WB[16];
+                acc_to_b_swap(Wv, WB);
 #pragma unroll
-            for (int m = 0; m < 16; m++) G = __builtin_amdgcn_mfma_f32_32x32x2f32(XT[m], RB[m], G, 0, 0, 0);
-            acc_to_b_swap(Wv, WB);
+                for (int kk = 0; kk < 2; kk++)
 #pragma unroll
-            for (int kk = 0; kk < 2; kk++) {
-                bf16x8 A, B;
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const float xv = XT[8 * kk + j];
-                    A[j] = (__bf16)(xv * xv);
-                    B[j] = (__bf16)WB[8 * kk + j];
-                }
-                Hd = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, Hd, 0, 0, 0);
+                    for (int j = 0; j < 8; j++) Wp[kk][j] = (__bf16)WB[8 * kk + j];
             }
             Zc = Zn;
+#pragma unroll
+            for (int k = 0; k < MK + 18; k++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix instruction
+                __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // then vector work
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 16; m++) G = __builtin_amdgcn_mfma_f32_32x32x2f32(XTp[m], RBp[m], G, 0, 0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++) {
+            bf16x8 A;
+#pragma unroll
+            for (int j = 0; j < 8; j++) A[j] = (__bf16)(XTp[8 * kk + j] * XTp[8 * kk + j]);
+            Hd = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Wp[kk], Hd, 0, 0, 0);
         }
         // gradient at s_{t-1}, the proposal increment, and the Jacobian
         // diagonal for an accepted step (rejected steps rewrite it below)
@@ -270,68 +298,83 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
             }
         }
 
-        // ---- pass 2: gradient at the proposal and log-likelihood difference
+        // ---- pass 2: gradient at the proposal and log-likelihood difference.
+        // Row tile rt is processed in four groups of four accumulator rows;
+        // group g also issues the gradient products of tile rt - 1 that use
+        // the B rows 4g..4g+3 (whose registers it then refills with tile
+        // rt's values) and a share of the predictor chains of tile rt + 1,
+        // so matrix and vector work interleave with few live registers.
+        // Elements with |dz| >= 8 are recomputed by a rare direct path.
         f32x16 Gt = zero;
         float dll_y = 0.f, dll_s = 0.f;
         Zc = z_chain<MK>(s_x, i, hh, SB);
         f32x16 dZc = z_chain<MK>(s_x, i, hh, DB);
-        for (int rt = 0; rt < nr; rt++) {
-            const float *xr = s_x + (32 * rt) * kXS;
-            const int rn = rt + 1 < nr ? rt + 1 : rt;
-            f32x16 Zn = zero, dZn = zero;
-            {
-                const float *xn = s_x + (32 * rn) * kXS;
+        float RtB[16];
 #pragma unroll
-                for (int m = 0; m < MK; m++) {
+        for (int m = 0; m < 16; m++) RtB[m] = 0.f;
+        for (int rt = 0; rt < nr; rt++) {
+            const int rn = rt + 1 < nr ? rt + 1 : rt;
+            const float *xn = s_x + (32 * rn) * kXS;
+            const float *xp = s_x + (32 * (rt > 0 ? rt - 1 : 0)) * kXS;
+            const float *yr = s_y + 32 * rt + 4 * hh;
+            f32x16 Zn = zero, dZn = zero;
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+#pragma unroll
+                for (int m = 4 * g; m < 4 * g + 4; m++)
+                    Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[(2 * m + hh) * kXS + i], RtB[m], Gt, 0, 0, 0);
+                constexpr int per = (MK + 3) / 4;
+#pragma unroll
+                for (int m = per * g; m < per * (g + 1) && m < MK; m++) {
                     const float a1 = xn[i * kXS + 2 * m + hh];
                     Zn = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, SB[m], Zn, 0, 0, 0);
                     dZn = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, DB[m], dZn, 0, 0, 0);
                 }
-            }
-            const float4 *y4 = (const float4 *)(s_y + 32 * rt + 4 * hh);
-            f32x16 Rt, Sp;
-            bool wide = false;
-#pragma unroll
-            for (int r = 0; r < 16; r++) {
-                const float dz = dZc[r];
-                float st, spd;
-                pass2_elem(Zc[r], dz, st, spd);
-                Rt[r] = st;
-                Sp[r] = spd;
-                wide |= !(dz > -8.f && dz < 30.f);
-            }
-            if (__builtin_amdgcn_ballot_w64(wide)) {  // rare: recompute out-of-range elements
-#pragma unroll
-                for (int r = 0; r < 16; r++) {
-                    const float dz = dZc[r];
-                    if (!(dz > -8.f && dz < 30.f)) {
-                        float st, spd;
-                        pass2_elem_wide(Zc[r], dz, st, spd);
-                        Rt[r] = st;
-                        Sp[r] = spd;
-                    }
-                }
-            }
-#pragma unroll
-            for (int g = 0; g < 4; g++) {
-                const float4 y4v = y4[2 * g];
+                const float4 y4v = *(const float4 *)(yr + 8 * g);
                 const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
+                float Rt[4];
+                bool wide = false;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const int r = 4 * g + q;
-                    Rt[r] = yv[q] - Rt[r];
-                    dll_y = fmaf(yv[q], dZc[r], dll_y);
-                    dll_s += Sp[r];
+                    const float dz = dZc[4 * g + q];
+                    float st, spd;
+                    pass2_elem(Zc[4 * g + q], dz, st, spd);
+                    const bool in = fabsf(dz) < 8.f;
+                    wide |= !in;
+                    Rt[q] = in ? yv[q] - st : 0.f;
+                    dll_s += in ? spd : 0.f;
+                    dll_y = fmaf(yv[q], dz, dll_y);
                 }
+                if (__builtin_amdgcn_ballot_w64(wide)) {  // rare
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const float dz = dZc[4 * g + q];
+                        if (!(fabsf(dz) < 8.f)) {
+                            float st, spd;
+                            pass2_elem_wide(Zc[4 * g + q], dz, st, spd);
+                            Rt[q] = yv[q] - st;
+                            dll_s += spd;
+                        }
+                    }
+                }
+                // accumulator rows 4g..4g+3 -> B rows 4g, 4g+2, 4g+1, 4g+3
+                const auto p0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(Rt[0]), __float_as_uint(Rt[1]),
+                                                                 false, false);
+                const auto p1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(Rt[2]), __float_as_uint(Rt[3]),
+                                                                 false, false);
+                RtB[4 * g] = __uint_as_float(p0[0]);
+                RtB[4 * g + 2] = __uint_as_float(p0[1]);
+                RtB[4 * g + 1] = __uint_as_float(p1[0]);
+                RtB[4 * g + 3] = __uint_as_float(p1[1]);
             }
-            float XT[16], RB[16];
-#pragma unroll
-            for (int m = 0; m < 16; m++) XT[m] = xr[(2 * m + hh) * kXS + i];
-            acc_to_b_swap(Rt, RB);
-#pragma unroll
-            for (int m = 0; m < 16; m++) Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(XT[m], RB[m], Gt, 0, 0, 0);
             Zc = Zn;
             dZc = dZn;
+        }
+        {
+            const float *xp = s_x + (32 * (nr - 1)) * kXS;
+#pragma unroll
+            for (int m = 0; m < 16; m++)
+                Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[(2 * m + hh) * kXS + i], RtB[m], Gt, 0, 0, 0);
         }
         const float dll = half_sum(dll_y - dll_s);
 

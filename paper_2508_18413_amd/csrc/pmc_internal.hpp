@@ -49,10 +49,14 @@ struct SegTile {
 
 // Per-tile convergence partials, written by every scan tile (neutral when the
 // tile does no work) and folded per chain by the status kernel.
+// A step counts as unsettled (it starts the next sweep's sliding window) when
+// its last change exceeds this fraction of the tolerance.
+constexpr float kFreezeRatio = 1.0f;
+
 struct TilePartial {
     float max_ratio;     // max |delta| / (atol + rtol |s_new|)
     uint32_t nonfinite;  // count of non-finite new iterate elements
-    int64_t first_bad;   // smallest global step index with ratio > 1 (INT64_MAX if none)
+    int64_t first_bad;   // smallest global step index with ratio > kFreezeRatio (INT64_MAX if none)
     double resid_sq;     // sum of squared residuals b_t = f_t(s_{t-1}) - s_t, FP64
     double resid_inf;    // max |b_t|
 };
@@ -60,7 +64,7 @@ struct TilePartial {
 // Per-chain Newton state, device resident.
 struct ChainStatus {
     int64_t win_start;   // first step of the active window (sliding window)
-    int64_t first_bad;   // first unconverged step of the last sweep
+    int64_t first_bad;   // first step of the last sweep not yet settled (ratio > kFreezeRatio)
     double resid_sq;
     double resid_inf;
     float max_ratio;
@@ -72,6 +76,8 @@ struct ChainStatus {
     uint32_t nonfinite;
     int32_t at_floor;    // 1 if stopped at the rounding floor
     int64_t best_front;  // furthest converged front seen
+    int64_t fb_prev;     // first_bad of the sweep before (the window starts at the earlier of
+                         // the two: a step is frozen once it met the tolerance twice in a row)
 };
 
 // Whole-problem status, read by the host after each sweep or graph replay.

@@ -364,7 +364,7 @@ __device__ __forceinline__ void part_add(Part &p, int64_t t, R delta, R snew, R 
     float r = delta_ratio<R>(delta, snew, atol, rtol);
     if (!(r == r)) r = INFINITY;
     if (!isfinite(snew)) p.nonfinite++;
-    if (r > 1.f && t < p.first_bad) p.first_bad = t;
+    if (r > kFreezeRatio && t < p.first_bad) p.first_bad = t;
     p.ratio = fmaxf(p.ratio, r);
     double bb = (double)b;
     p.rsq += bb * bb;
@@ -892,11 +892,16 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
                 cs.at_floor = 1;
                 cs.active = 0;
             } else if (a.skip_prefix && fb != INT64_MAX) {
-                // window start rounded down to a multiple of 4 (aligned vector loads)
+                // the window starts at the first step that has not met the
+                // tolerance in both of the last two sweeps (its frozen
+                // residual is then the second, smaller change), rounded down
+                // to a multiple of 4 (aligned vector loads)
                 const int64_t off = a.offsets[c];
-                const int64_t w = fb & ~(int64_t)3;
+                const int64_t f2 = fb < cs.fb_prev ? fb : cs.fb_prev;
+                const int64_t w = f2 & ~(int64_t)3;
                 cs.win_start = w > off ? w : off;
             }
+            cs.fb_prev = fb;
         }
     }
     // completion count: the last workgroup sees every chain's update

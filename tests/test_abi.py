@@ -52,7 +52,7 @@ def test_default_options():
     B, L = _lib()
     o = B.pmc_options()
     assert L.pmc_default_options(C.byref(o), B.PMC_F32) == B.PMC_OK
-    assert o.variant == B.PMC_QDEER_DIAG and o.atol == 1e-6 and o.damping == 1.0
+    assert o.variant == B.PMC_QDEER_DIAG and o.atol == 5e-7 and o.damping == 1.0
     assert o.skip_converged_prefix == 1 and o.floor_stall == 16
     assert L.pmc_default_options(C.byref(o), B.PMC_F64) == B.PMC_OK
     assert o.atol == 1e-12

@@ -180,7 +180,10 @@ def test_ula_gaussian_one_solve(ctx, pm, orc, dtype):
     first = r.trace[0].cpu().numpy()
     tol = 1e-12 if dtype == "f64" else 1e-5
     assert state_error(first, ref) <= tol
-    assert r.sweeps == 2 and r.status == 0
+    # the confirming sweep moves FP32 states by rounding only (a few ulps),
+    # which the default 5e-7 stop may count as one more change
+    assert r.sweeps == 2 if dtype == "f64" else r.sweeps <= 3
+    assert r.status == 0
 
 
 def _logreg_case(orc, T, eps, seed=0):
