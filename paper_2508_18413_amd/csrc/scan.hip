@@ -33,6 +33,15 @@ namespace {
 
 constexpr int kWave = 64;
 
+// Workgroup barrier that orders LDS only: the tile's global loads and stores
+// stay in flight across it (no thread reads another thread's global data).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------- affine maps
 template <typename R, int M>
 struct Aff {
@@ -195,56 +204,56 @@ __device__ void publish_inc(uint64_t *d, uint32_t epoch, const R (&v)[M])
     }
 }
 
-// Reads one descriptor.  Returns 2 with the inclusive value as a constant map
+// Reads one descriptor (every word is loaded at once, so one round trip
+// serves both forms).  Returns 2 with the inclusive value as a constant map
 // (a = 0, b = value), 1 with the aggregate, or 0 if not yet published.
 template <typename R, int M>
 __device__ int read_desc(const uint64_t *d, uint32_t epoch, Aff<R, M> &out)
 {
     using DS = Desc<R, M>;
     constexpr int P = Pieces<R>::n;
-    uint32_t ti = make_tag(epoch, kIncState), ta = make_tag(epoch, kAggState);
+    const uint32_t ti = make_tag(epoch, kIncState), ta = make_tag(epoch, kAggState);
+    uint64_t x[DS::kWords];
+#pragma unroll
+    for (int w = 0; w < DS::kWords; w++) x[w] = word_load(d + w);
     uint32_t p[P];
-    bool ok = true;
+    bool inc = true, agg = true;
     int w = 0;
 #pragma unroll
     for (int i = 0; i < M; i++) {
 #pragma unroll
-        for (int k = 0; k < P; k++) {
-            uint64_t x = word_load(d + w++);
-            ok &= (uint32_t)(x >> 32) == ti;
-            p[k] = (uint32_t)x;
+        for (int k = 0; k < P; k++, w++) {
+            inc &= (uint32_t)(x[w] >> 32) == ti;
+            p[k] = (uint32_t)x[w];
         }
         out.b[i] = Pieces<R>::join(p);
     }
-    if (ok) {
+    if (inc) {
 #pragma unroll
         for (int i = 0; i < M; i++)
 #pragma unroll
             for (int j = 0; j < M; j++) out.a[i][j] = R(0);
         return 2;
     }
-    ok = true;
 #pragma unroll
     for (int i = 0; i < M; i++) {
 #pragma unroll
         for (int j = 0; j < M; j++) {
 #pragma unroll
-            for (int k = 0; k < P; k++) {
-                uint64_t x = word_load(d + w++);
-                ok &= (uint32_t)(x >> 32) == ta;
-                p[k] = (uint32_t)x;
+            for (int k = 0; k < P; k++, w++) {
+                agg &= (uint32_t)(x[w] >> 32) == ta;
+                p[k] = (uint32_t)x[w];
             }
             out.a[i][j] = Pieces<R>::join(p);
         }
 #pragma unroll
-        for (int k = 0; k < P; k++) {
-            uint64_t x = word_load(d + w++);
-            ok &= (uint32_t)(x >> 32) == ta;
-            p[k] = (uint32_t)x;
+        for (int k = 0; k < P; k++, w++) {
+            agg &= (uint32_t)(x[w] >> 32) == ta;
+            p[k] = (uint32_t)x[w];
         }
         out.b[i] = Pieces<R>::join(p);
     }
-    return ok ? 1 : 0;
+    return agg ? 1 : 0;
 }
 
 // Wave-parallel look-back (wave 0 only).  `self` is this tile's descriptor id,
@@ -253,12 +262,16 @@ __device__ int read_desc(const uint64_t *d, uint32_t epoch, Aff<R, M> &out)
 // A predecessor that never publishes is a bug; after kSpinLimit polls the
 // look-back gives up, raises sync->pad and uses a zero carry, so the launch
 // ends and the host reports the failure instead of hanging the device.
-constexpr uint32_t kSpinLimit = 1u << 21;
+constexpr uint32_t kSpinLimit = 1u << 18;  // polls; with the naps, tens of ms to a fraction of a second
 
 template <typename R, int M>
 __device__ void lookback(uint64_t *desc, int64_t self, int64_t head, uint32_t epoch, R (&carry)[M],
                          ScanSync *sync)
 {
+    // Each round covers the 64 nearest unread predecessors.  While some are
+    // unpublished, only those lanes poll again, after a sleep that doubles up
+    // to about a memory round trip: polling every descriptor at full rate
+    // floods the uncached path the tiles' own data also uses.
     using DS = Desc<R, M>;
     const int lid = threadIdx.x % kWave;
     Aff<R, M> acc = aff_identity<R, M>();
@@ -266,22 +279,26 @@ __device__ void lookback(uint64_t *desc, int64_t self, int64_t head, uint32_t ep
     uint32_t spins = 0;
     for (;;) {
         const int64_t q = p - lid;
-        Aff<R, M> m;
-        int st = 3;  // 3: beyond the sequence head, never needed
-        if (q >= head) st = read_desc<R, M>(desc + (size_t)q * DS::kWords, epoch, m);
-        const uint64_t incmask = __ballot(st == 2);
-        const int first_inc = incmask ? __ffsll((unsigned long long)incmask) - 1 : kWave;
-        const uint64_t waitmask = __ballot(st == 0 && lid <= first_inc);
-        if (waitmask) {
+        Aff<R, M> m = aff_identity<R, M>();
+        int st = q >= head ? 0 : 3;  // 0 unpublished, 1 aggregate, 2 inclusive, 3 beyond the head
+        int nap = 1;
+        for (;;) {
+            if (st == 0) st = read_desc<R, M>(desc + (size_t)q * DS::kWords, epoch, m);
+            const uint64_t incmask = __ballot(st == 2);
+            const int first_inc = incmask ? __ffsll((unsigned long long)incmask) - 1 : kWave;
+            const uint64_t waitmask = __ballot(st == 0 && lid <= first_inc);
+            if (!waitmask) break;
             if (++spins >= kSpinLimit) {
                 if (lid == 0) atomicOr(&sync->pad, 1u);
 #pragma unroll
                 for (int i = 0; i < M; i++) carry[i] = R(0);
                 return;
             }
-            __builtin_amdgcn_s_sleep(2);
-            continue;
+            for (int k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(4);
+            nap = nap < 8 ? 2 * nap : 8;
         }
+        const uint64_t incmask = __ballot(st == 2);
+        const int first_inc = incmask ? __ffsll((unsigned long long)incmask) - 1 : kWave;
         // ordered fold m_0 o m_1 o ... o m_first_inc (lane 0 is the nearest tile)
         if (lid > first_inc || st == 3) m = aff_identity<R, M>();
 #pragma unroll
@@ -626,16 +643,20 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
     using A = Aff<R, M>;
     using DS = Desc<R, M>;
 
-    __shared__ uint32_t s_epoch;
     __shared__ A s_wagg[NW];
     __shared__ R s_carry[M];
     __shared__ Part s_part[NW];
 
     const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
-    if (tid == 0) s_epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint32_t id = blockIdx.x, epoch = s_epoch;
-    const int lane = (int)(id / (uint32_t)n_tiles), ti = (int)(id % (uint32_t)n_tiles);
+    // only wave 0 publishes and looks back; its epoch load overlaps the data loads
+    uint32_t epoch = 0;
+    if (wid == 0) epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Consecutive workgroups take the same tile index of consecutive lanes
+    // (planes), so the tiles in flight form n_lanes short look-back chains
+    // instead of one long chain through a single plane.
+    const uint32_t id = blockIdx.x;
+    const int n_lanes = (int)(gridDim.x / (uint32_t)n_tiles);
+    const int lane = (int)(id % (uint32_t)n_lanes), ti = (int)(id / (uint32_t)n_lanes);
 
     int64_t t0 = 0, t1 = 0;
     int head_ti = 0;
@@ -687,7 +708,7 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         A excl = shfl_up_aff(inc, 1);
         if (lid == 0) excl = aff_identity<R, M>();
         if (lid == kWave - 1) s_wagg[wid] = inc;
-        __syncthreads();
+        lds_barrier();
         A wpre = aff_identity<R, M>();
         for (int w = 0; w < wid; w++) wpre = compose(s_wagg[w], wpre);
         if (wid == 0) {
@@ -709,7 +730,7 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
                 for (int i = 0; i < M; i++) s_carry[i] = carry[i];
             }
         }
-        __syncthreads();
+        lds_barrier();
         R d[M];
 #pragma unroll
         for (int i = 0; i < M; i++) d[i] = s_carry[i];
@@ -755,11 +776,11 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
 #pragma unroll
         for (int m = 1; m < kWave; m <<= 1) part_merge(part, part_shfl_xor(part, m));
         if (lid == 0) s_part[wid] = part;
-        __syncthreads();
+        lds_barrier();
         if (tid == 0) {
             Part p = s_part[0];
             for (int w = 1; w < NW; w++) part_merge(p, s_part[w]);
-            TilePartial &tp = partials[id];
+            TilePartial &tp = partials[(size_t)lane * n_tiles + ti];
             tp.max_ratio = p.ratio;
             tp.nonfinite = p.nonfinite;
             tp.first_bad = p.first_bad;
@@ -1015,6 +1036,7 @@ int scan_tile_steps(pmc_dtype dt, int variant_m, int items, int block)
 {
     if (variant_m > 1) return 256 * (variant_m == 2 ? 4 : 2);
     if (dt == PMC_F64) return 256 * (items >= 8 ? 8 : 4);
+    if (block == 1024) return 1024 * (items >= 16 ? 16 : 8);
     if (block == 512) return 512 * (items >= 16 ? 16 : 8);
     return 256 * (items >= 16 ? 16 : (items >= 8 ? 8 : 4));
 }
@@ -1025,6 +1047,10 @@ pmc_status launch_newton_scan_diag(pmc_context *ctx, pmc_dtype dt, const NewtonS
     if (dt == PMC_F64) {
         if (items >= 8) return diag_newton<double, 256, 8>(ctx, a);
         return diag_newton<double, 256, 4>(ctx, a);
+    }
+    if (block == 1024) {
+        if (items >= 16) return diag_newton<float, 1024, 16>(ctx, a);
+        return diag_newton<float, 1024, 8>(ctx, a);
     }
     if (block == 512) {
         if (items >= 16) return diag_newton<float, 512, 16>(ctx, a);

@@ -165,8 +165,9 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         pl.scan_block = 256;
         pl.C_scan = 256 * pl.scan_items;
     } else {
-        pl.scan_items = ctx->diag_items ? ctx->diag_items : (pl.dt == PMC_F64 ? 8 : 16);
-        pl.scan_block = ctx->diag_block ? ctx->diag_block : 256;
+        // untuned default: 512 x 8 (the fastest of the tuned set at the shapes measured)
+        pl.scan_items = ctx->diag_items ? ctx->diag_items : 8;
+        pl.scan_block = ctx->diag_block ? ctx->diag_block : (pl.dt == PMC_F64 ? 256 : 512);
         pl.C_scan = scan_tile_steps(pl.dt, 1, pl.scan_items, pl.scan_block);
     }
     pl.C_eval = eval_tile_steps(t);
@@ -654,7 +655,7 @@ extern "C" pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, co
     if (base.dt == PMC_F64)
         cands = {{4, 256}, {8, 256}};
     else
-        cands = {{4, 256}, {8, 256}, {16, 256}, {8, 512}, {16, 512}};
+        cands = {{4, 256}, {8, 256}, {16, 256}, {8, 512}, {16, 512}, {8, 1024}, {16, 1024}};
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     // workspace: planes J, F, S (zero), per-tile partials for the smallest tile, tiles, chains
     const size_t plane = (size_t)base.ld * base.es * base.D;
