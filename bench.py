@@ -137,7 +137,7 @@ def main():
         "acceptance": r.n_accept / T,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": None, "kernel": "k_eval_logreg",
+                     "traffic": _traffic("k_eval_logreg_lds"), "kernel": "k_eval_logreg_lds",
                      "avg_launch_ms": eval_avg_ms, "steps_per_launch": steps_per_launch},
         "roofline_scan_in_solve": {"bound": "hbm", "achieved": scan_bytes / (scan_avg_ms * 1e-3) / 1e9,
                                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -160,7 +160,7 @@ def main():
     out["roofline_scan"] = {"bound": "hbm", "achieved": bytes_big / (scan_ms_big * 1e-3) / 1e9,
                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": bytes_big / (scan_ms_big * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                            "traffic": None, "kernel": "k_scan<DiagNewtonIO>",
+                            "traffic": _traffic("k_scan_diag_newton"), "kernel": "k_scan<DiagNewtonIO>",
                             "shape": "16 planes x 2^22 steps, FP32", "avg_launch_ms": scan_ms_big}
     del gx0, gxi, gtg
     torch.cuda.empty_cache()
@@ -216,6 +216,26 @@ def main():
         out["copy_calibration_bytes"] = {"read": 4 * n, "written": 4 * n}
         del src, dst
     print(json.dumps(out), flush=True)
+
+
+def _traffic(key):
+    """HBM bytes per launch of `key` from the committed counter summary
+    (profiles/traffic.json), or None if absent or if the kernel's sources
+    changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, "profiles", "traffic.json")) as f:
+            e = json.load(f)[key]
+        h = hashlib.sha256()
+        for src in e["sources"]:
+            with open(os.path.join(root, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest()[:16] != e["source_sha"]:
+            return None
+        return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _timed(fn, reps, torch, label=""):
