@@ -120,32 +120,18 @@ struct LdsArgs {
     float pp;
 };
 
-// Per-element work of pass 2 for the usual range of increments (-8 < dz < 30),
-// free of branches so that the compiler can overlap it with matrix
-// instructions: s = sigma(z), m = expm1(dz), w = s m,
-//   sigma(z + dz) = (s + w) / (1 + w),  softplus(z + dz) - softplus(z) = log1p(w),
-// with one reciprocal of (2 + w)(1 + w) serving both divisions.
-__device__ __forceinline__ void pass2_elem(float z, float dz, float &st, float &spd)
+// Per-element work of pass 2 for the usual range of increments (|dz| < 8),
+// free of branches: s = sigma(z), m = expm1(dz), w = s m, a = 1 + w,
+//   sigma(z + dz) = (s + w) / a,  softplus(z + dz) - softplus(z) = log1p(w),
+// with one reciprocal of a serving both.
+// Arguments are u = z log2(e) and du = dz log2(e) (the LDS copy of X is scaled).
+__device__ __forceinline__ void pass2_elem(float u, float du, float &st, float &spd)
 {
-    const float s = sigm(z);
-    float q = fmaf(dz, 1.f / 40320.f, 1.f / 5040.f);
-    q = fmaf(dz, q, 1.f / 720.f);
-    q = fmaf(dz, q, 1.f / 120.f);
-    q = fmaf(dz, q, 1.f / 24.f);
-    q = fmaf(dz, q, 1.f / 6.f);
-    q = fmaf(dz, q, 0.5f);
-    q = fmaf(dz, q, 1.f);
-    const float m = fabsf(dz) < 0.5f ? dz * q : fexp(dz) - 1.f;
-    const float w = s * m;
-    const float a1 = 1.f + w, a2 = 2.f + w;
-    const float R = frcp(a1 * a2);
-    const float r = w * a1 * R;  // w / (2 + w)
-    const float r2 = r * r;
-    float p = fmaf(r2, 2.f / 7.f, 2.f / 5.f);
-    p = fmaf(r2, p, 2.f / 3.f);
-    p = fmaf(r2, p, 2.f);
-    spd = fabsf(w) < 0.25f ? r * p : flog(a1);
-    st = (s + w) * a2 * R;
+    const float s = sigm2(u);
+    const float w = s * expm1_2(du);
+    const float a = 1.f + w, ra = frcp(a);
+    spd = log1p_ar(w, a, ra);
+    st = (s + w) * ra;
 }
 
 // The same quantities for any increment, written directly.
@@ -246,7 +232,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
                 const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const float sv = sigm(Zc[4 * g + q]);
+                    const float sv = sigm2(Zc[4 * g + q]);
                     R[4 * g + q] = yv[q] - sv;
                     Wv[4 * g + q] = fmaf(-sv, sv, sv);
                 }
@@ -288,10 +274,10 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
 #pragma unroll
             for (int m = 0; m < MK; m++) {
                 const int d = 2 * m + hh;
-                gB[m] = GB[m] - pp * SB[m];
+                gB[m] = fmaf(GB[m], kLn2, -pp * SB[m]);
                 DB[m] = d < D ? fmaf(eps, gB[m], c * noise[(size_t)tt * D + d]) : 0.f;
                 if (want_j && valid && d < D) {
-                    float jv = damp * fmaf(eps, -HB[m] - pp, 1.f);
+                    float jv = damp * fmaf(eps, fmaf(-HB[m], kLn2 * kLn2, -pp), 1.f);
                     if (clip > 0) jv = fminf(fmaxf(jv, -clip), clip);
                     J[(size_t)d * ld + t] = jv;
                 }
@@ -339,7 +325,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
                     const float dz = dZc[4 * g + q];
                     float st, spd;
                     pass2_elem(Zc[4 * g + q], dz, st, spd);
-                    const bool in = fabsf(dz) < 8.f;
+                    const bool in = fabsf(dz) < 8.f * kLog2e;
                     wide |= !in;
                     Rt[q] = in ? yv[q] - st : 0.f;
                     dll_s += in ? spd : 0.f;
@@ -349,9 +335,9 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
 #pragma unroll
                     for (int q = 0; q < 4; q++) {
                         const float dz = dZc[4 * g + q];
-                        if (!(fabsf(dz) < 8.f)) {
+                        if (!(fabsf(dz) < 8.f * kLog2e)) {
                             float st, spd;
-                            pass2_elem_wide(Zc[4 * g + q], dz, st, spd);
+                            pass2_elem_wide(Zc[4 * g + q] * kLn2, dz * kLn2, st, spd);
                             Rt[q] = yv[q] - st;
                             dll_s += spd;
                         }
@@ -376,7 +362,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
             for (int m = 0; m < 16; m++)
                 Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[(2 * m + hh) * kXS + i], RtB[m], Gt, 0, 0, 0);
         }
-        const float dll = half_sum(dll_y - dll_s);
+        const float dll = half_sum(fmaf(dll_y, kLn2, -dll_s));
 
         // ---- per step (both halves): log ratio, decision, f_t
         float GtB[16];
@@ -387,7 +373,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
             const int d = 2 * m + hh;
             if (d < D) {
                 const float x = SB[m], dl = DB[m], xt = x + dl;
-                const float gt = GtB[m] - pp * xt;
+                const float gt = fmaf(GtB[m], kLn2, -pp * xt);
                 const float sg = gB[m] + gt;
                 sn = fmaf(sg, sg, sn);
                 sx = fmaf(noise[(size_t)tt * D + d], sg, sx);
@@ -608,8 +594,10 @@ __global__ void k_logreg_frags(const float *X, int ldx, const float *y, int N, i
 }
 
 
-// LDS image: X rows padded to nr * 32, row stride kXS, zero columns beyond D,
-// followed by y padded with zeros.
+// LDS image: X log2(e) (predictor products then come out as arguments of
+// exp2; the gradient and Hessian sums are rescaled by ln 2 and ln^2 2), rows
+// padded to nr * 32, row stride kXS, zero columns beyond D, followed by y
+// padded with zeros.
 __global__ void k_logreg_lds_image(const float *X, int ldx, const float *y, int N, int D, int nr, float *xl)
 {
     const int nrow = nr * 32;
@@ -619,7 +607,7 @@ __global__ void k_logreg_lds_image(const float *X, int ldx, const float *y, int 
         float v = 0.f;
         if (k < (int64_t)nrow * kXS) {
             const int n = (int)(k / kXS), d = (int)(k % kXS);
-            if (n < N && d < D) v = X[(size_t)n * ldx + d];
+            if (n < N && d < D) v = X[(size_t)n * ldx + d] * kLog2e;
         } else {
             const int n = (int)(k - (int64_t)nrow * kXS);
             if (n < N) v = y[n];

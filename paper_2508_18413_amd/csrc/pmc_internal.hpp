@@ -195,6 +195,7 @@ struct NewtonScanArgs {
     double atol, rtol;
     double eps;             // leapfrog step (block2)
     void *trace;            // optional copy of S after the update, or nullptr
+    int defer_epoch;        // 1: the status fold that follows advances the scan epoch
 };
 
 // Steps per scan tile for a configuration (the host builds its tile map with it).
@@ -297,6 +298,7 @@ struct StatusArgs {
     int floor_stall;                  // > 0: stop a chain whose ratio has not improved for this
                                       // many sweeps while within 100x of the tolerance
     int64_t n_steps;
+    ScanSync *bump_epoch;             // non-null: the last workgroup advances this scan epoch
 };
 pmc_status launch_status(pmc_context *ctx, const StatusArgs &a);
 // PMC_ERR_HIP if any scan's look-back gave up since the context was created.

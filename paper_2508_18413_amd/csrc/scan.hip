@@ -799,7 +799,8 @@ __global__ void k_bump_epoch(ScanSync *sync)
 }
 
 template <class IO, int BLOCK, int ITEMS>
-pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, TilePartial *partials)
+pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, TilePartial *partials,
+                    bool bump = true)
 {
     using DS = Desc<typename IO::Real, IO::M>;
     const size_t n_desc = (size_t)n_lanes * n_tiles;
@@ -812,8 +813,10 @@ pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, Ti
     hipLaunchKernelGGL((k_scan<IO, BLOCK, ITEMS>), dim3((unsigned)n_desc), dim3(BLOCK), 0,
                        ctx->stream, io, ctx->sync, (uint64_t *)ctx->lb_desc, n_tiles, partials);
     PMC_TRY_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
-    PMC_TRY_HIP(hipGetLastError());
+    if (bump) {
+        hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
+        PMC_TRY_HIP(hipGetLastError());
+    }
     return PMC_OK;
 }
 
@@ -988,6 +991,11 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         g->nonfinite = v.f;
         g->n_accept = 0;
         g->next_steps = nsteps;
+        if (a.bump_epoch) {
+            ScanSync *sy = a.bump_epoch;
+            const uint32_t e = __hip_atomic_load(&sy->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sy->epoch, (e + 1) & 0x3fffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __hip_atomic_store(&g->fold_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -1020,7 +1028,7 @@ pmc_status diag_newton(pmc_context *ctx, const NewtonScanArgs &a)
 {
     SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
     DiagNewtonIO<R> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol, a.rtol};
-    return run_scan<DiagNewtonIO<R>, BLOCK, ITEMS>(ctx, io, a.n_lanes, a.n_tiles, a.partials);
+    return run_scan<DiagNewtonIO<R>, BLOCK, ITEMS>(ctx, io, a.n_lanes, a.n_tiles, a.partials, !a.defer_epoch);
 }
 template <typename R, int MM, int BLOCK, int ITEMS>
 pmc_status dense_newton(pmc_context *ctx, const NewtonScanArgs &a)
@@ -1028,7 +1036,7 @@ pmc_status dense_newton(pmc_context *ctx, const NewtonScanArgs &a)
     SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
     DenseNewtonIO<R, MM> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol,
                             a.rtol};
-    return run_scan<DenseNewtonIO<R, MM>, BLOCK, ITEMS>(ctx, io, 1, a.n_tiles, a.partials);
+    return run_scan<DenseNewtonIO<R, MM>, BLOCK, ITEMS>(ctx, io, 1, a.n_tiles, a.partials, !a.defer_epoch);
 }
 }  // namespace
 

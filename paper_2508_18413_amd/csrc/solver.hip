@@ -391,6 +391,8 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     sa.rtol = opts->rtol;
     sa.eps = prob->step_size;
     sa.trace = nullptr;
+    // the look-back scans leave the epoch advance to the status fold that follows
+    sa.defer_epoch = pl.jmode == JM_DIAG || pl.jmode == JM_NONE || pl.jmode == JM_DENSE_ROW;
     StatusArgs &sta = sw.st;
     sta.n_chains = pl.n_chains;
     sta.n_lanes = pl.n_lanes;
@@ -406,6 +408,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     sta.skip_prefix = opts->skip_converged_prefix;
     sta.floor_stall = opts->floor_stall;
     sta.n_steps = pl.n;
+    sta.bump_epoch = sa.defer_epoch ? ctx->sync : nullptr;
 
     GlobalStatus *hs = ctx->h_status;
     int sweeps_done = 0;
