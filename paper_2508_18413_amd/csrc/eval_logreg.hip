@@ -4,10 +4,11 @@
 // 32 x 32 x 2 FP32 matrix-core products over row tiles of 32 data points:
 //   pass 1:  Z = X S            (linear predictors at s_{t-1}),
 //            G = X^T (y - sigma(Z))              -> grad log-likelihood at s_{t-1}
+//            Hd = (X o X)^T (sigma(Z)(1 - sigma(Z)))  -> minus the Hessian diagonal,
 //   pass 2:  Z, dZ = X Delta    (predictors at s_{t-1} and their increment),
 //            G~ = X^T (y - sigma(Z + dZ))        -> grad at the proposal,
-//            Hd = (X o X)^T (sigma(Z)(1 - sigma(Z)))  -> minus the Hessian diagonal,
-//            sum_n [y dz - log1p(sigma(z) expm1(dz))]  -> log-likelihood difference,
+//            sum_n log(1 + sigma(z) (e^dz - 1))  -> the softplus part of the
+//            log-likelihood difference (its linear part is (X^T y) . Delta),
 // then one lane per step assembles the log Metropolis ratio in the
 // cancellation-free form (the proposal-density terms through g + g~), the
 // accept decision, f_t and the quasi-DEER Jacobian diagonal
@@ -96,6 +97,17 @@ __device__ __forceinline__ float half_sum(float v)
     return __uint_as_float(p[0]) + __uint_as_float(p[1]);
 }
 
+// The FP64 form of half_sum (both 32-bit words exchanged).
+__device__ __forceinline__ double half_sum_d(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    const double a0 = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+    const double a1 = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+    return a0 + a1;
+}
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------ LDS-resident evaluation
@@ -112,34 +124,30 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // 2 (8 kk + j) + hh).
 constexpr int kXS = 33;
 constexpr int kLdsWaves = 8;
-constexpr int kLdsMaxRowTiles = 36;  // 36 * 32 * 34 * 4 bytes = 153 KiB
+constexpr int kLdsMaxRowTiles = 36;  // (36 * 32 * 34 + 32) * 4 bytes = 153 KiB
 
 struct LdsArgs {
-    const float *xl;  // [nr * 32 * kXS] padded X followed by [nr * 32] padded y
+    const float *xl;  // [nr * 32 * kXS] padded X, [nr * 32] padded y, [32] X^T y
     int nr;
     float pp;
 };
 
-// Per-element work of pass 2 for the usual range of increments (|dz| < 8),
-// free of branches: s = sigma(z), m = expm1(dz), w = s m, a = 1 + w,
-//   sigma(z + dz) = (s + w) / a,  softplus(z + dz) - softplus(z) = log1p(w),
-// with one reciprocal of a serving both.
-// Arguments are u = z log2(e) and du = dz log2(e) (the LDS copy of X is scaled).
-__device__ __forceinline__ void pass2_elem(float u, float du, float &st, float &spd)
+// Per-element work of pass 2 for increments |dz| < 8, free of branches:
+// s = sigma(z), w = s (e^dz - 1), a = 1 + w gives
+//   sigma(z + dz) = (s + w) / a,  softplus(z + dz) - softplus(z) = log(a),
+// with one reciprocal of a serving the first; the caller multiplies the a of
+// four elements (each within [e^-8, e^8]) and takes one logarithm of the
+// product.  Everything downstream is an absolute-accuracy sum (the gradient
+// X^T r and the log-likelihood difference), so e^dz - 1 is formed directly:
+// its absolute error (one ulp of e^dz) is what the sums see either way.
+// Arguments are u = z log2(e) and du = dz log2(e) (the LDS copy of X is
+// scaled); returns y - sigma(z + dz) and a.
+__device__ __forceinline__ float pass2_elem(float u, float du, float y, float &a)
 {
     const float s = sigm2(u);
-    const float w = s * expm1_2(du);
-    const float a = 1.f + w, ra = frcp(a);
-    spd = log1p_ar(w, a, ra);
-    st = (s + w) * ra;
-}
-
-// The same quantities for any increment, written directly.
-__device__ __forceinline__ void pass2_elem_wide(float z, float dz, float &st, float &spd)
-{
-    const float zt = z + dz;
-    st = sigm(zt);
-    spd = softplus(zt) - softplus(z);
+    const float w = s * (__builtin_amdgcn_exp2f(du) - 1.f);
+    a = 1.f + w;
+    return fmaf(-(s + w), frcp(a), y);
 }
 
 template <int MK>
@@ -157,19 +165,20 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
     extern __shared__ float s_x[];
     const int nrow = f.nr * 32;
     {
-        const int nw = nrow * (kXS + 1);
+        const int nw = nrow * (kXS + 1) + 32;
         const float4 *src = (const float4 *)f.xl;
         float4 *dst = (float4 *)s_x;
         for (int k = threadIdx.x; k < nw / 4; k += blockDim.x) dst[k] = src[k];
     }
     __syncthreads();
     const float *s_y = s_x + nrow * kXS;
+    const float *s_xty = s_y + nrow;
     const int lane = threadIdx.x & 63, i = lane & 31, hh = lane >> 5;
     const int D = a.D, nr = f.nr;
     const int64_t ld = a.ld;
     const float *S = (const float *)a.S, *noise = (const float *)a.noise;
     float *F = (float *)a.F, *J = (float *)a.J;
-    const float eps = (float)a.eps, c = sqrtf(2.f * eps), hq = sqrtf(0.5f * eps), pp = f.pp;
+    const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
     const float damp = (float)a.damping, clip = (float)a.clip;
     const bool want_j = a.jmode == JM_DIAG;
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -290,9 +299,11 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
         // the B rows 4g..4g+3 (whose registers it then refills with tile
         // rt's values) and a share of the predictor chains of tile rt + 1,
         // so matrix and vector work interleave with few live registers.
-        // Elements with |dz| >= 8 are recomputed by a rare direct path.
+        // A group holding an element with |dz| >= 8 is redone by a rare
+        // direct path.  The softplus sums are kept in log2 units, one FP32
+        // partial per row tile added into an FP64 total.
         f32x16 Gt = zero;
-        float dll_y = 0.f, dll_s = 0.f;
+        double dll_s = 0.0;
         Zc = z_chain<MK>(s_x, i, hh, SB);
         f32x16 dZc = z_chain<MK>(s_x, i, hh, DB);
         float RtB[16];
@@ -304,6 +315,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
             const float *xp = s_x + (32 * (rt > 0 ? rt - 1 : 0)) * kXS;
             const float *yr = s_y + 32 * rt + 4 * hh;
             f32x16 Zn = zero, dZn = zero;
+            float tile_s = 0.f;
 #pragma unroll
             for (int g = 0; g < 4; g++) {
 #pragma unroll
@@ -318,31 +330,32 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
                 }
                 const float4 y4v = *(const float4 *)(yr + 8 * g);
                 const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
-                float Rt[4];
+                float Rt[4], av[4];
                 bool wide = false;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const float dz = dZc[4 * g + q];
-                    float st, spd;
-                    pass2_elem(Zc[4 * g + q], dz, st, spd);
-                    const bool in = fabsf(dz) < 8.f * kLog2e;
-                    wide |= !in;
-                    Rt[q] = in ? yv[q] - st : 0.f;
-                    dll_s += in ? spd : 0.f;
-                    dll_y = fmaf(yv[q], dz, dll_y);
+                    const float du = dZc[4 * g + q];
+                    Rt[q] = pass2_elem(Zc[4 * g + q], du, yv[q], av[q]);
+                    wide |= !(fabsf(du) < 8.f * kLog2e);
                 }
+                float lg = __builtin_amdgcn_logf((av[0] * av[1]) * (av[2] * av[3]));
                 if (__builtin_amdgcn_ballot_w64(wide)) {  // rare
+                    if (wide) {
+                        lg = 0.f;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const float dz = dZc[4 * g + q];
-                        if (!(fabsf(dz) < 8.f * kLog2e)) {
-                            float st, spd;
-                            pass2_elem_wide(Zc[4 * g + q] * kLn2, dz * kLn2, st, spd);
-                            Rt[q] = yv[q] - st;
-                            dll_s += spd;
+                        for (int q = 0; q < 4; q++) {
+                            const float u = Zc[4 * g + q], du = dZc[4 * g + q];
+                            if (fabsf(du) < 8.f * kLog2e) {
+                                lg += __builtin_amdgcn_logf(av[q]);
+                            } else {
+                                const float z = u * kLn2, zt = z + du * kLn2;
+                                Rt[q] = yv[q] - sigm(zt);
+                                lg += (softplus(zt) - softplus(z)) * kLog2e;
+                            }
                         }
                     }
                 }
+                tile_s += lg;
                 // accumulator rows 4g..4g+3 -> B rows 4g, 4g+2, 4g+1, 4g+3
                 const auto p0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(Rt[0]), __float_as_uint(Rt[1]),
                                                                  false, false);
@@ -353,6 +366,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
                 RtB[4 * g + 1] = __uint_as_float(p1[0]);
                 RtB[4 * g + 3] = __uint_as_float(p1[1]);
             }
+            dll_s += (double)tile_s;
             Zc = Zn;
             dZc = dZn;
         }
@@ -362,35 +376,43 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
             for (int m = 0; m < 16; m++)
                 Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[(2 * m + hh) * kXS + i], RtB[m], Gt, 0, 0, 0);
         }
-        const float dll = half_sum(fmaf(dll_y, kLn2, -dll_s));
+        // The log ratio is assembled in FP64 from here on: its terms (each up
+        // to ~10^2 on this posterior) cancel to O(1), and FP32 sums of them
+        // would add errors of ~10^-5 to a quantity compared against log u.
+        // Linear part of the log-likelihood difference: (X^T y) . Delta.
+        double dll_y = 0.0;
+#pragma unroll
+        for (int m = 0; m < MK; m++) dll_y = fma((double)s_xty[2 * m + hh], (double)DB[m], dll_y);
+        const double dll = half_sum_d(fma(-dll_s, (double)kLn2, dll_y));
 
         // ---- per step (both halves): log ratio, decision, f_t
         float GtB[16];
         acc_to_b_swap(Gt, GtB);
-        float sn = 0.f, sx = 0.f, dpr = 0.f;
+        double sn = 0.0, sx = 0.0, dpr = 0.0;
 #pragma unroll
         for (int m = 0; m < MK; m++) {
             const int d = 2 * m + hh;
             if (d < D) {
                 const float x = SB[m], dl = DB[m], xt = x + dl;
                 const float gt = fmaf(GtB[m], kLn2, -pp * xt);
-                const float sg = gB[m] + gt;
-                sn = fmaf(sg, sg, sn);
-                sx = fmaf(noise[(size_t)tt * D + d], sg, sx);
-                dpr = fmaf(dl, xt + x, dpr);
+                const double sg = (double)gB[m] + (double)gt;
+                sn = fma(sg, sg, sn);
+                sx = fma((double)noise[(size_t)tt * D + d], sg, sx);
+                dpr = fma((double)dl, (double)xt + (double)x, dpr);
             }
         }
-        sn = half_sum(sn);
-        sx = half_sum(sx);
-        dpr = half_sum(dpr);
+        sn = half_sum_d(sn);
+        sx = half_sum_d(sx);
+        dpr = half_sum_d(dpr);
         if (valid) {
             int acc = 1;
             float gate = INFINITY;
             if (!a.ula) {
-                const float ell = dll - 0.5f * pp * dpr - 0.25f * eps * sn - hq * sx;
-                const float la = ell < 0.f ? ell : 0.f;
-                gate = la - logf(((const float *)a.unif)[t]);
-                acc = gate > 0.f;
+                const double ell = dll - 0.5 * (double)pp * dpr - 0.25 * a.eps * sn - sqrt(0.5 * a.eps) * sx;
+                const double la = ell < 0.0 ? ell : 0.0;
+                const double gd = la - log((double)((const float *)a.unif)[t]);
+                gate = (float)gd;
+                acc = gd > 0.0;
                 if (!(ell == ell)) acc = 0;
             }
             float jrej = damp;
@@ -597,7 +619,7 @@ __global__ void k_logreg_frags(const float *X, int ldx, const float *y, int N, i
 // LDS image: X log2(e) (predictor products then come out as arguments of
 // exp2; the gradient and Hessian sums are rescaled by ln 2 and ln^2 2), rows
 // padded to nr * 32, row stride kXS, zero columns beyond D, followed by y
-// padded with zeros.
+// padded with zeros and by X^T y (32 entries, filled by k_logreg_xty).
 __global__ void k_logreg_lds_image(const float *X, int ldx, const float *y, int N, int D, int nr, float *xl)
 {
     const int nrow = nr * 32;
@@ -616,11 +638,24 @@ __global__ void k_logreg_lds_image(const float *X, int ldx, const float *y, int 
     }
 }
 
+// X^T y in FP64, rounded once; one thread per coordinate (D <= 32).
+__global__ void k_logreg_xty(const float *X, int ldx, const float *y, int N, int D, float *out)
+{
+    const int d = threadIdx.x;
+    if (d >= 32) return;
+    double acc = 0.0;
+    if (d < D)
+        for (int n = 0; n < N; n++) acc += (double)X[(size_t)n * ldx + d] * (double)y[n];
+    out[d] = (float)acc;
+}
+
+constexpr int kLdsImageFloats(int nr) { return nr * 32 * (kXS + 1) + 32; }
+
 template <int MK>
 hipError_t allow_lds()
 {
     return hipFuncSetAttribute((const void *)k_eval_logreg_lds<MK>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kLdsMaxRowTiles * 32 * (kXS + 1) * (int)sizeof(float));
+                               kLdsImageFloats(kLdsMaxRowTiles) * (int)sizeof(float));
 }
 
 }  // namespace
@@ -632,10 +667,13 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
     t.mk = mk <= 2 ? 2 : mk <= 4 ? 4 : mk <= 8 ? 8 : mk <= 13 ? 13 : 16;
     if (nr <= kLdsMaxRowTiles) {
         // LDS-resident path: one padded image of X and y
-        const size_t bl = sizeof(float) * (size_t)nr * 32 * (kXS + 1);
+        const size_t bl = sizeof(float) * (size_t)kLdsImageFloats(nr);
         PMC_TRY_HIP(hipMalloc(&t.xl, bl));
         hipLaunchKernelGGL(k_logreg_lds_image, dim3(64), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
                            (const float *)t.y, t.n_data, t.dim, nr, (float *)t.xl);
+        PMC_TRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_logreg_xty, dim3(1), dim3(32), 0, ctx->stream, (const float *)t.X, t.ldx,
+                           (const float *)t.y, t.n_data, t.dim, (float *)t.xl + (size_t)nr * 32 * (kXS + 1));
         PMC_TRY_HIP(hipGetLastError());
         PMC_TRY_HIP(allow_lds<2>());
         PMC_TRY_HIP(allow_lds<4>());
@@ -661,7 +699,7 @@ pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalAr
     if (a.n_tiles <= 0) return PMC_OK;
     if (t.xl) {
         LdsArgs f{(const float *)t.xl, t.nr, (float)(1.0 / t.prior_var)};
-        const size_t lds = sizeof(float) * (size_t)t.nr * 32 * (kXS + 1);
+        const size_t lds = sizeof(float) * (size_t)kLdsImageFloats(t.nr);
         const int want = (a.n_tiles + kLdsWaves - 1) / kLdsWaves;
         dim3 grid(std::max(1, std::min(want, ctx->n_cu > 0 ? ctx->n_cu : 256))), block(64 * kLdsWaves);
         switch (t.mk) {

@@ -25,24 +25,8 @@ __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x)
 
 __device__ __forceinline__ float sigm(float z) { return frcp(1.f + fexp(-z)); }
 
-// The same functions of u = z log2(e) (arguments already scaled for exp2).
+// The same function of u = z log2(e) (argument already scaled for exp2).
 __device__ __forceinline__ float sigm2(float u) { return frcp(1.f + __builtin_amdgcn_exp2f(-u)); }
-
-// expm1(u ln 2): Taylor polynomial in u through (u ln 2)^8 / 8! for
-// |u ln 2| < 1/2, exp2(u) - 1 elsewhere (as expm1 above).
-__device__ __forceinline__ float expm1_2(float u)
-{
-    // coefficients (ln 2)^k / k!, k = 8 .. 1
-    float q = fmaf(u, 1.32154868e-06f, 1.52527338e-05f);
-    q = fmaf(u, q, 1.54035304e-04f);
-    q = fmaf(u, q, 1.33335581e-03f);
-    q = fmaf(u, q, 9.61812911e-03f);
-    q = fmaf(u, q, 5.55041087e-02f);
-    q = fmaf(u, q, 2.40226507e-01f);
-    q = fmaf(u, q, 6.93147181e-01f);
-    const float big = __builtin_amdgcn_exp2f(u) - 1.f;
-    return fabsf(u) < 0.72134752f ? u * q : big;
-}
 
 __device__ __forceinline__ float expm1_s(float x)
 {

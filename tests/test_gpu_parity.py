@@ -193,10 +193,19 @@ def _logreg_case(orc, T, eps, seed=0):
     return ch, tg, s0
 
 
+# Near-tie band of FP32 chains: the bound on |g~ - g~*| that
+# test_logreg_gate_precision pins for one FP32 evaluation at given states.
+# On the logistic posterior the log ratio's terms reach ~1e2 and cancel to
+# O(1), so FP32 predictors and gradient sums leave errors of several 1e-6 in
+# g~; a decision flip closer to the threshold than that is a tie in FP32.
+F32_GATE_ERR = 2e-5
+
+
 def _check_mala(orc, tg, ch, s0, got_states, got_acc, tol=1e-5):
     x0 = s0.astype(np.float64)
+    band = F32_GATE_ERR if np.asarray(got_states).dtype == np.float32 else 1e-6
     st, acc, rep = compare_with_resync(
-        lambda f: orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u, force=f), got_acc)
+        lambda f: orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u, force=f), got_acc, tie_band=band)
     err = state_error(got_states, st)
     _say(f"  state_error={err:.3e} mismatches={rep}")
     assert not [x for x in rep if x[2] == "failure"], rep
@@ -213,6 +222,41 @@ def test_logreg_diag_fp32(ctx, pm, orc, T):
     _say(f"  sweeps={r.sweeps} status={r.status} ratio={r.max_ratio:.3g}")
     assert r.status == 0
     _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+def _gate_at(orc, tg, ch, s0, states):
+    """The oracle's g~* of every step taken from the given (FP32) states."""
+    prev = np.concatenate([np.asarray(s0)[None, :], np.asarray(states)[:-1]]).astype(np.float64)
+    return np.array([orc.mala_step(tg, ch.eps, prev[t], ch.xi[t], ch.u[t])[2] for t in range(prev.shape[0])])
+
+
+def test_logreg_gate_precision(ctx, pm, orc):
+    """One parallel evaluation at the oracle's trajectory (rounded to FP32)
+    and the sequential sampler along its own trajectory: each step's g~
+    against the oracle's g~* from the same FP32 states, and the decisions
+    wherever |g~*| exceeds that error."""
+    T = 2048
+    for seed in (0, 1):
+        ch, tg, s0 = _logreg_case(orc, T, 0.0015, seed=seed)
+        st, _, _ = orc.mala_chain(tg, ch.eps, s0.astype(np.float64), ch.xi, ch.u)
+        init = st.astype(np.float32)
+        ref = _gate_at(orc, tg, ch, s0, init)
+        g = pm.Target(ctx, ch.target)
+        r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=1,
+                     init_guess=_t(init))
+        got = r.gtilde.cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref)
+        _say(f"  seed {seed} parallel eval: max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}")
+        assert err.max() <= F32_GATE_ERR
+        clear = np.abs(ref) > F32_GATE_ERR
+        assert np.array_equal(r.accept.cpu().numpy()[clear].astype(bool), ref[clear] > 0)
+
+        rs = pm.sample_sequential(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u))
+        sst = rs.states.cpu().numpy()
+        ref = _gate_at(orc, tg, ch, s0, sst)
+        err = np.abs(rs.gtilde.cpu().numpy().astype(np.float64) - ref)
+        _say(f"  seed {seed} sequential: max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}")
+        assert err.max() <= F32_GATE_ERR
 
 
 def test_logreg_sequential_fp32(ctx, pm, orc):
