@@ -163,6 +163,7 @@ template <int MK>
 __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs a, LdsArgs f)
 {
     extern __shared__ float s_x[];
+    if (a.glob && a.glob->n_active == 0) return;  // a sweep queued past the last active chain
     const int nrow = f.nr * 32;
     {
         const int nw = nrow * (kXS + 1) + 32;

@@ -92,6 +92,7 @@ struct GlobalStatus {
     uint32_t nonfinite;
     int64_t n_accept;
     int64_t next_steps;  // steps the next sweep evaluates (active chains, from their windows)
+    int64_t eval_steps;  // steps evaluated by all sweeps so far
     uint32_t fold_ctr;   // status-fold completion counter; zero between launches
     uint32_t pad;
 };
@@ -109,6 +110,11 @@ struct ScanSync {
 // Slots of pmc_context::sync: 0 = single-pass scans (the others are spare).
 constexpr int kScanSyncSlot = 0;
 constexpr int kMaxSyncSlots = 4;
+
+// Sweeps a solve enqueues between two reads of the global status.  Sweeps
+// queued after the last chain has stopped find n_active == 0 and return at
+// once (each costs a few microseconds of launches).
+constexpr int kSweepBatch = 8;
 
 
 // ------------------------------------------------------------ targets
@@ -150,7 +156,7 @@ struct pmc_context {
     size_t pool_bytes = 0;
     pmc::GlobalStatus *h_status = nullptr;  // pinned host mirror
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t kev[3] = {nullptr, nullptr, nullptr};  // per-kernel timing
+    hipEvent_t kev[3 * pmc::kSweepBatch] = {};  // per-kernel timing of one batch of sweeps
     // tuning: items per thread of the diagonal scan (0 = default)
     int diag_items = 0;
     int diag_block = 0;
@@ -246,6 +252,7 @@ struct EvalArgs {
     int clip_inf;
     int jmode;
     const pmc::DevTarget *tg; // host copy of the target description (fields passed by value)
+    const GlobalStatus *glob = nullptr;  // n_active == 0 at launch: nothing left to evaluate
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);

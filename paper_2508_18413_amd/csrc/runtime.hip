@@ -194,12 +194,19 @@ pmc_status pmc_create(pmc_context **out, int device, void *hip_stream)
     if (hipMalloc((void **)&ctx->sync, sizeof(ScanSync) * kMaxSyncSlots) != hipSuccess ||
         hipMemset(ctx->sync, 0, sizeof(ScanSync) * kMaxSyncSlots) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_status, sizeof(GlobalStatus)) != hipSuccess ||
-        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
-        hipEventCreate(&ctx->kev[0]) != hipSuccess || hipEventCreate(&ctx->kev[1]) != hipSuccess ||
-        hipEventCreate(&ctx->kev[2]) != hipSuccess) {
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
         set_error("pmc_create: device initialisation failed");
         pmc_destroy(ctx);
         return PMC_ERR_HIP;
+    }
+    // timing-only events: no system-scope fence when they complete (the
+    // solver reads them after synchronising the stream)
+    for (hipEvent_t &e : ctx->kev) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+            set_error("pmc_create: event creation failed");
+            pmc_destroy(ctx);
+            return PMC_ERR_HIP;
+        }
     }
     *out = ctx;
     return PMC_OK;

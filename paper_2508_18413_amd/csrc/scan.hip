@@ -990,6 +990,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         g->max_ratio = v.r;
         g->nonfinite = v.f;
         g->n_accept = 0;
+        g->eval_steps += g->next_steps;  // what this sweep evaluated
         g->next_steps = nsteps;
         if (a.bump_epoch) {
             ScanSync *sy = a.bump_epoch;

@@ -224,11 +224,13 @@ struct Sweep {
     void *hier;  // matrix-core scan hierarchy workspace
 };
 
-pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, bool prof = false)
+// One Newton sweep: evaluation, scan, status fold.  ev (optional) receives
+// three events: before the evaluation, between evaluation and scan, after the scan.
+pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent_t *ev = nullptr)
 {
-    if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[0], ctx->stream));
+    if (ev) PMC_TRY_HIP(hipEventRecord(ev[0], ctx->stream));
     PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
-    if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[1], ctx->stream));
+    if (ev) PMC_TRY_HIP(hipEventRecord(ev[1], ctx->stream));
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
                                          (float *)sw.sa.S, sw.sa.ld, pl.D, pl.n, sw.sa.partials,
@@ -237,7 +239,7 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, bool pro
         PMC_TRY(launch_newton_scan_dense_small(ctx, pl.dt, pl.D, sw.sa));
     else
         PMC_TRY(launch_newton_scan_diag(ctx, pl.dt, sw.sa, pl.scan_items, pl.scan_block));
-    if (prof) PMC_TRY_HIP(hipEventRecord(ctx->kev[2], ctx->stream));
+    if (ev) PMC_TRY_HIP(hipEventRecord(ev[2], ctx->stream));
     PMC_TRY(launch_status(ctx, sw.st));
     return PMC_OK;
 }
@@ -340,7 +342,17 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
                                hipMemcpyHostToDevice, st));
     PMC_TRY_HIP(hipMemcpyAsync(d_chains, hc.data(), sizeof(ChainStatus) * hc.size(),
                                hipMemcpyHostToDevice, st));
-    PMC_TRY_HIP(hipMemsetAsync(d_glob, 0, sizeof(GlobalStatus), st));
+    {
+        // the first sweep evaluates every step of every non-empty chain
+        GlobalStatus *g0 = ctx->h_status;
+        memset(g0, 0, sizeof(*g0));
+        for (int c = 0; c < pl.n_chains; c++) {
+            g0->n_active += hc[c].active;
+            g0->n_converged += hc[c].converged;
+        }
+        g0->next_steps = pl.n;
+        PMC_TRY_HIP(hipMemcpyAsync(d_glob, g0, sizeof(GlobalStatus), hipMemcpyHostToDevice, st));
+    }
     if (pl.jmode == JM_NONE)  // Picard: J = 0 through the diagonal scan
         PMC_TRY_HIP(hipMemsetAsync(J, 0, (size_t)pl.ld * pl.es * pl.D, st));
 
@@ -375,6 +387,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     ea.clip_inf = opts->clip_inf_norm;
     ea.jmode = pl.jmode == JM_NONE ? JM_NONE : pl.jmode;
     ea.tg = pl.tg;
+    ea.glob = d_glob;
     NewtonScanArgs &sa = sw.sa;
     sa.n_lanes = pl.n_lanes;
     sa.ld = pl.ld;
@@ -413,7 +426,6 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     GlobalStatus *hs = ctx->h_status;
     int sweeps_done = 0;
     float prof_eval_ms = 0, prof_scan_ms = 0;
-    int64_t prof_steps = 0;
     PMC_REQUIRE(!(opts->profile_kernels && opts->graph_sweeps > 0),
                 "pmc_solve: profile_kernels needs graph_sweeps = 0");
     if (opts->graph_sweeps > 0) {
@@ -454,26 +466,33 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
         if (rc != PMC_OK) return rc;
         PMC_TRY_HIP(he);
     } else {
+        // Sweeps are enqueued in batches between reads of the global status;
+        // sweeps past the last active chain return at once.  A trace keeps one
+        // sweep per batch so that its rows after convergence stay untouched.
         const bool prof = opts->profile_kernels != 0;
-        // steps the first sweep evaluates: every step of every non-empty chain
-        int64_t act_steps = pl.n;
-        for (int it = 0; it < pl.max_iter; it++) {
-            PMC_TRY(one_sweep(ctx, pl, sw, prof));
-            if (opts->trace_out)
-                PMC_TRY(planes_to_rows(ctx, pl.dt, S,
-                                       (char *)opts->trace_out + (size_t)it * pl.n * pl.D * pl.es,
-                                       pl.n, pl.D, pl.ld));
+        const int batch = opts->trace_out ? 1 : kSweepBatch;
+        for (int it = 0; it < pl.max_iter;) {
+            const int nb = std::min(batch, pl.max_iter - it);
+            for (int j = 0; j < nb; j++) {
+                PMC_TRY(one_sweep(ctx, pl, sw, prof ? &ctx->kev[3 * j] : nullptr));
+                if (opts->trace_out)
+                    PMC_TRY(planes_to_rows(ctx, pl.dt, S,
+                                           (char *)opts->trace_out + (size_t)(it + j) * pl.n * pl.D * pl.es,
+                                           pl.n, pl.D, pl.ld));
+            }
             PMC_TRY_HIP(hipMemcpyAsync(hs, d_glob, sizeof(GlobalStatus), hipMemcpyDeviceToHost, st));
             PMC_TRY_HIP(hipStreamSynchronize(st));
             if (prof) {
-                float me = 0, msc = 0;
-                PMC_TRY_HIP(hipEventElapsedTime(&me, ctx->kev[0], ctx->kev[1]));
-                PMC_TRY_HIP(hipEventElapsedTime(&msc, ctx->kev[1], ctx->kev[2]));
-                prof_eval_ms += me;
-                prof_scan_ms += msc;
-                prof_steps += act_steps;
-                act_steps = hs->next_steps;  // from the status fold of this sweep
+                // only sweeps in which some chain was still active
+                for (int j = 0; j < nb && it + j < hs->sweeps; j++) {
+                    float me = 0, msc = 0;
+                    PMC_TRY_HIP(hipEventElapsedTime(&me, ctx->kev[3 * j], ctx->kev[3 * j + 1]));
+                    PMC_TRY_HIP(hipEventElapsedTime(&msc, ctx->kev[3 * j + 1], ctx->kev[3 * j + 2]));
+                    prof_eval_ms += me;
+                    prof_scan_ms += msc;
+                }
             }
+            it += nb;
             sweeps_done = hs->sweeps;
             if (hs->n_active == 0) break;
         }
@@ -501,7 +520,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
         res->elapsed_ms = ms;
         res->eval_ms = prof_eval_ms;
         res->scan_ms = prof_scan_ms;
-        res->eval_steps = prof_steps;
+        res->eval_steps = opts->profile_kernels ? hs->eval_steps : 0;
         if (res->sweeps_per_chain)
             for (int c = 0; c < pl.n_chains; c++) res->sweeps_per_chain[c] = hc[c].sweeps;
     }
