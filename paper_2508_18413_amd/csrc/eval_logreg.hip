@@ -639,15 +639,23 @@ __global__ void k_logreg_lds_image(const float *X, int ldx, const float *y, int 
     }
 }
 
-// X^T y in FP64, rounded once; one thread per coordinate (D <= 32).
-__global__ void k_logreg_xty(const float *X, int ldx, const float *y, int N, int D, float *out)
+// X^T y in FP64, rounded once: one workgroup per coordinate d < 32 (zero
+// beyond D), strided partial sums folded in a fixed order.
+__global__ void __launch_bounds__(256) k_logreg_xty(const float *X, int ldx, const float *y, int N, int D,
+                                                   float *out)
 {
-    const int d = threadIdx.x;
-    if (d >= 32) return;
+    __shared__ double s_p[256];
+    const int d = blockIdx.x, tid = threadIdx.x;
     double acc = 0.0;
     if (d < D)
-        for (int n = 0; n < N; n++) acc += (double)X[(size_t)n * ldx + d] * (double)y[n];
-    out[d] = (float)acc;
+        for (int n = tid; n < N; n += 256) acc += (double)X[(size_t)n * ldx + d] * (double)y[n];
+    s_p[tid] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) s_p[tid] += s_p[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) out[d] = (float)s_p[0];
 }
 
 constexpr int kLdsImageFloats(int nr) { return nr * 32 * (kXS + 1) + 32; }
@@ -673,7 +681,7 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
         hipLaunchKernelGGL(k_logreg_lds_image, dim3(64), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
                            (const float *)t.y, t.n_data, t.dim, nr, (float *)t.xl);
         PMC_TRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_logreg_xty, dim3(1), dim3(32), 0, ctx->stream, (const float *)t.X, t.ldx,
+        hipLaunchKernelGGL(k_logreg_xty, dim3(32), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
                            (const float *)t.y, t.n_data, t.dim, (float *)t.xl + (size_t)nr * 32 * (kXS + 1));
         PMC_TRY_HIP(hipGetLastError());
         PMC_TRY_HIP(allow_lds<2>());
