@@ -645,7 +645,6 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
 
     __shared__ A s_wagg[NW];
     __shared__ R s_carry[M];
-    __shared__ Part s_part[NW];
 
     const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
     // only wave 0 publishes and looks back; its epoch load overlaps the data loads
@@ -773,19 +772,17 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
     }
 
     if constexpr (HasPartials<IO>::value) {
+        // one partial per wave (the status fold merges them), so no wave
+        // waits for the others at the end of the tile
 #pragma unroll
         for (int m = 1; m < kWave; m <<= 1) part_merge(part, part_shfl_xor(part, m));
-        if (lid == 0) s_part[wid] = part;
-        lds_barrier();
-        if (tid == 0) {
-            Part p = s_part[0];
-            for (int w = 1; w < NW; w++) part_merge(p, s_part[w]);
-            TilePartial &tp = partials[(size_t)lane * n_tiles + ti];
-            tp.max_ratio = p.ratio;
-            tp.nonfinite = p.nonfinite;
-            tp.first_bad = p.first_bad;
-            tp.resid_sq = p.rsq;
-            tp.resid_inf = p.rinf;
+        if (lid == 0) {
+            TilePartial &tp = partials[((size_t)lane * n_tiles + ti) * NW + wid];
+            tp.max_ratio = part.ratio;
+            tp.nonfinite = part.nonfinite;
+            tp.first_bad = part.first_bad;
+            tp.resid_sq = part.rsq;
+            tp.resid_inf = part.rinf;
         }
     }
 }
@@ -875,11 +872,14 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
     ChainStatus &cs = a.chains[c];
     if (cs.active) {  // uniform per block
         const int k0 = a.chain_tile_begin[c], ntc = a.chain_tile_begin[c + 1] - k0;
-        const int64_t cnt = (int64_t)a.n_lanes * ntc;
+        const int ppt = a.parts_per_tile;
+        const int64_t per_lane = (int64_t)ntc * ppt;  // this chain's partials in one lane, contiguous
+        const int64_t cnt = (int64_t)a.n_lanes * per_lane;
         Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
         for (int64_t i = tid; i < cnt; i += kStatusThreads) {
-            const int l = (int)(i / ntc), k = k0 + (int)(i - (int64_t)l * ntc);
-            const TilePartial &p = a.partials[(size_t)l * a.n_tiles + k];
+            const int l = (int)(i / per_lane);
+            const int64_t r = i - (int64_t)l * per_lane;
+            const TilePartial &p = a.partials[((size_t)l * a.n_tiles + k0) * ppt + r];
             v.r = fmaxf(v.r, p.max_ratio);
             v.fb = p.first_bad < v.fb ? p.first_bad : v.fb;
             v.q += p.resid_sq;
@@ -1040,6 +1040,13 @@ pmc_status dense_newton(pmc_context *ctx, const NewtonScanArgs &a)
     return run_scan<DenseNewtonIO<R, MM>, BLOCK, ITEMS>(ctx, io, 1, a.n_tiles, a.partials, !a.defer_epoch);
 }
 }  // namespace
+
+int scan_parts_per_tile(pmc_dtype dt, int variant_m, int block)
+{
+    if (variant_m > 1 || dt == PMC_F64) return 256 / kWave;
+    if (block == 1024 || block == 512) return block / kWave;
+    return 256 / kWave;
+}
 
 int scan_tile_steps(pmc_dtype dt, int variant_m, int items, int block)
 {
