@@ -197,7 +197,7 @@ struct NewtonScanArgs {
     const void *J;          // diag: [n_lanes, ld]; block2 (leapfrog): h [n_lanes, ld]
     const void *F;          // [n_lanes, ld] (block2: [2*n_lanes, ld], x planes then v planes)
     void *S;                // [n_lanes, ld] in/out (block2: [2*n_lanes, ld])
-    TilePartial *partials;  // [n_lanes * n_tiles * partials per tile]
+    TilePartial *partials;  // [n_lanes * n_tiles]
     double atol, rtol;
     double eps;             // leapfrog step (block2)
     void *trace;            // optional copy of S after the update, or nullptr
@@ -206,8 +206,6 @@ struct NewtonScanArgs {
 
 // Steps per scan tile for a configuration (the host builds its tile map with it).
 int scan_tile_steps(pmc_dtype dt, int variant_m, int items, int block);
-// Convergence partials the scan writes per tile (one per wave of its block).
-int scan_parts_per_tile(pmc_dtype dt, int variant_m, int block);
 pmc_status launch_newton_scan_diag(pmc_context *ctx, pmc_dtype dt, const NewtonScanArgs &a,
                                    int items, int block);
 pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64_t T, const void *a,
@@ -297,8 +295,7 @@ struct StatusArgs {
     const SegTile *tiles;
     int n_tiles;
     const int32_t *chain_tile_begin;  // [n_chains+1] scan-tile ranges per chain
-    const TilePartial *partials;      // [n_lanes][n_tiles][parts_per_tile]
-    int parts_per_tile;
+    const TilePartial *partials;
     ChainStatus *chains;
     GlobalStatus *global;
     const uint8_t *accept;            // [n_steps] or nullptr

@@ -645,8 +645,11 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
 
     __shared__ A s_wagg[NW];
     __shared__ R s_carry[M];
+    __shared__ Part s_part[NW];
+    __shared__ uint32_t s_cnt;
 
     const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
+    if (tid == 0) s_cnt = 0;  // ordered before the waves' arrivals by the barriers below
     // only wave 0 publishes and looks back; its epoch load overlaps the data loads
     uint32_t epoch = 0;
     if (wid == 0) epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -772,12 +775,31 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
     }
 
     if constexpr (HasPartials<IO>::value) {
-        // one partial per wave (the status fold merges them), so no wave
-        // waits for the others at the end of the tile
+        // Each wave folds its partial and leaves it in LDS; the wave that
+        // arrives last (LDS counter) folds the NW of them across its lanes
+        // and writes the tile's partial, so no wave waits for the others.
 #pragma unroll
         for (int m = 1; m < kWave; m <<= 1) part_merge(part, part_shfl_xor(part, m));
-        if (lid == 0) {
-            TilePartial &tp = partials[((size_t)lane * n_tiles + ti) * NW + wid];
+        TilePartial &tp = partials[(size_t)lane * n_tiles + ti];
+        bool write = false;
+        if (!active) {
+            write = wid == 0;  // every wave holds the neutral partial
+        } else {
+            uint32_t arrived = 0;
+            if (lid == 0) {
+                s_part[wid] = part;
+                arrived = __hip_atomic_fetch_add(&s_cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            arrived = __shfl(arrived, 0, kWave);
+            if (arrived == NW - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                part = lid < NW ? s_part[lid] : part_neutral();
+#pragma unroll
+                for (int m = 1; m < NW; m <<= 1) part_merge(part, part_shfl_xor(part, m));
+                write = true;
+            }
+        }
+        if (write && lid == 0) {
             tp.max_ratio = part.ratio;
             tp.nonfinite = part.nonfinite;
             tp.first_bad = part.first_bad;
@@ -872,14 +894,11 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
     ChainStatus &cs = a.chains[c];
     if (cs.active) {  // uniform per block
         const int k0 = a.chain_tile_begin[c], ntc = a.chain_tile_begin[c + 1] - k0;
-        const int ppt = a.parts_per_tile;
-        const int64_t per_lane = (int64_t)ntc * ppt;  // this chain's partials in one lane, contiguous
-        const int64_t cnt = (int64_t)a.n_lanes * per_lane;
+        const int64_t cnt = (int64_t)a.n_lanes * ntc;
         Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
         for (int64_t i = tid; i < cnt; i += kStatusThreads) {
-            const int l = (int)(i / per_lane);
-            const int64_t r = i - (int64_t)l * per_lane;
-            const TilePartial &p = a.partials[((size_t)l * a.n_tiles + k0) * ppt + r];
+            const int l = (int)(i / ntc), k = k0 + (int)(i - (int64_t)l * ntc);
+            const TilePartial &p = a.partials[(size_t)l * a.n_tiles + k];
             v.r = fmaxf(v.r, p.max_ratio);
             v.fb = p.first_bad < v.fb ? p.first_bad : v.fb;
             v.q += p.resid_sq;
@@ -1040,13 +1059,6 @@ pmc_status dense_newton(pmc_context *ctx, const NewtonScanArgs &a)
     return run_scan<DenseNewtonIO<R, MM>, BLOCK, ITEMS>(ctx, io, 1, a.n_tiles, a.partials, !a.defer_epoch);
 }
 }  // namespace
-
-int scan_parts_per_tile(pmc_dtype dt, int variant_m, int block)
-{
-    if (variant_m > 1 || dt == PMC_F64) return 256 / kWave;
-    if (block == 1024 || block == 512) return block / kWave;
-    return 256 / kWave;
-}
 
 int scan_tile_steps(pmc_dtype dt, int variant_m, int items, int block)
 {

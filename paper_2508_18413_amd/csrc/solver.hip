@@ -38,7 +38,6 @@ struct Plan {
     int jmode;
     int n_lanes;
     int scan_items, scan_block, C_scan, C_eval;
-    int ppt;  // convergence partials per scan tile
     std::vector<int64_t> offs;
     std::vector<SegTile> etiles, stiles;
     std::vector<int32_t> ctb;
@@ -161,12 +160,10 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         pl.scan_items = 1;
         pl.scan_block = 256;
         pl.C_scan = dense_mfma_unit();
-        pl.ppt = 1;
     } else if (pl.jmode == JM_DENSE_ROW) {
         pl.scan_items = pl.D == 2 ? 4 : 2;
         pl.scan_block = 256;
         pl.C_scan = 256 * pl.scan_items;
-        pl.ppt = scan_parts_per_tile(pl.dt, pl.D, pl.scan_block);
     } else {
         // untuned default (FP32): 512 x 8 below 2^23 elements per scan, where
         // launch latency dominates and every configuration takes about the
@@ -176,7 +173,6 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         const bool big = (int64_t)pl.n_lanes * pl.n >= (int64_t(1) << 23);
         pl.scan_block = ctx->diag_block ? ctx->diag_block : (pl.dt == PMC_F64 ? 256 : big ? 1024 : 512);
         pl.C_scan = scan_tile_steps(pl.dt, 1, pl.scan_items, pl.scan_block);
-        pl.ppt = scan_parts_per_tile(pl.dt, 1, pl.scan_block);
     }
     pl.C_eval = eval_tile_steps(t);
     build_tiles(pl.offs, pl.C_scan, pl.stiles, &pl.ctb);
@@ -218,7 +214,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     pl.o_stiles = take(sizeof(SegTile) * std::max<size_t>(pl.stiles.size(), 1));
     pl.o_ctb = take(sizeof(int32_t) * pl.ctb.size());
     pl.o_offs = take(sizeof(int64_t) * pl.offs.size());
-    pl.o_part = take(sizeof(TilePartial) * std::max<size_t>((size_t)pl.n_lanes * pl.stiles.size() * pl.ppt, 1));
+    pl.o_part = take(sizeof(TilePartial) * std::max<size_t>((size_t)pl.n_lanes * pl.stiles.size(), 1));
     pl.o_chains = take(sizeof(ChainStatus) * pl.n_chains);
     pl.o_global = take(sizeof(GlobalStatus));
     pl.total = off;
@@ -421,7 +417,6 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     sta.n_tiles = (int)pl.stiles.size();
     sta.chain_tile_begin = d_ctb;
     sta.partials = d_part;
-    sta.parts_per_tile = pl.ppt;
     sta.chains = d_chains;
     sta.global = d_glob;
     sta.accept = nullptr;
@@ -702,8 +697,7 @@ extern "C" pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, co
         return o;
     };
     const size_t oJ = take(plane), oF = take(plane), oS = take(plane),
-                 oP = take(sizeof(TilePartial) * base.D * tiles.size() * (1024 / 64)),
-                 oT = take(sizeof(SegTile) * tiles.size()),
+                 oP = take(sizeof(TilePartial) * base.D * tiles.size()), oT = take(sizeof(SegTile) * tiles.size()),
                  oC = take(sizeof(int32_t) * ctb.size()), oO = take(sizeof(int64_t) * base.offs.size()),
                  oCh = take(sizeof(ChainStatus) * base.n_chains);
     PMC_TRY(ensure_pool(ctx, off));
