@@ -126,7 +126,10 @@ typedef struct {
                                  without it, rounding-level changes of that prefix can keep
                                  flipping a near-tie accept decision further on              */
     int graph_sweeps;         /* > 0: replay a captured HIP graph of this many sweeps between
-                                 host convergence checks; 0: one host check per sweep       */
+                                 host convergence checks; 0: enqueue sweeps 8 at a time
+                                 between checks (one at a time with trace_out).  Sweeps
+                                 queued after every chain has stopped return at once and
+                                 are not counted                                            */
     void *trace_out;          /* DEVICE or NULL: iterate after every sweep, [max_iter, n_steps, D] */
     size_t trace_bytes;       /* size of trace_out                                           */
     int floor_stall;          /* > 0: stop a chain at its rounding floor after this many sweeps
