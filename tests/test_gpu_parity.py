@@ -337,6 +337,32 @@ def test_graph_mode_matches_eager(ctx, pm):
         assert r1.sweeps == r0.sweeps
 
 
+def test_sweep_batches_and_max_iter(ctx, pm):
+    """Sweeps are enqueued several at a time between status reads: a solve
+    capped by max_iter runs exactly max_iter sweeps, a solve capped at its own
+    sweep count equals the uncapped one (sweeps queued after convergence change
+    nothing), and the profiled step count covers the executed sweeps only."""
+    _say("sweep batches and max_iter")
+    ch = W.funnel_chain(T=3000, seed=5)
+    g = pm.Target(ctx, ch.target)
+    args = (ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u))
+    r = pm.solve(*args, variant="diag", max_iter=3001)
+    assert r.status == 0
+    for cap in (1, 7, 8, 13):
+        if cap >= r.sweeps:
+            continue
+        rc = pm.solve(*args, variant="diag", max_iter=cap)
+        assert rc.status == pm.B.PMC_NOT_CONVERGED, cap
+        assert rc.sweeps == cap and rc.sweeps_per_chain == [cap], (cap, rc.sweeps)
+    rx = pm.solve(*args, variant="diag", max_iter=r.sweeps)
+    assert rx.status == 0 and rx.sweeps == r.sweeps
+    assert torch.equal(rx.states, r.states) and torch.equal(rx.accept, r.accept)
+    rp = pm.solve(*args, variant="diag", max_iter=3001, profile_kernels=True)
+    assert torch.equal(rp.states, r.states) and rp.sweeps == r.sweeps
+    assert 0 < rp.eval_steps <= r.sweeps * 3000
+    assert rp.eval_steps >= 3000  # the first sweep evaluates every step
+
+
 def test_sliding_window_prefix_skip(ctx, pm, orc):
     _say("sliding window")
     ch, tg, s0 = _logreg_case(orc, 4096, 0.0015, seed=1)
