@@ -449,8 +449,10 @@ struct DiagNewtonIO {
         if (trace) trace[i] = s;
         part_add<R>(p, t, dc[0], s, e.b[0], atol, rtol);
     }
-    // four consecutive steps from a 16-byte aligned index (FP32 only)
+    // Vector form (FP32): four consecutive steps from a 16-byte aligned index
+    // (the planes' stride ld is a multiple of 64).
     static constexpr bool kVec = sizeof(R) == 4;
+    __device__ bool vec_ok(int64_t t0) const { return (t0 & 3) == 0; }
     __device__ void load4(int lane, int64_t t, Aff<R, 1> *e, Extra *x) const
     {
         const size_t i = (size_t)lane * ld + t;
@@ -465,17 +467,34 @@ struct DiagNewtonIO {
             x[q].f[0] = ff[q];
         }
     }
-    __device__ void store1(int lane, int64_t t, R s) const
+    // steps t .. t+nv-1 (nv <= 4) with the carry d entering step t; d leaves
+    // as the carry after the last one
+    __device__ void update4(int lane, int64_t t, int nv, const Aff<R, 1> *e, const Extra *x, R (&d)[1],
+                            Part &p) const
     {
         const size_t i = (size_t)lane * ld + t;
-        S[i] = s;
-        if (trace) trace[i] = s;
-    }
-    __device__ void store4(int lane, int64_t t, const R *s4) const
-    {
-        const size_t i = (size_t)lane * ld + t;
-        *(float4 *)(S + i) = make_float4(s4[0], s4[1], s4[2], s4[3]);
-        if (trace) *(float4 *)(trace + i) = make_float4(s4[0], s4[1], s4[2], s4[3]);
+        R sv[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (q < nv) {
+                const R dp = d[0];
+                d[0] = fma(e[q].a[0][0], dp, e[q].b[0]);
+                sv[q] = fma(e[q].a[0][0], dp, x[q].f[0]);
+                part_add<R>(p, t + q, d[0], sv[q], e[q].b[0], atol, rtol);
+            }
+        }
+        if (nv == 4) {
+            *(float4 *)(S + i) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+            if (trace) *(float4 *)(trace + i) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                if (q < nv) {
+                    S[i + q] = sv[q];
+                    if (trace) trace[i + q] = sv[q];
+                }
+            }
+        }
     }
 };
 
@@ -553,6 +572,38 @@ struct DiagLinIO {
     {
         out[(size_t)lane * g.T + t] = dc[0];
     }
+    // Vector form (FP32): needs 16-byte aligned plane offsets, so T % 4 == 0.
+    static constexpr bool kVec = sizeof(R) == 4;
+    __device__ bool vec_ok(int64_t t0) const { return (t0 & 3) == 0 && (g.T & 3) == 0; }
+    __device__ void load4(int lane, int64_t t, Aff<R, 1> *e, Extra *) const
+    {
+        const size_t i = (size_t)lane * g.T + t;
+        const float4 a4 = *(const float4 *)(a + i), b4 = *(const float4 *)(b + i);
+        const float aa[4] = {a4.x, a4.y, a4.z, a4.w}, bb[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            e[q].a[0][0] = aa[q];
+            e[q].b[0] = bb[q];
+        }
+    }
+    __device__ void update4(int lane, int64_t t, int nv, const Aff<R, 1> *e, const Extra *, R (&d)[1],
+                            Part &) const
+    {
+        const size_t i = (size_t)lane * g.T + t;
+        R v[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (q < nv) d[0] = fma(e[q].a[0][0], d[0], e[q].b[0]);
+            v[q] = d[0];
+        }
+        if (nv == 4) {
+            *(float4 *)(out + i) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (q < nv) out[i + q] = v[q];
+        }
+    }
 };
 
 struct Block2LinIO {
@@ -581,6 +632,58 @@ struct Block2LinIO {
         const size_t i = (size_t)lane * g.T + t;
         out[i] = dc[0];
         out[pl + i] = dc[1];
+    }
+    // Vector form: needs 16-byte aligned plane offsets, so T % 4 == 0.
+    static constexpr bool kVec = true;
+    __device__ bool vec_ok(int64_t t0) const { return (t0 & 3) == 0 && (g.T & 3) == 0; }
+    __device__ void load4(int lane, int64_t t, Aff<float, 2> *e, Extra *) const
+    {
+        const size_t pl = (size_t)n_lanes * g.T;
+        const size_t i = (size_t)lane * g.T + t;
+        float v[6][4];
+        const float *src[6] = {coef + i, coef + pl + i, coef + 2 * pl + i, coef + 3 * pl + i, rhs + i, rhs + pl + i};
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const float4 w = *(const float4 *)src[k];
+            v[k][0] = w.x, v[k][1] = w.y, v[k][2] = w.z, v[k][3] = w.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            e[q].a[0][0] = v[0][q];
+            e[q].a[0][1] = v[1][q];
+            e[q].a[1][0] = v[2][q];
+            e[q].a[1][1] = v[3][q];
+            e[q].b[0] = v[4][q];
+            e[q].b[1] = v[5][q];
+        }
+    }
+    __device__ void update4(int lane, int64_t t, int nv, const Aff<float, 2> *e, const Extra *, float (&d)[2],
+                            Part &) const
+    {
+        const size_t pl = (size_t)n_lanes * g.T;
+        const size_t i = (size_t)lane * g.T + t;
+        float p[4], q4[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (q < nv) {
+                float dp[2] = {d[0], d[1]};
+                apply(e[q], dp, d);
+            }
+            p[q] = d[0];
+            q4[q] = d[1];
+        }
+        if (nv == 4) {
+            *(float4 *)(out + i) = make_float4(p[0], p[1], p[2], p[3]);
+            *(float4 *)(out + pl + i) = make_float4(q4[0], q4[1], q4[2], q4[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                if (q < nv) {
+                    out[i + q] = p[q];
+                    out[pl + i + q] = q4[q];
+                }
+            }
+        }
     }
 };
 
@@ -670,7 +773,7 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         typename IO::Extra x[ITEMS];
         const int64_t base = t0 + (int64_t)tid * ITEMS;
         bool vec = false;
-        if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) vec = (t0 & 3) == 0;
+        if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) vec = io.vec_ok(t0);
         if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) {
             if (vec) {
 #pragma unroll
@@ -742,21 +845,9 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
             if (vec) {
 #pragma unroll
                 for (int i = 0; i < ITEMS; i += 4) {
-                    R sv[4];
-                    const bool full = base + i + 3 < t1;
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        if (base + i + q < t1) {
-                            R dp[M];
-#pragma unroll
-                            for (int k = 0; k < M; k++) dp[k] = d[k];
-                            apply(e[i + q], dp, d);
-                            sv[q] = fma(e[i + q].a[0][0], dp[0], x[i + q].f[0]);
-                            part_add<R>(part, base + i + q, d[0], sv[q], e[i + q].b[0], io.atol, io.rtol);
-                            if (!full) io.store1(lane, base + i + q, sv[q]);
-                        }
-                    }
-                    if (full) io.store4(lane, base + i, sv);
+                    const int64_t left = t1 - (base + i);
+                    const int nv = left >= 4 ? 4 : left > 0 ? (int)left : 0;
+                    if (nv > 0) io.update4(lane, base + i, nv, &e[i], &x[i], d, part);
                 }
             }
         }
@@ -1118,15 +1209,28 @@ pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64
         DiagLinIO<double> io{LinGeom{T, nt}, (const double *)a, (const double *)b, (double *)out};
         return run_scan<DiagLinIO<double>, 256, 8>(ctx, io, n_lanes, nt, nullptr);
     }
-    constexpr int C = 256 * 16;
+    // the Newton scan's rule: larger tiles (fewer look-back hops) for large scans
+    if ((int64_t)n_lanes * T >= (int64_t(1) << 23)) {
+        constexpr int C = 1024 * 8;
+        int nt = (int)((T + C - 1) / C);
+        DiagLinIO<float> io{LinGeom{T, nt}, (const float *)a, (const float *)b, (float *)out};
+        return run_scan<DiagLinIO<float>, 1024, 8>(ctx, io, n_lanes, nt, nullptr);
+    }
+    constexpr int C = 512 * 8;
     int nt = (int)((T + C - 1) / C);
     DiagLinIO<float> io{LinGeom{T, nt}, (const float *)a, (const float *)b, (float *)out};
-    return run_scan<DiagLinIO<float>, 256, 16>(ctx, io, n_lanes, nt, nullptr);
+    return run_scan<DiagLinIO<float>, 512, 8>(ctx, io, n_lanes, nt, nullptr);
 }
 
 pmc_status launch_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
                                 const void *rhs, void *out)
 {
+    if ((int64_t)n_lanes * T >= (int64_t(1) << 22)) {
+        constexpr int C = 1024 * 4;
+        int nt = (int)((T + C - 1) / C);
+        Block2LinIO io{LinGeom{T, nt}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};
+        return run_scan<Block2LinIO, 1024, 4>(ctx, io, n_lanes, nt, nullptr);
+    }
     constexpr int C = 256 * 4;
     int nt = (int)((T + C - 1) / C);
     Block2LinIO io{LinGeom{T, nt}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};

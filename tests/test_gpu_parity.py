@@ -82,6 +82,38 @@ def test_linrec_diag_large(ctx, pm, orc):
     assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
 
 
+def test_linrec_diag_large_vector_tiles(ctx, pm, orc):
+    """8 lanes x 2^20 steps: the large-scan tiles (1024 x 8) with vector loads;
+    exact carries (a = 1, b = 1) and a random recursion against the oracle."""
+    _say("linrec_diag 8 x 2^20 (large tiles, vector path)")
+    L, T = 8, 1 << 20
+    ones = torch.ones((L, T), device=DEV)
+    out = pm.linrec_diag(ctx, ones, ones)
+    ref = torch.arange(1, T + 1, device=DEV, dtype=torch.float32)
+    assert all(torch.equal(out[k], ref) for k in range(L))
+    rng = np.random.default_rng(11)
+    a = rng.uniform(-0.99, 0.99, size=(L, T)).astype(np.float32)
+    b = rng.normal(size=(L, T)).astype(np.float32)
+    out = pm.linrec_diag(ctx, _t(a), _t(b)).cpu().numpy().astype(np.float64)
+    ref = orc.linrec_diag(a.T, b.T).T
+    assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_linrec_block2_large_vector_tiles(ctx, pm, orc):
+    """2 lanes x 2^21 steps: the large-scan tiles (1024 x 4) with vector loads."""
+    _say("linrec_block2 2 x 2^21 (large tiles, vector path)")
+    L, T = 2, 1 << 21
+    rng = np.random.default_rng(12)
+    coef = rng.uniform(-0.6, 0.6, size=(4, L, T)).astype(np.float32)
+    rhs = rng.normal(size=(2, L, T)).astype(np.float32)
+    out = pm.linrec_block2(ctx, _t(coef), _t(rhs)).cpu().numpy().astype(np.float64)
+    c = coef.astype(np.float64)
+    r = rhs.astype(np.float64)
+    p, q = orc.linrec_block2(c[0].T, c[1].T, c[2].T, c[3].T, r[0].T, r[1].T)
+    ref = np.stack([p.T, q.T])
+    assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
+
+
 @pytest.mark.parametrize("T", [1, 1000, 5001])
 def test_linrec_block2(ctx, pm, orc, T):
     _say(f"linrec_block2 T={T}")
