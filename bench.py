@@ -165,6 +165,43 @@ def main():
     del gx0, gxi, gtg
     torch.cuda.empty_cache()
 
+    # ---- the standalone recursions at large shapes (diagonal: 16 x 2^22,
+    # 12 B per element; 2x2 block: 8 x 2^22, 32 B per element), HIP events on
+    # the context's stream around whole calls (each call synchronises its
+    # stream to report look-back failures, so this is a per-call rate; the
+    # kernel-only durations are in the kernel trace)
+    def _ev_ms(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    la = torch.rand((16, 1 << 22), device=dev, generator=gen) * 0.5 + 0.5
+    lb = torch.randn((16, 1 << 22), device=dev, generator=gen)
+    ms_d = _ev_ms(lambda: pm.linrec_diag(ctx, la, lb))
+    del la, lb
+    lc = torch.rand((4, 8, 1 << 22), device=dev, generator=gen) * 0.6 - 0.3
+    lr = torch.randn((2, 8, 1 << 22), device=dev, generator=gen)
+    ms_b = _ev_ms(lambda: pm.linrec_block2(ctx, lc, lr))
+    del lc, lr
+    torch.cuda.empty_cache()
+    bd, bb = 12.0 * 16 * (1 << 22), 32.0 * 8 * (1 << 22)
+    out["roofline_linrec"] = {
+        "diag": {"bound": "hbm", "achieved": bd / (ms_d * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": bd / (ms_d * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_call_ms": ms_d,
+                 "kernel": "k_scan<DiagLinIO>", "shape": "16 planes x 2^22 steps, FP32"},
+        "block2": {"bound": "hbm", "achieved": bb / (ms_b * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": bb / (ms_b * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_call_ms": ms_b,
+                   "kernel": "k_scan<Block2LinIO>", "shape": "8 lanes x 2^22 steps, 2x2 blocks, FP32"}}
+    _log(f"[bench] standalone recursions: diag {ms_d:.3f} ms, block2 {ms_b:.3f} ms")
+
     # ---- the step size as specified (0.02): run and report
     if not args.no_as_specified:
         ch2 = W.logreg_chain(T=T, seed=0, eps=0.02)
