@@ -505,8 +505,9 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
 
     // ---- pass 2: gradient at the proposal, Hessian diagonal, log-likelihood difference
     f32x16 Gt = zero, Hd = zero;
-    float dll = 0.f;
+    double dll = 0.0;  // FP32 partial per row tile, FP64 total
     for (int rt = 0; rt < f.nr; rt++) {
+        float dtile = 0.f;
         const float *xa = f.xa + (size_t)rt * MK * 64 + lane;
         const float *xta = f.xta + (size_t)rt * 16 * 64 + lane;
         const float *x2ta = f.x2ta + (size_t)rt * 16 * 64 + lane;
@@ -527,8 +528,9 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
             shifted(z, dz, s, st, spd);
             Rt[r] = yv - st;
             Wv[r] = s * (1.f - s);
-            dll += yv * dz - spd;
+            dtile += yv * dz - spd;
         }
+        dll += (double)dtile;
         {
             float RB[16];
             acc_to_b(Rt, RB, hh);
@@ -549,14 +551,15 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
         sgt[crow(r, hh) * 33 + j] = Gt[r];
         shd[crow(r, hh) * 33 + j] = Hd[r];
     }
-    dll += __shfl_xor(dll, 32, 64);
+    dll += __shfl_xor(dll, 32, 64);  // the two halves in the same order on both
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (hh != 0 || !valid) return;
 
-    // ---- one lane per step: log ratio, decision, f_t, Jacobian diagonal
-    float sn = 0.f, sx = 0.f, dpr = 0.f;
+    // ---- one lane per step: log ratio (assembled in FP64 from the FP32
+    // products, as in the LDS-resident kernel), decision, f_t, Jacobian diagonal
+    double sn = 0.0, sx = 0.0, dpr = 0.0;
     for (int d = 0; d < D; d++) {
         const float x = head ? s0[d] : S[(size_t)d * ld + t - 1];
         const float xi = noise[(size_t)t * D + d];
@@ -564,18 +567,19 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
         const float dl = fmaf(eps, g, c * xi);
         const float xt = x + dl;
         const float gt = sgt[d * 33 + j] - pp * xt;
-        const float s = g + gt;
-        sn = fmaf(s, s, sn);
-        sx = fmaf(xi, s, sx);
-        dpr = fmaf(dl, xt + x, dpr);
+        const double s = (double)g + (double)gt;
+        sn = fma(s, s, sn);
+        sx = fma((double)xi, s, sx);
+        dpr = fma((double)dl, (double)xt + (double)x, dpr);
     }
     int acc = 1;
     float gate = INFINITY;
     if (!a.ula) {
-        const float ell = dll - 0.5f * pp * dpr - 0.25f * eps * sn - sqrtf(0.5f * eps) * sx;
-        const float la = ell < 0.f ? ell : 0.f;
-        gate = la - logf(((const float *)a.unif)[t]);
-        acc = gate > 0.f;
+        const double ell = dll - 0.5 * (double)pp * dpr - 0.25 * a.eps * sn - sqrt(0.5 * a.eps) * sx;
+        const double la = ell < 0.0 ? ell : 0.0;
+        const double gd = la - log((double)((const float *)a.unif)[t]);
+        gate = (float)gd;
+        acc = gd > 0.0;
         if (!(ell == ell)) acc = 0;
     }
     float *F = (float *)a.F;

@@ -302,20 +302,34 @@ pmc_status launch_sequential(pmc_context *ctx, const DevTarget &t, const SeqArgs
         if (t.dtype == PMC_F64) return seq_dm<double, Funnel>(ctx, a, D, (double)t.theta);
         return seq_dm<float, Funnel>(ctx, a, D, (float)t.theta);
     case PMC_TARGET_LOGREG: {
-        if (t.n_data > 4 * 256) {
-            set_error("sequential logreg sampler supports n_data <= 1024");
+        // 256 threads x 4 rows up to 1024 data points, 512 x 4 up to 2048
+        if (t.n_data > 4 * 512) {
+            set_error("sequential logreg sampler supports n_data <= 2048");
             return PMC_ERR_UNSUPPORTED;
         }
         const float pp = (float)(1.0 / t.prior_var);
         const float *X = (const float *)t.X, *y = (const float *)t.y;
-        dim3 grid(a.n_chains), block(256);
-        switch (t.ldx) {
-        case 4: hipLaunchKernelGGL((k_seq_logreg<4, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-        case 8: hipLaunchKernelGGL((k_seq_logreg<8, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-        case 16: hipLaunchKernelGGL((k_seq_logreg<16, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-        case 25: hipLaunchKernelGGL((k_seq_logreg<25, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-        case 32: hipLaunchKernelGGL((k_seq_logreg<32, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
-        default: set_error("logreg: unsupported padded dimension %d", t.ldx); return PMC_ERR_UNSUPPORTED;
+        dim3 grid(a.n_chains);
+        if (t.n_data <= 4 * 256) {
+            dim3 block(256);
+            switch (t.ldx) {
+            case 4: hipLaunchKernelGGL((k_seq_logreg<4, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 8: hipLaunchKernelGGL((k_seq_logreg<8, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 16: hipLaunchKernelGGL((k_seq_logreg<16, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 25: hipLaunchKernelGGL((k_seq_logreg<25, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 32: hipLaunchKernelGGL((k_seq_logreg<32, 256, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            default: set_error("logreg: unsupported padded dimension %d", t.ldx); return PMC_ERR_UNSUPPORTED;
+            }
+        } else {
+            dim3 block(512);
+            switch (t.ldx) {
+            case 4: hipLaunchKernelGGL((k_seq_logreg<4, 512, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 8: hipLaunchKernelGGL((k_seq_logreg<8, 512, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 16: hipLaunchKernelGGL((k_seq_logreg<16, 512, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 25: hipLaunchKernelGGL((k_seq_logreg<25, 512, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            case 32: hipLaunchKernelGGL((k_seq_logreg<32, 512, 4>), grid, block, 0, ctx->stream, a, X, y, t.n_data, pp); break;
+            default: set_error("logreg: unsupported padded dimension %d", t.ldx); return PMC_ERR_UNSUPPORTED;
+            }
         }
         PMC_TRY_HIP(hipGetLastError());
         return PMC_OK;

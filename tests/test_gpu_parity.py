@@ -291,6 +291,22 @@ def test_logreg_gate_precision(ctx, pm, orc):
         assert err.max() <= F32_GATE_ERR
 
 
+def test_logreg_large_n_fallback_fp32(ctx, pm, orc):
+    """N = 1300 data points, more 32-row tiles than the LDS image holds: the
+    evaluation takes its operands from global memory instead."""
+    _say("logreg N=1300 D=8 fp32 (global-memory evaluation)")
+    ch = W.logreg_chain(T=2048, seed=3, eps=0.001, n_data=1300, dim=8)
+    tg = oracle_target(ch.target)
+    s0 = oracle_burnin(tg, ch).astype(np.float32)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=2049)
+    _say(f"  sweeps={r.sweeps} status={r.status} acceptance={r.n_accept / 2048:.3f}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+    rs = pm.sample_sequential(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u))
+    _check_mala(orc, tg, ch, s0, rs.states.cpu().numpy(), rs.accept.cpu().numpy())
+
+
 def test_logreg_sequential_fp32(ctx, pm, orc):
     _say("logreg sequential fp32")
     ch, tg, s0 = _logreg_case(orc, 4096, 0.0015)
