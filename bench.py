@@ -341,6 +341,21 @@ def other_workload(args, pm, W, np, torch):
             res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status, "n_floor": r.n_floor,
                          "vs_sequential": ts / tp,
                          "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+        # the matrix-core dense scan inside the solve, per sweep (HIP events):
+        # HBM bytes = J read by the up and the down sweep + F, S read + S
+        # written; matrix work = one 32 x 32 x 32 product per step (up sweep)
+        for name, jp, jbytes, peak in (("dense_scan_bf16", "bf16", 2048, 2500.0),
+                                       ("dense_scan_f32", "f32", 4096, PEAK_FP32_VECTOR_TFLOPS)):
+            r = pm.solve(ctx, g, ch.eps, x0, xi, u, variant="dense", jac_prec=jp, max_iter=16,
+                         profile_kernels=True)
+            sms = r.scan_ms / r.sweeps
+            nbytes = ch.T * (2.0 * jbytes + 3 * 4 * 32)
+            flops = ch.T * 2.0 * 32 ** 3
+            res[name] = {"scan_ms_per_sweep": sms, "sweeps_timed": r.sweeps,
+                         "hbm": {"achieved": nbytes / (sms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": nbytes / (sms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+                         "mfma": {"achieved": flops / (sms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                                  "frac": flops / (sms * 1e-3) / 1e12 / peak}}
         r = pm.solve(ctx, g, ch.eps, x0, xi, u, variant="diag", max_iter=16385)
         dF = ((2.0 / ch.T) * r.states).contiguous()
         (dth, dep), ta = _timed(lambda: pm.adjoint(ctx, g, ch.eps, x0, xi, u, r.states, r.accept, dF),

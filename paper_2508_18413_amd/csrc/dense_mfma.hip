@@ -38,7 +38,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kU = 32;  // elements per unit
+constexpr int kU = 32;  // elements per level-0 unit
+constexpr int kU1 = 8;  // maps per unit at levels >= 1 (more, shorter chains)
 constexpr int kWPB = 4; // waves (units) per block
 
 __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
@@ -129,29 +130,22 @@ struct ChainB {
         return c;
     }
     // accumulator -> B layout: lane h = 0 needs rows 0-7 and 16-23, lane h = 1
-    // rows 8-15 and 24-31; swap registers {4-7, 12-15} (h = 0) with {0-3, 8-11}
-    // (h = 1) between lanes l and l ^ 32.
-    __device__ void from_acc(const f32x16 &c, int h)
+    // rows 8-15 and 24-31.  The gfx950 lane-half swap (upper 32 lanes of its
+    // first operand <-> lower 32 lanes of its second) applied to the register
+    // pairs (c[q], c[4+q]) and (c[8+q], c[12+q]) leaves exactly those rows in
+    // b[0][q], b[0][4+q], b[1][q], b[1][4+q] on both halves.
+    __device__ void from_acc(const f32x16 &c, int)
     {
-        float r0[4], r1[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            r0[q] = __shfl_xor(h ? c[q] : c[4 + q], 32, 64);
-            r1[q] = __shfl_xor(h ? c[8 + q] : c[12 + q], 32, 64);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            if (h == 0) {
-                b[0][q] = (__bf16)c[q];
-                b[0][4 + q] = (__bf16)r0[q];
-                b[1][q] = (__bf16)c[8 + q];
-                b[1][4 + q] = (__bf16)r1[q];
-            } else {
-                b[0][q] = (__bf16)r0[q];
-                b[0][4 + q] = (__bf16)c[4 + q];
-                b[1][q] = (__bf16)r1[q];
-                b[1][4 + q] = (__bf16)c[12 + q];
-            }
+            const auto p0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[q]), __float_as_uint(c[4 + q]),
+                                                             false, false);
+            const auto p1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[8 + q]),
+                                                             __float_as_uint(c[12 + q]), false, false);
+            b[0][q] = (__bf16)__uint_as_float(p0[0]);
+            b[0][4 + q] = (__bf16)__uint_as_float(p0[1]);
+            b[1][q] = (__bf16)__uint_as_float(p1[0]);
+            b[1][4 + q] = (__bf16)__uint_as_float(p1[1]);
         }
     }
 };
@@ -170,20 +164,21 @@ struct ChainF {
         for (int m = 0; m < 16; m++) c = __builtin_amdgcn_mfma_f32_32x32x2f32(A.at(m), b[m], c, 0, 0, 0);
         return c;
     }
-    // lane h needs rows of parity h: h = 0 sends its odd rows (registers 2q+1),
-    // h = 1 its even rows (registers 2q), q = 0..7.
-    __device__ void from_acc(const f32x16 &c, int h)
+    // lane h needs rows of parity h (B row 2 m + h).  Register 4g + w holds row
+    // 8g + 4h + w; the lane-half swap of the pairs (c[4g], c[4g+1]) and
+    // (c[4g+2], c[4g+3]) gives (b[4g], b[4g+2]) and (b[4g+1], b[4g+3]).
+    __device__ void from_acc(const f32x16 &c, int)
     {
-        float rc[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) rc[q] = __shfl_xor(h ? c[2 * q] : c[2 * q + 1], 32, 64);
-#pragma unroll
-        for (int m = 0; m < 16; m++) {
-            const int g = m >> 2, w = m & 3;
-            if (h == 0)
-                b[m] = w < 2 ? c[4 * g + 2 * w] : rc[2 * g + (w - 2)];
-            else
-                b[m] = w < 2 ? rc[2 * g + w] : c[4 * g + 2 * (w - 2) + 1];
+        for (int g = 0; g < 4; g++) {
+            const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[4 * g]), __float_as_uint(c[4 * g + 1]),
+                                                            false, false);
+            const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[4 * g + 2]),
+                                                            __float_as_uint(c[4 * g + 3]), false, false);
+            b[4 * g] = __uint_as_float(p[0]);
+            b[4 * g + 2] = __uint_as_float(p[1]);
+            b[4 * g + 1] = __uint_as_float(q[0]);
+            b[4 * g + 3] = __uint_as_float(q[1]);
         }
     }
 };
@@ -247,15 +242,15 @@ struct MapIn {  // levels >= 1: B vectors [n, 32]
 // ---------------------------------------------------------------- up pass
 template <class Frag, class Chain, class In>
 __global__ void __launch_bounds__(64 * kWPB)
-k_up(const void *Jv, In in, int64_t n, float4 *Pout, float *Bout)
+k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout)
 {
     __shared__ float s_t[kWPB][32 * 33];
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
-    if (u * kU >= n) return;
-    const int64_t t0 = u * kU;
-    const int cnt = (int)min((int64_t)kU, n - t0);
+    if (u * unit >= n) return;
+    const int64_t t0 = u * unit;
+    const int cnt = (int)min((int64_t)unit, n - t0);
     Chain P;
     P.identity(i, h);
     f32x16 c;
@@ -284,14 +279,14 @@ k_up(const void *Jv, In in, int64_t n, float4 *Pout, float *Bout)
 // ------------------------------------------------------------- down pass
 // Level >= 1: carries of the children.  carry_in == nullptr means zero.
 __global__ void __launch_bounds__(64 * kWPB)
-k_down_maps(const float4 *P, const float *B, int64_t n, const float *carry_in, float *carry_out)
+k_down_maps(const float4 *P, const float *B, int64_t n, int unit, const float *carry_in, float *carry_out)
 {
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
-    if (u * kU >= n) return;
-    const int64_t t0 = u * kU;
-    const int cnt = (int)min((int64_t)kU, n - t0);
+    if (u * unit >= n) return;
+    const int64_t t0 = u * unit;
+    const int cnt = (int)min((int64_t)unit, n - t0);
     float *v = s_v[w];
     if (h == 0) v[i] = carry_in ? carry_in[(size_t)u * 32 + i] : 0.f;
     wave_lds_sync();
@@ -438,7 +433,7 @@ __global__ void k_pack(const float *A, int D, int64_t T, void *out, int bf16)
     }
 }
 
-inline unsigned blocks_for(int64_t n) { return (unsigned)(((n + kU - 1) / kU + kWPB - 1) / kWPB); }
+inline unsigned blocks_for(int64_t n, int unit = kU) { return (unsigned)(((n + unit - 1) / unit + kWPB - 1) / kWPB); }
 
 }  // namespace
 
@@ -447,10 +442,12 @@ size_t dense_mfma_ws_bytes(int64_t n)
 {
     size_t b = 0;
     int64_t m = n;
-    while (m > kU) {
-        const int64_t u = (m + kU - 1) / kU;
+    int unit = kU;
+    while (m > unit) {
+        const int64_t u = (m + unit - 1) / unit;
         b += align_up((size_t)u * 1024 * 4, 256) + 2 * align_up((size_t)u * 32 * 4, 256);
         m = u;
+        unit = kU1;
     }
     return b + 256;
 }
@@ -470,8 +467,10 @@ static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0
     std::vector<Lv> lv;
     int64_t m = n;
     char *p = ws;
-    while (m > kU) {
-        const int64_t u = (m + kU - 1) / kU;
+    int unit = kU;  // level 0 groups 32 steps, the levels above kU1 maps
+    while (m > unit) {
+        const int64_t u = (m + unit - 1) / unit;
+        unit = kU1;
         Lv L;
         L.n = u;
         L.P = (float4 *)p;
@@ -489,18 +488,18 @@ static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0
     }
     // up
     hipLaunchKernelGGL((k_up<Frag, Chain, In>), dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream, J,
-                       in0, n, lv[0].P, lv[0].B);
+                       in0, n, kU, lv[0].P, lv[0].B);
     for (size_t k = 1; k < lv.size(); k++)
-        hipLaunchKernelGGL((k_up<FragF, ChainF, MapIn>), dim3(blocks_for(lv[k - 1].n)), dim3(64 * kWPB),
-                           0, ctx->stream, (const void *)lv[k - 1].P, MapIn{lv[k - 1].B}, lv[k - 1].n,
+        hipLaunchKernelGGL((k_up<FragF, ChainF, MapIn>), dim3(blocks_for(lv[k - 1].n, kU1)), dim3(64 * kWPB),
+                           0, ctx->stream, (const void *)lv[k - 1].P, MapIn{lv[k - 1].B}, lv[k - 1].n, kU1,
                            lv[k].P, lv[k].B);
-    // top: the last level's maps (<= 32) from a zero carry
+    // top: the last level's maps (<= kU1) from a zero carry
     const Lv &top = lv.back();
     hipLaunchKernelGGL(k_down_maps, dim3(1), dim3(64 * kWPB), 0, ctx->stream, (const float4 *)top.P,
-                       (const float *)top.B, top.n, (const float *)nullptr, top.carry);
+                       (const float *)top.B, top.n, kU1, (const float *)nullptr, top.carry);
     for (int k = (int)lv.size() - 2; k >= 0; k--)
-        hipLaunchKernelGGL(k_down_maps, dim3(blocks_for(lv[k].n)), dim3(64 * kWPB), 0, ctx->stream,
-                           (const float4 *)lv[k].P, (const float *)lv[k].B, lv[k].n,
+        hipLaunchKernelGGL(k_down_maps, dim3(blocks_for(lv[k].n, kU1)), dim3(64 * kWPB), 0, ctx->stream,
+                           (const float4 *)lv[k].P, (const float *)lv[k].B, lv[k].n, kU1,
                            (const float *)lv[k + 1].carry, lv[k].carry);
     PMC_TRY_HIP(hipGetLastError());
     *carry0 = lv[0].carry;
