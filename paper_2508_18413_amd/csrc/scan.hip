@@ -1038,14 +1038,17 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
             cs.fb_prev = fb;
         }
     }
-    // completion count: the last workgroup sees every chain's update
+    // completion count: the last workgroup sees every chain's update (a
+    // single workgroup is its own last one and needs neither the device-scope
+    // fences nor the counter)
+    const bool single = gridDim.x == 1;
     __shared__ int s_last;
-    __threadfence();
+    if (!single) __threadfence();
     __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&a.global->fold_ctr, 1u) == gridDim.x - 1;
+    if (tid == 0) s_last = single || atomicAdd(&a.global->fold_ctr, 1u) == gridDim.x - 1;
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
+    if (!single) __threadfence();
     __shared__ int s_cnt[kStatusThreads / 64][4];
     Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
     int nact = 0, nconv = 0, nfloor = 0, sweeps = 0;
@@ -1107,7 +1110,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
             const uint32_t e = __hip_atomic_load(&sy->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&sy->epoch, (e + 1) & 0x3fffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __hip_atomic_store(&g->fold_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!single) __hip_atomic_store(&g->fold_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
