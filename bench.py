@@ -10,7 +10,7 @@ puts the sampler at the Langevin stability edge (acceptance ~0.2 %) and is run
 and reported separately under "as_specified".  Inputs are resident in HBM when
 the timed region starts.
 
-Prints one JSON line.  --gpus > 1 is rejected: this build targets one GPU.
+Prints one JSON line.  --gpus > 1 is rejected: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -50,7 +50,7 @@ def main():
                          "measurements of the remaining configurations")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
     PMC_OK = 0,
     PMC_ERR_INVALID = 1,     /* bad argument (null pointer, size, enum, layout)      */
-    PMC_ERR_UNSUPPORTED = 2, /* valid request that this build does not implement     */
+    PMC_ERR_UNSUPPORTED = 2, /* valid request that the library does not implement   */
     PMC_ERR_OOM = 3,         /* device allocation failed or workspace too small      */
     PMC_ERR_HIP = 4,         /* HIP runtime error (no device, launch failure, ...)   */
     PMC_NOT_CONVERGED = 5,   /* soft: max_iter reached; outputs hold the last iterate */
