@@ -61,7 +61,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"libpmcmc.so not built ({LIB_PATH}); run __graft_entry__.build()")
+            raise RuntimeError(f"libpmcmc.so not built ({LIB_PATH}); run python paper_2508_18413_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp, i64, st = C.c_void_p, C.c_int64, C.c_int
         sig = {

@@ -119,7 +119,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     case PMC_PICARD: pl.jmode = JM_NONE; break;
     case PMC_DEER_DENSE:
         if (t.kind == PMC_TARGET_LOGREG) {
-            set_error("pmc_solve: dense DEER on logistic regression is not built");
+            set_error("pmc_solve: dense DEER on logistic regression is not implemented");
             return PMC_ERR_UNSUPPORTED;
         }
         pl.n_lanes = 1;
