@@ -18,7 +18,8 @@
 // Descriptor words are 64-bit (tag << 32 | 32-bit payload piece) written and
 // read with agent-scope atomics, so every word validates itself and no memory
 // fence is needed between payload and flag.  Tags carry a per-launch epoch
-// that a one-thread kernel advances after each scan (descriptors never need
+// that a one-thread kernel advances after each scan, or, inside a Newton
+// solve, the status fold that follows the scan (descriptors never need
 // clearing; captured graphs can replay the scan).  A tile's id is its
 // workgroup index: workgroups are dispatched in index order on each XCD, so a
 // tile's predecessors were scheduled before it, and no per-tile counter (a
