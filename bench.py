@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="end with a plain device copy of MIB MiB (FP32), the reference "
                          "kernel for scaling hardware byte counters")
+    ap.add_argument("--products", default="split16", choices=["split16", "f32"],
+                    help="matrix products of the logistic-regression evaluation: split-FP16 "
+                         "terms on the FP16 matrix cores (default) or FP32 matrix instructions")
     ap.add_argument("--workload", default="logreg",
                     choices=["logreg", "banana", "hmc", "funnel", "batched"],
                     help="logreg (default) is the benchmark line; the others print "
@@ -67,7 +70,8 @@ def main():
     T, eps = args.T, args.eps
     ch = W.logreg_chain(T=T, seed=0, eps=eps)
     ctx = pm.Context(0)
-    tg = pm.Target(ctx, ch.target)
+    tg = pm.Target(ctx, dict(ch.target, products=args.products))
+    eval_kernel = "k_eval_logreg_h" if args.products == "split16" else "k_eval_logreg_lds"
     # burn-in (3 MALA steps) by the GPU sequential sampler, outside the timed region
     b = pm.sample_sequential(ctx, tg, eps, torch.tensor(ch.x0, device=dev),
                              torch.tensor(ch.burn_xi, device=dev), torch.tensor(ch.burn_u, device=dev))
@@ -122,6 +126,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "products": args.products,
         "data": "synthetic",
         "config": {"workload": f"mala-logreg-d{D}-n{N}-T{T}-eps{eps}-quasi-deer",
                    "T": T, "D": D, "n_data": N, "eps": eps, "variant": "diag",
@@ -137,7 +142,7 @@ def main():
         "acceptance": r.n_accept / T,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": _traffic("k_eval_logreg_lds"), "kernel": "k_eval_logreg_lds",
+                     "traffic": _traffic(eval_kernel), "kernel": eval_kernel,
                      "avg_launch_ms": eval_avg_ms, "steps_per_launch": steps_per_launch},
         "roofline_scan_in_solve": {"bound": "hbm", "achieved": scan_bytes / (scan_avg_ms * 1e-3) / 1e9,
                                    "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -73,6 +73,17 @@ typedef enum { PMC_JAC_F32 = 0, PMC_JAC_BF16 = 1 } pmc_jac_prec;
  * sigma'(g~) (x~ - x) (d g~/dx)^T. */
 typedef enum { PMC_GATE_FROZEN = 0, PMC_GATE_SURROGATE = 1 } pmc_gate;
 
+/* How the logistic-regression evaluation forms its matrix products (FP32
+ * targets).  SPLIT16 writes each operand as hi + lo, two FP16 numbers, and sums
+ * lo*hi + hi*lo + hi*hi on the FP16 matrix cores with FP32 accumulation (the
+ * error-compensated half-precision product of Markidis et al. 2018 and Ootomo
+ * & Yokota 2022: about 2^-22 of each product is dropped, against 2^-24 for
+ * FP32; operands are brought to FP16's range by exact power-of-two scalings);
+ * it needs n_data <= 1216.  AUTO takes SPLIT16 where that holds and FP32
+ * matrix instructions elsewhere; SPLIT16 requested for more data points is
+ * PMC_ERR_UNSUPPORTED at pmc_target_create. */
+typedef enum { PMC_PRODUCTS_AUTO = 0, PMC_PRODUCTS_F32 = 1, PMC_PRODUCTS_SPLIT16 = 2 } pmc_products;
+
 typedef struct pmc_context pmc_context; /* opaque: device, stream, workspace pool, tuning table */
 typedef struct pmc_target pmc_target;   /* opaque: device copy of a target's parameters        */
 
@@ -89,6 +100,7 @@ typedef struct {
     int n_data;          /* LOGREG                                 */
     double prior_var;    /* LOGREG:   prior N(0, prior_var I)      */
     double theta;        /* FUNNEL:   neck log-scale               */
+    pmc_products products; /* LOGREG: matrix-product arithmetic (0 = AUTO) */
 } pmc_target_desc;
 
 /* One or more independent chains on one target, concatenated along time.

@@ -18,6 +18,7 @@ __all__ = ["Context", "Target", "solve", "sample_sequential", "linrec_diag", "li
 
 VARIANTS = {"dense": B.PMC_DEER_DENSE, "diag": B.PMC_QDEER_DIAG, "block2": B.PMC_QDEER_BLOCK2,
             "picard": B.PMC_PICARD}
+PRODUCTS = {"auto": B.PMC_PRODUCTS_AUTO, "f32": B.PMC_PRODUCTS_F32, "split16": B.PMC_PRODUCTS_SPLIT16}
 KINDS = {"gaussian": B.PMC_TARGET_GAUSSIAN, "banana": B.PMC_TARGET_BANANA,
          "logreg": B.PMC_TARGET_LOGREG, "funnel": B.PMC_TARGET_FUNNEL}
 
@@ -102,6 +103,7 @@ class Target:
             keep += [X, y]
             d.X, d.y, d.n_data = X.data_ptr(), y.data_ptr(), X.shape[0]
             d.prior_var = float(spec.get("prior_var", 1.0))
+            d.products = PRODUCTS[spec.get("products", "auto")]
         elif self.kind == "funnel":
             d.theta = float(spec["theta"])
         torch.cuda.synchronize(ctx.device)

@@ -20,12 +20,13 @@ PMC_TARGET_GAUSSIAN, PMC_TARGET_BANANA, PMC_TARGET_LOGREG, PMC_TARGET_FUNNEL = 0
 PMC_DEER_DENSE, PMC_QDEER_DIAG, PMC_QDEER_BLOCK2, PMC_PICARD = 0, 1, 2, 3
 PMC_JAC_F32, PMC_JAC_BF16 = 0, 1
 PMC_GATE_FROZEN, PMC_GATE_SURROGATE = 0, 1
+PMC_PRODUCTS_AUTO, PMC_PRODUCTS_F32, PMC_PRODUCTS_SPLIT16 = 0, 1, 2
 
 
 class pmc_target_desc(C.Structure):
     _fields_ = [("kind", C.c_int), ("dim", C.c_int), ("dtype", C.c_int), ("mean", C.c_void_p),
                 ("prec", C.c_void_p), ("X", C.c_void_p), ("y", C.c_void_p), ("n_data", C.c_int),
-                ("prior_var", C.c_double), ("theta", C.c_double)]
+                ("prior_var", C.c_double), ("theta", C.c_double), ("products", C.c_int)]
 
 
 class pmc_problem(C.Structure):

@@ -26,6 +26,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include "logistic.hpp"
 #include "pmc_internal.hpp"
@@ -150,6 +152,72 @@ __device__ __forceinline__ float pass2_elem(float u, float du, float y, float &a
     return fmaf(-(s + w), frcp(a), y);
 }
 
+// Per-step epilogue shared by the LDS-resident kernels (both lane halves hold
+// the step; B layout, coordinate 2 m + hh in register m).  The log ratio is
+// assembled in FP64: its terms (each up to ~10^2 on this posterior) cancel to
+// O(1), and FP32 sums of them would add errors of ~10^-5 to a quantity
+// compared against log u.  The linear part of the log-likelihood difference
+// is (X^T y) . Delta; dll_s is the softplus part in log2 units; gsc[m] turns
+// the accumulated proposal gradient into natural units.
+template <int MK>
+__device__ __forceinline__ void finish_step(const EvalArgs &a, const float *s_xty, const f32x16 &Gt, double dll_s,
+                                            const float (&SB)[MK], const float (&DB)[MK], const float (&gB)[MK],
+                                            const float (&gsc)[MK], float pp, int hh, int64_t ld, int64_t t,
+                                            int64_t tt, bool valid, bool want_j, float damp, float clip)
+{
+    const int D = a.D;
+    const float *noise = (const float *)a.noise;
+    float *F = (float *)a.F, *J = (float *)a.J;
+    double dll_y = 0.0;
+#pragma unroll
+    for (int m = 0; m < MK; m++) dll_y = fma((double)s_xty[2 * m + hh], (double)DB[m], dll_y);
+    const double dll = half_sum_d(fma(-dll_s, (double)kLn2, dll_y));
+
+    float GtB[16];
+    acc_to_b_swap(Gt, GtB);
+    double sn = 0.0, sx = 0.0, dpr = 0.0;
+#pragma unroll
+    for (int m = 0; m < MK; m++) {
+        const int d = 2 * m + hh;
+        if (d < D) {
+            const float x = SB[m], dl = DB[m], xt = x + dl;
+            const float gt = fmaf(GtB[m], gsc[m], -pp * xt);
+            const double sg = (double)gB[m] + (double)gt;
+            sn = fma(sg, sg, sn);
+            sx = fma((double)noise[(size_t)tt * D + d], sg, sx);
+            dpr = fma((double)dl, (double)xt + (double)x, dpr);
+        }
+    }
+    sn = half_sum_d(sn);
+    sx = half_sum_d(sx);
+    dpr = half_sum_d(dpr);
+    if (!valid) return;
+    int acc = 1;
+    float gate = INFINITY;
+    if (!a.ula) {
+        const double ell = dll - 0.5 * (double)pp * dpr - 0.25 * a.eps * sn - sqrt(0.5 * a.eps) * sx;
+        const double la = ell < 0.0 ? ell : 0.0;
+        const double gd = la - log((double)((const float *)a.unif)[t]);
+        gate = (float)gd;
+        acc = gd > 0.0;
+        if (!(ell == ell)) acc = 0;
+    }
+    float jrej = damp;
+    if (clip > 0) jrej = fminf(fmaxf(jrej, -clip), clip);
+#pragma unroll
+    for (int m = 0; m < MK; m++) {
+        const int d = 2 * m + hh;
+        if (d < D) {
+            F[(size_t)d * ld + t] = acc ? SB[m] + DB[m] : SB[m];
+            if (want_j && !acc) J[(size_t)d * ld + t] = jrej;
+        }
+    }
+    if (hh == 0) {
+        if (a.accept) a.accept[t] = (uint8_t)acc;
+        if (a.gtilde) a.gtilde[t] = gate;
+    }
+}
+
 template <int MK>
 __device__ __forceinline__ f32x16 z_chain(const float *xr, int i, int hh, const float (&v)[MK])
 {
@@ -178,7 +246,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
     const int D = a.D, nr = f.nr;
     const int64_t ld = a.ld;
     const float *S = (const float *)a.S, *noise = (const float *)a.noise;
-    float *F = (float *)a.F, *J = (float *)a.J;
+    float *J = (float *)a.J;
     const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
     const float damp = (float)a.damping, clip = (float)a.clip;
     const bool want_j = a.jmode == JM_DIAG;
@@ -377,60 +445,379 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
             for (int m = 0; m < 16; m++)
                 Gt = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[(2 * m + hh) * kXS + i], RtB[m], Gt, 0, 0, 0);
         }
-        // The log ratio is assembled in FP64 from here on: its terms (each up
-        // to ~10^2 on this posterior) cancel to O(1), and FP32 sums of them
-        // would add errors of ~10^-5 to a quantity compared against log u.
-        // Linear part of the log-likelihood difference: (X^T y) . Delta.
-        double dll_y = 0.0;
+        float gsc[MK];
 #pragma unroll
-        for (int m = 0; m < MK; m++) dll_y = fma((double)s_xty[2 * m + hh], (double)DB[m], dll_y);
-        const double dll = half_sum_d(fma(-dll_s, (double)kLn2, dll_y));
+        for (int m = 0; m < MK; m++) gsc[m] = kLn2;
+        finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip);
+    }
+}
 
-        // ---- per step (both halves): log ratio, decision, f_t
-        float GtB[16];
-        acc_to_b_swap(Gt, GtB);
-        double sn = 0.0, sx = 0.0, dpr = 0.0;
+// ------------------------------------------ split-FP16 matrix-core evaluation
+// The same evaluation with every product formed on the FP16 matrix cores
+// (32 x 32 x 16 per instruction, FP32 accumulation) from a two-term split of
+// each operand: v = hi + lo with hi = fp16(v) and lo = fp16(v - hi), both
+// rounded to nearest, and
+//   A B ~ A_lo B_hi + A_hi B_lo + A_hi B_hi
+// (the error-compensated half-precision product of Markidis et al. 2018 and
+// Ootomo & Yokota 2022; the dropped A_lo B_lo and the rounding of lo leave
+// about 2^-22 of each product, and each instruction adds 16 products before
+// it rounds into the accumulator).  An FP16 instruction does 16x the work of
+// an FP32 one in half the cycles, so the three terms cost about a sixth of
+// the FP32 products.
+//
+// LDS image (written once per target, copied into LDS per workgroup): the hi
+// and lo planes of X log2(e) as FP16, 32 entries per row, then y and X^T y in
+// FP32.  Coordinates and rows are stored in the orders the two products read:
+//   Z = X S:      lane (i, hh), slot j of contraction block kk reads row i,
+//                 coordinate d = 16 kk + 2 j + hh, stored at column
+//                 16 kk + 8 hh + j, so a lane's eight slots are one 16-byte read;
+//                 the B operand is then s[2 m + hh] with m = 8 kk + j, which is
+//                 the epilogue's register order.
+//   G = X^T R:    lane (d = i, hh), slot j of block kk pairs with accumulator
+//                 register 8 kk + j of R, that is row crow(8 kk + j, hh) of the
+//                 tile, stored at position 16 kk + 2 j + hh, so R is an operand
+//                 without any exchange between lanes, and the two lane halves
+//                 read rows one position apart (distinct LDS banks).
+// Operand ranges.  FP16 keeps 11 significant bits only down to 2^-14, so
+// every operand is brought to a known range by exact power-of-two scalings
+// before it is split: column d of X log2(e) is stored times 2^e_d with its
+// largest entry in [4, 8) (the Hessian weights use hi^2 < 2^6), and the image
+// carries c_d = 2^-e_d; the iterate and the increment enter as s_d c_d and
+// Delta_d c_d, so X S and X Delta need no correction, and the gradients come
+// out per coordinate times 2^e_d.  Per 32-step tile the scaled increment is
+// taken to a maximum in [2^13, 2^14) and the scaled iterate, when its maximum
+// lies outside [2^-3, 2^14), to the same range (both undone on the products).
+// The residuals R lie in [-1, 1].  Entries far below their operand's maximum
+// keep an absolute error of about 2^-25 of the scaled unit, far below the
+// rounding of the largest terms.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kHW = 32;               // FP16 entries per image row
+constexpr int kHMaxRowTiles = 38;     // 38 * 4224 + 256 bytes = 157 KiB
+
+// hi plane, lo plane, y (FP32), X^T y (32 FP32), c_d (32 FP32)
+constexpr size_t kHImageBytes(int nr) { return (size_t)nr * 32 * (4 * kHW + 4) + 2 * 32 * 4; }
+
+// storage column of coordinate d, storage position of tile row r
+__host__ __device__ constexpr int h_col(int d) { return (d & 16) | ((d & 1) << 3) | ((d >> 1) & 7); }
+__host__ __device__ constexpr int h_row(int r) { return (r & ~7) | ((r & 3) << 1) | ((r >> 2) & 1); }
+
+struct HArgs {
+    const void *img;  // kHImageBytes(nr) bytes, layout above
+    int nr;
+    float pp;
+};
+
+// v = hi + lo, both FP16 rounded to nearest
+__device__ __forceinline__ void split8(const float (&v)[8], f16x8 &h, f16x8 &l)
+{
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+        const f32x2 x = {v[j], v[j + 1]};
+        const f16x2 hp = __builtin_convertvector(x, f16x2);
+        const f32x2 r = {v[j] - (float)hp[0], v[j + 1] - (float)hp[1]};
+        const f16x2 lp = __builtin_convertvector(r, f16x2);
+        h[j] = hp[0];
+        h[j + 1] = hp[1];
+        l[j] = lp[0];
+        l[j + 1] = lp[1];
+    }
+}
+
+__device__ __forceinline__ f32x16 mfma3(const f16x8 &ah, const f16x8 &al, const f16x8 &bh, const f16x8 &bl,
+                                        f32x16 c)
+{
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, c, 0, 0, 0);
+}
+
+// A operand of G = X^T R for block kk of a row tile: rows 16 kk + 2 j + hh
+// (storage order), column h_col(d)
+__device__ __forceinline__ f16x8 g_operand(const _Float16 *plane, int base)
+{
+    f16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; j++) v[j] = plane[base + 2 * kHW * j];
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// the MK entries of a B-layout vector (m = 8 kk + j), scaled by 2^e, as KB
+// split operands
+template <int MK, int KB>
+__device__ __forceinline__ void split_b(const float (&v)[MK], int e, f16x8 (&h)[KB], f16x8 (&l)[KB])
+{
+#pragma unroll
+    for (int kk = 0; kk < KB; kk++) {
+        float w[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) w[j] = 8 * kk + j < MK ? ldexpf(v[8 * kk + j], e) : 0.f;
+        split8(w, h[kk], l[kk]);
+    }
+}
+
+template <int MK>
+__global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a, HArgs f)
+{
+    constexpr int KB = MK > 8 ? 2 : 1;
+    extern __shared__ float4 s_img[];
+    if (a.glob && a.glob->n_active == 0) return;  // a sweep queued past the last active chain
+    const int nrow = f.nr * 32;
+    {
+        const int n4 = (int)(kHImageBytes(f.nr) / 16);
+        const float4 *src = (const float4 *)f.img;
+        for (int k = threadIdx.x; k < n4; k += blockDim.x) s_img[k] = src[k];
+    }
+    __syncthreads();
+    const _Float16 *s_hi = (const _Float16 *)s_img;
+    const _Float16 *s_lo = s_hi + nrow * kHW;
+    const float *s_y = (const float *)(s_lo + nrow * kHW);
+    const float *s_xty = s_y + nrow;
+    const int lane = threadIdx.x & 63, i = lane & 31, hh = lane >> 5;
+    const int D = a.D, nr = f.nr;
+    const int64_t ld = a.ld;
+    const float *S = (const float *)a.S, *noise = (const float *)a.noise;
+    float *J = (float *)a.J;
+    float csc[MK], gsc[MK];  // c_d and ln(2) c_d of coordinate 2 m + hh
+#pragma unroll
+    for (int m = 0; m < MK; m++) {
+        csc[m] = s_xty[32 + 2 * m + hh];
+        gsc[m] = kLn2 * csc[m];
+    }
+    const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
+    const float damp = (float)a.damping, clip = (float)a.clip;
+    const bool want_j = a.jmode == JM_DIAG;
+    const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // per-lane offsets: the Z operand row (storage order) and the G operand column
+    const int zoff = h_row(i) * kHW + 8 * hh;
+    const int goff = hh * kHW + h_col(i);
+
+    const int n_waves = gridDim.x * kLdsWaves;
+    for (int tix = blockIdx.x * kLdsWaves + (threadIdx.x >> 6); tix < a.n_tiles; tix += n_waves) {
+        const SegTile tl = a.tiles[tix];
+        const ChainStatus &cs = a.chains[tl.chain];
+        if (!cs.active || tl.start + tl.len <= cs.win_start) continue;
+        const int64_t t = tl.start + i;
+        const bool valid = i < tl.len && t >= cs.win_start;
+        const int64_t tt = i < tl.len ? t : tl.start;
+        const bool head = (tt == a.offsets[tl.chain]);
+        const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
+
+        float SB[MK], SC[MK];
+        float smax = 0.f;
 #pragma unroll
         for (int m = 0; m < MK; m++) {
             const int d = 2 * m + hh;
-            if (d < D) {
-                const float x = SB[m], dl = DB[m], xt = x + dl;
-                const float gt = fmaf(GtB[m], kLn2, -pp * xt);
-                const double sg = (double)gB[m] + (double)gt;
-                sn = fma(sg, sg, sn);
-                sx = fma((double)noise[(size_t)tt * D + d], sg, sx);
-                dpr = fma((double)dl, (double)xt + (double)x, dpr);
-            }
+            SB[m] = d < D ? (head ? s0[d] : S[(size_t)d * ld + tt - 1]) : 0.f;
+            SC[m] = SB[m] * csc[m];
+            smax = fmaxf(smax, fabsf(SC[m]));
         }
-        sn = half_sum_d(sn);
-        sx = half_sum_d(sx);
-        dpr = half_sum_d(dpr);
-        if (valid) {
-            int acc = 1;
-            float gate = INFINITY;
-            if (!a.ula) {
-                const double ell = dll - 0.5 * (double)pp * dpr - 0.25 * a.eps * sn - sqrt(0.5 * a.eps) * sx;
-                const double la = ell < 0.0 ? ell : 0.0;
-                const double gd = la - log((double)((const float *)a.unif)[t]);
-                gate = (float)gd;
-                acc = gd > 0.0;
-                if (!(ell == ell)) acc = 0;
+        // scaled iterate outside [2^-3, 2^14): taken to [2^13, 2^14) (Z undone by 2^-es)
+        smax = wave_max(smax);
+        const int es = __builtin_amdgcn_readfirstlane(
+            (smax >= 16384.f || smax < 0.125f) && smax > 0.f && smax < INFINITY ? 13 - ilogbf(smax) : 0);
+        f16x8 Sh[KB], Sl[KB];
+        split_b<MK, KB>(SC, es, Sh, Sl);
+
+        // ---- pass 1: gradient and Hessian diagonal at s_{t-1}; iteration rt
+        // issues the predictors of tile rt + 1 and the products of tile rt - 1
+        // around the sigmoids of tile rt.
+        f32x16 G = zero, Hd = zero;
+        f32x16 Zc = zero;
+#pragma unroll
+        for (int kk = 0; kk < KB; kk++)
+            Zc = mfma3(*(const f16x8 *)(s_hi + zoff + 16 * kk), *(const f16x8 *)(s_lo + zoff + 16 * kk), Sh[kk],
+                       Sl[kk], Zc);
+        if (es)
+#pragma unroll
+            for (int r = 0; r < 16; r++) Zc[r] = ldexpf(Zc[r], -es);
+        f16x8 Rh[2], Rl[2], Wh[2], Xh[2], Xl[2];
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) Rh[kk][j] = Rl[kk][j] = Wh[kk][j] = Xh[kk][j] = Xl[kk][j] = (_Float16)0.f;
+        for (int rt = 0; rt < nr; rt++) {
+            const int rn = rt + 1 < nr ? rt + 1 : rt;
+            f32x16 Zn = zero;
+#pragma unroll
+            for (int kk = 0; kk < KB; kk++) {
+                const int o = (32 * rn) * kHW + zoff + 16 * kk;
+                Zn = mfma3(*(const f16x8 *)(s_hi + o), *(const f16x8 *)(s_lo + o), Sh[kk], Sl[kk], Zn);
             }
-            float jrej = damp;
-            if (clip > 0) jrej = fminf(fmaxf(jrej, -clip), clip);
+#pragma unroll
+            for (int kk = 0; kk < 2; kk++) {
+                G = mfma3(Xh[kk], Xl[kk], Rh[kk], Rl[kk], G);
+                Hd = __builtin_amdgcn_mfma_f32_32x32x16_f16(Xh[kk] * Xh[kk], Wh[kk], Hd, 0, 0, 0);
+            }
+            const float4 *y4 = (const float4 *)(s_y + 32 * rt + 4 * hh);
+            float Rv[16], Wv[16];
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const float4 y4v = y4[2 * g];
+                const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const float sv = sigm2(Zc[4 * g + q]);
+                    Rv[4 * g + q] = yv[q] - sv;
+                    Wv[4 * g + q] = fmaf(-sv, sv, sv);
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 2; kk++) {
+                float r8[8], w8[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    r8[j] = Rv[8 * kk + j];
+                    w8[j] = Wv[8 * kk + j];
+                }
+                split8(r8, Rh[kk], Rl[kk]);
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    const f32x2 x = {w8[j], w8[j + 1]};
+                    const f16x2 hp = __builtin_convertvector(x, f16x2);
+                    Wh[kk][j] = hp[0];
+                    Wh[kk][j + 1] = hp[1];
+                }
+                const int o = (32 * rt + 16 * kk) * kHW + goff;
+                Xh[kk] = g_operand(s_hi, o);
+                Xl[kk] = g_operand(s_lo, o);
+            }
+            if (es)
+#pragma unroll
+                for (int r = 0; r < 16; r++) Zn[r] = ldexpf(Zn[r], -es);
+            Zc = Zn;
+        }
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++) {
+            G = mfma3(Xh[kk], Xl[kk], Rh[kk], Rl[kk], G);
+            Hd = __builtin_amdgcn_mfma_f32_32x32x16_f16(Xh[kk] * Xh[kk], Wh[kk], Hd, 0, 0, 0);
+        }
+        float gB[MK], DB[MK], DC[MK];
+        float dmax = 0.f;
+        {
+            float GB[16], HB[16];
+            acc_to_b_swap(G, GB);
+            acc_to_b_swap(Hd, HB);
 #pragma unroll
             for (int m = 0; m < MK; m++) {
                 const int d = 2 * m + hh;
-                if (d < D) {
-                    F[(size_t)d * ld + t] = acc ? SB[m] + DB[m] : SB[m];
-                    if (want_j && !acc) J[(size_t)d * ld + t] = jrej;
+                gB[m] = fmaf(GB[m], gsc[m], -pp * SB[m]);
+                DB[m] = d < D ? fmaf(eps, gB[m], c * noise[(size_t)tt * D + d]) : 0.f;
+                DC[m] = DB[m] * csc[m];
+                dmax = fmaxf(dmax, fabsf(DC[m]));
+                if (want_j && valid && d < D) {
+                    float jv = damp * fmaf(eps, fmaf(-HB[m], gsc[m] * gsc[m], -pp), 1.f);
+                    if (clip > 0) jv = fminf(fmaxf(jv, -clip), clip);
+                    J[(size_t)d * ld + t] = jv;
                 }
             }
-            if (hh == 0) {
-                if (a.accept) a.accept[t] = (uint8_t)acc;
-                if (a.gtilde) a.gtilde[t] = gate;
-            }
         }
+        // the increment is scaled to a maximum in [2^13, 2^14) before it is split
+        dmax = wave_max(dmax);
+        const int ed = __builtin_amdgcn_readfirstlane(dmax > 0.f && dmax < INFINITY ? 13 - ilogbf(dmax) : 0);
+        const float dsc = ldexpf(1.f, -ed);
+        f16x8 Dh[KB], Dl[KB];
+        split_b<MK, KB>(DC, ed, Dh, Dl);
+
+        // ---- pass 2: gradient at the proposal and the log-likelihood
+        // difference.  Block kk of row tile rt issues the proposal-gradient
+        // products of tile rt - 1 that use R~ registers 8 kk .. 8 kk + 7
+        // (then refilled with tile rt's values) and block kk of the predictor
+        // chains of tile rt + 1.
+        f32x16 Gt = zero;
+        double dll_s = 0.0;
+        Zc = zero;
+        f32x16 dZc = zero;
+#pragma unroll
+        for (int kk = 0; kk < KB; kk++) {
+            const f16x8 ah = *(const f16x8 *)(s_hi + zoff + 16 * kk), al = *(const f16x8 *)(s_lo + zoff + 16 * kk);
+            Zc = mfma3(ah, al, Sh[kk], Sl[kk], Zc);
+            dZc = mfma3(ah, al, Dh[kk], Dl[kk], dZc);
+        }
+        if (es)
+#pragma unroll
+            for (int r = 0; r < 16; r++) Zc[r] = ldexpf(Zc[r], -es);
+        f16x8 Th[2], Tl[2];
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) Th[kk][j] = Tl[kk][j] = (_Float16)0.f;
+        for (int rt = 0; rt < nr; rt++) {
+            const int rn = rt + 1 < nr ? rt + 1 : rt, rp = rt > 0 ? rt - 1 : 0;
+            const float *yr = s_y + 32 * rt + 4 * hh;
+            f32x16 Zn = zero, dZn = zero;
+            float tile_s = 0.f;
+#pragma unroll
+            for (int kk = 0; kk < 2; kk++) {
+                {
+                    const int o = (32 * rp + 16 * kk) * kHW + goff;
+                    Gt = mfma3(g_operand(s_hi, o), g_operand(s_lo, o), Th[kk], Tl[kk], Gt);
+                }
+                if (kk < KB) {
+                    const int o = (32 * rn) * kHW + zoff + 16 * kk;
+                    const f16x8 ah = *(const f16x8 *)(s_hi + o), al = *(const f16x8 *)(s_lo + o);
+                    Zn = mfma3(ah, al, Sh[kk], Sl[kk], Zn);
+                    dZn = mfma3(ah, al, Dh[kk], Dl[kk], dZn);
+                }
+                float r8[8];
+#pragma unroll
+                for (int gg = 0; gg < 2; gg++) {
+                    const int g = 2 * kk + gg;
+                    const float4 y4v = *(const float4 *)(yr + 8 * g);
+                    const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
+                    float Rt[4], av[4];
+                    bool wide = false;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const float du = dZc[4 * g + q] * dsc;
+                        Rt[q] = pass2_elem(Zc[4 * g + q], du, yv[q], av[q]);
+                        wide |= !(fabsf(du) < 8.f * kLog2e);
+                    }
+                    float lg = __builtin_amdgcn_logf((av[0] * av[1]) * (av[2] * av[3]));
+                    if (__builtin_amdgcn_ballot_w64(wide)) {  // rare
+                        if (wide) {
+                            lg = 0.f;
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                const float u = Zc[4 * g + q], du = dZc[4 * g + q] * dsc;
+                                if (fabsf(du) < 8.f * kLog2e) {
+                                    lg += __builtin_amdgcn_logf(av[q]);
+                                } else {
+                                    const float z = u * kLn2, zt = z + du * kLn2;
+                                    Rt[q] = yv[q] - sigm(zt);
+                                    lg += (softplus(zt) - softplus(z)) * kLog2e;
+                                }
+                            }
+                        }
+                    }
+                    tile_s += lg;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) r8[4 * gg + q] = Rt[q];
+                }
+                split8(r8, Th[kk], Tl[kk]);
+            }
+            dll_s += (double)tile_s;
+            if (es)
+#pragma unroll
+                for (int r = 0; r < 16; r++) Zn[r] = ldexpf(Zn[r], -es);
+            Zc = Zn;
+            dZc = dZn;
+        }
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++) {
+            const int o = (32 * (nr - 1) + 16 * kk) * kHW + goff;
+            Gt = mfma3(g_operand(s_hi, o), g_operand(s_lo, o), Th[kk], Tl[kk], Gt);
+        }
+        finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip);
     }
 }
 
@@ -664,11 +1051,44 @@ __global__ void __launch_bounds__(256) k_logreg_xty(const float *X, int ldx, con
 
 constexpr int kLdsImageFloats(int nr) { return nr * 32 * (kXS + 1) + 32; }
 
+// Per-column scalings of the split-FP16 image: X_nd log2(e) 2^e_d is stored,
+// and c_d = 2^-e_d.
+struct HScale {
+    float mul[32], c[32];
+};
+
+// Split-FP16 image (layout at k_eval_logreg_h): hi and lo planes of the scaled
+// X in storage order, then y padded with zeros; X^T y (k_logreg_xty) and c_d
+// follow.
+__global__ void k_logreg_h_image(const float *X, int ldx, const float *y, int N, int D, int nr, HScale sc,
+                                 _Float16 *hi, float *yp)
+{
+    const int nrow = nr * 32;
+    _Float16 *lo = hi + (size_t)nrow * kHW;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nrow * kHW; k += gridDim.x * blockDim.x) {
+        const int pos = k / kHW, p = k % kHW, q = pos & 31;
+        const int r = (q & ~7) | ((q & 1) << 2) | ((q >> 1) & 3);  // h_row(r) = q
+        const int d = (p & 16) | ((p & 7) << 1) | ((p >> 3) & 1);  // h_col(d) = p
+        const int n = (pos & ~31) + r;
+        const float v = (n < N && d < D) ? X[(size_t)n * ldx + d] * sc.mul[d] : 0.f;
+        const _Float16 h = (_Float16)v;
+        hi[k] = h;
+        lo[k] = (_Float16)(v - (float)h);
+    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nrow; k += gridDim.x * blockDim.x)
+        yp[k] = k < N ? y[k] : 0.f;
+    if (blockIdx.x == 0 && threadIdx.x < 32) yp[nrow + 32 + threadIdx.x] = sc.c[threadIdx.x];
+}
+
 template <int MK>
 hipError_t allow_lds()
 {
-    return hipFuncSetAttribute((const void *)k_eval_logreg_lds<MK>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kLdsImageFloats(kLdsMaxRowTiles) * (int)sizeof(float));
+    const hipError_t e = hipFuncSetAttribute((const void *)k_eval_logreg_lds<MK>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             kLdsImageFloats(kLdsMaxRowTiles) * (int)sizeof(float));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_eval_logreg_h<MK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kHImageBytes(kHMaxRowTiles));
 }
 
 }  // namespace
@@ -678,7 +1098,38 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
     const int nr = (t.n_data + 31) / 32, mk = (t.dim + 1) / 2;
     t.nr = nr;
     t.mk = mk <= 2 ? 2 : mk <= 4 ? 4 : mk <= 8 ? 8 : mk <= 13 ? 13 : 16;
-    if (nr <= kLdsMaxRowTiles) {
+    if (t.products != PMC_PRODUCTS_F32) {
+        // split-FP16 products need the image in LDS
+        if (nr <= kHMaxRowTiles) {
+            // column scalings: largest |X_nd| log2(e) 2^e_d in [4, 8)
+            std::vector<float> hx((size_t)t.n_data * t.ldx);
+            PMC_TRY_HIP(hipMemcpyAsync(hx.data(), t.X, sizeof(float) * hx.size(), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+            HScale sc;
+            for (int d = 0; d < 32; d++) {
+                float mx = 0.f;
+                if (d < t.dim)
+                    for (int n = 0; n < t.n_data; n++) mx = std::max(mx, std::fabs(hx[(size_t)n * t.ldx + d]));
+                const float v = mx * kLog2e;
+                const int e = (v > 0.f && std::isfinite(v)) ? 2 - std::ilogb(v) : 0;
+                sc.mul[d] = std::ldexp(kLog2e, e);
+                sc.c[d] = std::ldexp(1.f, -e);
+            }
+            PMC_TRY_HIP(hipMalloc(&t.xh, kHImageBytes(nr)));
+            float *yp = (float *)((char *)t.xh + (size_t)nr * 32 * kHW * 2 * sizeof(_Float16));
+            hipLaunchKernelGGL(k_logreg_h_image, dim3(64), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
+                               (const float *)t.y, t.n_data, t.dim, nr, sc, (_Float16 *)t.xh, yp);
+            PMC_TRY_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_logreg_xty, dim3(32), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
+                               (const float *)t.y, t.n_data, t.dim, yp + (size_t)nr * 32);
+            PMC_TRY_HIP(hipGetLastError());
+        } else if (t.products == PMC_PRODUCTS_SPLIT16) {
+            set_error("logreg target: split-FP16 products need n_data <= %d", 32 * kHMaxRowTiles);
+            return PMC_ERR_UNSUPPORTED;
+        }
+    }
+    if (!t.xh && nr <= kLdsMaxRowTiles) {
         // LDS-resident path: one padded image of X and y
         const size_t bl = sizeof(float) * (size_t)kLdsImageFloats(nr);
         PMC_TRY_HIP(hipMalloc(&t.xl, bl));
@@ -688,6 +1139,8 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
         hipLaunchKernelGGL(k_logreg_xty, dim3(32), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
                            (const float *)t.y, t.n_data, t.dim, (float *)t.xl + (size_t)nr * 32 * (kXS + 1));
         PMC_TRY_HIP(hipGetLastError());
+    }
+    if (t.xh || t.xl) {
         PMC_TRY_HIP(allow_lds<2>());
         PMC_TRY_HIP(allow_lds<4>());
         PMC_TRY_HIP(allow_lds<8>());
@@ -710,6 +1163,22 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
 {
     if (a.n_tiles <= 0) return PMC_OK;
+    if (t.xh) {
+        HArgs f{t.xh, t.nr, (float)(1.0 / t.prior_var)};
+        const size_t lds = kHImageBytes(t.nr);
+        const int want = (a.n_tiles + kLdsWaves - 1) / kLdsWaves;
+        dim3 grid(std::max(1, std::min(want, ctx->n_cu > 0 ? ctx->n_cu : 256))), block(64 * kLdsWaves);
+        switch (t.mk) {
+        case 2: hipLaunchKernelGGL(k_eval_logreg_h<2>, grid, block, lds, ctx->stream, a, f); break;
+        case 4: hipLaunchKernelGGL(k_eval_logreg_h<4>, grid, block, lds, ctx->stream, a, f); break;
+        case 8: hipLaunchKernelGGL(k_eval_logreg_h<8>, grid, block, lds, ctx->stream, a, f); break;
+        case 13: hipLaunchKernelGGL(k_eval_logreg_h<13>, grid, block, lds, ctx->stream, a, f); break;
+        case 16: hipLaunchKernelGGL(k_eval_logreg_h<16>, grid, block, lds, ctx->stream, a, f); break;
+        default: set_error("logreg eval: unsupported dimension"); return PMC_ERR_UNSUPPORTED;
+        }
+        PMC_TRY_HIP(hipGetLastError());
+        return PMC_OK;
+    }
     if (t.xl) {
         LdsArgs f{(const float *)t.xl, t.nr, (float)(1.0 / t.prior_var)};
         const size_t lds = sizeof(float) * (size_t)kLdsImageFloats(t.nr);

@@ -134,6 +134,8 @@ struct DevTarget {
     int nr = 0, mk = 0;
     void *xa = nullptr, *xta = nullptr, *x2ta = nullptr, *ypad = nullptr;
     void *xl = nullptr;    // LDS image of X and y (small data sets)
+    void *xh = nullptr;    // split-FP16 LDS image of X, with y and X^T y
+    int products = 0;      // pmc_products
 };
 
 }  // namespace pmc

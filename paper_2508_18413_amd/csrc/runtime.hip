@@ -289,8 +289,11 @@ pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *d, pmc_tar
             set_error("logreg target: dim <= 32 (got %d)", d->dim);
             return PMC_ERR_UNSUPPORTED;
         }
+        PMC_REQUIRE(d->products >= PMC_PRODUCTS_AUTO && d->products <= PMC_PRODUCTS_SPLIT16,
+                    "logreg target: unknown products mode %d", (int)d->products);
         t.ldx = ldx;
         t.n_data = d->n_data;
+        t.products = d->products;
         PMC_TRY_HIP(hipMalloc(&t.X, 4 * (size_t)ldx * d->n_data));
         PMC_TRY_HIP(hipMalloc(&t.y, 4 * (size_t)d->n_data));
         PMC_TRY_HIP(hipMemsetAsync(t.X, 0, 4 * (size_t)ldx * d->n_data, ctx->stream));
@@ -321,7 +324,7 @@ pmc_status pmc_target_destroy(pmc_target *tgt)
     if (tgt->t.prec) (void)hipFree(tgt->t.prec);
     if (tgt->t.X) (void)hipFree(tgt->t.X);
     if (tgt->t.y) (void)hipFree(tgt->t.y);
-    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl})
+    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl, tgt->t.xh})
         if (q) (void)hipFree(q);
     delete tgt;
     return PMC_OK;

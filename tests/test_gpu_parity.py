@@ -245,11 +245,12 @@ def _check_mala(orc, tg, ch, s0, got_states, got_acc, tol=1e-5):
     return err, rep
 
 
+@pytest.mark.parametrize("products", ["split16", "f32"])
 @pytest.mark.parametrize("T", [4096, 5000])
-def test_logreg_diag_fp32(ctx, pm, orc, T):
-    _say(f"logreg diag fp32 T={T}")
+def test_logreg_diag_fp32(ctx, pm, orc, T, products):
+    _say(f"logreg diag fp32 T={T} products={products}")
     ch, tg, s0 = _logreg_case(orc, T, 0.0015)
-    g = pm.Target(ctx, ch.target)
+    g = pm.Target(ctx, dict(ch.target, products=products))
     r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=T + 1)
     _say(f"  sweeps={r.sweeps} status={r.status} ratio={r.max_ratio:.3g}")
     assert r.status == 0
@@ -263,25 +264,27 @@ def _gate_at(orc, tg, ch, s0, states):
 
 
 def test_logreg_gate_precision(ctx, pm, orc):
-    """One parallel evaluation at the oracle's trajectory (rounded to FP32)
-    and the sequential sampler along its own trajectory: each step's g~
-    against the oracle's g~* from the same FP32 states, and the decisions
-    wherever |g~*| exceeds that error."""
+    """One parallel evaluation at the oracle's trajectory (rounded to FP32),
+    with either product arithmetic, and the sequential sampler along its own
+    trajectory: each step's g~ against the oracle's g~* from the same FP32
+    states, and the decisions wherever |g~*| exceeds that error."""
     T = 2048
     for seed in (0, 1):
         ch, tg, s0 = _logreg_case(orc, T, 0.0015, seed=seed)
         st, _, _ = orc.mala_chain(tg, ch.eps, s0.astype(np.float64), ch.xi, ch.u)
         init = st.astype(np.float32)
         ref = _gate_at(orc, tg, ch, s0, init)
-        g = pm.Target(ctx, ch.target)
-        r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=1,
-                     init_guess=_t(init))
-        got = r.gtilde.cpu().numpy().astype(np.float64)
-        err = np.abs(got - ref)
-        _say(f"  seed {seed} parallel eval: max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}")
-        assert err.max() <= F32_GATE_ERR
-        clear = np.abs(ref) > F32_GATE_ERR
-        assert np.array_equal(r.accept.cpu().numpy()[clear].astype(bool), ref[clear] > 0)
+        for products in ("split16", "f32"):
+            g = pm.Target(ctx, dict(ch.target, products=products))
+            r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=1,
+                         init_guess=_t(init))
+            got = r.gtilde.cpu().numpy().astype(np.float64)
+            err = np.abs(got - ref)
+            _say(f"  seed {seed} parallel eval ({products}): max |g~ - g~*| = {err.max():.3e}, "
+                 f"p99 {np.quantile(err, 0.99):.3e}")
+            assert err.max() <= F32_GATE_ERR
+            clear = np.abs(ref) > F32_GATE_ERR
+            assert np.array_equal(r.accept.cpu().numpy()[clear].astype(bool), ref[clear] > 0)
 
         rs = pm.sample_sequential(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u))
         sst = rs.states.cpu().numpy()
@@ -289,6 +292,53 @@ def test_logreg_gate_precision(ctx, pm, orc):
         err = np.abs(rs.gtilde.cpu().numpy().astype(np.float64) - ref)
         _say(f"  seed {seed} sequential: max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}")
         assert err.max() <= F32_GATE_ERR
+
+
+def test_logreg_products_routing(ctx, pm):
+    """Split-FP16 products need the LDS image (n_data <= 1216): asked for with
+    more data points they are refused at target creation, and AUTO then runs
+    the FP32-product kernels, bit for bit what asking for FP32 products gives."""
+    _say("logreg products routing")
+    from paper_2508_18413_amd._binding import PMCError
+    ch = W.logreg_chain(T=1024, seed=5, eps=0.001, n_data=1300, dim=8)
+    with pytest.raises(PMCError, match="split-FP16"):
+        pm.Target(ctx, dict(ch.target, products="split16"))
+    outs = []
+    for products in ("auto", "f32"):
+        g = pm.Target(ctx, dict(ch.target, products=products))
+        outs.append(pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag",
+                             max_iter=60))
+    assert torch.equal(outs[0].states, outs[1].states)
+    assert torch.equal(outs[0].accept, outs[1].accept)
+
+
+@pytest.mark.parametrize("x_scale,w_scale,prior_var", [(1e-4, 2e4, 1e10), (100.0, 1e-2, 1.0),
+                                                       (1.0, 1e-3, 1e-6)])
+def test_logreg_split16_scaled_data(ctx, pm, orc, x_scale, w_scale, prior_var):
+    """Data and coefficients far from unit scale: columns of X of order 1e-4 or
+    1e2, iterates of order 1e4 or 1e-3.  The split-FP16 path brings every
+    operand to FP16's range with power-of-two scalings (per column of X, and
+    per 32-step tile for the iterate and the increment); parity with the
+    oracle as for any FP32 chain."""
+    _say(f"logreg split16 scaled data X*{x_scale} w*{w_scale} prior_var={prior_var}")
+    r = np.random.default_rng(11)
+    N, D, T = 256, 8, 2048
+    X = (r.standard_normal((N, D)) * x_scale).astype(np.float32)
+    w = r.standard_normal(D) * w_scale
+    p = 1.0 / (1.0 + np.exp(-(X.astype(np.float64) @ w)))
+    y = (r.random(N) < p).astype(np.float32)
+    # step size from the curvature at w: proposal variance 2 eps = 0.5 / max_d H_dd
+    h = (X.astype(np.float64) ** 2 * (p * (1 - p))[:, None]).sum(axis=0) + 1.0 / prior_var
+    eps = 0.25 / h.max()
+    target = dict(kind="logreg", dim=D, X=X, y=y, prior_var=prior_var)
+    ch = W.Chain(target=target, eps=eps, x0=w.astype(np.float32),
+                 xi=r.standard_normal((T, D)).astype(np.float32), u=r.random(T).astype(np.float32))
+    tg = oracle_target(target)
+    g = pm.Target(ctx, dict(target, products="split16"))
+    res = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=T + 1)
+    _say(f"  eps={eps:.3g} sweeps={res.sweeps} status={res.status} acceptance={res.n_accept / T:.3f}")
+    assert res.status == 0
+    _check_mala(orc, tg, ch, ch.x0, res.states.cpu().numpy(), res.accept.cpu().numpy())
 
 
 def test_logreg_large_n_fallback_fp32(ctx, pm, orc):
