@@ -510,6 +510,22 @@ struct HArgs {
     float pp;
 };
 
+// x - hi for hi in the low or high half of a packed FP16 pair: one
+// mixed-precision fused multiply-add (hi widened exactly; the difference is
+// exact in FP32)
+__device__ __forceinline__ float sub_f16_lo(uint32_t hp, float x)
+{
+    float r;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hp), "v"(x));
+    return r;
+}
+__device__ __forceinline__ float sub_f16_hi(uint32_t hp, float x)
+{
+    float r;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hp), "v"(x));
+    return r;
+}
+
 // v = hi + lo, both FP16 rounded to nearest
 __device__ __forceinline__ void split8(const float (&v)[8], f16x8 &h, f16x8 &l)
 {
@@ -517,7 +533,8 @@ __device__ __forceinline__ void split8(const float (&v)[8], f16x8 &h, f16x8 &l)
     for (int j = 0; j < 8; j += 2) {
         const f32x2 x = {v[j], v[j + 1]};
         const f16x2 hp = __builtin_convertvector(x, f16x2);
-        const f32x2 r = {v[j] - (float)hp[0], v[j + 1] - (float)hp[1]};
+        const uint32_t hb = __builtin_bit_cast(uint32_t, hp);
+        const f32x2 r = {sub_f16_lo(hb, v[j]), sub_f16_hi(hb, v[j + 1])};
         const f16x2 lp = __builtin_convertvector(r, f16x2);
         h[j] = hp[0];
         h[j + 1] = hp[1];
@@ -587,12 +604,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
     const int64_t ld = a.ld;
     const float *S = (const float *)a.S, *noise = (const float *)a.noise;
     float *J = (float *)a.J;
-    float csc[MK], gsc[MK];  // c_d and ln(2) c_d of coordinate 2 m + hh
-#pragma unroll
-    for (int m = 0; m < MK; m++) {
-        csc[m] = s_xty[32 + 2 * m + hh];
-        gsc[m] = kLn2 * csc[m];
-    }
+    const float *s_csc = s_xty + 32;  // c_d
     const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
     const float damp = (float)a.damping, clip = (float)a.clip;
     const bool want_j = a.jmode == JM_DIAG;
@@ -618,7 +630,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
         for (int m = 0; m < MK; m++) {
             const int d = 2 * m + hh;
             SB[m] = d < D ? (head ? s0[d] : S[(size_t)d * ld + tt - 1]) : 0.f;
-            SC[m] = SB[m] * csc[m];
+            SC[m] = SB[m] * s_csc[2 * m + hh];
             smax = fmaxf(smax, fabsf(SC[m]));
         }
         // scaled iterate outside [2^-3, 2^14): taken to [2^13, 2^14) (Z undone by 2^-es)
@@ -710,12 +722,13 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
 #pragma unroll
             for (int m = 0; m < MK; m++) {
                 const int d = 2 * m + hh;
-                gB[m] = fmaf(GB[m], gsc[m], -pp * SB[m]);
+                const float cd = s_csc[2 * m + hh], gs = kLn2 * cd;
+                gB[m] = fmaf(GB[m], gs, -pp * SB[m]);
                 DB[m] = d < D ? fmaf(eps, gB[m], c * noise[(size_t)tt * D + d]) : 0.f;
-                DC[m] = DB[m] * csc[m];
+                DC[m] = DB[m] * cd;
                 dmax = fmaxf(dmax, fabsf(DC[m]));
                 if (want_j && valid && d < D) {
-                    float jv = damp * fmaf(eps, fmaf(-HB[m], gsc[m] * gsc[m], -pp), 1.f);
+                    float jv = damp * fmaf(eps, fmaf(-HB[m], gs * gs, -pp), 1.f);
                     if (clip > 0) jv = fminf(fmaxf(jv, -clip), clip);
                     J[(size_t)d * ld + t] = jv;
                 }
@@ -768,41 +781,43 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
                     Zn = mfma3(ah, al, Sh[kk], Sl[kk], Zn);
                     dZn = mfma3(ah, al, Dh[kk], Dl[kk], dZn);
                 }
-                float r8[8];
+                // accumulator registers 8 kk .. 8 kk + 7; the a of all eight
+                // (each within [e^-8, e^8]) share one logarithm
+                float r8[8], av[8];
+                bool wide = false;
 #pragma unroll
                 for (int gg = 0; gg < 2; gg++) {
-                    const int g = 2 * kk + gg;
-                    const float4 y4v = *(const float4 *)(yr + 8 * g);
+                    const float4 y4v = *(const float4 *)(yr + 8 * (2 * kk + gg));
                     const float yv[4] = {y4v.x, y4v.y, y4v.z, y4v.w};
-                    float Rt[4], av[4];
-                    bool wide = false;
 #pragma unroll
                     for (int q = 0; q < 4; q++) {
-                        const float du = dZc[4 * g + q] * dsc;
-                        Rt[q] = pass2_elem(Zc[4 * g + q], du, yv[q], av[q]);
+                        const int r = 8 * kk + 4 * gg + q;
+                        const float du = dZc[r] * dsc;
+                        r8[4 * gg + q] = pass2_elem(Zc[r], du, yv[q], av[4 * gg + q]);
                         wide |= !(fabsf(du) < 8.f * kLog2e);
                     }
-                    float lg = __builtin_amdgcn_logf((av[0] * av[1]) * (av[2] * av[3]));
-                    if (__builtin_amdgcn_ballot_w64(wide)) {  // rare
-                        if (wide) {
-                            lg = 0.f;
+                }
+                float lg = __builtin_amdgcn_logf(((av[0] * av[1]) * (av[2] * av[3])) *
+                                                 ((av[4] * av[5]) * (av[6] * av[7])));
+                if (__builtin_amdgcn_ballot_w64(wide)) {  // rare
+                    if (wide) {
+                        lg = 0.f;
 #pragma unroll
-                            for (int q = 0; q < 4; q++) {
-                                const float u = Zc[4 * g + q], du = dZc[4 * g + q] * dsc;
-                                if (fabsf(du) < 8.f * kLog2e) {
-                                    lg += __builtin_amdgcn_logf(av[q]);
-                                } else {
-                                    const float z = u * kLn2, zt = z + du * kLn2;
-                                    Rt[q] = yv[q] - sigm(zt);
-                                    lg += (softplus(zt) - softplus(z)) * kLog2e;
-                                }
+                        for (int q = 0; q < 8; q++) {
+                            const int r = 8 * kk + q;
+                            const float u = Zc[r], du = dZc[r] * dsc;
+                            if (fabsf(du) < 8.f * kLog2e) {
+                                lg += __builtin_amdgcn_logf(av[q]);
+                            } else {
+                                const float yq = yr[8 * (2 * kk + (q >> 2)) + (q & 3)];
+                                const float z = u * kLn2, zt = z + du * kLn2;
+                                r8[q] = yq - sigm(zt);
+                                lg += (softplus(zt) - softplus(z)) * kLog2e;
                             }
                         }
                     }
-                    tile_s += lg;
-#pragma unroll
-                    for (int q = 0; q < 4; q++) r8[4 * gg + q] = Rt[q];
                 }
+                tile_s += lg;
                 split8(r8, Th[kk], Tl[kk]);
             }
             dll_s += (double)tile_s;
@@ -817,6 +832,9 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
             const int o = (32 * (nr - 1) + 16 * kk) * kHW + goff;
             Gt = mfma3(g_operand(s_hi, o), g_operand(s_lo, o), Th[kk], Tl[kk], Gt);
         }
+        float gsc[MK];
+#pragma unroll
+        for (int m = 0; m < MK; m++) gsc[m] = kLn2 * s_csc[2 * m + hh];
         finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip);
     }
 }
