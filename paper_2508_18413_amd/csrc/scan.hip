@@ -605,6 +605,29 @@ struct DiagLinIO {
                 if (q < nv) out[i + q] = v[q];
         }
     }
+    // Correction of a chunk scanned from a zero carry: v <- a v step by step
+    // (v the carry's image), added to the stored values.
+    __device__ void fix4(int lane, int64_t t, int nv, const Aff<R, 1> *e, R (&v)[1]) const
+    {
+        const size_t i = (size_t)lane * g.T + t;
+        if (nv == 4) {
+            float4 o = *(const float4 *)(out + i);
+            float w[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                v[0] = e[q].a[0][0] * v[0];
+                w[q] += v[0];
+            }
+            *(float4 *)(out + i) = make_float4(w[0], w[1], w[2], w[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (q < nv) {
+                    v[0] = e[q].a[0][0] * v[0];
+                    out[i + q] += v[0];
+                }
+        }
+    }
 };
 
 struct Block2LinIO {
@@ -684,6 +707,37 @@ struct Block2LinIO {
                     out[pl + i + q] = q4[q];
                 }
             }
+        }
+    }
+    __device__ void fix4(int lane, int64_t t, int nv, const Aff<float, 2> *e, float (&v)[2]) const
+    {
+        const size_t pl = (size_t)n_lanes * g.T;
+        const size_t i = (size_t)lane * g.T + t;
+        if (nv == 4) {
+            float4 o0 = *(const float4 *)(out + i), o1 = *(const float4 *)(out + pl + i);
+            float w0[4] = {o0.x, o0.y, o0.z, o0.w}, w1[4] = {o1.x, o1.y, o1.z, o1.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float p = e[q].a[0][0] * v[0] + e[q].a[0][1] * v[1];
+                const float r = e[q].a[1][0] * v[0] + e[q].a[1][1] * v[1];
+                v[0] = p;
+                v[1] = r;
+                w0[q] += p;
+                w1[q] += r;
+            }
+            *(float4 *)(out + i) = make_float4(w0[0], w0[1], w0[2], w0[3]);
+            *(float4 *)(out + pl + i) = make_float4(w1[0], w1[1], w1[2], w1[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (q < nv) {
+                    const float p = e[q].a[0][0] * v[0] + e[q].a[0][1] * v[1];
+                    const float r = e[q].a[1][0] * v[0] + e[q].a[1][1] * v[1];
+                    v[0] = p;
+                    v[1] = r;
+                    out[i + q] += p;
+                    out[pl + i + q] += r;
+                }
         }
     }
 };
@@ -901,6 +955,172 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
     }
 }
 
+// ---------------------------------------------- chunked scan (long recursions)
+// For long standalone recursions each workgroup owns one contiguous chunk of
+// a lane and streams it tile by tile: the next tile's loads are issued before
+// the current tile is scanned, and the carry between tiles stays in
+// registers, so the chunk is scanned as if its carry-in were zero without any
+// wait on other workgroups.  Then one look-back per chunk (over the chunk
+// aggregates, all published at about the same time) gives the true carry-in
+// c, and the stored values get the correction v_t = A_t v_{t-1}, v = c at the
+// chunk start (the exact difference between the two scans, by linearity).
+// The correction stops after the first tile whose outgoing v is exactly zero
+// in FP32, so the result is that of the full correction for any
+// coefficients; when the products of the A_t decay (|a| < 1) that is the
+// chunk's first tile or two.  Every workgroup of a launch is resident (at
+// most one per compute unit, or a single chunk per lane), so the look-back
+// always finds its predecessors running.  The streaming pass keeps DEPTH - 1
+// tiles loading while it scans one (register buffers in an unrolled loop).
+template <class IO, int BLOCK, int ITEMS, int DEPTH>
+__global__ void __launch_bounds__(BLOCK)
+k_scan_chunked(IO io, ScanSync *sync, uint64_t *desc, int n_chunks, int64_t chunk_len)
+{
+    using R = typename IO::Real;
+    constexpr int M = IO::M;
+    constexpr int NW = BLOCK / kWave;
+    constexpr int C = BLOCK * ITEMS;
+    using A = Aff<R, M>;
+    using DS = Desc<R, M>;
+    static_assert(ITEMS % 4 == 0, "vector tiles");
+    static_assert(DEPTH == 2 || DEPTH == 3, "tiles in flight");
+
+    __shared__ A s_wagg[2][NW];
+    __shared__ R s_carry[M];
+
+    const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
+    uint32_t epoch = 0;
+    if (wid == 0) epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int n_lanes = (int)(gridDim.x / (uint32_t)n_chunks);
+    const int lane = (int)(blockIdx.x % (uint32_t)n_lanes), k = (int)(blockIdx.x / (uint32_t)n_lanes);
+    // whole tiles only (the host launches this kernel when C divides T, and
+    // chunk_len is a multiple of C): no load or store is conditional, so the
+    // next tile's loads stay in flight while the current tile is scanned
+    const int64_t c0 = (int64_t)k * chunk_len;
+    const int64_t c1 = c0 + chunk_len < io.g.T ? c0 + chunk_len : io.g.T;
+    const int n_t = (int)((c1 - c0) / C);
+    typename IO::Extra xd[ITEMS];
+
+    auto load_tile = [&](int j, A (&e)[ITEMS]) {
+        const int64_t base = c0 + (int64_t)j * C + (int64_t)tid * ITEMS;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) io.load4(lane, base + i, &e[i], &xd[i]);
+    };
+    // Tile scan: the map taking the tile's carry-in to this thread's carry-in,
+    // and the tile's total map.
+    auto scan_tile = [&](const A (&e)[ITEMS], int par, A &pre, A &total) {
+        A agg = e[0];
+#pragma unroll
+        for (int i = 1; i < ITEMS; i++) agg = compose(e[i], agg);
+        A inc = agg;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            A o = shfl_up_aff(inc, off);
+            if (lid >= off) inc = compose(inc, o);
+        }
+        A excl = shfl_up_aff(inc, 1);
+        if (lid == 0) excl = aff_identity<R, M>();
+        if (lid == kWave - 1) s_wagg[par][wid] = inc;
+        lds_barrier();
+        A wpre = aff_identity<R, M>();
+        for (int w = 0; w < wid; w++) wpre = compose(s_wagg[par][w], wpre);
+        total = wpre;
+        for (int w = wid; w < NW; w++) total = compose(s_wagg[par][w], total);
+        pre = compose(excl, wpre);
+    };
+    R d[M];
+#pragma unroll
+    for (int i = 0; i < M; i++) d[i] = R(0);
+    A chunk = aff_identity<R, M>();
+    Part part = part_neutral();
+    auto zero_carry_tile = [&](const A (&e)[ITEMS], int j) {
+        A pre, total;
+        scan_tile(e, j & 1, pre, total);
+        R dt[M];
+        apply(pre, d, dt);
+        const int64_t base = c0 + (int64_t)j * C + (int64_t)tid * ITEMS;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) io.update4(lane, base + i, 4, &e[i], &xd[i], dt, part);
+        apply(total, d, d);
+        chunk = compose(total, chunk);
+    };
+
+    // ---- 1: the chunk from a zero carry.  DEPTH register buffers rotate
+    // through an unrolled loop, so DEPTH - 1 tiles are loading while one is
+    // scanned (a prefetch past the last tile reloads the last tile).
+    auto tile_at = [&](int j) { return j < n_t ? j : n_t - 1; };
+    A ea[ITEMS], eb[ITEMS];
+    load_tile(0, ea);
+    if constexpr (DEPTH == 2) {
+        for (int j = 0; j < n_t; j += 2) {
+            load_tile(tile_at(j + 1), eb);
+            zero_carry_tile(ea, j);
+            load_tile(tile_at(j + 2), ea);
+            if (j + 1 < n_t) zero_carry_tile(eb, j + 1);
+        }
+    } else {
+        A ec[ITEMS];
+        load_tile(tile_at(1), eb);
+        int j = 0;
+        for (; j + 3 <= n_t; j += 3) {
+            load_tile(tile_at(j + 2), ec);
+            zero_carry_tile(ea, j);
+            load_tile(tile_at(j + 3), ea);
+            zero_carry_tile(eb, j + 1);
+            load_tile(tile_at(j + 4), eb);
+            zero_carry_tile(ec, j + 2);
+        }
+        if (j < n_t) zero_carry_tile(ea, j);
+        if (j + 1 < n_t) zero_carry_tile(eb, j + 1);
+    }
+
+    // ---- 2: carry-in of the chunk
+    if (wid == 0) {
+        R carry[M];
+#pragma unroll
+        for (int i = 0; i < M; i++) carry[i] = R(0);
+        const int64_t self = (int64_t)lane * n_chunks + k;
+        if (k != 0) {
+            if (lid == 0) publish_agg<R, M>(desc + (size_t)self * DS::kWords, epoch, chunk);
+            lookback<R, M>(desc, self, (int64_t)lane * n_chunks, epoch, carry, sync);
+        }
+        if (lid == 0) {
+            R outv[M];
+            apply(chunk, carry, outv);
+            publish_inc<R, M>(desc + (size_t)self * DS::kWords, epoch, outv);
+#pragma unroll
+            for (int i = 0; i < M; i++) s_carry[i] = carry[i];
+        }
+    }
+    lds_barrier();
+
+    // ---- 3: correction of the chunk's head
+    R v[M];
+    bool live = false;
+#pragma unroll
+    for (int i = 0; i < M; i++) {
+        v[i] = s_carry[i];
+        live |= v[i] != R(0);
+    }
+    for (int j = 0; j < n_t && live; j++) {
+        load_tile(j, ea);
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++)
+#pragma unroll
+            for (int r = 0; r < M; r++) ea[i].b[r] = R(0);
+        A pre, total;
+        scan_tile(ea, (n_t + j) & 1, pre, total);
+        R vt[M];
+        apply(pre, v, vt);
+        const int64_t base = c0 + (int64_t)j * C + (int64_t)tid * ITEMS;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) io.fix4(lane, base + i, 4, &ea[i], vt);
+        apply(total, v, v);
+        live = false;
+#pragma unroll
+        for (int i = 0; i < M; i++) live |= v[i] != R(0);
+    }
+}
+
 // Advances the descriptor epoch after a scan, so the next launch (or graph
 // replay) ignores every descriptor this one wrote.
 __global__ void k_bump_epoch(ScanSync *sync)
@@ -928,6 +1148,34 @@ pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, Ti
         hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
         PMC_TRY_HIP(hipGetLastError());
     }
+    return PMC_OK;
+}
+
+// Chunked scan of a long standalone recursion whose length is a multiple of
+// the tile: one chunk per compute unit.
+template <class IO, int BLOCK, int ITEMS, int DEPTH>
+pmc_status run_scan_chunked(pmc_context *ctx, const IO &io, int n_lanes, int64_t T)
+{
+    using DS = Desc<typename IO::Real, IO::M>;
+    constexpr int C = BLOCK * ITEMS;
+    const int n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+    int want = n_lanes >= n_cu ? 1 : n_cu / n_lanes;
+    const int64_t tiles = T / C;
+    if (want > tiles) want = (int)tiles;
+    const int64_t chunk_len = (tiles + want - 1) / want * C;
+    const int n_chunks = (int)((T + chunk_len - 1) / chunk_len);
+    const size_t n_wg = (size_t)n_lanes * n_chunks;
+    if (n_wg == 0) return PMC_OK;
+    if (n_wg > 0x7fffffffULL) {
+        set_error("scan: %zu chunks exceed the launch limit", n_wg);
+        return PMC_ERR_UNSUPPORTED;
+    }
+    PMC_TRY(ensure_lb_desc(ctx, n_wg * DS::kWords * sizeof(uint64_t)));
+    hipLaunchKernelGGL((k_scan_chunked<IO, BLOCK, ITEMS, DEPTH>), dim3((unsigned)n_wg), dim3(BLOCK), 0, ctx->stream, io,
+                       ctx->sync, (uint64_t *)ctx->lb_desc, n_chunks, chunk_len);
+    PMC_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
+    PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;
 }
 
@@ -1213,6 +1461,11 @@ pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64
         DiagLinIO<double> io{LinGeom{T, nt}, (const double *)a, (const double *)b, (double *)out};
         return run_scan<DiagLinIO<double>, 256, 8>(ctx, io, n_lanes, nt, nullptr);
     }
+    // long recursions: chunked scan (one chunk per compute unit)
+    if ((int64_t)n_lanes * T >= (int64_t(1) << 23) && T % (1024 * 8) == 0) {
+        DiagLinIO<float> io{LinGeom{T, 0}, (const float *)a, (const float *)b, (float *)out};
+        return run_scan_chunked<DiagLinIO<float>, 1024, 8, 3>(ctx, io, n_lanes, T);
+    }
     // the Newton scan's rule: larger tiles (fewer look-back hops) for large scans
     if ((int64_t)n_lanes * T >= (int64_t(1) << 23)) {
         constexpr int C = 1024 * 8;
@@ -1229,6 +1482,10 @@ pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64
 pmc_status launch_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
                                 const void *rhs, void *out)
 {
+    if ((int64_t)n_lanes * T >= (int64_t(1) << 22) && T % (1024 * 4) == 0) {
+        Block2LinIO io{LinGeom{T, 0}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};
+        return run_scan_chunked<Block2LinIO, 1024, 4, 2>(ctx, io, n_lanes, T);
+    }
     if ((int64_t)n_lanes * T >= (int64_t(1) << 22)) {
         constexpr int C = 1024 * 4;
         int nt = (int)((T + C - 1) / C);

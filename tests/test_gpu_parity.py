@@ -83,8 +83,9 @@ def test_linrec_diag_large(ctx, pm, orc):
 
 
 def test_linrec_diag_large_vector_tiles(ctx, pm, orc):
-    """8 lanes x 2^20 steps: the large-scan tiles (1024 x 8) with vector loads;
-    exact carries (a = 1, b = 1) and a random recursion against the oracle."""
+    """8 lanes x 2^20 steps (the chunked scan): exact carries (a = 1, b = 1,
+    where the correction covers every chunk in full) and a random recursion
+    against the oracle."""
     _say("linrec_diag 8 x 2^20 (large tiles, vector path)")
     L, T = 8, 1 << 20
     ones = torch.ones((L, T), device=DEV)
@@ -99,8 +100,46 @@ def test_linrec_diag_large_vector_tiles(ctx, pm, orc):
     assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("L,T,lo,hi,zeros", [(5, (1 << 21) + 8192 * 3, -0.99, 0.99, True),
+                                             (3, (1 << 22) - 8192, 0.999, 1.0, False),
+                                             (300, 1 << 15, -0.9, 0.9, False)])
+def test_linrec_diag_chunked(ctx, pm, orc, L, T, lo, hi, zeros):
+    """Long recursions whose length is a multiple of the 8192-step tile take
+    the chunked scan (each workgroup scans its chunk from a zero carry, then
+    corrects the chunk's head with the true carry): chunk counts off the
+    powers of two (a short last chunk), exact zeros in a (a correction ends
+    at once), slowly decaying products (the correction runs over many tiles),
+    and more lanes than compute units (one chunk per lane)."""
+    _say(f"linrec_diag chunked L={L} T={T} a in [{lo}, {hi}] zeros={zeros}")
+    rng = np.random.default_rng(L + T)
+    a = rng.uniform(lo, hi, size=(L, T)).astype(np.float32)
+    if zeros:
+        a[:, ::4099] = 0.0
+    b = rng.normal(size=(L, T)).astype(np.float32)
+    out = pm.linrec_diag(ctx, _t(a), _t(b)).cpu().numpy().astype(np.float64)
+    ref = orc.linrec_diag(a.T, b.T).T
+    err = np.max(np.abs(out - ref)) / max(1.0, np.max(np.abs(ref)))
+    _say(f"  max error / scale = {err:.3e}")
+    assert err <= 2e-5
+
+
+def test_linrec_block2_chunked(ctx, pm, orc):
+    """2 x 2 blocks through the chunked scan: 5 lanes x (2^20 + 7 x 4096) steps."""
+    _say("linrec_block2 chunked 5 x (2^20 + 7 x 4096)")
+    L, T = 5, (1 << 20) + 7 * 4096
+    rng = np.random.default_rng(13)
+    coef = rng.uniform(-0.6, 0.6, size=(4, L, T)).astype(np.float32)
+    rhs = rng.normal(size=(2, L, T)).astype(np.float32)
+    out = pm.linrec_block2(ctx, _t(coef), _t(rhs)).cpu().numpy().astype(np.float64)
+    c = coef.astype(np.float64)
+    r = rhs.astype(np.float64)
+    p, q = orc.linrec_block2(c[0].T, c[1].T, c[2].T, c[3].T, r[0].T, r[1].T)
+    ref = np.stack([p.T, q.T])
+    assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
+
+
 def test_linrec_block2_large_vector_tiles(ctx, pm, orc):
-    """2 lanes x 2^21 steps: the large-scan tiles (1024 x 4) with vector loads."""
+    """2 lanes x 2^21 steps (the chunked scan for 2 x 2 blocks)."""
     _say("linrec_block2 2 x 2^21 (large tiles, vector path)")
     L, T = 2, 1 << 21
     rng = np.random.default_rng(12)
