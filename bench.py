@@ -106,6 +106,24 @@ def main():
     seq_value = T / (seq_ms / 1e3)
     par_vs_seq = (r.states - rs.states).abs().max().item()
 
+    # the same solves with FP32 matrix products (the products' arithmetic
+    # is the only difference), reported beside the headline
+    f32_products = None
+    if args.products != "f32":
+        tg32 = pm.Target(ctx, dict(ch.target, products="f32"))
+        pm.solve(ctx, tg32, eps, s0, xi, u, **solve_kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r32 = [pm.solve(ctx, tg32, eps, s0, xi, u, **solve_kw) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall32 = (time.perf_counter() - t2) / args.steps
+        ev32 = sum(x.eval_ms for x in r32) / sum(x.sweeps for x in r32)
+        f32_products = {"value": T / wall32, "ms_per_step": 1e3 * wall32,
+                        "speedup_vs_sequential": (T / wall32) / seq_value, "newton_iters": r32[-1].sweeps,
+                        "eval_avg_launch_ms": ev32, "kernel": "k_eval_logreg_lds",
+                        "max_abs_minus_split16": (r32[-1].states - r.states).abs().max().item()}
+        del tg32
+
     # roofline of the dominant kernel (the evaluation kernel), live HIP events
     N, D = ch.target["X"].shape
     flops_per_step = 10.0 * N * D  # grad at x and x~ (4ND each) + Hessian diagonal (2ND)
@@ -139,6 +157,7 @@ def main():
         "sequential": {"value": seq_value, "unit": "chain-steps/s", "ms": seq_ms},
         "speedup_vs_sequential": value / seq_value,
         "max_abs_parallel_minus_sequential": par_vs_seq,
+        "f32_products": f32_products,
         "acceptance": r.n_accept / T,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
@@ -186,26 +205,41 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    # standalone recursions: the scan kernel's own duration (HIP events the
+    # library records around it on its stream) and the synchronising call's
+    def _kernel_ms(fn, reps=10):
+        fn()
+        ks = []
+        for _ in range(reps):
+            fn()
+            ks.append(ctx.last_scan_ms())
+        return sum(ks) / len(ks)
+
     gen = torch.Generator(device=dev)
     gen.manual_seed(3)
+    ctx.set_scan_timing(True)
     la = torch.rand((16, 1 << 22), device=dev, generator=gen) * 0.5 + 0.5
     lb = torch.randn((16, 1 << 22), device=dev, generator=gen)
+    kd = _kernel_ms(lambda: pm.linrec_diag(ctx, la, lb))
     ms_d = _ev_ms(lambda: pm.linrec_diag(ctx, la, lb))
     del la, lb
     lc = torch.rand((4, 8, 1 << 22), device=dev, generator=gen) * 0.6 - 0.3
     lr = torch.randn((2, 8, 1 << 22), device=dev, generator=gen)
+    kb = _kernel_ms(lambda: pm.linrec_block2(ctx, lc, lr))
     ms_b = _ev_ms(lambda: pm.linrec_block2(ctx, lc, lr))
+    ctx.set_scan_timing(False)
     del lc, lr
     torch.cuda.empty_cache()
     bd, bb = 12.0 * 16 * (1 << 22), 32.0 * 8 * (1 << 22)
     out["roofline_linrec"] = {
-        "diag": {"bound": "hbm", "achieved": bd / (ms_d * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                 "frac": bd / (ms_d * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_call_ms": ms_d,
-                 "kernel": "k_scan<DiagLinIO>", "shape": "16 planes x 2^22 steps, FP32"},
-        "block2": {"bound": "hbm", "achieved": bb / (ms_b * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                   "frac": bb / (ms_b * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_call_ms": ms_b,
-                   "kernel": "k_scan<Block2LinIO>", "shape": "8 lanes x 2^22 steps, 2x2 blocks, FP32"}}
-    _log(f"[bench] standalone recursions: diag {ms_d:.3f} ms, block2 {ms_b:.3f} ms")
+        "diag": {"bound": "hbm", "achieved": bd / (kd * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": bd / (kd * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": kd, "avg_call_ms": ms_d,
+                 "kernel": "k_scan_chunked<DiagLinIO>", "shape": "16 planes x 2^22 steps, FP32"},
+        "block2": {"bound": "hbm", "achieved": bb / (kb * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": bb / (kb * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": kb, "avg_call_ms": ms_b,
+                   "kernel": "k_scan_chunked<Block2LinIO>", "shape": "8 lanes x 2^22 steps, 2x2 blocks, FP32"}}
+    _log(f"[bench] standalone recursions: diag kernel {kd:.3f} ms (call {ms_d:.3f}), "
+         f"block2 kernel {kb:.3f} ms (call {ms_b:.3f})")
 
     # ---- the step size as specified (0.02): run and report
     if not args.no_as_specified:

@@ -242,6 +242,15 @@ pmc_status pmc_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const voi
 pmc_status pmc_linrec_dense(pmc_context *ctx, pmc_dtype dtype, pmc_jac_prec jac_prec, int D,
                             int64_t T, const void *A, const void *b, void *out);
 
+/* Kernel timing of the two recursions above.  With on != 0, pmc_linrec_diag
+ * and pmc_linrec_block2 record HIP events around their scan kernel on the
+ * context's stream (the calls still synchronise before returning);
+ * pmc_last_scan_ms writes that kernel's duration in milliseconds for the
+ * most recent such call to the HOST float *ms (0 before any).  Off by
+ * default. */
+pmc_status pmc_set_scan_timing(pmc_context *ctx, int on);
+pmc_status pmc_last_scan_ms(pmc_context *ctx, float *ms);
+
 /* ---- tuning --------------------------------------------------------------- */
 /* Times the scan tile configurations for this problem's shape on the device
  * and stores the fastest in the context (and, if cache_path != NULL, in a

@@ -64,6 +64,16 @@ class Context:
         self._stream = stream
         B.check(B.lib().pmc_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
 
+    def set_scan_timing(self, on: bool):
+        """pmc_set_scan_timing: time the scan kernel of linrec_diag / linrec_block2."""
+        B.check(B.lib().pmc_set_scan_timing(self.h, int(bool(on))))
+
+    def last_scan_ms(self) -> float:
+        """pmc_last_scan_ms: kernel time of the most recent timed recursion call."""
+        ms = C.c_float()
+        B.check(B.lib().pmc_last_scan_ms(self.h, C.byref(ms)))
+        return ms.value
+
     def close(self):
         if getattr(self, "h", None):
             B.lib().pmc_destroy(self.h)

@@ -86,6 +86,8 @@ def lib():
             "pmc_linrec_block2": [vp, C.c_int, i64, vp, vp, vp],
             "pmc_linrec_dense": [vp, C.c_int, C.c_int, C.c_int, i64, vp, vp, vp],
             "pmc_autotune": [vp, C.POINTER(pmc_problem), C.POINTER(pmc_options), C.c_char_p],
+            "pmc_set_scan_timing": [vp, C.c_int],
+            "pmc_last_scan_ms": [vp, C.POINTER(C.c_float)],
         }
         for name, args in sig.items():
             f = getattr(L, name)

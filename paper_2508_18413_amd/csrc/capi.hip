@@ -19,6 +19,7 @@ pmc_status pmc_linrec_diag(pmc_context *ctx, pmc_dtype dtype, int n_lanes, int64
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     PMC_TRY(launch_linrec_diag(ctx, dtype, n_lanes, T, a, b, out));
     PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->scan_timing) PMC_TRY_HIP(hipEventElapsedTime(&ctx->last_scan_ms, ctx->kev[0], ctx->kev[1]));
     return check_scan_health(ctx);
 }
 
@@ -33,6 +34,7 @@ pmc_status pmc_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const voi
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     PMC_TRY(launch_linrec_block2(ctx, n_lanes, T, coef, rhs, out));
     PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->scan_timing) PMC_TRY_HIP(hipEventElapsedTime(&ctx->last_scan_ms, ctx->kev[0], ctx->kev[1]));
     return check_scan_health(ctx);
 }
 
@@ -60,6 +62,21 @@ pmc_status pmc_linrec_dense(pmc_context *ctx, pmc_dtype dtype, pmc_jac_prec jac_
     }
     PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
     return check_scan_health(ctx);
+}
+
+pmc_status pmc_set_scan_timing(pmc_context *ctx, int on)
+{
+    PMC_REQUIRE(ctx, "pmc_set_scan_timing: ctx is NULL");
+    ctx->scan_timing = on != 0;
+    ctx->last_scan_ms = 0.f;
+    return PMC_OK;
+}
+
+pmc_status pmc_last_scan_ms(pmc_context *ctx, float *ms)
+{
+    PMC_REQUIRE(ctx && ms, "pmc_last_scan_ms: ctx and ms must be non-NULL");
+    *ms = ctx->last_scan_ms;
+    return PMC_OK;
 }
 
 }  // extern "C"

@@ -162,6 +162,9 @@ struct pmc_context {
     // tuning: items per thread of the diagonal scan (0 = default)
     int diag_items = 0;
     int diag_block = 0;
+    // kernel timing of the standalone recursions (events kev[0], kev[1])
+    int scan_timing = 0;
+    float last_scan_ms = 0.f;
 };
 
 namespace pmc {

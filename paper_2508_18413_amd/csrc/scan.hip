@@ -1129,9 +1129,11 @@ __global__ void k_bump_epoch(ScanSync *sync)
     __hip_atomic_store(&sync->epoch, (e + 1) & 0x3fffffffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// With `timed`, the scan kernel (not the epoch advance) is bracketed by the
+// context's events kev[0] and kev[1].
 template <class IO, int BLOCK, int ITEMS>
 pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, TilePartial *partials,
-                    bool bump = true)
+                    bool bump = true, bool timed = false)
 {
     using DS = Desc<typename IO::Real, IO::M>;
     const size_t n_desc = (size_t)n_lanes * n_tiles;
@@ -1141,9 +1143,11 @@ pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, Ti
         return PMC_ERR_UNSUPPORTED;
     }
     PMC_TRY(ensure_lb_desc(ctx, n_desc * DS::kWords * sizeof(uint64_t)));
+    if (timed) PMC_TRY_HIP(hipEventRecord(ctx->kev[0], ctx->stream));
     hipLaunchKernelGGL((k_scan<IO, BLOCK, ITEMS>), dim3((unsigned)n_desc), dim3(BLOCK), 0,
                        ctx->stream, io, ctx->sync, (uint64_t *)ctx->lb_desc, n_tiles, partials);
     PMC_TRY_HIP(hipGetLastError());
+    if (timed) PMC_TRY_HIP(hipEventRecord(ctx->kev[1], ctx->stream));
     if (bump) {
         hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
         PMC_TRY_HIP(hipGetLastError());
@@ -1154,7 +1158,7 @@ pmc_status run_scan(pmc_context *ctx, const IO &io, int n_lanes, int n_tiles, Ti
 // Chunked scan of a long standalone recursion whose length is a multiple of
 // the tile: one chunk per compute unit.
 template <class IO, int BLOCK, int ITEMS, int DEPTH>
-pmc_status run_scan_chunked(pmc_context *ctx, const IO &io, int n_lanes, int64_t T)
+pmc_status run_scan_chunked(pmc_context *ctx, const IO &io, int n_lanes, int64_t T, bool timed)
 {
     using DS = Desc<typename IO::Real, IO::M>;
     constexpr int C = BLOCK * ITEMS;
@@ -1171,9 +1175,11 @@ pmc_status run_scan_chunked(pmc_context *ctx, const IO &io, int n_lanes, int64_t
         return PMC_ERR_UNSUPPORTED;
     }
     PMC_TRY(ensure_lb_desc(ctx, n_wg * DS::kWords * sizeof(uint64_t)));
+    if (timed) PMC_TRY_HIP(hipEventRecord(ctx->kev[0], ctx->stream));
     hipLaunchKernelGGL((k_scan_chunked<IO, BLOCK, ITEMS, DEPTH>), dim3((unsigned)n_wg), dim3(BLOCK), 0, ctx->stream, io,
                        ctx->sync, (uint64_t *)ctx->lb_desc, n_chunks, chunk_len);
     PMC_TRY_HIP(hipGetLastError());
+    if (timed) PMC_TRY_HIP(hipEventRecord(ctx->kev[1], ctx->stream));
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;
@@ -1455,47 +1461,49 @@ pmc_status launch_newton_scan_dense_small(pmc_context *ctx, pmc_dtype dt, int D,
 pmc_status launch_linrec_diag(pmc_context *ctx, pmc_dtype dt, int n_lanes, int64_t T, const void *a,
                               const void *b, void *out)
 {
+    const bool timed = ctx->scan_timing != 0;
     if (dt == PMC_F64) {
         constexpr int C = 256 * 8;
         int nt = (int)((T + C - 1) / C);
         DiagLinIO<double> io{LinGeom{T, nt}, (const double *)a, (const double *)b, (double *)out};
-        return run_scan<DiagLinIO<double>, 256, 8>(ctx, io, n_lanes, nt, nullptr);
+        return run_scan<DiagLinIO<double>, 256, 8>(ctx, io, n_lanes, nt, nullptr, true, timed);
     }
     // long recursions: chunked scan (one chunk per compute unit)
     if ((int64_t)n_lanes * T >= (int64_t(1) << 23) && T % (1024 * 8) == 0) {
         DiagLinIO<float> io{LinGeom{T, 0}, (const float *)a, (const float *)b, (float *)out};
-        return run_scan_chunked<DiagLinIO<float>, 1024, 8, 3>(ctx, io, n_lanes, T);
+        return run_scan_chunked<DiagLinIO<float>, 1024, 8, 3>(ctx, io, n_lanes, T, timed);
     }
     // the Newton scan's rule: larger tiles (fewer look-back hops) for large scans
     if ((int64_t)n_lanes * T >= (int64_t(1) << 23)) {
         constexpr int C = 1024 * 8;
         int nt = (int)((T + C - 1) / C);
         DiagLinIO<float> io{LinGeom{T, nt}, (const float *)a, (const float *)b, (float *)out};
-        return run_scan<DiagLinIO<float>, 1024, 8>(ctx, io, n_lanes, nt, nullptr);
+        return run_scan<DiagLinIO<float>, 1024, 8>(ctx, io, n_lanes, nt, nullptr, true, timed);
     }
     constexpr int C = 512 * 8;
     int nt = (int)((T + C - 1) / C);
     DiagLinIO<float> io{LinGeom{T, nt}, (const float *)a, (const float *)b, (float *)out};
-    return run_scan<DiagLinIO<float>, 512, 8>(ctx, io, n_lanes, nt, nullptr);
+    return run_scan<DiagLinIO<float>, 512, 8>(ctx, io, n_lanes, nt, nullptr, true, timed);
 }
 
 pmc_status launch_linrec_block2(pmc_context *ctx, int n_lanes, int64_t T, const void *coef,
                                 const void *rhs, void *out)
 {
+    const bool timed = ctx->scan_timing != 0;
     if ((int64_t)n_lanes * T >= (int64_t(1) << 22) && T % (1024 * 4) == 0) {
         Block2LinIO io{LinGeom{T, 0}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};
-        return run_scan_chunked<Block2LinIO, 1024, 4, 2>(ctx, io, n_lanes, T);
+        return run_scan_chunked<Block2LinIO, 1024, 4, 2>(ctx, io, n_lanes, T, timed);
     }
     if ((int64_t)n_lanes * T >= (int64_t(1) << 22)) {
         constexpr int C = 1024 * 4;
         int nt = (int)((T + C - 1) / C);
         Block2LinIO io{LinGeom{T, nt}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};
-        return run_scan<Block2LinIO, 1024, 4>(ctx, io, n_lanes, nt, nullptr);
+        return run_scan<Block2LinIO, 1024, 4>(ctx, io, n_lanes, nt, nullptr, true, timed);
     }
     constexpr int C = 256 * 4;
     int nt = (int)((T + C - 1) / C);
     Block2LinIO io{LinGeom{T, nt}, n_lanes, (const float *)coef, (const float *)rhs, (float *)out};
-    return run_scan<Block2LinIO, 256, 4>(ctx, io, n_lanes, nt, nullptr);
+    return run_scan<Block2LinIO, 256, 4>(ctx, io, n_lanes, nt, nullptr, true, timed);
 }
 
 pmc_status launch_linrec_dense_small(pmc_context *ctx, int D, int64_t T, const double *A,

@@ -138,6 +138,28 @@ def test_linrec_block2_chunked(ctx, pm, orc):
     assert np.max(np.abs(out - ref)) <= 2e-5 * max(1.0, np.max(np.abs(ref)))
 
 
+def test_scan_timing(pm):
+    """pmc_set_scan_timing / pmc_last_scan_ms: off by default (0), then the
+    scan kernel's own duration, shorter than the synchronising call."""
+    import time
+    c = pm.Context(0)
+    try:
+        a = torch.full((16, 1 << 20), 0.5, device=DEV)
+        b = torch.ones((16, 1 << 20), device=DEV)
+        pm.linrec_diag(c, a, b)
+        assert c.last_scan_ms() == 0.0
+        c.set_scan_timing(True)
+        t0 = time.perf_counter()
+        out = pm.linrec_diag(c, a, b)
+        call_ms = 1e3 * (time.perf_counter() - t0)
+        ms = c.last_scan_ms()
+        _say(f"  scan kernel {ms:.4f} ms, call {call_ms:.4f} ms")
+        assert 0.0 < ms < call_ms
+        assert torch.allclose(out[:, -1], torch.full((16,), 2.0, device=DEV))
+    finally:
+        c.close()
+
+
 def test_linrec_block2_large_vector_tiles(ctx, pm, orc):
     """2 lanes x 2^21 steps (the chunked scan for 2 x 2 blocks)."""
     _say("linrec_block2 2 x 2^21 (large tiles, vector path)")
