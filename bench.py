@@ -233,10 +233,12 @@ def main():
     bd, bb = 12.0 * 16 * (1 << 22), 32.0 * 8 * (1 << 22)
     out["roofline_linrec"] = {
         "diag": {"bound": "hbm", "achieved": bd / (kd * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                 "frac": bd / (kd * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": kd, "avg_call_ms": ms_d,
+                 "frac": bd / (kd * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic("k_scan_chunked_diag"),
+                 "avg_launch_ms": kd, "avg_call_ms": ms_d,
                  "kernel": "k_scan_chunked<DiagLinIO>", "shape": "16 planes x 2^22 steps, FP32"},
         "block2": {"bound": "hbm", "achieved": bb / (kb * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                   "frac": bb / (kb * 1e-3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": kb, "avg_call_ms": ms_b,
+                   "frac": bb / (kb * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic("k_scan_chunked_block2"),
+                   "avg_launch_ms": kb, "avg_call_ms": ms_b,
                    "kernel": "k_scan_chunked<Block2LinIO>", "shape": "8 lanes x 2^22 steps, 2x2 blocks, FP32"}}
     _log(f"[bench] standalone recursions: diag kernel {kd:.3f} ms (call {ms_d:.3f}), "
          f"block2 kernel {kb:.3f} ms (call {ms_b:.3f})")
