@@ -184,7 +184,7 @@ def main():
     out["roofline_scan"] = {"bound": "hbm", "achieved": bytes_big / (scan_ms_big * 1e-3) / 1e9,
                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": bytes_big / (scan_ms_big * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                            "traffic": _traffic("k_scan_diag_newton"), "kernel": "k_scan<DiagNewtonIO>",
+                            "traffic": _traffic("k_scan_newton_chunked"), "kernel": "k_scan_newton_chunked",
                             "shape": "16 planes x 2^22 steps, FP32", "avg_launch_ms": scan_ms_big}
     del gx0, gxi, gtg
     torch.cuda.empty_cache()

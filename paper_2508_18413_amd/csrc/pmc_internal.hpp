@@ -207,6 +207,8 @@ struct NewtonScanArgs {
     double eps;             // leapfrog step (block2)
     void *trace;            // optional copy of S after the update, or nullptr
     int defer_epoch;        // 1: the status fold that follows advances the scan epoch
+    int n_chains;           // chains in the tile map (0: unknown)
+    int64_t n_steps;        // steps over all chains
 };
 
 // Steps per scan tile for a configuration (the host builds its tile map with it).

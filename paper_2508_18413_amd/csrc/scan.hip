@@ -1121,6 +1121,276 @@ k_scan_chunked(IO io, ScanSync *sync, uint64_t *desc, int n_chunks, int64_t chun
     }
 }
 
+// ------------------------------------------ chunked Newton scan (one chain)
+// The quasi-DEER update of one long chain (eq. 4 applied to the residual of
+// eq. 1): S_t <- F_t + J_t d_{t-1}, d_t = J_t d_{t-1} + F_t - S_t over the
+// window [w, T) (before w the iterate is frozen: S kept, d = 0), with the
+// chunked scheme of k_scan_chunked:
+//  1. each workgroup scans its chunk of whole tiles from a zero carry, writes
+//     the local iterate in place and each tile's convergence partial from the
+//     local d; while the product of the chunk's J so far is non-zero it also
+//     writes the local d into the F plane (F is not read again in the sweep);
+//  2. one look-back per chunk gives the true carry c;
+//  3. while that product is non-zero and v (v_t = J_t v_{t-1}, v = c at the
+//     chunk start) is non-zero: d_t = d_t(local) + v_t, S_t += v_t, and the
+//     tile's partial is recomputed from them (its residual fields, which do
+//     not depend on the carry, are kept).
+// Tiles before the window get neutral partials, as the tiled scan gives them.
+struct NewtonChunkArgs {
+    int n_tiles;               // T / C
+    int64_t ld;                // plane stride
+    const ChainStatus *chains; // chain 0
+    const float *J;
+    float *F, *S;
+    TilePartial *partials;     // [n_lanes, n_tiles]
+    double atol, rtol;
+};
+
+__device__ __forceinline__ void part_store(TilePartial &tp, const Part &p)
+{
+    tp.max_ratio = p.ratio;
+    tp.nonfinite = p.nonfinite;
+    tp.first_bad = p.first_bad;
+    tp.resid_sq = p.rsq;
+    tp.resid_inf = p.rinf;
+}
+
+template <int BLOCK, int ITEMS>
+__global__ void __launch_bounds__(BLOCK, 1)
+k_scan_newton_chunked(NewtonChunkArgs a, ScanSync *sync, uint64_t *desc, int n_chunks)
+{
+    constexpr int NW = BLOCK / kWave;
+    constexpr int C = BLOCK * ITEMS;
+    using A = Aff<float, 1>;
+    using DS = Desc<float, 1>;
+    static_assert(ITEMS % 4 == 0, "vector tiles");
+
+    __shared__ A s_wagg[2][NW];
+    __shared__ Part s_part[2][NW];
+    __shared__ float s_carry;
+
+    const ChainStatus &cs = a.chains[0];
+    if (!cs.active) return;  // the status fold skips an inactive chain
+    const int tid = threadIdx.x, wid = tid / kWave, lid = tid % kWave;
+    uint32_t epoch = 0;
+    if (wid == 0) epoch = __hip_atomic_load(&sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int n_lanes = (int)(gridDim.x / (uint32_t)n_chunks);
+    const int lane = (int)(blockIdx.x % (uint32_t)n_lanes), k = (int)(blockIdx.x / (uint32_t)n_lanes);
+    const int64_t ws = cs.win_start > 0 ? cs.win_start : 0;
+    const int tw = (int)(ws / C);  // tile holding the window start
+    TilePartial *parts = a.partials + (size_t)lane * a.n_tiles;
+    for (int j = k * BLOCK + tid; j < tw; j += n_chunks * BLOCK) {
+        Part p = part_neutral();
+        part_store(parts[j], p);
+    }
+    const int tpc = (a.n_tiles - tw + n_chunks - 1) / n_chunks;
+    const int j0 = tw + k * tpc;
+    const int j1 = j0 + tpc < a.n_tiles ? j0 + tpc : a.n_tiles;
+    if (j0 >= j1) return;  // an empty chunk is last in its lane: nothing waits for it
+    const int n_t = j1 - j0;
+    const size_t pl = (size_t)lane * a.ld;
+    const float *Jp = a.J + pl;
+    float *Fp = a.F + pl, *Sp = a.S + pl;
+    const float atol = (float)a.atol, rtol = (float)a.rtol;
+
+    // phase 1 items: J, F, S as loaded (nothing is computed from them before
+    // the tile is scanned, so the loads of the next tiles stay in flight)
+    struct Item {
+        float j, f, s;
+    };
+    auto load_tile = [&](int jt, Item (&e)[ITEMS]) {
+        const int64_t base = (int64_t)jt * C + (int64_t)tid * ITEMS;
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) {
+            const float4 j4 = *(const float4 *)(Jp + base + i), f4 = *(const float4 *)(Fp + base + i),
+                         s4 = *(const float4 *)(Sp + base + i);
+            e[i] = Item{j4.x, f4.x, s4.x};
+            e[i + 1] = Item{j4.y, f4.y, s4.y};
+            e[i + 2] = Item{j4.z, f4.z, s4.z};
+            e[i + 3] = Item{j4.w, f4.w, s4.w};
+        }
+    };
+    // Tile scan over the items' maps: the map from the tile's carry-in to this
+    // thread's, and the tile's total map.
+    auto scan_tile = [&](auto map_of, int par, A &pre, A &total) {
+        A agg = map_of(0);
+#pragma unroll
+        for (int i = 1; i < ITEMS; i++) agg = compose(map_of(i), agg);
+        A inc = agg;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            A o = shfl_up_aff(inc, off);
+            if (lid >= off) inc = compose(inc, o);
+        }
+        A excl = shfl_up_aff(inc, 1);
+        if (lid == 0) excl = aff_identity<float, 1>();
+        if (lid == kWave - 1) s_wagg[par][wid] = inc;
+        lds_barrier();
+        A wpre = aff_identity<float, 1>();
+        for (int w = 0; w < wid; w++) wpre = compose(s_wagg[par][w], wpre);
+        total = wpre;
+        for (int w = wid; w < NW; w++) total = compose(s_wagg[par][w], total);
+        pre = compose(excl, wpre);
+    };
+    // each wave leaves its folded partial in s_part[par]; after the next
+    // barrier wave 0 folds the NW of them
+    auto leave_part = [&](Part p, int par) {
+#pragma unroll
+        for (int m = 1; m < kWave; m <<= 1) part_merge(p, part_shfl_xor(p, m));
+        if (lid == 0) s_part[par][wid] = p;
+    };
+    auto fold_prev = [&](int par) {
+        Part p = lid < NW ? s_part[par][lid] : part_neutral();
+#pragma unroll
+        for (int m = 1; m < NW; m <<= 1) part_merge(p, part_shfl_xor(p, m));
+        return p;
+    };
+
+    // ---- 1: the chunk from a zero carry.  A step's map is (J, F - S) and
+    // S_new = J d_{t-1} + F; an element before the window is (1, 0) with
+    // S_new = S (the frozen iterate passes through).
+    float d = 0.f;
+    A chunk = aff_identity<float, 1>();
+    auto zero_carry_tile = [&](const Item (&e)[ITEMS], int j) {
+        const int jt = j0 + j;
+        const int64_t base = (int64_t)jt * C + (int64_t)tid * ITEMS;
+        A pre, total;
+        scan_tile(
+            [&](int i) {
+                const bool frozen = base + i < ws;
+                A m;
+                m.a[0][0] = frozen ? 1.f : e[i].j;
+                m.b[0] = frozen ? 0.f : e[i].f - e[i].s;
+                return m;
+            },
+            j & 1, pre, total);
+        if (wid == 0 && j > 0) {
+            const Part p = fold_prev((j - 1) & 1);
+            if (lid == 0) part_store(parts[jt - 1], p);
+        }
+        const bool keep_d = k != 0 && chunk.a[0][0] != 0.f;  // uniform
+        float dt = fmaf(pre.a[0][0], d, pre.b[0]);
+        Part p = part_neutral();
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) {
+            float sv[4], dv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const Item &it = e[i + q];
+                const bool frozen = base + i + q < ws;
+                const float aa = frozen ? 1.f : it.j, bb = frozen ? 0.f : it.f - it.s;
+                const float dp = dt;
+                dt = fmaf(aa, dp, bb);
+                sv[q] = fmaf(aa, dp, frozen ? it.s : it.f);
+                dv[q] = dt;
+                if (!frozen) part_add<float>(p, base + i + q, dt, sv[q], bb, a.atol, a.rtol);
+            }
+            *(float4 *)(Sp + base + i) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+            if (keep_d) *(float4 *)(Fp + base + i) = make_float4(dv[0], dv[1], dv[2], dv[3]);
+        }
+        leave_part(p, j & 1);
+        d = fmaf(total.a[0][0], d, total.b[0]);
+        chunk = compose(total, chunk);
+    };
+    {
+        Item ea[ITEMS], eb[ITEMS];
+        auto tile_at = [&](int j) { return j0 + (j < n_t ? j : n_t - 1); };
+        load_tile(tile_at(0), ea);
+        for (int j = 0; j < n_t; j += 2) {
+            load_tile(tile_at(j + 1), eb);
+            zero_carry_tile(ea, j);
+            load_tile(tile_at(j + 2), ea);
+            if (j + 1 < n_t) zero_carry_tile(eb, j + 1);
+        }
+    }
+    lds_barrier();
+    if (wid == 0) {
+        const Part p = fold_prev((n_t - 1) & 1);
+        if (lid == 0) part_store(parts[j1 - 1], p);
+    }
+
+    // ---- 2: carry-in of the chunk
+    if (wid == 0) {
+        float carry[1] = {0.f};
+        const int64_t self = (int64_t)lane * n_chunks + k;
+        if (k != 0) {
+            if (lid == 0) publish_agg<float, 1>(desc + (size_t)self * DS::kWords, epoch, chunk);
+            lookback<float, 1>(desc, self, (int64_t)lane * n_chunks, epoch, carry, sync);
+        }
+        if (lid == 0) {
+            float outv[1];
+            apply(chunk, carry, outv);
+            publish_inc<float, 1>(desc + (size_t)self * DS::kWords, epoch, outv);
+            s_carry = carry[0];
+        }
+    }
+    __syncthreads();  // the carry, and this workgroup's partials for phase 3
+
+    // ---- 3: correction of the chunk's head (chunks after the first, which
+    // have no element before the window)
+    float v = s_carry, P = 1.f;
+    int j = 0;
+    for (; j < n_t && v != 0.f && P != 0.f; j++) {
+        const int jt = j0 + j;
+        const int64_t base = (int64_t)jt * C + (int64_t)tid * ITEMS;
+        float jv[ITEMS], dl[ITEMS], sl[ITEMS];  // J, the local d (in F), the local iterate (in S)
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) {
+            const float4 j4 = *(const float4 *)(Jp + base + i), f4 = *(const float4 *)(Fp + base + i),
+                         s4 = *(const float4 *)(Sp + base + i);
+            jv[i] = j4.x, jv[i + 1] = j4.y, jv[i + 2] = j4.z, jv[i + 3] = j4.w;
+            dl[i] = f4.x, dl[i + 1] = f4.y, dl[i + 2] = f4.z, dl[i + 3] = f4.w;
+            sl[i] = s4.x, sl[i + 1] = s4.y, sl[i + 2] = s4.z, sl[i + 3] = s4.w;
+        }
+        A pre, total;
+        scan_tile(
+            [&](int i) {
+                A m;
+                m.a[0][0] = jv[i];
+                m.b[0] = 0.f;
+                return m;
+            },
+            (n_t + j) & 1, pre, total);
+        if (wid == 0 && j > 0) {
+            Part p = fold_prev((n_t + j - 1) & 1);
+            if (lid == 0) {
+                const TilePartial &old = parts[jt - 1];
+                p.rsq = old.resid_sq;
+                p.rinf = old.resid_inf;
+                part_store(parts[jt - 1], p);
+            }
+        }
+        float vt = pre.a[0][0] * v;
+        Part p = part_neutral();
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 4) {
+            float sv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                vt = jv[i + q] * vt;
+                sv[q] = sl[i + q] + vt;
+                part_add<float>(p, base + i + q, dl[i + q] + vt, sv[q], 0.f, a.atol, a.rtol);
+            }
+            *(float4 *)(Sp + base + i) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+        }
+        leave_part(p, (n_t + j) & 1);
+        v = total.a[0][0] * v;
+        P *= total.a[0][0];
+    }
+    if (j > 0) {
+        lds_barrier();
+        if (wid == 0) {
+            Part p = fold_prev((n_t + j - 1) & 1);
+            if (lid == 0) {
+                const TilePartial &old = parts[j0 + j - 1];
+                p.rsq = old.resid_sq;
+                p.rinf = old.resid_inf;
+                part_store(parts[j0 + j - 1], p);
+            }
+        }
+    }
+}
+
 // Advances the descriptor epoch after a scan, so the next launch (or graph
 // replay) ignores every descriptor this one wrote.
 __global__ void k_bump_epoch(ScanSync *sync)
@@ -1392,9 +1662,39 @@ __global__ void __launch_bounds__(256) k_count_accept(const uint8_t *__restrict_
 
 // ------------------------------------------------------------ launchers
 namespace {
+// The chunked Newton scan: one chain, whole 8192-step tiles (512 threads x 16
+// steps: the tiled scan's tile, with the registers for two tiles in flight),
+// no trace, large scans.
+pmc_status newton_chunked(pmc_context *ctx, const NewtonScanArgs &a)
+{
+    constexpr int BLOCK = 512, ITEMS = 16;
+    using DS = Desc<float, 1>;
+    const int n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+    int n_chunks = a.n_lanes >= n_cu ? 1 : n_cu / a.n_lanes;
+    if (n_chunks > a.n_tiles) n_chunks = a.n_tiles;
+    const size_t n_wg = (size_t)a.n_lanes * n_chunks;
+    PMC_TRY(ensure_lb_desc(ctx, n_wg * DS::kWords * sizeof(uint64_t)));
+    NewtonChunkArgs c{a.n_tiles, a.ld, a.chains, (const float *)a.J, (float *)a.F, (float *)a.S, a.partials,
+                      a.atol, a.rtol};
+    hipLaunchKernelGGL((k_scan_newton_chunked<BLOCK, ITEMS>), dim3((unsigned)n_wg), dim3(BLOCK), 0, ctx->stream, c,
+                       ctx->sync, (uint64_t *)ctx->lb_desc, n_chunks);
+    PMC_TRY_HIP(hipGetLastError());
+    if (!a.defer_epoch) {
+        hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, ctx->stream, ctx->sync);
+        PMC_TRY_HIP(hipGetLastError());
+    }
+    return PMC_OK;
+}
+
 template <typename R, int BLOCK, int ITEMS>
 pmc_status diag_newton(pmc_context *ctx, const NewtonScanArgs &a)
 {
+    if constexpr (sizeof(R) == 4 && BLOCK == 1024 && ITEMS == 8) {
+        constexpr int C = BLOCK * ITEMS;
+        if (a.n_chains == 1 && !a.trace && a.n_steps % C == 0 && a.n_tiles == a.n_steps / C &&
+            a.ld == a.n_steps && (int64_t)a.n_lanes * a.n_steps >= (int64_t(1) << 23))
+            return newton_chunked(ctx, a);
+    }
     SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
     DiagNewtonIO<R> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol, a.rtol};
     return run_scan<DiagNewtonIO<R>, BLOCK, ITEMS>(ctx, io, a.n_lanes, a.n_tiles, a.partials, !a.defer_epoch);

@@ -408,6 +408,8 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     sa.rtol = opts->rtol;
     sa.eps = prob->step_size;
     sa.trace = nullptr;
+    sa.n_chains = pl.n_chains;
+    sa.n_steps = pl.n;
     // the look-back scans leave the epoch advance to the status fold that follows
     sa.defer_epoch = pl.jmode == JM_DIAG || pl.jmode == JM_NONE || pl.jmode == JM_DENSE_ROW;
     StatusArgs &sta = sw.st;

@@ -279,6 +279,40 @@ def test_ula_gaussian_one_solve(ctx, pm, orc, dtype):
     assert r.status == 0
 
 
+def test_newton_chunked_scan_ula_gaussian(ctx, pm, orc):
+    """A single chain of 16 x 2^19 steps takes the chunked Newton scan (the
+    scan tile divides T and the scan is large): ULA on a correlated Gaussian,
+    quasi-DEER to the tolerance, against the FP64 oracle."""
+    _say("chunked Newton scan: ULA Gaussian D=16 T=2^19")
+    T = 1 << 19
+    ch = W.gaussian_chain(T, seed=5, eps=0.1, dim=16, dtype=np.float32, lam_lo=0.3)
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), None, sampler="ula", variant="diag", max_iter=200)
+    _say(f"  sweeps={r.sweeps} status={r.status} ratio={r.max_ratio:.3g}")
+    assert r.status == 0
+    ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0.astype(np.float64), ch.xi, None, ula=True)
+    err = state_error(r.states.cpu().numpy(), ref)
+    _say(f"  state_error={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_newton_chunked_scan_logreg(ctx, pm, orc):
+    """MALA on a logistic posterior (200 x 32 data, T = 2^18): the chunked
+    Newton scan under the sliding window (the window start moves into the
+    chunks' tiles) against the FP64 oracle."""
+    _say("chunked Newton scan: MALA logreg D=32 N=200 T=2^18")
+    T = 1 << 18
+    ch = W.logreg_chain(T=T, seed=7, eps=0.002, n_data=200, dim=32)
+    tg = oracle_target(ch.target)
+    s0 = oracle_burnin(tg, ch).astype(np.float32)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=T + 1)
+    _say(f"  sweeps={r.sweeps} status={r.status} ratio={r.max_ratio:.3g} acceptance={r.n_accept / T:.3f}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
 def _logreg_case(orc, T, eps, seed=0):
     ch = W.logreg_chain(T=T, seed=seed, eps=eps)
     tg = oracle_target(ch.target)
