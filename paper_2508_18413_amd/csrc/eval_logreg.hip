@@ -137,17 +137,18 @@ struct LdsArgs {
 // Per-element work of pass 2 for increments |dz| < 8, free of branches:
 // s = sigma(z), w = s (e^dz - 1), a = 1 + w gives
 //   sigma(z + dz) = (s + w) / a,  softplus(z + dz) - softplus(z) = log(a),
-// with one reciprocal of a serving the first; the caller multiplies the a of
-// four elements (each within [e^-8, e^8]) and takes one logarithm of the
-// product.  Everything downstream is an absolute-accuracy sum (the gradient
+// with one reciprocal of a serving the first; the callers multiply the a of
+// four (FP32 products) or eight (split-FP16 products) elements, each within
+// [e^-8, e^8], and take one logarithm of the product.  Everything downstream is an absolute-accuracy sum (the gradient
 // X^T r and the log-likelihood difference), so e^dz - 1 is formed directly:
-// its absolute error (one ulp of e^dz) is what the sums see either way.
+// its absolute error (one ulp of e^dz, carried through one fused
+// multiply-add) is what the sums see either way.
 // Arguments are u = z log2(e) and du = dz log2(e) (the LDS copy of X is
 // scaled); returns y - sigma(z + dz) and a.
 __device__ __forceinline__ float pass2_elem(float u, float du, float y, float &a)
 {
     const float s = sigm2(u);
-    const float w = s * (__builtin_amdgcn_exp2f(du) - 1.f);
+    const float w = fmaf(s, __builtin_amdgcn_exp2f(du), -s);  // s (e^dz - 1), one rounding
     a = 1.f + w;
     return fmaf(-(s + w), frcp(a), y);
 }

@@ -79,3 +79,36 @@ def test_binding_has_no_fallback(monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", os.path.join(ROOT, "does-not-exist.so"))
     with pytest.raises(RuntimeError):
         B.lib()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structures of the binding have the size and field offsets
+    that a C compiler gives the header's structs (gcc on this host)."""
+    import shutil
+    import subprocess
+    from paper_2508_18413_amd import _binding as B
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [B.pmc_target_desc, B.pmc_problem, B.pmc_options, B.pmc_result]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "pmcmc.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f in st._fields_:
+            lines.append(f'  printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            s, f, v = line.split()
+            got[(s, f)] = int(v)
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "size")] == C.sizeof(st), name
+        for f in st._fields_:
+            assert got[(name, f[0])] == getattr(st, f[0]).offset, (name, f[0])
