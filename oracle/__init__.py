@@ -10,8 +10,10 @@ Contents
   step Jacobians, sequential linear recursions, tangent/adjoint derivatives);
 * ``newton_reference``: Algorithm 1 of the paper (Appendix A.1) in FP64, the
   linearised recursion of Sec. 2 eq. 2/3 (dense), eq. 4 (diagonal), the block
-  quasi-DEER recursion of Appendix A.3, or Picard (J = 0), solved by a plain
-  sequential loop;
+  quasi-DEER recursion of Appendix A.3, Picard (J = 0), or the diagonal
+  estimated from one Rademacher probe per step and sweep (Sec. 4 eq. 10),
+  solved by a plain sequential loop;
+* ``probe_sign`` / ``splitmix64``: the counter-based signs of that probe;
 * ``bidiagonal_bruteforce``: the Newton linear system written as one block
   lower-bidiagonal matrix and solved by LAPACK (numpy.linalg.solve).
 
@@ -322,6 +324,34 @@ def mala_adjoint(tg, eps, x0, xi, states, accept, dFds, ula=False, want_lambda=F
 
 # --------------------------------------------- Newton reference (Alg. 1)
 
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 (Steele, Lea & Flood 2014): the output function applied to
+    x + 0x9E3779B97F4A7C15, all arithmetic modulo 2^64."""
+    z = (x + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def probe_sign(seed: int, sweep: int, t: int, d: int) -> float:
+    """Rademacher sign of coordinate d at global step t in sweep `sweep`
+    (0-based): -1 if the top bit of m(m(m(seed) ^ sweep) ^ (1024 t + d)) is
+    set, else +1, with m = splitmix64."""
+    h = splitmix64(splitmix64(splitmix64(seed & _M64) ^ (sweep & _M64)) ^ ((1024 * t + d) & _M64))
+    return -1.0 if h >> 63 else 1.0
+
+
+def hutchinson_diag(J, z):
+    """The one-probe estimate z o (J z) of diag(J) (Sec. 4 eq. 10): its mean over
+    the Rademacher distribution of z is diag(J)."""
+    J = np.asarray(J, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    return z * (J @ z)
+
+
 def _structure(J, variant, D):
     """Project a dense Jacobian onto the variant's structure."""
     if variant == "dense":
@@ -342,14 +372,16 @@ def _structure(J, variant, D):
 
 
 def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=None, tol=0.0,
-                     full_trace=True):
+                     full_trace=True, probe_seed=0):
     """Algorithm 1 (Appendix A.1) with the update of Sec. 2 eq. 2, in FP64.
 
     step_and_jac(t, s_prev) -> (f_t(s_prev), df_t/ds(s_prev)) for t = 0..T-1.
     Each sweep linearises every step at the current guess, then solves
     s_t^{new} = f_t(s_{t-1}) + J_t (s_{t-1}^{new} - s_{t-1}) sequentially.
-    Stops when max_t |s^{new}_t - s_t|_inf <= tol, or after max_iter sweeps
-    (default T + 1).  Returns (final trajectory, list of iterates, sweeps).
+    variant "hutchinson" takes J_t = diag(z o (J z)) with z the probe signs
+    of (probe_seed, sweep, t).  Stops when max_t |s^{new}_t - s_t|_inf <= tol,
+    or after max_iter sweeps (default T + 1).  Returns (final trajectory,
+    list of iterates, sweeps).
     """
     s0 = np.asarray(s0, dtype=np.float64)
     D = s0.shape[0]
@@ -363,7 +395,11 @@ def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=N
         for t in range(T):
             prev = s0 if t == 0 else S[t - 1]
             F[t], J = step_and_jac(t, prev)
-            Js[t] = _structure(J, variant, D)
+            if variant == "hutchinson":
+                z = np.array([probe_sign(probe_seed, it, t, d) for d in range(D)])
+                Js[t] = np.diag(hutchinson_diag(J, z))
+            else:
+                Js[t] = _structure(J, variant, D)
         new = np.empty((T, D))
         for t in range(T):
             if t == 0:

@@ -80,7 +80,7 @@ CASES = {
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("variant", ["dense", "diag", "picard"])
+@pytest.mark.parametrize("variant", ["dense", "diag", "picard", "hutchinson"])
 def test_causal_exactness_bruteforce(orc, case, variant):
     ch = CASES[case]()
     tg = oracle_target(ch.target)
@@ -88,7 +88,7 @@ def test_causal_exactness_bruteforce(orc, case, variant):
     T = ch.T
     ref, _, _ = orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u)
     S, trace, it = orc.newton_reference(_mala_provider(orc, tg, ch), x0, T, variant=variant,
-                                        max_iter=T, tol=-1.0)
+                                        max_iter=T, tol=-1.0, probe_seed=11)
     for i, Si in enumerate(trace):
         np.testing.assert_array_equal(Si[:i], ref[:i])
     np.testing.assert_array_equal(S, ref)
@@ -132,3 +132,53 @@ def test_leapfrog_gaussian_one_solve_full_deer(orc):
     S2, _, it2 = orc.newton_reference(sj, s0, L, variant="block2", tol=1e-12)
     np.testing.assert_allclose(S2, r["traj"][0], atol=1e-10)
     assert it2 >= it
+
+
+# ------------------------------------------- stochastic diagonal (Sec. 4 eq. 10)
+
+@pytest.mark.parametrize("D", [1, 2, 5, 10])
+def test_hutchinson_identity_bruteforce(orc, D):
+    """The mean of z o (J z) over all 2^D sign vectors is diag(J), exactly."""
+    import itertools
+    rng = np.random.default_rng(D)
+    J = rng.normal(size=(D, D))
+    acc = np.zeros(D)
+    for signs in itertools.product((-1.0, 1.0), repeat=D):
+        acc += orc.hutchinson_diag(J, np.array(signs))
+    np.testing.assert_allclose(acc / 2 ** D, np.diag(J), rtol=0, atol=1e-13)
+
+
+def test_hutchinson_probe_is_a_directional_derivative(orc):
+    """One probe's estimate z_d (J z)_d against z_d times the central
+    difference of the MALA step along z (decision frozen), O(h^2)."""
+    ch = W.banana_chain(8, seed=3)
+    tg = oracle_target(ch.target)
+    x = np.array([0.7, -0.4])
+    xi, u = np.asarray(ch.xi[2], dtype=np.float64), float(ch.u[2])
+    F, J, acc = orc.mala_jac(tg, ch.eps, x, xi, u)
+    h = 1e-5
+    for seed in range(4):
+        z = np.array([orc.probe_sign(seed, 0, 2, d) for d in range(2)])
+        fp = orc.mala_step(tg, ch.eps, x + h * z, xi, u, force=acc)[0]
+        fm = orc.mala_step(tg, ch.eps, x - h * z, xi, u, force=acc)[0]
+        jvp = (np.asarray(fp) - np.asarray(fm)) / (2 * h)
+        np.testing.assert_allclose(orc.hutchinson_diag(J, z), z * jvp, rtol=0, atol=1e-8)
+
+
+def test_probe_signs_balanced_and_fresh_per_sweep(orc):
+    z0 = np.array([[orc.probe_sign(5, 0, t, d) for d in range(8)] for t in range(2048)])
+    z1 = np.array([[orc.probe_sign(5, 1, t, d) for d in range(8)] for t in range(2048)])
+    assert set(np.unique(z0)) == {-1.0, 1.0}
+    assert abs(z0.mean()) < 0.03 and abs(z1.mean()) < 0.03
+    assert abs(np.mean(z0 == z1) - 0.5) < 0.03
+
+
+def test_hutchinson_newton_fixed_point(orc):
+    """Newton with the probed diagonal still converges to the sequential trace."""
+    ch = W.banana_chain(64, seed=2)
+    tg = oracle_target(ch.target)
+    x0 = np.asarray(ch.x0, dtype=np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u)
+    S, _, it = orc.newton_reference(_mala_provider(orc, tg, ch), x0, ch.T, variant="hutchinson",
+                                    tol=1e-13, probe_seed=3)
+    np.testing.assert_allclose(S, ref, rtol=0, atol=1e-12)
