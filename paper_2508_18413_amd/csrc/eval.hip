@@ -41,6 +41,18 @@ __device__ __forceinline__ R clampj(R v, double damping, double clip, int clip_i
     return v;
 }
 
+// SplitMix64 (Steele, Lea & Flood 2014): the output function applied to
+// x + 0x9E3779B97F4A7C15, modulo 2^64.  The probe sign of coordinate d at
+// global step t in a chain's sweep i is the top bit of
+// m(m(m(seed) ^ i) ^ (1024 t + d)).
+__device__ __forceinline__ uint64_t probe_mix(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // ------------------------------------------------ per-lane eval (small D)
 template <class Tg, typename R, int JM>
 __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
@@ -124,9 +136,31 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
     const R ea = acc ? eps : R(0);
 
     if (JM == JM_DIAG) {
+        R *J = (R *)a.J;
+        if (a.probes) {
+            // z o (J z) with J z = z + eps H z (+ the rank-one surrogate term)
+            R z[DM], hz[DM];
+            const uint64_t hs = probe_mix(probe_mix(a.probe_seed) ^ (uint64_t)(uint32_t)cs.sweeps);
+#pragma unroll
+            for (int d = 0; d < DM; d++)
+                z[d] = d < D ? ((probe_mix(hs ^ (uint64_t)(1024 * t + d)) >> 63) ? R(-1) : R(1)) : R(0);
+            tg.hvp(x, z, hz);
+            R dz = R(0);
+            if (surr)
+#pragma unroll
+                for (int d = 0; d < DM; d++) dz = fma(dldx[d], z[d], dz);
+#pragma unroll
+            for (int d = 0; d < DM; d++) {
+                if (d < D) {
+                    R jz = fma(ea, hz[d], z[d]);
+                    if (surr) jz = fma(coef * dl[d], dz, jz);
+                    J[(size_t)d * ld + t] = clampj(z[d] * jz, a.damping, a.clip, 0);
+                }
+            }
+            return;
+        }
         R h[DM];
         tg.hess_diag(x, h);
-        R *J = (R *)a.J;
 #pragma unroll
         for (int d = 0; d < DM; d++) {
             if (d < D) {

@@ -260,6 +260,8 @@ struct EvalArgs {
     int jmode;
     const pmc::DevTarget *tg; // host copy of the target description (fields passed by value)
     const GlobalStatus *glob = nullptr;  // n_active == 0 at launch: nothing left to evaluate
+    int probes = 0;           // 1: probed diagonal z o (J z) instead of diag(J) (JM_DIAG)
+    uint64_t probe_seed = 0;
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);

@@ -155,6 +155,15 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         return PMC_ERR_UNSUPPORTED;
     }
     PMC_REQUIRE(!(o->graph_sweeps > 0 && o->trace_out), "pmc_solve: trace_out needs graph_sweeps = 0");
+    PMC_REQUIRE(o->jac_probes == 0 || o->jac_probes == 1, "pmc_solve: jac_probes is 0 or 1");
+    if (o->jac_probes) {
+        PMC_REQUIRE(o->variant == PMC_QDEER_DIAG, "pmc_solve: jac_probes needs the diagonal variant");
+        if (t.kind == PMC_TARGET_LOGREG) {
+            set_error("pmc_solve: the logistic-regression evaluation forms the exact Hessian diagonal; "
+                      "probed diagonals are not implemented for it");
+            return PMC_ERR_UNSUPPORTED;
+        }
+    }
 
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) {
         pl.scan_items = 1;
@@ -390,6 +399,8 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     ea.clip = opts->clip;
     ea.clip_inf = opts->clip_inf_norm;
     ea.jmode = pl.jmode == JM_NONE ? JM_NONE : pl.jmode;
+    ea.probes = opts->jac_probes;
+    ea.probe_seed = opts->probe_seed;
     ea.tg = pl.tg;
     ea.glob = d_glob;
     NewtonScanArgs &sa = sw.sa;

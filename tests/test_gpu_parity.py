@@ -313,6 +313,62 @@ def test_newton_chunked_scan_logreg(ctx, pm, orc):
     _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
 
 
+def test_probed_diagonal_trace_banana_fp64(ctx, pm, orc):
+    """Stochastic diagonal (Sec. 4 eq. 10, one Rademacher probe per step and
+    sweep): every sweep's iterate against the oracle's Newton reference with
+    the same counter-based signs (FP64, no sliding window)."""
+    _say("probed diagonal: banana FP64 trace")
+    ch, tg = _banana(orc, T=48, seed=6)
+    g = pm.Target(ctx, ch.target, dtype=torch.float64)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=49,
+                 want_trace=True, skip_converged_prefix=False, jac_probes=1, probe_seed=9)
+    xi, u = np.asarray(ch.xi, dtype=np.float64), np.asarray(ch.u, dtype=np.float64)
+
+    def sj(t, s):
+        F, J, _ = orc.mala_jac(tg, ch.eps, s, xi[t], u[t])
+        return F, J
+    _, ref_trace, _ = orc.newton_reference(sj, np.asarray(ch.x0, dtype=np.float64), ch.T,
+                                           variant="hutchinson", max_iter=r.sweeps, tol=-1.0, probe_seed=9)
+    tr = r.trace.cpu().numpy()
+    _say(f"  sweeps={r.sweeps} status={r.status}")
+    assert r.status == 0
+    for i in range(r.sweeps):
+        assert np.max(np.abs(tr[i] - ref_trace[i + 1])) <= 1e-11, i
+
+
+@pytest.mark.parametrize("case", ["banana_f64", "gaussian_f32"])
+def test_probed_diagonal_converges_to_sequential(ctx, pm, orc, case):
+    """The probed diagonal changes the sweeps, not the fixed point."""
+    _say(f"probed diagonal: {case}")
+    if case == "banana_f64":
+        ch, tg = _banana(orc, T=1024, seed=8)
+        g = pm.Target(ctx, ch.target, dtype=torch.float64)
+        r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=ch.T + 1,
+                     jac_probes=1, probe_seed=4)
+        ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, ch.u)
+        tol = 1e-10
+    else:
+        ch = W.gaussian_chain(4096, seed=9, eps=0.1, dim=8, dtype=np.float32, lam_lo=0.3)
+        tg = oracle_target(ch.target)
+        g = pm.Target(ctx, ch.target)
+        r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), None, sampler="ula", variant="diag",
+                     max_iter=400, jac_probes=1, probe_seed=4)
+        ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0.astype(np.float64), ch.xi, None, ula=True)
+        tol = 1e-5
+    err = state_error(r.states.cpu().numpy(), ref)
+    _say(f"  sweeps={r.sweeps} status={r.status} state_error={err:.3e}")
+    assert r.status == 0
+    assert err <= tol
+
+
+def test_probed_diagonal_logreg_is_refused(ctx, pm):
+    from paper_2508_18413_amd._binding import PMCError
+    ch = W.logreg_chain(T=256, seed=1, eps=0.002, n_data=50, dim=4)
+    g = pm.Target(ctx, ch.target)
+    with pytest.raises(PMCError, match="probed diagonals"):
+        pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", jac_probes=1)
+
+
 def _logreg_case(orc, T, eps, seed=0):
     ch = W.logreg_chain(T=T, seed=seed, eps=eps)
     tg = oracle_target(ch.target)
