@@ -368,7 +368,8 @@ def other_workload(args, pm, W, np, torch):
         for name, kw in [("diag", dict(variant="diag")), ("dense_clip_inf", dict(variant="dense", clip=1.0,
                                                                                   clip_inf_norm=True)),
                          ("dense", dict(variant="dense")), ("picard", dict(variant="picard")),
-                         ("diag_graph8", dict(variant="diag", graph_sweeps=8))]:
+                         ("diag_graph8", dict(variant="diag", graph_sweeps=8)),
+                         ("diag_probed", dict(variant="diag", jac_probes=1, probe_seed=1))]:
             r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=1025, **kw), reps, torch, name)
             res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status,
                          "chain_steps_per_s": 1024 / tp, "vs_sequential": ts / tp,
@@ -395,7 +396,8 @@ def other_workload(args, pm, W, np, torch):
         rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, ch.eps, x0, xi, u), reps, torch, "sequential")
         res["sequential_ms"] = 1e3 * ts
         for name, kw in [("diag", dict(variant="diag")), ("dense_f32", dict(variant="dense", jac_prec="f32")),
-                         ("dense_bf16", dict(variant="dense", jac_prec="bf16"))]:
+                         ("dense_bf16", dict(variant="dense", jac_prec="bf16")),
+                         ("diag_probed", dict(variant="diag", jac_probes=1, probe_seed=1))]:
             r, tp = _timed(lambda: pm.solve(ctx, g, ch.eps, x0, xi, u, max_iter=16385, **kw), reps, torch,
                            name)
             res[name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status, "n_floor": r.n_floor,
