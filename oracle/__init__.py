@@ -14,6 +14,8 @@ Contents
   estimated from one Rademacher probe per step and sweep (Sec. 4 eq. 10),
   solved by a plain sequential loop;
 * ``probe_sign`` / ``splitmix64``: the counter-based signs of that probe;
+* ``damp_and_clip``: the damped, entrywise- or norm-clipped Jacobian of full
+  DEER;
 * ``bidiagonal_bruteforce``: the Newton linear system written as one block
   lower-bidiagonal matrix and solved by LAPACK (numpy.linalg.solve).
 
@@ -350,6 +352,21 @@ def hutchinson_diag(J, z):
     J = np.asarray(J, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
     return z * (J @ z)
+
+
+def damp_and_clip(J, damping=1.0, clip=0.0, inf_norm=False):
+    """The damped and clipped Jacobian that full DEER is run with (the paper
+    damps full DEER, Sec. 2 and App. A; the two clip forms are this
+    project's reading): kappa J, then either every entry clamped to
+    [-clip, clip], or the whole matrix scaled by clip / ||kappa J||_inf when
+    that row-sum norm exceeds clip.  clip <= 0 leaves kappa J."""
+    J = float(damping) * np.asarray(J, dtype=np.float64)
+    if clip <= 0:
+        return J
+    if inf_norm:
+        nrm = np.max(np.sum(np.abs(J), axis=1))
+        return J * (clip / nrm) if nrm > clip else J
+    return np.clip(J, -clip, clip)
 
 
 def _structure(J, variant, D):

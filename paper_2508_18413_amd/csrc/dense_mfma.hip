@@ -242,8 +242,9 @@ struct MapIn {  // levels >= 1: B vectors [n, 32]
 // ---------------------------------------------------------------- up pass
 template <class Frag, class Chain, class In>
 __global__ void __launch_bounds__(64 * kWPB)
-k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout)
+k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout, const GlobalStatus *glob)
 {
+    if (glob && glob->n_active == 0) return;  // Newton: the chain has stopped
     __shared__ float s_t[kWPB][32 * 33];
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
@@ -279,8 +280,10 @@ k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout)
 // ------------------------------------------------------------- down pass
 // Level >= 1: carries of the children.  carry_in == nullptr means zero.
 __global__ void __launch_bounds__(64 * kWPB)
-k_down_maps(const float4 *P, const float *B, int64_t n, int unit, const float *carry_in, float *carry_out)
+k_down_maps(const float4 *P, const float *B, int64_t n, int unit, const float *carry_in, float *carry_out,
+            const GlobalStatus *glob)
 {
+    if (glob && glob->n_active == 0) return;
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
@@ -312,8 +315,13 @@ struct PartW {
 template <class Frag>
 __global__ void __launch_bounds__(64 * kWPB)
 k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int64_t n,
-               const float *carry_in, TilePartial *partials, double atol, double rtol, float *trace)
+               const float *carry_in, TilePartial *partials, double atol, double rtol, float *trace,
+               const GlobalStatus *glob)
 {
+    // Once the status fold has stopped the chain, the sweeps still queued
+    // behind it must leave S alone: F and J are no longer refreshed, and
+    // re-applying S <- F + J delta with them need not stay bounded.
+    if (glob && glob->n_active == 0) return;
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
@@ -456,7 +464,7 @@ size_t dense_mfma_ws_bytes(int64_t n)
 // returns the carries for the level-0 units (nullptr if T <= 32).
 template <class Frag, class Chain, class In>
 static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0, int64_t n, char *ws,
-                                  const float **carry0)
+                                  const float **carry0, const GlobalStatus *glob = nullptr)
 {
     struct Lv {
         int64_t n;      // elements of this level (maps of the level below)
@@ -488,19 +496,19 @@ static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0
     }
     // up
     hipLaunchKernelGGL((k_up<Frag, Chain, In>), dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream, J,
-                       in0, n, kU, lv[0].P, lv[0].B);
+                       in0, n, kU, lv[0].P, lv[0].B, glob);
     for (size_t k = 1; k < lv.size(); k++)
         hipLaunchKernelGGL((k_up<FragF, ChainF, MapIn>), dim3(blocks_for(lv[k - 1].n, kU1)), dim3(64 * kWPB),
                            0, ctx->stream, (const void *)lv[k - 1].P, MapIn{lv[k - 1].B}, lv[k - 1].n, kU1,
-                           lv[k].P, lv[k].B);
+                           lv[k].P, lv[k].B, glob);
     // top: the last level's maps (<= kU1) from a zero carry
     const Lv &top = lv.back();
     hipLaunchKernelGGL(k_down_maps, dim3(1), dim3(64 * kWPB), 0, ctx->stream, (const float4 *)top.P,
-                       (const float *)top.B, top.n, kU1, (const float *)nullptr, top.carry);
+                       (const float *)top.B, top.n, kU1, (const float *)nullptr, top.carry, glob);
     for (int k = (int)lv.size() - 2; k >= 0; k--)
         hipLaunchKernelGGL(k_down_maps, dim3(blocks_for(lv[k].n, kU1)), dim3(64 * kWPB), 0, ctx->stream,
                            (const float4 *)lv[k].P, (const float *)lv[k].B, lv[k].n, kU1,
-                           (const float *)lv[k + 1].carry, lv[k].carry);
+                           (const float *)lv[k + 1].carry, lv[k].carry, glob);
     PMC_TRY_HIP(hipGetLastError());
     *carry0 = lv[0].carry;
     return PMC_OK;
@@ -508,18 +516,18 @@ static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0
 
 pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
                                     float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
-                                    double atol, double rtol, float *trace, void *ws)
+                                    double atol, double rtol, float *trace, void *ws, const GlobalStatus *glob)
 {
     const float *c0 = nullptr;
     Lvl0In in{F, S, ld, D};
     if (bf16) {
-        PMC_TRY((dense_hierarchy<FragB, ChainB, Lvl0In>(ctx, J, in, n, (char *)ws, &c0)));
+        PMC_TRY((dense_hierarchy<FragB, ChainB, Lvl0In>(ctx, J, in, n, (char *)ws, &c0, glob)));
         hipLaunchKernelGGL(k_down0_newton<FragB>, dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream,
-                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace);
+                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob);
     } else {
-        PMC_TRY((dense_hierarchy<FragF, ChainF, Lvl0In>(ctx, J, in, n, (char *)ws, &c0)));
+        PMC_TRY((dense_hierarchy<FragF, ChainF, Lvl0In>(ctx, J, in, n, (char *)ws, &c0, glob)));
         hipLaunchKernelGGL(k_down0_newton<FragF>, dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream,
-                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace);
+                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob);
     }
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;

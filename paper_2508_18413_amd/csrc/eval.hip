@@ -279,10 +279,8 @@ pmc_status launch_eval(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
             set_error("logistic regression runs in F32");
             return PMC_ERR_UNSUPPORTED;
         }
-        if (a.jmode != JM_DIAG && a.jmode != JM_NONE) {
-            set_error("logistic regression eval: dense Jacobians use the dense logreg kernel");
-            return PMC_ERR_UNSUPPORTED;
-        }
+        // dense modes: the kernel writes f_t and the decisions only; the
+        // Jacobians come from launch_logreg_dense_jac
         if (a.gate == PMC_GATE_SURROGATE && !a.ula) {
             set_error("logistic regression eval supports the frozen gate only");
             return PMC_ERR_UNSUPPORTED;

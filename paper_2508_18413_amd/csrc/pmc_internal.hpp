@@ -136,6 +136,10 @@ struct DevTarget {
     void *xl = nullptr;    // LDS image of X and y (small data sets)
     void *xh = nullptr;    // split-FP16 LDS image of X, with y and X^T y
     int products = 0;      // pmc_products
+    // full-DEER operand tables (built on the first dense solve): X and the
+    // pair products x_d x_e in BF16 matrix-core order
+    void *dxa = nullptr, *dpb = nullptr;
+    int dnb = 0, dnpt = 0, dgrp = 0;
 };
 
 }  // namespace pmc
@@ -266,6 +270,13 @@ struct EvalArgs {
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
 pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
+// Full-DEER Jacobians on the logistic posterior: operand tables (once per
+// target), then per sweep the pair sums H [n, 32 dnpt] and the dense J image
+// (BF16 or FP32) from the evaluation's accept decisions.
+pmc_status logreg_dense_tables(pmc_context *ctx, DevTarget &t);
+int logreg_dense_pair_cols(int D);  // row stride of H (D <= 32)
+pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n, float *H,
+                                   bool f32);
 // Tile length the eval kernel for this target expects.
 int eval_tile_steps(const DevTarget &tg);
 
@@ -290,7 +301,8 @@ size_t dense_mfma_ws_bytes(int64_t n);
 int dense_mfma_unit();
 pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
                                     float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
-                                    double atol, double rtol, float *trace, void *ws);
+                                    double atol, double rtol, float *trace, void *ws,
+                                    const GlobalStatus *glob);  // n_active == 0 at launch: no-op
 pmc_status launch_linrec_dense_mfma(pmc_context *ctx, int bf16, int D, int64_t T, const float *A,
                                     const float *b, float *out);
 // Same on J already in the fragment layout; ws: dense_mfma_ws_bytes(T) bytes.

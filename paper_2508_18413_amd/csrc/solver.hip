@@ -44,6 +44,8 @@ struct Plan {
     size_t o_S, o_F, o_J, o_hier, o_acc, o_gt, o_etiles, o_stiles, o_ctb, o_offs, o_part, o_chains,
         o_global, total;
     int max_iter;
+    bool logreg_dense = false;  // dense J of the logistic posterior (pair sums in o_hpair)
+    size_t o_hpair = 0;
 };
 
 void build_tiles(const std::vector<int64_t> &offs, int C, std::vector<SegTile> &tiles,
@@ -118,11 +120,21 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     case PMC_QDEER_DIAG: pl.jmode = JM_DIAG; break;
     case PMC_PICARD: pl.jmode = JM_NONE; break;
     case PMC_DEER_DENSE:
-        if (t.kind == PMC_TARGET_LOGREG) {
-            set_error("pmc_solve: dense DEER on logistic regression is not implemented");
-            return PMC_ERR_UNSUPPORTED;
-        }
         pl.n_lanes = 1;
+        if (t.kind == PMC_TARGET_LOGREG) {
+            // Jacobians from the pair-sum kernels, composed by the matrix-core scan
+            if (pl.D > 32) {
+                set_error("pmc_solve: dense DEER on logistic regression supports D <= 32 (got %d)", pl.D);
+                return PMC_ERR_UNSUPPORTED;
+            }
+            if (p->n_chains != 1) {
+                set_error("pmc_solve: matrix-core dense DEER solves one chain per call");
+                return PMC_ERR_UNSUPPORTED;
+            }
+            pl.jmode = o->jac_prec == PMC_JAC_BF16 ? JM_DENSE_BF16 : JM_DENSE_F32;
+            pl.logreg_dense = true;
+            break;
+        }
         if (pl.dt == PMC_F64 || (pl.D <= 4 && o->jac_prec == PMC_JAC_F32)) {
             if (pl.D > 4) {
                 set_error("pmc_solve: FP64 dense DEER supports D <= 4 (got %d)", pl.D);
@@ -217,6 +229,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     pl.o_J = take(std::max<size_t>(jb, 256));
     pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? dense_mfma_ws_bytes(pl.n)
                                                                          : 256);
+    if (pl.logreg_dense) pl.o_hpair = take(sizeof(float) * (size_t)pl.n * logreg_dense_pair_cols(pl.D));
     pl.o_acc = take(std::max<int64_t>(pl.n, 1));
     pl.o_gt = take(4 * std::max<int64_t>(pl.n, 1));
     pl.o_etiles = take(sizeof(SegTile) * std::max<size_t>(pl.etiles.size(), 1));
@@ -235,6 +248,7 @@ struct Sweep {
     NewtonScanArgs sa;
     StatusArgs st;
     void *hier;  // matrix-core scan hierarchy workspace
+    float *hpair = nullptr;  // pair sums of the logistic Hessian (dense DEER)
 };
 
 // One Newton sweep: evaluation, scan, status fold.  ev (optional) receives
@@ -243,11 +257,13 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
 {
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[0], ctx->stream));
     PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
+    if (pl.logreg_dense)
+        PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, sw.hpair, pl.jmode == JM_DENSE_F32));
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[1], ctx->stream));
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
                                          (float *)sw.sa.S, sw.sa.ld, pl.D, pl.n, sw.sa.partials,
-                                         sw.sa.atol, sw.sa.rtol, nullptr, sw.hier));
+                                         sw.sa.atol, sw.sa.rtol, nullptr, sw.hier, sw.ea.glob));
     else if (pl.jmode == JM_DENSE_ROW)
         PMC_TRY(launch_newton_scan_dense_small(ctx, pl.dt, pl.D, sw.sa));
     else
@@ -377,6 +393,11 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
 
     Sweep sw;
     sw.hier = ws + pl.o_hier;
+    if (pl.logreg_dense) {
+        // operand tables: derived data of the target, built by its first dense solve
+        PMC_TRY(logreg_dense_tables(ctx, const_cast<DevTarget &>(*pl.tg)));
+        sw.hpair = (float *)(ws + pl.o_hpair);
+    }
     EvalArgs &ea = sw.ea;
     ea.tiles = d_et;
     ea.n_tiles = (int)pl.etiles.size();

@@ -736,3 +736,57 @@ def test_batched_full_size_sampled(ctx, pm, orc):
     for c in pick:
         o0, o1 = int(b.offsets[c]), int(b.offsets[c + 1])
         _check_mala(orc, tg, _as_chain(b, c), s0[c], st[o0:o1].cpu().numpy(), acc[o0:o1].cpu().numpy())
+
+
+@pytest.mark.parametrize("clip", [False, True])
+@pytest.mark.parametrize("jac", ["bf16", "f32"])
+def test_logreg_dense_jacobian_one_sweep(ctx, pm, orc, jac, clip):
+    """Full-DEER Jacobians of the logistic posterior (pair-sum kernels): one
+    ULA sweep (no accept decisions) from a perturbed guess against the
+    oracle's FP64 sweep with the exact, damped and clipped Jacobians.  The
+    Jacobian's part of the update, S1 - F, is matched to 2 % (BF16 operands);
+    the sweep with the diagonal alone misses it by far more, so the
+    off-diagonal entries are checked too."""
+    _say(f"logreg dense J one sweep jac={jac} clip={clip}")
+    T = 1024
+    ch = W.logreg_chain(T=T, seed=3, eps=0.0015)
+    tg = oracle_target(ch.target)
+    x0 = ch.x0.astype(np.float64)
+    xi = ch.xi.astype(np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, xi, None, ula=True)
+    guess = (ref + 0.05 * np.random.default_rng(7).standard_normal(ref.shape)).astype(np.float32)
+    g64 = guess.astype(np.float64)
+    g = pm.Target(ctx, ch.target)
+    kw = dict(clip=1.0, clip_inf_norm=True) if clip else {}
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), None, sampler="ula", variant="dense", jac_prec=jac,
+                 init_guess=_t(guess), max_iter=1, want_trace=True, **kw)
+    got = r.trace[0].cpu().numpy().astype(np.float64)
+
+    def sj(t, s):
+        F, J, _ = orc.mala_jac(tg, ch.eps, s, xi[t], 0.5, ula=True)
+        return F, orc.damp_and_clip(J, 1.0, clip=1.0 if clip else 0.0, inf_norm=clip)
+    want, _, _ = orc.newton_reference(sj, x0, T, variant="dense", init=g64, max_iter=1, full_trace=False)
+    diag, _, _ = orc.newton_reference(sj, x0, T, variant="diag", init=g64, max_iter=1, full_trace=False)
+    F = np.array([sj(t, x0 if t == 0 else g64[t - 1])[0] for t in range(T)])
+    jterm = np.max(np.abs(want - F))
+    err = np.max(np.abs(got - want))
+    miss = np.max(np.abs(diag - want))
+    _say(f"  |J part| {jterm:.3e}  gpu error {err:.3e}  diagonal-only miss {miss:.3e}")
+    assert jterm > 1e-2
+    assert err <= 0.02 * jterm
+    assert miss >= 5 * err
+
+
+@pytest.mark.parametrize("jac", ["bf16", "f32"])
+def test_logreg_dense_deer_mala(ctx, pm, orc, jac):
+    """Full DEER with the infinity-norm clip on the logistic posterior (MALA,
+    frozen gate) converges to the FP64 sequential chain."""
+    _say(f"logreg dense DEER mala jac={jac}")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="dense", jac_prec=jac, clip=1.0,
+                 clip_inf_norm=True, max_iter=ch.T + 1)
+    rd = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=ch.T + 1)
+    _say(f"  dense sweeps={r.sweeps} (diag {rd.sweeps}) status={r.status} floor={r.n_floor}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())

@@ -182,3 +182,44 @@ def test_hutchinson_newton_fixed_point(orc):
     S, _, it = orc.newton_reference(_mala_provider(orc, tg, ch), x0, ch.T, variant="hutchinson",
                                     tol=1e-13, probe_seed=3)
     np.testing.assert_allclose(S, ref, rtol=0, atol=1e-12)
+
+
+def test_damp_and_clip_forms(orc):
+    """The two clip forms against their definitions, entry by entry and by
+    the row-sum norm, on matrices above and below the clip level."""
+    rng = np.random.default_rng(5)
+    for scale in (0.1, 3.0):
+        J = scale * rng.standard_normal((6, 6))
+        kJ = 0.8 * J
+        np.testing.assert_array_equal(orc.damp_and_clip(J, 0.8), kJ)
+        E = orc.damp_and_clip(J, 0.8, clip=0.5)
+        for i in range(6):
+            for k in range(6):
+                assert E[i, k] == (0.5 if kJ[i, k] > 0.5 else -0.5 if kJ[i, k] < -0.5 else kJ[i, k])
+        N = orc.damp_and_clip(J, 0.8, clip=1.5, inf_norm=True)
+        rows = [sum(abs(kJ[i, k]) for k in range(6)) for i in range(6)]
+        want = min(max(rows), 1.5)
+        assert abs(np.max(np.sum(np.abs(N), axis=1)) - want) <= 1e-12 * want
+        # a positive multiple of J: the direction of every row is kept
+        ratio = N[np.abs(J) > 0] / J[np.abs(J) > 0]
+        assert np.all(ratio > 0) and np.ptp(ratio) <= 1e-12 * np.max(ratio)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_clipped_dense_newton_is_causally_exact(orc, case):
+    """Any Jacobian keeps the exact front: after sweep i the first i steps
+    equal the sequential chain, so the norm-clipped dense iteration of full
+    DEER reaches the trace in at most T sweeps."""
+    ch = CASES[case]()
+    tg = oracle_target(ch.target)
+    x0 = np.asarray(ch.x0, dtype=np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u)
+    sj0 = _mala_provider(orc, tg, ch)
+
+    def sj(t, s):
+        F, J = sj0(t, s)
+        return F, orc.damp_and_clip(J, 1.0, clip=0.5, inf_norm=True)
+    S, trace, it = orc.newton_reference(sj, x0, ch.T, variant="dense", max_iter=ch.T, tol=-1.0)
+    for i, Si in enumerate(trace):
+        np.testing.assert_array_equal(Si[:i], ref[:i])
+    np.testing.assert_array_equal(S, ref)
