@@ -137,6 +137,29 @@ def main():
                         "max_abs_minus_split16": (r32[-1].states - r.states).abs().max().item()}
         del tg32
 
+    # full DEER on the same chain: D x D Jacobians from the pair-sum kernels
+    # (BF16 matrix-core products), infinity-norm clip 1, composed by the
+    # matrix-core dense scan; per-sweep times from one solve with kernel events
+    # (the "eval" events bracket the evaluation, the pair sums and the
+    # Jacobian image; the "scan" events the dense scan)
+    dk = dict(variant="dense", jac_prec="bf16", clip=1.0, clip_inf_norm=True, max_iter=T + 1, atol=TOL, rtol=TOL)
+    pm.solve(ctx, tg, eps, s0, xi, u, **dk)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    rdn = [pm.solve(ctx, tg, eps, s0, xi, u, **dk) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    walld = (time.perf_counter() - t4) / args.steps
+    pdn = pm.solve(ctx, tg, eps, s0, xi, u, **dict(dk, profile_kernels=True))
+    dense_deer = {"value": T / walld, "unit": "chain-steps/s", "ms_per_step": 1e3 * walld,
+                  "speedup_vs_sequential": (T / walld) / seq_value, "newton_iters": rdn[-1].sweeps,
+                  "status": rdn[-1].status, "jac_prec": "bf16", "clip_inf_norm": 1.0,
+                  "eval_and_jacobian_ms_per_sweep": pdn.eval_ms / pdn.sweeps,
+                  "dense_scan_ms_per_sweep": pdn.scan_ms / pdn.sweeps,
+                  "max_abs_minus_quasi_deer": (rdn[-1].states - r.states).abs().max().item(),
+                  "max_abs_parallel_minus_sequential": (rdn[-1].states - rs.states).abs().max().item()}
+    del rdn, pdn
+    torch.cuda.empty_cache()
+
     # roofline of the dominant kernel (the evaluation kernel), live HIP events
     N, D = ch.target["X"].shape
     flops_per_step = 10.0 * N * D  # grad at x and x~ (4ND each) + Hessian diagonal (2ND)
@@ -173,6 +196,7 @@ def main():
         "speedup_vs_sequential": value / seq_value,
         "max_abs_parallel_minus_sequential": par_vs_seq,
         "f32_products": f32_products,
+        "dense_deer": dense_deer,
         "acceptance": r.n_accept / T,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,

@@ -40,26 +40,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kDenseWaves = 4;  // 32-step tiles per workgroup
-constexpr int kMaxGroup = 12;   // pair tiles accumulated per pass over the data
+// pair tiles accumulated per pass over the data: each pass recomputes M^T
+// and w, but 3 tiles (about 125 registers) leave room for 4 wavefronts per
+// SIMD to hide the operand loads, which is faster than 4 tiles (3 per SIMD),
+// 6 (2) or all 11 of D = 25 in one pass (1)
+constexpr int kMaxGroup = 3;
 
 __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
+// eight FP32 values to BF16, round to nearest even (v_cvt_pk_bf16_f32)
 __device__ __forceinline__ bf16x8 pack8(const float *v)
 {
-    uint4 q;
-    q.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-    q.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-    q.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
-    q.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
-    return __builtin_bit_cast(bf16x8, q);
+    const f32x8 x = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+    return __builtin_convertvector(x, bf16x8);
 }
 
 // pair index of (d, e), d <= e, in the row-major upper triangle of a D x D matrix
@@ -147,29 +142,53 @@ __global__ void __launch_bounds__(64 * kDenseWaves) k_logreg_dense_h(DenseHArgs 
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[g][r] = 0.f;
 
+    // the next data tile's fragments are requested before this one is
+    // multiplied (the last tile reloads itself, so every load is
+    // unconditional); the compiler may still move them, and the occupancy
+    // above is what hides their latency
+    const size_t pstep = 2 * (size_t)a.npt * 64;
+    const uint4 *xa = a.xa + lane;
+    const uint4 *pb = a.pb + (size_t)pt0 * 64 + lane;
+    uint4 nx[2], np[2 * G];
+    nx[0] = xa[0];
+    nx[1] = xa[64];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        np[g] = pb[g * 64];
+        np[G + g] = pb[(a.npt + g) * 64];
+    }
     for (int nb = 0; nb < a.nb_count; nb++) {
-        const uint4 *xa = a.xa + (size_t)nb * 128 + lane;
+        uint4 cx[2] = {nx[0], nx[1]}, cp[2 * G];
+#pragma unroll
+        for (int k = 0; k < 2 * G; k++) cp[k] = np[k];
+        const int nn = nb + 1 < a.nb_count ? nb + 1 : nb;
+        nx[0] = xa[(size_t)nn * 128];
+        nx[1] = xa[(size_t)nn * 128 + 64];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            np[g] = pb[nn * pstep + g * 64];
+            np[G + g] = pb[nn * pstep + (a.npt + g) * 64];
+        }
         f32x16 m;
 #pragma unroll
         for (int r = 0; r < 16; r++) m[r] = 0.f;
-        m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xa[0]), sb[0], m, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xa[64]), sb[1], m, 0, 0, 0);
-        // w = sigma (1 - sigma) = e / (1 + e)^2 with e = exp(-|m|)
+        m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, cx[0]), sb[0], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, cx[1]), sb[1], m, 0, 0, 0);
+        // w = sigma (1 - sigma) = e / (1 + e)^2 with e = exp(-|m|); the
+        // hardware reciprocal is ample for a Jacobian rounded to BF16
         float w[16];
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const float e = __expf(-fabsf(m[r]));
             const float s = 1.f + e;
-            w[r] = e / (s * s);
+            w[r] = e * __builtin_amdgcn_rcpf(s * s);
         }
         const bf16x8 w0 = pack8(w), w1 = pack8(w + 8);
-        const uint4 *pb = a.pb + ((size_t)nb * 2 * a.npt + pt0) * 64 + lane;
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, __builtin_bit_cast(bf16x8, pb[g * 64]), acc[g], 0,
-                                                            0, 0);
-            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                w1, __builtin_bit_cast(bf16x8, pb[(a.npt + g) * 64]), acc[g], 0, 0, 0);
+            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, __builtin_bit_cast(bf16x8, cp[g]), acc[g], 0, 0, 0);
+            acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, __builtin_bit_cast(bf16x8, cp[G + g]), acc[g], 0, 0,
+                                                            0);
         }
     }
 
@@ -247,11 +266,12 @@ __global__ void __launch_bounds__(256) k_logreg_dense_j(DenseJArgs a)
     }
 }
 
-// pair tiles accumulated per pass: all of them up to kMaxGroup, else half
+// pair tiles accumulated per pass: the fewest passes of at most kMaxGroup
+// tiles, split evenly
 int pair_group(int D)
 {
-    const int npt0 = (D * (D + 1) / 2 + 31) / 32;
-    return npt0 <= kMaxGroup ? npt0 : (npt0 + 1) / 2;
+    const int npt0 = (D * (D + 1) / 2 + 31) / 32, passes = (npt0 + kMaxGroup - 1) / kMaxGroup;
+    return (npt0 + passes - 1) / passes;
 }
 
 }  // namespace
@@ -316,15 +336,6 @@ pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const E
         PMC_DENSE_H_CASE(1)
         PMC_DENSE_H_CASE(2)
         PMC_DENSE_H_CASE(3)
-        PMC_DENSE_H_CASE(4)
-        PMC_DENSE_H_CASE(5)
-        PMC_DENSE_H_CASE(6)
-        PMC_DENSE_H_CASE(7)
-        PMC_DENSE_H_CASE(8)
-        PMC_DENSE_H_CASE(9)
-        PMC_DENSE_H_CASE(10)
-        PMC_DENSE_H_CASE(11)
-        PMC_DENSE_H_CASE(12)
 #undef PMC_DENSE_H_CASE
     default: set_error("logreg dense Jacobian: group %d", g); return PMC_ERR_UNSUPPORTED;
     }

@@ -738,18 +738,26 @@ def test_batched_full_size_sampled(ctx, pm, orc):
         _check_mala(orc, tg, _as_chain(b, c), s0[c], st[o0:o1].cpu().numpy(), acc[o0:o1].cpu().numpy())
 
 
+# (dim, n_data, eps): 11 pair tiles in 4 passes over 32 full data tiles; one
+# pair tile and a padded second data tile; 17 pair tiles (the last ragged) in
+# 6 passes over 10 data tiles (the last ragged)
+DENSE_SHAPES = {"d25n1000": (25, 1000, 0.0015), "d5n50": (5, 50, 0.02), "d32n300": (32, 300, 0.003)}
+
+
+@pytest.mark.parametrize("shape", list(DENSE_SHAPES))
 @pytest.mark.parametrize("clip", [False, True])
 @pytest.mark.parametrize("jac", ["bf16", "f32"])
-def test_logreg_dense_jacobian_one_sweep(ctx, pm, orc, jac, clip):
+def test_logreg_dense_jacobian_one_sweep(ctx, pm, orc, jac, clip, shape):
     """Full-DEER Jacobians of the logistic posterior (pair-sum kernels): one
     ULA sweep (no accept decisions) from a perturbed guess against the
     oracle's FP64 sweep with the exact, damped and clipped Jacobians.  The
     Jacobian's part of the update, S1 - F, is matched to 2 % (BF16 operands);
-    the sweep with the diagonal alone misses it by far more, so the
+    at D = 25 the sweep with the diagonal alone misses it by far more, so the
     off-diagonal entries are checked too."""
-    _say(f"logreg dense J one sweep jac={jac} clip={clip}")
+    dim, n_data, eps = DENSE_SHAPES[shape]
+    _say(f"logreg dense J one sweep jac={jac} clip={clip} D={dim} N={n_data}")
     T = 1024
-    ch = W.logreg_chain(T=T, seed=3, eps=0.0015)
+    ch = W.logreg_chain(T=T, seed=3, eps=eps, n_data=n_data, dim=dim)
     tg = oracle_target(ch.target)
     x0 = ch.x0.astype(np.float64)
     xi = ch.xi.astype(np.float64)
@@ -774,7 +782,8 @@ def test_logreg_dense_jacobian_one_sweep(ctx, pm, orc, jac, clip):
     _say(f"  |J part| {jterm:.3e}  gpu error {err:.3e}  diagonal-only miss {miss:.3e}")
     assert jterm > 1e-2
     assert err <= 0.02 * jterm
-    assert miss >= 5 * err
+    if dim == 25:
+        assert miss >= 5 * err
 
 
 @pytest.mark.parametrize("jac", ["bf16", "f32"])
