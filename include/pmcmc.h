@@ -199,7 +199,16 @@ pmc_status pmc_workspace_size(pmc_context *ctx, const pmc_problem *prob, const p
 pmc_status pmc_default_options(pmc_options *opts, pmc_dtype dtype);
 /* Solves every chain of `prob` by parallel Newton iterations.  `workspace`
  * is DEVICE memory of at least pmc_workspace_size bytes, or NULL to use the
- * context's pool.  res (HOST) may be NULL. */
+ * context's pool.  res (HOST) may be NULL.
+ * PMC_DEER_DENSE: F32 states with D <= 32 use the matrix-core scan (one chain
+ * per call; jac_prec F32 with D <= 4, or F64 states, the vector scan).  On
+ * the logistic posterior the Jacobians I + a_t eps Hess log p(s_{t-1}) are
+ * formed from BF16 matrix-core pair sums of X^T diag(w) X (Sec. 2 with the
+ * model of App. B.1); the first dense solve on a target allocates its
+ * operand tables (about 1 KiB per 32 data points and 32 variable pairs,
+ * kept until pmc_target_destroy), so concurrent first dense solves on one
+ * target are not allowed.  Undamped full DEER on that posterior takes large
+ * excursions; clip_inf_norm with clip = 1 keeps it stable. */
 pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
                      void *workspace, size_t ws_bytes, pmc_result *res);
 
