@@ -41,18 +41,6 @@ __device__ __forceinline__ R clampj(R v, double damping, double clip, int clip_i
     return v;
 }
 
-// SplitMix64 (Steele, Lea & Flood 2014): the output function applied to
-// x + 0x9E3779B97F4A7C15, modulo 2^64.  The probe sign of coordinate d at
-// global step t in a chain's sweep i is the top bit of
-// m(m(m(seed) ^ i) ^ (1024 t + d)).
-__device__ __forceinline__ uint64_t probe_mix(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 // ------------------------------------------------ per-lane eval (small D)
 template <class Tg, typename R, int JM>
 __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)

@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
     float *J = (float *)a.J;
     const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
     const float damp = (float)a.damping, clip = (float)a.clip;
-    const bool want_j = a.jmode == JM_DIAG;
+    const bool want_j = a.jmode == JM_DIAG && !a.probes;  // probes: launch_logreg_probe_diag writes J
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
     // tiles are dealt to waves round-robin (tile costs are uniform; the idle
@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
     const float *s_csc = s_xty + 32;  // c_d
     const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
     const float damp = (float)a.damping, clip = (float)a.clip;
-    const bool want_j = a.jmode == JM_DIAG;
+    const bool want_j = a.jmode == JM_DIAG && !a.probes;  // probes: launch_logreg_probe_diag writes J
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     // per-lane offsets: the Z operand row (storage order) and the G operand column
     const int zoff = h_row(i) * kHW + 8 * hh;
@@ -996,7 +996,7 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
         const float g = sg[d * 33 + j] - pp * x;
         const float xt = x + fmaf(eps, g, c * noise[(size_t)t * D + d]);
         F[(size_t)d * ld + t] = acc ? xt : x;
-        if (a.jmode == JM_DIAG) {
+        if (a.jmode == JM_DIAG && !a.probes) {
             const float hdd = -shd[d * 33 + j] - pp;
             float jv = (float)a.damping * fmaf(ea, hdd, 1.f);
             if (a.clip > 0) jv = fminf(fmaxf(jv, (float)-a.clip), (float)a.clip);

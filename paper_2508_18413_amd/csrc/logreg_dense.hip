@@ -25,6 +25,13 @@
 // per-lane evaluation does, and writes the matrix-core A-operand image the
 // dense scan reads (BF16, 2 KiB per step, or FP32, 4 KiB per step).
 //
+// k_logreg_probe_diag: quasi-DEER with the one-probe diagonal z o (J z) of
+// Sec. 4 eq. 10.  For 32 steps per wavefront, M^T = X S^T and V^T = X Z^T
+// (Z the probe signs), U = w o V in the accumulator, then X^T U, whose
+// B operand is again the accumulator (the table xt orders X^T's K slots the
+// same way), gives (X^T W X z)_d; the diagonal planes receive
+// damping (1 + a_t eps z_d (H z)_d) with H z = -X^T W X z - z / prior_var.
+//
 // Register layouts (lane l, i = l % 32, h = l / 32), as in the dense scan:
 //   A operand (32 x 16): A[i][8 h + j], j = 0..7;
 //   B operand (16 x 32): B[8 h + j][i];
@@ -63,16 +70,26 @@ __host__ __device__ __forceinline__ int pair_index(int d, int e, int D) { return
 // Operand tables, one thread per 8-value fragment:
 //   xa[nb][kd][l] = X[32 nb + i][16 kd + 8 h + j]                   (A of M^T)
 //   pb[nb][q][pt][l] slot j = P[32 nb + 16 q + 8 (j / 4) + 4 h + j % 4][32 pt + i]
-// zero outside the data and the pairs.
+//   xt[nb][q][l]  slot j = X[32 nb + 16 q + 8 (j / 4) + 4 h + j % 4][i]  (A of X^T U)
+// zero outside the data, the coordinates and the pairs.
 __global__ void k_logreg_dense_tables(const float *X, int ldx, int N, int D, int nb_count, int npt,
-                                      uint4 *xa, uint4 *pb)
+                                      uint4 *xa, uint4 *pb, uint4 *xt)
 {
     const int64_t n_xa = (int64_t)nb_count * 2 * 64, n_pb = (int64_t)nb_count * 2 * npt * 64;
     const int np = D * (D + 1) / 2;
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n_xa + n_pb;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < 2 * n_xa + n_pb;
          id += (int64_t)gridDim.x * blockDim.x) {
         float v[8];
-        if (id < n_xa) {
+        if (id >= n_xa + n_pb) {
+            const int64_t k = id - n_xa - n_pb;
+            const int l = (int)(k % 64), q = (int)((k / 64) % 2), nb = (int)(k / 128);
+            const int d = l & 31, h = l >> 5;
+            for (int j = 0; j < 8; j++) {
+                const int n = 32 * nb + 16 * q + 8 * (j >> 2) + 4 * h + (j & 3);
+                v[j] = (n < N && d < D) ? X[(size_t)n * ldx + d] : 0.f;
+            }
+            xt[k] = __builtin_bit_cast(uint4, pack8(v));
+        } else if (id < n_xa) {
             const int l = (int)(id % 64), kd = (int)((id / 64) % 2), nb = (int)(id / 128);
             const int n = 32 * nb + (l & 31), h = l >> 5;
             for (int j = 0; j < 8; j++) {
@@ -266,6 +283,91 @@ __global__ void __launch_bounds__(256) k_logreg_dense_j(DenseJArgs a)
     }
 }
 
+struct ProbeArgs {
+    const uint4 *xa, *xt;
+    int nb_count;
+    const float *S, *s0;  // [D, ld], [D]
+    int64_t ld, n;
+    int D;
+    const uint8_t *accept;
+    float eps, pp, damping, clip;
+    const ChainStatus *chain;  // its sweep counter selects the probe
+    uint64_t seed;
+    float *J;                  // [D, ld]
+    const GlobalStatus *glob;
+};
+
+__device__ __forceinline__ float probe_sign(uint64_t hs, int64_t t, int d)
+{
+    return (probe_mix(hs ^ (uint64_t)(1024 * t + d)) >> 63) ? -1.f : 1.f;
+}
+
+__global__ void __launch_bounds__(64 * kDenseWaves) k_logreg_probe_diag(ProbeArgs a)
+{
+    const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+    const int64_t t0 = ((int64_t)blockIdx.x * kDenseWaves + (threadIdx.x >> 6)) * 32;
+    if (t0 >= a.n) return;  // uniform per wavefront
+    if (a.glob && a.glob->n_active == 0) return;
+    const int64_t t = t0 + i;
+    const bool live = t < a.n;
+    const uint64_t hs = probe_mix(probe_mix(a.seed) ^ (uint64_t)(uint32_t)a.chain->sweeps);
+
+    // B operands: s_{t-1} and the probe z_t, coordinates 16 kd + 8 h + j
+    bf16x8 sb[2], zb[2];
+#pragma unroll
+    for (int kd = 0; kd < 2; kd++) {
+        float v[8], z[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int d = 16 * kd + 8 * h + j;
+            const bool in = live && d < a.D;
+            v[j] = in ? (t == 0 ? a.s0[d] : a.S[(size_t)d * a.ld + t - 1]) : 0.f;
+            z[j] = in ? probe_sign(hs, t, d) : 0.f;
+        }
+        sb[kd] = pack8(v);
+        zb[kd] = pack8(z);
+    }
+    f32x16 P;
+#pragma unroll
+    for (int r = 0; r < 16; r++) P[r] = 0.f;
+    for (int nb = 0; nb < a.nb_count; nb++) {
+        const bf16x8 x0 = __builtin_bit_cast(bf16x8, a.xa[(size_t)nb * 128 + lane]);
+        const bf16x8 x1 = __builtin_bit_cast(bf16x8, a.xa[(size_t)nb * 128 + 64 + lane]);
+        f32x16 m, v;
+#pragma unroll
+        for (int r = 0; r < 16; r++) m[r] = v[r] = 0.f;
+        m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, sb[0], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, sb[1], m, 0, 0, 0);
+        v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, zb[0], v, 0, 0, 0);
+        v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, zb[1], v, 0, 0, 0);
+        float u[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const float e = __expf(-fabsf(m[r]));
+            const float s = 1.f + e;
+            u[r] = e * __builtin_amdgcn_rcpf(s * s) * v[r];
+        }
+        P = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a.xt[(size_t)nb * 128 + lane]),
+                                                    pack8(u), P, 0, 0, 0);
+        P = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a.xt[(size_t)nb * 128 + 64 + lane]),
+                                                    pack8(u + 8), P, 0, 0, 0);
+    }
+    // register r: (X^T W X z)_d for d = 8 (r / 4) + 4 h + r % 4 at step t
+    if (!live) return;
+    const float ea = a.accept[t] ? a.eps : 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int d = crow(r, h);
+        if (d < a.D) {
+            const float z = probe_sign(hs, t, d);
+            const float hz = -P[r] - a.pp * z;
+            float jv = a.damping * fmaf(ea, z * hz, 1.f);
+            if (a.clip > 0.f) jv = fminf(fmaxf(jv, -a.clip), a.clip);
+            a.J[(size_t)d * a.ld + t] = jv;
+        }
+    }
+}
+
 // pair tiles accumulated per pass: the fewest passes of at most kMaxGroup
 // tiles, split evenly
 int pair_group(int D)
@@ -287,31 +389,34 @@ pmc_status logreg_dense_tables(pmc_context *ctx, DevTarget &t)
 {
     if (t.dxa) return PMC_OK;
     if (t.dim > 32) {
-        set_error("dense DEER on logistic regression supports D <= 32 (got %d)", t.dim);
+        set_error("matrix-core Jacobians of logistic regression support D <= 32 (got %d)", t.dim);
         return PMC_ERR_UNSUPPORTED;
     }
     const int grp = pair_group(t.dim), nbc = (t.n_data + 31) / 32, npt = logreg_dense_pair_cols(t.dim) / 32;
     const size_t bxa = (size_t)nbc * 2 * 64 * 16, bpb = (size_t)nbc * 2 * npt * 64 * 16;
-    void *xa = nullptr, *pb = nullptr;
+    void *xa = nullptr, *pb = nullptr, *xt = nullptr;
     PMC_TRY_HIP(hipMalloc(&xa, bxa));
-    if (hipMalloc(&pb, bpb) != hipSuccess) {
+    if (hipMalloc(&pb, bpb) != hipSuccess || hipMalloc(&xt, bxa) != hipSuccess) {
         (void)hipFree(xa);
-        set_error("dense DEER tables: out of device memory (%zu bytes)", bxa + bpb);
+        if (pb) (void)hipFree(pb);
+        set_error("dense DEER tables: out of device memory (%zu bytes)", 2 * bxa + bpb);
         return PMC_ERR_OOM;
     }
-    const int64_t work = (int64_t)(bxa + bpb) / 16;
+    const int64_t work = (int64_t)(2 * bxa + bpb) / 16;
     const int blocks = (int)std::min<int64_t>((work + 255) / 256, 4096);
     hipLaunchKernelGGL(k_logreg_dense_tables, dim3(blocks), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
-                       t.n_data, t.dim, nbc, npt, (uint4 *)xa, (uint4 *)pb);
+                       t.n_data, t.dim, nbc, npt, (uint4 *)xa, (uint4 *)pb, (uint4 *)xt);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         (void)hipFree(xa);
         (void)hipFree(pb);
+        (void)hipFree(xt);
         set_error("dense DEER tables: %s", hipGetErrorString(e));
         return PMC_ERR_HIP;
     }
     t.dxa = xa;
     t.dpb = pb;
+    t.dxt = xt;
     t.dnb = nbc;
     t.dnpt = npt;
     t.dgrp = grp;
@@ -344,6 +449,20 @@ pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const E
                   (float)a.damping, (float)a.clip, a.clip_inf, f32 ? 1 : 0, a.J, a.glob};
     PMC_REQUIRE((n + 3) / 4 <= 0x7fffffff, "logreg dense Jacobian: too many steps");
     hipLaunchKernelGGL(k_logreg_dense_j, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, ctx->stream, ja);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n)
+{
+    if (n <= 0) return PMC_OK;
+    PMC_REQUIRE(t.dxa && t.dxt, "logreg probed diagonal: tables not built");
+    const int64_t gx = ((n + 31) / 32 + kDenseWaves - 1) / kDenseWaves;
+    PMC_REQUIRE(gx <= 0x7fffffff, "logreg probed diagonal: too many steps");
+    ProbeArgs pa{(const uint4 *)t.dxa, (const uint4 *)t.dxt, t.dnb, (const float *)a.S, (const float *)a.s0,
+                 a.ld, n, t.dim, a.accept, (float)a.eps, (float)(1.0 / t.prior_var), (float)a.damping,
+                 (float)a.clip, a.chains, a.probe_seed, (float *)a.J, a.glob};
+    hipLaunchKernelGGL(k_logreg_probe_diag, dim3((unsigned)gx), dim3(64 * kDenseWaves), 0, ctx->stream, pa);
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;
 }

@@ -138,7 +138,7 @@ struct DevTarget {
     int products = 0;      // pmc_products
     // full-DEER operand tables (built on the first dense solve): X and the
     // pair products x_d x_e in BF16 matrix-core order
-    void *dxa = nullptr, *dpb = nullptr;
+    void *dxa = nullptr, *dpb = nullptr, *dxt = nullptr;
     int dnb = 0, dnpt = 0, dgrp = 0;
 };
 
@@ -268,6 +268,18 @@ struct EvalArgs {
     uint64_t probe_seed = 0;
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
+
+// SplitMix64 (Steele, Lea & Flood 2014): the output function applied to
+// x + 0x9E3779B97F4A7C15, modulo 2^64.  The probe sign of coordinate d at
+// global step t in a chain's sweep i is the top bit of
+// m(m(m(seed) ^ i) ^ (1024 t + d)) (1: -1, 0: +1).
+__device__ __forceinline__ uint64_t probe_mix(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
 pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
 // Full-DEER Jacobians on the logistic posterior: operand tables (once per
@@ -275,6 +287,9 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
 // (BF16 or FP32) from the evaluation's accept decisions.
 pmc_status logreg_dense_tables(pmc_context *ctx, DevTarget &t);
 int logreg_dense_pair_cols(int D);  // row stride of H (D <= 32)
+// One-probe diagonal z o (J z) on the logistic posterior (Sec. 4 eq. 10):
+// J z through X^T (w o X z) on BF16 matrix cores; writes the diagonal planes.
+pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n);
 pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n, float *H,
                                    bool f32);
 // Tile length the eval kernel for this target expects.

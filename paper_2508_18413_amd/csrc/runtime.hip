@@ -324,7 +324,7 @@ pmc_status pmc_target_destroy(pmc_target *tgt)
     if (tgt->t.prec) (void)hipFree(tgt->t.prec);
     if (tgt->t.X) (void)hipFree(tgt->t.X);
     if (tgt->t.y) (void)hipFree(tgt->t.y);
-    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl, tgt->t.xh, tgt->t.dxa, tgt->t.dpb})
+    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl, tgt->t.xh, tgt->t.dxa, tgt->t.dpb, tgt->t.dxt})
         if (q) (void)hipFree(q);
     delete tgt;
     return PMC_OK;

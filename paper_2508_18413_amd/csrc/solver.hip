@@ -45,6 +45,7 @@ struct Plan {
         o_global, total;
     int max_iter;
     bool logreg_dense = false;  // dense J of the logistic posterior (pair sums in o_hpair)
+    bool logreg_probe = false;  // probed diagonal of the logistic posterior
     size_t o_hpair = 0;
 };
 
@@ -171,9 +172,12 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     if (o->jac_probes) {
         PMC_REQUIRE(o->variant == PMC_QDEER_DIAG, "pmc_solve: jac_probes needs the diagonal variant");
         if (t.kind == PMC_TARGET_LOGREG) {
-            set_error("pmc_solve: the logistic-regression evaluation forms the exact Hessian diagonal; "
-                      "probed diagonals are not implemented for it");
-            return PMC_ERR_UNSUPPORTED;
+            // J z through the matrix-core kernel of logreg_dense.hip
+            if (p->n_chains != 1 || pl.D > 32) {
+                set_error("pmc_solve: probed diagonals on logistic regression solve one chain with D <= 32");
+                return PMC_ERR_UNSUPPORTED;
+            }
+            pl.logreg_probe = true;
         }
     }
 
@@ -259,6 +263,7 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
     PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
     if (pl.logreg_dense)
         PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, sw.hpair, pl.jmode == JM_DENSE_F32));
+    if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, sw.ea, pl.n));
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[1], ctx->stream));
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
@@ -393,10 +398,11 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
 
     Sweep sw;
     sw.hier = ws + pl.o_hier;
-    if (pl.logreg_dense) {
-        // operand tables: derived data of the target, built by its first dense solve
+    if (pl.logreg_dense || pl.logreg_probe) {
+        // operand tables: derived data of the target, built by its first
+        // dense or probed solve
         PMC_TRY(logreg_dense_tables(ctx, const_cast<DevTarget &>(*pl.tg)));
-        sw.hpair = (float *)(ws + pl.o_hpair);
+        if (pl.logreg_dense) sw.hpair = (float *)(ws + pl.o_hpair);
     }
     EvalArgs &ea = sw.ea;
     ea.tiles = d_et;
