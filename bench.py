@@ -160,6 +160,23 @@ def main():
     del rdn, pdn
     torch.cuda.empty_cache()
 
+    # quasi-DEER with the one-probe diagonal z o (J z) (Sec. 4 eq. 10) on the
+    # same chain: J z on the matrix cores, a fresh probe every sweep
+    pk = dict(solve_kw, jac_probes=1, probe_seed=1)
+    pm.solve(ctx, tg, eps, s0, xi, u, **pk)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    rpb = [pm.solve(ctx, tg, eps, s0, xi, u, **pk) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wallp = (time.perf_counter() - t5) / args.steps
+    ppb = pm.solve(ctx, tg, eps, s0, xi, u, **dict(pk, profile_kernels=True))
+    diag_probed = {"value": T / wallp, "unit": "chain-steps/s", "ms_per_step": 1e3 * wallp,
+                   "speedup_vs_sequential": (T / wallp) / seq_value, "newton_iters": rpb[-1].sweeps,
+                   "status": rpb[-1].status, "eval_and_probe_ms_per_sweep": ppb.eval_ms / ppb.sweeps,
+                   "max_abs_minus_quasi_deer": (rpb[-1].states - r.states).abs().max().item(),
+                   "max_abs_parallel_minus_sequential": (rpb[-1].states - rs.states).abs().max().item()}
+    del rpb, ppb
+
     # roofline of the dominant kernel (the evaluation kernel), live HIP events
     N, D = ch.target["X"].shape
     flops_per_step = 10.0 * N * D  # grad at x and x~ (4ND each) + Hessian diagonal (2ND)
@@ -197,6 +214,7 @@ def main():
         "max_abs_parallel_minus_sequential": par_vs_seq,
         "f32_products": f32_products,
         "dense_deer": dense_deer,
+        "diag_probed": diag_probed,
         "acceptance": r.n_accept / T,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,

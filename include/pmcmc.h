@@ -149,11 +149,12 @@ typedef struct {
                                  of its converged front) while its ratio is <= 100; 0: never */
     int profile_kernels;      /* != 0 (graph_sweeps = 0 only): time every eval and scan launch
                                  with HIP events on the context's stream (pmc_result.*_ms)    */
-    int jac_probes;           /* PMC_QDEER_DIAG, targets other than LOGREG.  0 (default): the
-                                 exact diagonal of J_t.  1: the stochastic estimate z o (J_t z)
-                                 (Sec. 4 eq. 10; its mean over Rademacher z is diag J_t), one
-                                 probe per step and sweep; the fixed point is unchanged, the
-                                 sweep count is not.  LOGREG gives PMC_ERR_UNSUPPORTED        */
+    int jac_probes;           /* PMC_QDEER_DIAG.  0 (default): the exact diagonal of J_t.
+                                 1: the stochastic estimate z o (J_t z) (Sec. 4 eq. 10; its
+                                 mean over Rademacher z is diag J_t), one probe per step and
+                                 sweep; the fixed point is unchanged, the sweep count is not.
+                                 LOGREG forms J_t z on BF16 matrix cores and solves one chain
+                                 per call (more give PMC_ERR_UNSUPPORTED)                     */
     uint64_t probe_seed;      /* sign of coordinate d at global step t in sweep i (counted from
                                  0 per chain): -1 if the top bit of m(m(m(probe_seed) ^ i) ^
                                  (1024 t + d)) is set, else +1, where m(x) is SplitMix64 (the
