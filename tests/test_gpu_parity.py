@@ -854,3 +854,26 @@ def test_logreg_dense_deer_mala(ctx, pm, orc, jac):
     _say(f"  dense sweeps={r.sweeps} (diag {rd.sweeps}) status={r.status} floor={r.n_floor}")
     assert r.status == 0
     _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+
+
+@pytest.mark.parametrize("jac", ["bf16", "f32"])
+def test_dense_batched_sweeps_match_single_sweeps(ctx, pm, jac):
+    """Sweeps are queued 8 at a time between status reads; once a chain
+    stops, the queued sweeps must leave its states alone.  A dense solve with
+    a trace (one sweep per status read) and one without give the same states
+    bit for bit (a 32-dimensional funnel chain and a 25-dimensional logistic
+    chain, matrix-core dense scan)."""
+    _say(f"dense batched vs single sweeps {jac}")
+    # both solves run to convergence (unconverged funnel iterates can be
+    # non-finite, which no comparison can call equal)
+    for ch, kw in ((W.funnel_chain(T=512, seed=2), {}),
+                   (W.logreg_chain(T=2048, seed=5, eps=0.0015), dict(clip=1.0, clip_inf_norm=True))):
+        g = pm.Target(ctx, ch.target)
+        args = (ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u))
+        a = pm.solve(*args, variant="dense", jac_prec=jac, max_iter=ch.T + 1, **kw)
+        b = pm.solve(*args, variant="dense", jac_prec=jac, max_iter=ch.T + 1, want_trace=True, **kw)
+        _say(f"  {ch.meta['workload']}: sweeps {a.sweeps} / {b.sweeps} status {a.status} / {b.status}")
+        assert a.status == 0 and b.status == 0
+        assert a.sweeps == b.sweeps
+        assert bool(torch.isfinite(a.states).all())
+        assert torch.equal(a.states, b.states)
