@@ -153,8 +153,7 @@ typedef struct {
                                  1: the stochastic estimate z o (J_t z) (Sec. 4 eq. 10; its
                                  mean over Rademacher z is diag J_t), one probe per step and
                                  sweep; the fixed point is unchanged, the sweep count is not.
-                                 LOGREG forms J_t z on BF16 matrix cores and solves one chain
-                                 per call (more give PMC_ERR_UNSUPPORTED)                     */
+                                 LOGREG forms J_t z on BF16 matrix cores (D <= 32)            */
     uint64_t probe_seed;      /* sign of coordinate d at global step t in sweep i (counted from
                                  0 per chain): -1 if the top bit of m(m(m(probe_seed) ^ i) ^
                                  (1024 t + d)) is set, else +1, where m(x) is SplitMix64 (the

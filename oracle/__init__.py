@@ -389,14 +389,15 @@ def _structure(J, variant, D):
 
 
 def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=None, tol=0.0,
-                     full_trace=True, probe_seed=0):
+                     full_trace=True, probe_seed=0, step0=0):
     """Algorithm 1 (Appendix A.1) with the update of Sec. 2 eq. 2, in FP64.
 
     step_and_jac(t, s_prev) -> (f_t(s_prev), df_t/ds(s_prev)) for t = 0..T-1.
     Each sweep linearises every step at the current guess, then solves
     s_t^{new} = f_t(s_{t-1}) + J_t (s_{t-1}^{new} - s_{t-1}) sequentially.
     variant "hutchinson" takes J_t = diag(z o (J z)) with z the probe signs
-    of (probe_seed, sweep, t).  Stops when max_t |s^{new}_t - s_t|_inf <= tol,
+    of (probe_seed, sweep, step0 + t): step0 is the chain's first global step
+    when the chain is one of a batch laid end to end.  Stops when max_t |s^{new}_t - s_t|_inf <= tol,
     or after max_iter sweeps (default T + 1).  Returns (final trajectory,
     list of iterates, sweeps).
     """
@@ -413,7 +414,7 @@ def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=N
             prev = s0 if t == 0 else S[t - 1]
             F[t], J = step_and_jac(t, prev)
             if variant == "hutchinson":
-                z = np.array([probe_sign(probe_seed, it, t, d) for d in range(D)])
+                z = np.array([probe_sign(probe_seed, it, step0 + t, d) for d in range(D)])
                 Js[t] = np.diag(hutchinson_diag(J, z))
             else:
                 Js[t] = _structure(J, variant, D)

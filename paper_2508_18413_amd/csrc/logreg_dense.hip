@@ -286,16 +286,30 @@ __global__ void __launch_bounds__(256) k_logreg_dense_j(DenseJArgs a)
 struct ProbeArgs {
     const uint4 *xa, *xt;
     int nb_count;
-    const float *S, *s0;  // [D, ld], [D]
+    const float *S, *s0;  // [D, ld], [n_chains, D]
     int64_t ld, n;
     int D;
     const uint8_t *accept;
     float eps, pp, damping, clip;
-    const ChainStatus *chain;  // its sweep counter selects the probe
+    const int64_t *offsets;     // [n_chains + 1] first step of each chain
+    int n_chains;
+    const ChainStatus *chains;  // a chain's sweep counter selects its probe
     uint64_t seed;
-    float *J;                  // [D, ld]
+    float *J;                   // [D, ld]
     const GlobalStatus *glob;
 };
+
+// chain of global step t (offsets ascending, offsets[0] = 0 <= t < offsets[n_chains])
+__device__ __forceinline__ int chain_of(const int64_t *offsets, int n_chains, int64_t t)
+{
+    int lo = 0, hi = n_chains - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 __device__ __forceinline__ float probe_sign(uint64_t hs, int64_t t, int d)
 {
@@ -310,7 +324,11 @@ __global__ void __launch_bounds__(64 * kDenseWaves) k_logreg_probe_diag(ProbeArg
     if (a.glob && a.glob->n_active == 0) return;
     const int64_t t = t0 + i;
     const bool live = t < a.n;
-    const uint64_t hs = probe_mix(probe_mix(a.seed) ^ (uint64_t)(uint32_t)a.chain->sweeps);
+    // this step's chain: its first step takes s0 of the chain, its sweep
+    // counter picks the probe
+    const int c = live ? chain_of(a.offsets, a.n_chains, t) : 0;
+    const bool head = live && t == a.offsets[c];
+    const uint64_t hs = probe_mix(probe_mix(a.seed) ^ (uint64_t)(uint32_t)a.chains[c].sweeps);
 
     // B operands: s_{t-1} and the probe z_t, coordinates 16 kd + 8 h + j
     bf16x8 sb[2], zb[2];
@@ -321,7 +339,7 @@ __global__ void __launch_bounds__(64 * kDenseWaves) k_logreg_probe_diag(ProbeArg
         for (int j = 0; j < 8; j++) {
             const int d = 16 * kd + 8 * h + j;
             const bool in = live && d < a.D;
-            v[j] = in ? (t == 0 ? a.s0[d] : a.S[(size_t)d * a.ld + t - 1]) : 0.f;
+            v[j] = in ? (head ? a.s0[(size_t)c * a.D + d] : a.S[(size_t)d * a.ld + t - 1]) : 0.f;
             z[j] = in ? probe_sign(hs, t, d) : 0.f;
         }
         sb[kd] = pack8(v);
@@ -453,15 +471,17 @@ pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const E
     return PMC_OK;
 }
 
-pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n)
+pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n,
+                                    int n_chains)
 {
     if (n <= 0) return PMC_OK;
     PMC_REQUIRE(t.dxa && t.dxt, "logreg probed diagonal: tables not built");
     const int64_t gx = ((n + 31) / 32 + kDenseWaves - 1) / kDenseWaves;
     PMC_REQUIRE(gx <= 0x7fffffff, "logreg probed diagonal: too many steps");
+    PMC_REQUIRE(n_chains >= 1, "logreg probed diagonal: no chains");
     ProbeArgs pa{(const uint4 *)t.dxa, (const uint4 *)t.dxt, t.dnb, (const float *)a.S, (const float *)a.s0,
                  a.ld, n, t.dim, a.accept, (float)a.eps, (float)(1.0 / t.prior_var), (float)a.damping,
-                 (float)a.clip, a.chains, a.probe_seed, (float *)a.J, a.glob};
+                 (float)a.clip, a.offsets, n_chains, a.chains, a.probe_seed, (float *)a.J, a.glob};
     hipLaunchKernelGGL(k_logreg_probe_diag, dim3((unsigned)gx), dim3(64 * kDenseWaves), 0, ctx->stream, pa);
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;

@@ -289,7 +289,8 @@ pmc_status logreg_dense_tables(pmc_context *ctx, DevTarget &t);
 int logreg_dense_pair_cols(int D);  // row stride of H (D <= 32)
 // One-probe diagonal z o (J z) on the logistic posterior (Sec. 4 eq. 10):
 // J z through X^T (w o X z) on BF16 matrix cores; writes the diagonal planes.
-pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n);
+pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n,
+                                    int n_chains);
 pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n, float *H,
                                    bool f32);
 // Tile length the eval kernel for this target expects.

@@ -173,8 +173,8 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         PMC_REQUIRE(o->variant == PMC_QDEER_DIAG, "pmc_solve: jac_probes needs the diagonal variant");
         if (t.kind == PMC_TARGET_LOGREG) {
             // J z through the matrix-core kernel of logreg_dense.hip
-            if (p->n_chains != 1 || pl.D > 32) {
-                set_error("pmc_solve: probed diagonals on logistic regression solve one chain with D <= 32");
+            if (pl.D > 32) {
+                set_error("pmc_solve: probed diagonals on logistic regression support D <= 32 (got %d)", pl.D);
                 return PMC_ERR_UNSUPPORTED;
             }
             pl.logreg_probe = true;
@@ -263,7 +263,7 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
     PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
     if (pl.logreg_dense)
         PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, sw.hpair, pl.jmode == JM_DENSE_F32));
-    if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, sw.ea, pl.n));
+    if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, sw.ea, pl.n, pl.n_chains));
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[1], ctx->stream));
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,

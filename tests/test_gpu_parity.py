@@ -361,14 +361,64 @@ def test_probed_diagonal_converges_to_sequential(ctx, pm, orc, case):
     assert err <= tol
 
 
-def test_probed_diagonal_logreg_batch_is_refused(ctx, pm):
-    from paper_2508_18413_amd._binding import PMCError
-    ch = W.logreg_chain(T=256, seed=1, eps=0.002, n_data=50, dim=4)
-    g = pm.Target(ctx, ch.target)
-    s0 = np.stack([ch.x0, ch.x0])
-    with pytest.raises(PMCError, match="probed diagonals"):
-        pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), offsets=[0, 100, 256], variant="diag",
-                 jac_probes=1)
+def test_logreg_probed_diagonal_batch_one_sweep(ctx, pm, orc):
+    """The probed logistic diagonal for chains laid end to end (lengths not
+    multiples of 32, so 32-step groups straddle chains): one ULA sweep from a
+    perturbed guess, each chain against the oracle's FP64 Hutchinson sweep
+    drawn at the chain's global steps and started from its own s0."""
+    _say("logreg probed diagonal batch one sweep")
+    b = W.logreg_batch(seed=6, n_chains=3, lo=200, hi=700, eps=0.0015)
+    tg = oracle_target(b.target)
+    rng = np.random.default_rng(9)
+    guess = np.empty_like(b.xi)
+    refs = []
+    for c in range(b.n_chains):
+        o0, o1 = b.offsets[c], b.offsets[c + 1]
+        ref, _, _ = orc.mala_chain(tg, b.eps, b.x0[c].astype(np.float64), b.xi[o0:o1].astype(np.float64), None,
+                                   ula=True)
+        guess[o0:o1] = ref + 0.05 * rng.standard_normal(ref.shape)
+        refs.append(ref)
+    g = pm.Target(ctx, b.target)
+    r = pm.solve(ctx, g, b.eps, _t(b.x0), _t(b.xi), None, sampler="ula", offsets=list(b.offsets), variant="diag",
+                 jac_probes=1, probe_seed=77, init_guess=_t(guess), max_iter=1, want_trace=True)
+    got = r.trace[0].cpu().numpy().astype(np.float64)
+    _say(f"  lens={np.diff(b.offsets).tolist()}")
+    for c in range(b.n_chains):
+        o0, o1 = int(b.offsets[c]), int(b.offsets[c + 1])
+        x0 = b.x0[c].astype(np.float64)
+        xi = b.xi[o0:o1].astype(np.float64)
+        g64 = guess[o0:o1].astype(np.float64)
+
+        def sj(t, s):
+            F, J, _ = orc.mala_jac(tg, b.eps, s, xi[t], 0.5, ula=True)
+            return F, J
+        want, _, _ = orc.newton_reference(sj, x0, o1 - o0, variant="hutchinson", init=g64, max_iter=1,
+                                          full_trace=False, probe_seed=77, step0=o0)
+        F = np.array([sj(t, x0 if t == 0 else g64[t - 1])[0] for t in range(o1 - o0)])
+        jterm = np.max(np.abs(want - F))
+        err = np.max(np.abs(got[o0:o1] - want))
+        _say(f"  chain {c}: |J part| {jterm:.3e}  gpu error {err:.3e}")
+        assert err <= 0.02 * jterm
+
+
+def test_logreg_probed_diagonal_batch_mala(ctx, pm, orc):
+    """Batched uneven chains with the probed diagonal converge, each to its
+    FP64 sequential chain."""
+    _say("logreg probed diagonal batch mala")
+    b = W.logreg_batch(seed=3, n_chains=6, lo=1, hi=9000, eps=0.0015)
+    lens = np.diff(b.offsets)
+    tg = oracle_target(b.target)
+    s0 = np.stack([oracle_burnin(tg, _as_chain(b, c)) for c in range(b.n_chains)]).astype(np.float32)
+    g = pm.Target(ctx, b.target)
+    r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), variant="diag", jac_probes=1,
+                 probe_seed=5, max_iter=int(lens.max()) + 1)
+    _say(f"  lens={lens.tolist()} sweeps/chain={r.sweeps_per_chain}")
+    assert r.status == 0 and r.n_converged == b.n_chains
+    st = r.states.cpu().numpy()
+    acc = r.accept.cpu().numpy()
+    for c in range(b.n_chains):
+        o0, o1 = b.offsets[c], b.offsets[c + 1]
+        _check_mala(orc, tg, _as_chain(b, c), s0[c], st[o0:o1], acc[o0:o1])
 
 
 @pytest.mark.parametrize("shape", ["d25n1000", "d5n50", "d32n300"])
@@ -877,3 +927,35 @@ def test_dense_batched_sweeps_match_single_sweeps(ctx, pm, jac):
         assert a.sweeps == b.sweeps
         assert bool(torch.isfinite(a.states).all())
         assert torch.equal(a.states, b.states)
+
+
+@pytest.mark.parametrize("jac", ["bf16", "f32"])
+def test_logreg_dense_jacobian_ragged_entry_clip(ctx, pm, orc, jac):
+    """Full-DEER Jacobians with the entrywise clip (every entry clamped to
+    [-0.5, 0.5], the diagonal included) on a chain whose length is not a
+    multiple of the 32-step groups: one ULA sweep against the oracle's FP64
+    sweep with the same clip."""
+    _say(f"logreg dense J ragged entry clip jac={jac}")
+    T = 1000
+    ch = W.logreg_chain(T=T, seed=7, eps=0.0015)
+    tg = oracle_target(ch.target)
+    x0 = ch.x0.astype(np.float64)
+    xi = ch.xi.astype(np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, xi, None, ula=True)
+    guess = (ref + 0.05 * np.random.default_rng(10).standard_normal(ref.shape)).astype(np.float32)
+    g64 = guess.astype(np.float64)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), None, sampler="ula", variant="dense", jac_prec=jac,
+                 clip=0.5, init_guess=_t(guess), max_iter=1, want_trace=True)
+    got = r.trace[0].cpu().numpy().astype(np.float64)
+
+    def sj(t, s):
+        F, J, _ = orc.mala_jac(tg, ch.eps, s, xi[t], 0.5, ula=True)
+        return F, orc.damp_and_clip(J, 1.0, clip=0.5)
+    want, _, _ = orc.newton_reference(sj, x0, T, variant="dense", init=g64, max_iter=1, full_trace=False)
+    F = np.array([sj(t, x0 if t == 0 else g64[t - 1])[0] for t in range(T)])
+    jterm = np.max(np.abs(want - F))
+    err = np.max(np.abs(got - want))
+    _say(f"  |J part| {jterm:.3e}  gpu error {err:.3e}")
+    assert jterm > 1e-2
+    assert err <= 0.02 * jterm
