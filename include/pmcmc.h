@@ -158,6 +158,11 @@ typedef struct {
                                  0 per chain): -1 if the top bit of m(m(m(probe_seed) ^ i) ^
                                  (1024 t + d)) is set, else +1, where m(x) is SplitMix64 (the
                                  output function of x + 0x9E3779B97F4A7C15)                   */
+    const void *basis;        /* NULL (default), or DEVICE [D, D] row-major orthogonal Q in the
+                                 state dtype: quasi-DEER (or Picard) iterates z = Q^T s and
+                                 takes diag(Q^T J_t Q) (Sec. 4 eq. 11); the states, trace and
+                                 initial guess stay in s.  Targets other than LOGREG, no
+                                 probes; Q is read during the solve and must outlive it       */
 } pmc_options;
 
 typedef struct {

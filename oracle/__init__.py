@@ -16,6 +16,8 @@ Contents
 * ``probe_sign`` / ``splitmix64``: the counter-based signs of that probe;
 * ``damp_and_clip``: the damped, entrywise- or norm-clipped Jacobian of full
   DEER;
+* ``rotated_provider``: the chain in orthogonally rotated coordinates
+  (Sec. 4 eq. 11), whose quasi-DEER diagonal is diag(Q^T J Q);
 * ``bidiagonal_bruteforce``: the Newton linear system written as one block
   lower-bidiagonal matrix and solved by LAPACK (numpy.linalg.solve).
 
@@ -367,6 +369,19 @@ def damp_and_clip(J, damping=1.0, clip=0.0, inf_norm=False):
         nrm = np.max(np.sum(np.abs(J), axis=1))
         return J * (clip / nrm) if nrm > clip else J
     return np.clip(J, -clip, clip)
+
+
+def rotated_provider(step_and_jac, Q):
+    """The chain in the coordinates z = Q^T s of an orthogonal Q (Sec. 4
+    eq. 11): z_t = Q^T f_t(Q z_{t-1}) with Jacobian Q^T J_t Q.  Wraps a
+    step_and_jac(t, s_prev) provider of newton_reference; its initial state
+    must be given as Q^T s_0."""
+    Q = np.asarray(Q, dtype=np.float64)
+
+    def sj(t, z_prev):
+        F, J = step_and_jac(t, Q @ np.asarray(z_prev, dtype=np.float64))
+        return Q.T @ F, Q.T @ J @ Q
+    return sj
 
 
 def _structure(J, variant, D):

@@ -176,7 +176,7 @@ def _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out
 def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rtol=None,
              max_iter=0, damping=1.0, clip=0.0, clip_inf_norm=False, skip_converged_prefix=True,
              graph_sweeps=0, trace=None, floor_stall=None, profile_kernels=False, jac_probes=0,
-             probe_seed=0):
+             probe_seed=0, basis=None):
     o = B.pmc_options()
     B.check(B.lib().pmc_default_options(C.byref(o), _dtype_code(dtype)))
     o.variant = VARIANTS[variant]
@@ -193,6 +193,9 @@ def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rt
         o.floor_stall = int(floor_stall)
     o.profile_kernels = int(bool(profile_kernels))
     o.jac_probes, o.probe_seed = int(jac_probes), int(probe_seed)
+    if basis is not None:
+        # device tensor [D, D] in the state dtype, kept alive by the caller
+        o.basis = basis.data_ptr()
     if trace is not None:
         o.trace_out = trace.data_ptr()
         o.trace_bytes = trace.numel() * trace.element_size()

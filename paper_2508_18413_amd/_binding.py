@@ -43,7 +43,8 @@ class pmc_options(C.Structure):
                 ("damping", C.c_double), ("clip", C.c_double), ("clip_inf_norm", C.c_int),
                 ("skip_converged_prefix", C.c_int), ("graph_sweeps", C.c_int),
                 ("trace_out", C.c_void_p), ("trace_bytes", C.c_size_t), ("floor_stall", C.c_int),
-                ("profile_kernels", C.c_int), ("jac_probes", C.c_int), ("probe_seed", C.c_uint64)]
+                ("profile_kernels", C.c_int), ("jac_probes", C.c_int), ("probe_seed", C.c_uint64),
+                ("basis", C.c_void_p)]
 
 
 class pmc_result(C.Structure):

@@ -67,6 +67,21 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
             xi[d] = R(0);
         }
     }
+    // orthogonal reparameterisation (Sec. 4 eq. 11): the planes hold
+    // z = Q^T s, so the previous state is s = Q z (the chain's s0 is in s)
+    const R *Q = (const R *)a.basis;
+    if (Q && !head) {
+        R z[DM];
+#pragma unroll
+        for (int d = 0; d < DM; d++) z[d] = x[d];
+#pragma unroll
+        for (int d = 0; d < DM; d++) {
+            R v = R(0);
+            if (d < D)
+                for (int k = 0; k < D; k++) v = fma(Q[(size_t)d * D + k], z[k], v);
+            x[d] = v;
+        }
+    }
     const R eps = (R)a.eps;
     const R c = sqrt(R(2) * eps);
     tg.grad(x, g);
@@ -94,9 +109,23 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
         if (!(ell == ell)) acc = 0;
     }
     R *F = (R *)a.F;
+    if (Q) {
+        // F~ = Q^T f
 #pragma unroll
-    for (int d = 0; d < DM; d++)
-        if (d < D) F[(size_t)d * ld + t] = acc ? xt[d] : x[d];
+        for (int k = 0; k < DM; k++) {
+            if (k < D) {
+                R v = R(0);
+#pragma unroll
+                for (int d = 0; d < DM; d++)
+                    if (d < D) v = fma(Q[(size_t)d * D + k], acc ? xt[d] : x[d], v);
+                F[(size_t)k * ld + t] = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < DM; d++)
+            if (d < D) F[(size_t)d * ld + t] = acc ? xt[d] : x[d];
+    }
     if (a.accept) a.accept[t] = (uint8_t)acc;
     if (a.gtilde) a.gtilde[t] = (float)gate;
     if (JM == JM_NONE) return;
@@ -125,6 +154,29 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
 
     if (JM == JM_DIAG) {
         R *J = (R *)a.J;
+        if (Q) {
+            // diag(Q^T J Q): 1 + eps a q_k^T H q_k (+ the surrogate's
+            // coef (q_k . dl)(dl/dx . q_k)) for each column q_k of Q
+            for (int k = 0; k < D; k++) {
+                R q[DM], hq[DM];
+#pragma unroll
+                for (int d = 0; d < DM; d++) q[d] = d < D ? Q[(size_t)d * D + k] : R(0);
+                tg.hvp(x, q, hq);
+                R qhq = R(0), qdl = R(0), qg = R(0);
+#pragma unroll
+                for (int d = 0; d < DM; d++) {
+                    qhq = fma(q[d], hq[d], qhq);
+                    if (surr) {
+                        qdl = fma(q[d], dl[d], qdl);
+                        qg = fma(dldx[d], q[d], qg);
+                    }
+                }
+                R j = fma(ea, qhq, R(1));
+                if (surr) j = fma(coef * qdl, qg, j);
+                J[(size_t)k * ld + t] = clampj(j, a.damping, a.clip, 0);
+            }
+            return;
+        }
         if (a.probes) {
             // z o (J z) with J z = z + eps H z (+ the rank-one surrogate term)
             R z[DM], hz[DM];

@@ -179,6 +179,9 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Layout helpers: row-major [n, D] <-> dimension-major planes [D, ld].
 pmc_status rows_to_planes(pmc_context *ctx, pmc_dtype dt, const void *rows, void *planes, int64_t n,
                           int D, int64_t ld);
+// out planes = Q in (or Q^T in when transpose), Q row-major [D, D], D <= 32
+pmc_status rotate_planes(pmc_context *ctx, pmc_dtype dt, const void *Q, const void *in, void *out, int64_t n,
+                         int D, int64_t ld, bool transpose);
 pmc_status planes_to_rows(pmc_context *ctx, pmc_dtype dt, const void *planes, void *rows, int64_t n,
                           int D, int64_t ld);
 // planes[d][t] = s0[chain(t)][d] (d_offsets: device [n_chains+1])
@@ -265,6 +268,7 @@ struct EvalArgs {
     const pmc::DevTarget *tg; // host copy of the target description (fields passed by value)
     const GlobalStatus *glob = nullptr;  // n_active == 0 at launch: nothing left to evaluate
     int probes = 0;           // 1: probed diagonal z o (J z) instead of diag(J) (JM_DIAG)
+    const void *basis = nullptr;  // [D, D] orthogonal Q: iterates are z = Q^T s (per-lane targets)
     uint64_t probe_seed = 0;
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);

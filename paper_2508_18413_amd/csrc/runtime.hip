@@ -96,7 +96,37 @@ __global__ void k_broadcast_s0(const R *s0, const int64_t *offsets, int n_chains
     }
     for (int d = 0; d < D; d++) planes[(size_t)d * ld + t] = s0[(size_t)lo * D + d];
 }
+// out[d][t] = sum_e M[d][e] in[e][t], M = Q or Q^T (Q row-major D x D, D <= 32)
+template <typename R>
+__global__ void k_rotate_planes(const R *Q, const R *in, R *out, int64_t n, int D, int64_t ld, int transpose)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    R v[32];
+    for (int e = 0; e < D; e++) v[e] = in[(size_t)e * ld + t];
+    for (int d = 0; d < D; d++) {
+        R acc = R(0);
+        for (int e = 0; e < D; e++) acc = fma(transpose ? Q[(size_t)e * D + d] : Q[(size_t)d * D + e], v[e], acc);
+        out[(size_t)d * ld + t] = acc;
+    }
+}
 }  // namespace
+
+pmc_status rotate_planes(pmc_context *ctx, pmc_dtype dt, const void *Q, const void *in, void *out, int64_t n,
+                         int D, int64_t ld, bool transpose)
+{
+    if (n == 0) return PMC_OK;
+    PMC_REQUIRE(D >= 1 && D <= 32, "rotate_planes: D <= 32 (got %d)", D);
+    dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (dt == PMC_F64)
+        hipLaunchKernelGGL(k_rotate_planes<double>, g, b, 0, ctx->stream, (const double *)Q, (const double *)in,
+                           (double *)out, n, D, ld, transpose ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_rotate_planes<float>, g, b, 0, ctx->stream, (const float *)Q, (const float *)in,
+                           (float *)out, n, D, ld, transpose ? 1 : 0);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
 
 pmc_status rows_to_planes(pmc_context *ctx, pmc_dtype dt, const void *rows, void *planes, int64_t n,
                           int D, int64_t ld)

@@ -46,6 +46,8 @@ struct Plan {
     int max_iter;
     bool logreg_dense = false;  // dense J of the logistic posterior (pair sums in o_hpair)
     bool logreg_probe = false;  // probed diagonal of the logistic posterior
+    const void *basis = nullptr;  // orthogonal reparameterisation (iterates z = Q^T s)
+    size_t o_rot = 0;             // rotation scratch planes [D, ld]
     size_t o_hpair = 0;
 };
 
@@ -181,6 +183,14 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         }
     }
 
+    if (o->basis) {
+        PMC_REQUIRE(is_device_ptr(o->basis), "pmc_solve: basis must be a device pointer");
+        if (t.kind == PMC_TARGET_LOGREG || !(pl.jmode == JM_DIAG || pl.jmode == JM_NONE) || o->jac_probes) {
+            set_error("pmc_solve: basis applies to quasi-DEER or Picard without probes on the per-step targets");
+            return PMC_ERR_UNSUPPORTED;
+        }
+        pl.basis = o->basis;
+    }
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) {
         pl.scan_items = 1;
         pl.scan_block = 256;
@@ -234,6 +244,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? dense_mfma_ws_bytes(pl.n)
                                                                          : 256);
     if (pl.logreg_dense) pl.o_hpair = take(sizeof(float) * (size_t)pl.n * logreg_dense_pair_cols(pl.D));
+    if (pl.basis) pl.o_rot = take(plane * pl.D);
     pl.o_acc = take(std::max<int64_t>(pl.n, 1));
     pl.o_gt = take(4 * std::max<int64_t>(pl.n, 1));
     pl.o_etiles = take(sizeof(SegTile) * std::max<size_t>(pl.etiles.size(), 1));
@@ -395,6 +406,12 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
         PMC_TRY(rows_to_planes(ctx, pl.dt, prob->init_guess, S, pl.n, pl.D, pl.ld));
     else
         PMC_TRY(broadcast_s0(ctx, pl.dt, prob->s0, d_offs, pl.n_chains, S, pl.n, pl.D, pl.ld));
+    void *rot = pl.basis ? ws + pl.o_rot : nullptr;
+    if (pl.basis) {
+        // the iteration runs on z = Q^T s
+        PMC_TRY(rotate_planes(ctx, pl.dt, pl.basis, S, rot, pl.n, pl.D, pl.ld, true));
+        PMC_TRY_HIP(hipMemcpyAsync(S, rot, (size_t)pl.ld * pl.es * pl.D, hipMemcpyDeviceToDevice, st));
+    }
 
     Sweep sw;
     sw.hier = ws + pl.o_hier;
@@ -427,6 +444,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     ea.clip_inf = opts->clip_inf_norm;
     ea.jmode = pl.jmode == JM_NONE ? JM_NONE : pl.jmode;
     ea.probes = opts->jac_probes;
+    ea.basis = pl.basis;
     ea.probe_seed = opts->probe_seed;
     ea.tg = pl.tg;
     ea.glob = d_glob;
@@ -519,10 +537,16 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
             const int nb = std::min(batch, pl.max_iter - it);
             for (int j = 0; j < nb; j++) {
                 PMC_TRY(one_sweep(ctx, pl, sw, prof ? &ctx->kev[3 * j] : nullptr));
-                if (opts->trace_out)
-                    PMC_TRY(planes_to_rows(ctx, pl.dt, S,
+                if (opts->trace_out) {
+                    const void *src = S;
+                    if (pl.basis) {
+                        PMC_TRY(rotate_planes(ctx, pl.dt, pl.basis, S, rot, pl.n, pl.D, pl.ld, false));
+                        src = rot;
+                    }
+                    PMC_TRY(planes_to_rows(ctx, pl.dt, src,
                                            (char *)opts->trace_out + (size_t)(it + j) * pl.n * pl.D * pl.es,
                                            pl.n, pl.D, pl.ld));
+                }
             }
             PMC_TRY_HIP(hipMemcpyAsync(hs, d_glob, sizeof(GlobalStatus), hipMemcpyDeviceToHost, st));
             PMC_TRY_HIP(hipStreamSynchronize(st));
@@ -541,7 +565,12 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
             if (hs->n_active == 0) break;
         }
     }
-    PMC_TRY(planes_to_rows(ctx, pl.dt, S, prob->out_states, pl.n, pl.D, pl.ld));
+    if (pl.basis) {
+        PMC_TRY(rotate_planes(ctx, pl.dt, pl.basis, S, rot, pl.n, pl.D, pl.ld, false));  // s = Q z
+        PMC_TRY(planes_to_rows(ctx, pl.dt, rot, prob->out_states, pl.n, pl.D, pl.ld));
+    } else {
+        PMC_TRY(planes_to_rows(ctx, pl.dt, S, prob->out_states, pl.n, pl.D, pl.ld));
+    }
     PMC_TRY_HIP(hipEventRecord(ctx->ev1, st));
     // final accept count
     sta.accept = acc;

@@ -959,3 +959,70 @@ def test_logreg_dense_jacobian_ragged_entry_clip(ctx, pm, orc, jac):
     _say(f"  |J part| {jterm:.3e}  gpu error {err:.3e}")
     assert jterm > 1e-2
     assert err <= 0.02 * jterm
+
+
+def _orthogonal(D, seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((D, D)))
+    return q * np.sign(np.diag(r))
+
+
+def test_basis_eigenbasis_ula_gaussian(ctx, pm, orc):
+    """Orthogonal reparameterisation (Sec. 4 eq. 11): ULA on a Gaussian in
+    the eigenbasis of its precision has a diagonal Jacobian, so the first
+    quasi-DEER sweep there is exact Newton and already gives the chain (to
+    FP32 rounding), while the first sweep in the original coordinates is far
+    off.  The tolerance-based stop then takes a few more sweeps in FP32:
+    rounding moves the iterate by about the tolerance, amplified by the
+    recursion's coefficients near 1; it still stops sooner than the plain
+    iteration."""
+    _say("basis: eigenbasis ULA gaussian D=16")
+    ch = W.gaussian_chain(5000, seed=6, eps=0.2, dim=16, dtype=np.float32, lam_lo=0.3)
+    tg = oracle_target(ch.target)
+    _, Q = np.linalg.eigh(np.asarray(ch.target["prec"], dtype=np.float64))
+    g = pm.Target(ctx, ch.target)
+    q = _t(Q.astype(np.float32))
+    args = (ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), None)
+    r = pm.solve(*args, sampler="ula", variant="diag", basis=q, max_iter=200, want_trace=True)
+    r0 = pm.solve(*args, sampler="ula", variant="diag", max_iter=200, want_trace=True)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, ch.x0, ch.xi, None, ula=True)
+    e1 = state_error(r.trace[0].cpu().numpy(), ref)
+    e1_plain = state_error(r0.trace[0].cpu().numpy(), ref)
+    _say(f"  first sweep error {e1:.2e} (plain {e1_plain:.2e}); sweeps {r.sweeps} (plain {r0.sweeps})")
+    assert e1 <= 1e-5 and e1_plain > 1e-3
+    assert r.status == 0 and r.sweeps < r0.sweeps
+    assert state_error(r.states.cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["banana_f64", "funnel_f32"])
+def test_basis_random_rotation_mala(ctx, pm, orc, kind):
+    """Quasi-DEER in randomly rotated coordinates (diag of Q^T J Q, states
+    rotated in and out) converges to the FP64 sequential chain."""
+    _say(f"basis: random rotation {kind}")
+    if kind == "banana_f64":
+        ch, td, tol = W.banana_chain(1024, seed=2), torch.float64, 1e-10
+    else:
+        ch, td, tol = W.funnel_chain(T=1024, seed=3), torch.float32, 1e-5
+    tg = oracle_target(ch.target)
+    D = ch.x0.shape[0]
+    q = _t(_orthogonal(D, 11), td)
+    g = pm.Target(ctx, ch.target, dtype=td)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0, td), _t(ch.xi, td), _t(ch.u, td), variant="diag", basis=q,
+                 max_iter=ch.T + 1)
+    r0 = pm.solve(ctx, g, ch.eps, _t(ch.x0, td), _t(ch.xi, td), _t(ch.u, td), variant="diag", max_iter=ch.T + 1)
+    _say(f"  rotated sweeps={r.sweeps} plain sweeps={r0.sweeps} status={r.status}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, np.asarray(ch.x0), r.states.cpu().numpy(), r.accept.cpu().numpy(), tol)
+
+
+def test_basis_is_refused_where_it_does_not_apply(ctx, pm):
+    from paper_2508_18413_amd._binding import PMCError
+    ch = W.logreg_chain(T=256, seed=1, eps=0.002, n_data=50, dim=4)
+    g = pm.Target(ctx, ch.target)
+    q = _t(np.eye(4, dtype=np.float32))
+    with pytest.raises(PMCError, match="basis"):
+        pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", basis=q)
+    fch = W.funnel_chain(T=256, seed=1)
+    fg = pm.Target(ctx, fch.target)
+    with pytest.raises(PMCError, match="basis"):
+        pm.solve(ctx, fg, fch.eps, _t(fch.x0), _t(fch.xi), _t(fch.u), variant="dense",
+                 basis=_t(np.eye(32, dtype=np.float32)))

@@ -223,3 +223,44 @@ def test_clipped_dense_newton_is_causally_exact(orc, case):
     for i, Si in enumerate(trace):
         np.testing.assert_array_equal(Si[:i], ref[:i])
     np.testing.assert_array_equal(S, ref)
+
+
+def _random_orthogonal(D, seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((D, D)))
+    return q * np.sign(np.diag(r))
+
+
+def test_rotated_eigenbasis_makes_ula_gaussian_diagonal_exact(orc):
+    """ULA on a Gaussian is affine with the constant Jacobian I - eps P; in
+    the eigenbasis of the precision P that Jacobian is diagonal, so quasi-DEER
+    there is exact Newton and one sweep gives the chain, while quasi-DEER in
+    the original coordinates does not."""
+    ch = W.gaussian_chain(64, seed=4, eps=0.2, dim=6, lam_lo=0.3)
+    tg = oracle_target(ch.target)
+    x0 = np.asarray(ch.x0, dtype=np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, ch.xi, None, ula=True)
+    P = np.asarray(ch.target["prec"], dtype=np.float64)
+    _, Q = np.linalg.eigh(P)
+    sj = _mala_provider(orc, tg, ch, ula=True)
+    Z, trace, _ = orc.newton_reference(orc.rotated_provider(sj, Q), Q.T @ x0, ch.T, variant="diag",
+                                       init=np.tile(Q.T @ x0, (ch.T, 1)), max_iter=1)
+    np.testing.assert_allclose(Z @ Q.T, ref, atol=1e-11)
+    S, _, _ = orc.newton_reference(sj, x0, ch.T, variant="diag", max_iter=1)
+    assert np.max(np.abs(S - ref)) > 1e-3
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rotated_quasi_deer_reaches_the_chain(orc, case):
+    """With a random orthogonal Q the rotated quasi-DEER iteration keeps the
+    exact front (after sweep i the first i steps, rotated back, equal the
+    sequential chain up to rounding) and its fixed point is the chain."""
+    ch = CASES[case]()
+    tg = oracle_target(ch.target)
+    x0 = np.asarray(ch.x0, dtype=np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u)
+    Q = _random_orthogonal(x0.shape[0], 3)
+    sj = orc.rotated_provider(_mala_provider(orc, tg, ch), Q)
+    Z, trace, _ = orc.newton_reference(sj, Q.T @ x0, ch.T, variant="diag", max_iter=ch.T, tol=-1.0)
+    for i, Zi in enumerate(trace):
+        np.testing.assert_allclose(Zi[:i] @ Q.T, ref[:i], atol=1e-10)
+    np.testing.assert_allclose(Z @ Q.T, ref, atol=1e-10)
