@@ -161,8 +161,10 @@ typedef struct {
     const void *basis;        /* NULL (default), or DEVICE [D, D] row-major orthogonal Q in the
                                  state dtype: quasi-DEER (or Picard) iterates z = Q^T s and
                                  takes diag(Q^T J_t Q) (Sec. 4 eq. 11); the states, trace and
-                                 initial guess stay in s.  Targets other than LOGREG, no
-                                 probes; Q is read during the solve and must outlive it       */
+                                 initial guess stay in s.  Per-step targets: no probes.
+                                 LOGREG: solved as the rotated model (design X Q, noise
+                                 Q^T xi) with any variant it supports, allocating the rotated
+                                 copies for the call.  Q must outlive the call              */
 } pmc_options;
 
 typedef struct {

@@ -185,11 +185,14 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
 
     if (o->basis) {
         PMC_REQUIRE(is_device_ptr(o->basis), "pmc_solve: basis must be a device pointer");
-        if (t.kind == PMC_TARGET_LOGREG || !(pl.jmode == JM_DIAG || pl.jmode == JM_NONE) || o->jac_probes) {
-            set_error("pmc_solve: basis applies to quasi-DEER or Picard without probes on the per-step targets");
-            return PMC_ERR_UNSUPPORTED;
+        // the logistic posterior is solved as the rotated model (solve_logreg_rotated)
+        if (t.kind != PMC_TARGET_LOGREG) {
+            if (!(pl.jmode == JM_DIAG || pl.jmode == JM_NONE) || o->jac_probes) {
+                set_error("pmc_solve: basis applies to quasi-DEER or Picard without probes");
+                return PMC_ERR_UNSUPPORTED;
+            }
+            pl.basis = o->basis;
         }
-        pl.basis = o->basis;
     }
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) {
         pl.scan_items = 1;
@@ -289,6 +292,112 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
     return PMC_OK;
 }
 
+// out[r][k] = sum_d in[r][d] M[d][k] with M = Q, or Q^T when transpose (FP32, D <= 32)
+__global__ void k_rotate_rows(const float *in, int64_t rows, int ld_in, const float *Q, int D, int transpose,
+                              float *out, int ld_out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    float v[32];
+    for (int d = 0; d < D; d++) v[d] = in[(size_t)r * ld_in + d];
+    for (int k = 0; k < D; k++) {
+        float acc = 0.f;
+        for (int d = 0; d < D; d++) acc = fmaf(v[d], transpose ? Q[(size_t)k * D + d] : Q[(size_t)d * D + k], acc);
+        out[(size_t)r * ld_out + k] = acc;
+    }
+}
+
+pmc_status rotate_rows(pmc_context *ctx, const void *in, int64_t rows, int ld_in, const void *Q, int D,
+                       bool transpose, void *out, int ld_out)
+{
+    if (rows <= 0) return PMC_OK;
+    PMC_REQUIRE(D >= 1 && D <= 32 && (rows + 255) / 256 <= 0x7fffffff, "rotate_rows: bad shape");
+    hipLaunchKernelGGL(k_rotate_rows, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, ctx->stream,
+                       (const float *)in, rows, ld_in, (const float *)Q, D, transpose ? 1 : 0, (float *)out, ld_out);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
+// The logistic posterior in the coordinates z = Q^T s (Sec. 4 eq. 11) is the
+// same model with design X Q (the prior N(0, prior_var I) is unchanged by a
+// rotation) and MALA noise Q^T xi, so quasi-DEER's diag(Q^T J Q) is the
+// rotated model's exact Jacobian diagonal.  The rotated target, noise, s0
+// and initial guess are formed on the device, the rotated problem is solved
+// with every variant the target supports, and the states and trace are
+// rotated back.  Allocates the rotated copies for the duration of the call.
+pmc_status solve_logreg_rotated(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts, void *workspace,
+                                size_t ws_bytes, pmc_result *res)
+{
+    const DevTarget &t = prob->target->t;
+    const int D = t.dim, nc = prob->n_chains;
+    const int64_t n = prob->n_steps;
+    PMC_REQUIRE(is_device_ptr(opts->basis), "pmc_solve: basis must be a device pointer");
+    PMC_REQUIRE(nc >= 1 && n >= 0 && D <= 32, "pmc_solve: bad rotated logistic problem");
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    pmc_target rt;
+    rt.device = prob->target->device;
+    rt.t.kind = t.kind;
+    rt.t.dtype = t.dtype;
+    rt.t.dim = D;
+    rt.t.n_data = t.n_data;
+    rt.t.ldx = t.ldx;
+    rt.t.prior_var = t.prior_var;
+    rt.t.theta = t.theta;
+    rt.t.products = t.products;
+    rt.t.y = t.y;  // shared, not freed here
+    float *xi = nullptr, *s0 = nullptr, *guess = nullptr, *zout = nullptr, *ztrace = nullptr;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (void *q : {(void *)rt.t.X, rt.t.xa, rt.t.xta, rt.t.x2ta, rt.t.ypad, rt.t.xl, rt.t.xh, rt.t.dxa,
+                        rt.t.dpb, rt.t.dxt, (void *)xi, (void *)s0, (void *)guess, (void *)zout, (void *)ztrace})
+            if (q) (void)hipFree(q);
+    };
+    pmc_status st = PMC_OK;
+    auto run = [&]() -> pmc_status {
+        const size_t xb = 4 * (size_t)t.ldx * t.n_data, rb = 4 * (size_t)std::max<int64_t>(n, 1) * D;
+        PMC_TRY_HIP(hipMalloc(&rt.t.X, xb));
+        PMC_TRY_HIP(hipMemsetAsync(rt.t.X, 0, xb, ctx->stream));
+        PMC_TRY(rotate_rows(ctx, t.X, t.n_data, t.ldx, opts->basis, D, false, rt.t.X, t.ldx));  // X Q
+        PMC_TRY(logreg_build_frags(ctx, rt.t));
+        PMC_TRY_HIP(hipMalloc(&xi, rb));
+        PMC_TRY_HIP(hipMalloc(&s0, 4 * (size_t)nc * D));
+        PMC_TRY_HIP(hipMalloc(&zout, rb));
+        PMC_TRY(rotate_rows(ctx, prob->noise, n, D, opts->basis, D, false, xi, D));  // rows (Q^T xi)^T
+        PMC_TRY(rotate_rows(ctx, prob->s0, nc, D, opts->basis, D, false, s0, D));
+        pmc_problem p2 = *prob;
+        pmc_options o2 = *opts;
+        o2.basis = nullptr;
+        p2.target = &rt;
+        p2.noise = xi;
+        p2.s0 = s0;
+        p2.out_states = zout;
+        if (prob->init_guess) {
+            PMC_TRY_HIP(hipMalloc(&guess, rb));
+            PMC_TRY(rotate_rows(ctx, prob->init_guess, n, D, opts->basis, D, false, guess, D));
+            p2.init_guess = guess;
+        }
+        if (opts->trace_out) {
+            // rows of sweeps that do not run come back as the caller left them
+            PMC_TRY_HIP(hipMalloc(&ztrace, opts->trace_bytes));
+            PMC_TRY_HIP(hipMemcpyAsync(ztrace, opts->trace_out, opts->trace_bytes, hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+            PMC_TRY(rotate_rows(ctx, opts->trace_out, (int64_t)(opts->trace_bytes / (4 * (size_t)D)), D, opts->basis,
+                                D, false, ztrace, D));
+            o2.trace_out = ztrace;
+        }
+        st = pmc_solve(ctx, &p2, &o2, workspace, ws_bytes, res);
+        if (st != PMC_OK && st != PMC_NOT_CONVERGED) return st;
+        PMC_TRY(rotate_rows(ctx, zout, n, D, opts->basis, D, true, prob->out_states, D));  // s = Q z
+        if (opts->trace_out)
+            PMC_TRY(rotate_rows(ctx, ztrace, (int64_t)(opts->trace_bytes / (4 * (size_t)D)), D, opts->basis, D, true,
+                                opts->trace_out, D));
+        return st;
+    };
+    const pmc_status r = run();
+    release();
+    return r;
+}
+
 }  // namespace
 }  // namespace pmc
 
@@ -330,6 +439,8 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
 {
     Plan pl;
     PMC_TRY(make_plan(ctx, prob, opts, pl));
+    if (opts->basis && prob->target->t.kind == PMC_TARGET_LOGREG)
+        return solve_logreg_rotated(ctx, prob, opts, workspace, ws_bytes, res);
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     if (res) {
         int32_t *spc = res->sweeps_per_chain;

@@ -1016,13 +1016,31 @@ def test_basis_random_rotation_mala(ctx, pm, orc, kind):
 
 def test_basis_is_refused_where_it_does_not_apply(ctx, pm):
     from paper_2508_18413_amd._binding import PMCError
-    ch = W.logreg_chain(T=256, seed=1, eps=0.002, n_data=50, dim=4)
-    g = pm.Target(ctx, ch.target)
-    q = _t(np.eye(4, dtype=np.float32))
-    with pytest.raises(PMCError, match="basis"):
-        pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="diag", basis=q)
     fch = W.funnel_chain(T=256, seed=1)
     fg = pm.Target(ctx, fch.target)
     with pytest.raises(PMCError, match="basis"):
         pm.solve(ctx, fg, fch.eps, _t(fch.x0), _t(fch.xi), _t(fch.u), variant="dense",
                  basis=_t(np.eye(32, dtype=np.float32)))
+
+
+@pytest.mark.parametrize("probes", [0, 1])
+def test_basis_logreg_rotated_model(ctx, pm, orc, probes):
+    """The logistic posterior with an orthogonal basis is solved as the
+    rotated model (design X Q, noise Q^T xi) and rotated back: it converges
+    to the FP64 chain in the original coordinates, with the exact or the
+    probed diagonal, and its trace comes back in s."""
+    _say(f"basis: logistic posterior, random rotation, probes={probes}")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015)
+    g = pm.Target(ctx, ch.target)
+    q = _t(_orthogonal(25, 12).astype(np.float32))
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", basis=q, jac_probes=probes,
+                 max_iter=ch.T + 1)
+    r0 = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=ch.T + 1)
+    _say(f"  rotated sweeps={r.sweeps} plain sweeps={r0.sweeps} status={r.status}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
+    rt = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", basis=q, jac_probes=probes,
+                  max_iter=r.sweeps + 3, want_trace=True)
+    last = rt.trace[rt.sweeps - 1]
+    assert (last - rt.states).abs().max().item() <= 1e-5
+    assert bool(torch.isnan(rt.trace[rt.sweeps:]).all())
