@@ -47,6 +47,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kDenseWaves = 4;  // 32-step tiles per workgroup
+constexpr int kMaxPairCols = 32 * 33 / 2;  // D (D + 1) / 2 at D = 32
 // pair tiles accumulated per pass over the data: each pass recomputes M^T
 // and w, but 3 tiles (about 125 registers) leave room for 4 wavefronts per
 // SIMD to hide the operand loads, which is faster than 4 tiles (3 per SIMD),
@@ -240,7 +241,15 @@ __global__ void __launch_bounds__(256) k_logreg_dense_j(DenseJArgs a)
     if (t >= a.n) return;  // uniform per wavefront
     if (a.glob && a.glob->n_active == 0) return;
     const float ea = a.accept[t] ? a.eps : 0.f;
+    // the step's pair sums, read coalesced into LDS, then gathered per entry
+    __shared__ float s_h[4][kMaxPairCols];
+    float *sh = s_h[threadIdx.x >> 6];
     const float *Ht = a.H + t * a.hld;
+    const int np = a.D * (a.D + 1) / 2;
+    for (int p = lane; p < np; p += 64) sh[p] = Ht[p];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float v[16];
     float rs = 0.f;
 #pragma unroll
@@ -249,7 +258,7 @@ __global__ void __launch_bounds__(256) k_logreg_dense_j(DenseJArgs a)
         const int k = a.f32 ? 2 * c + h : 16 * (c >> 3) + 8 * h + (c & 7);
         float x = 0.f;
         if (i < a.D && k < a.D) {
-            const float hs = Ht[i <= k ? pair_index(i, k, a.D) : pair_index(k, i, a.D)];
+            const float hs = sh[i <= k ? pair_index(i, k, a.D) : pair_index(k, i, a.D)];
             x = i == k ? fmaf(-ea, hs + a.pp, 1.f) : -ea * hs;
         }
         v[c] = x;
