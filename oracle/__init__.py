@@ -7,17 +7,18 @@ in ``paper_2508_18413_amd``; the two meet only at the seeded input arrays.
 Contents
 --------
 * ctypes bindings of ``oracle.c`` (targets, sequential MALA/ULA/HMC chains,
-  step Jacobians, sequential linear recursions, tangent/adjoint derivatives);
+  whole HMC transitions as chain steps with their Jacobians, step Jacobians,
+  sequential linear recursions, tangent/adjoint derivatives);
 * ``newton_reference``: Algorithm 1 of the paper (Appendix A.1) in FP64, the
   linearised recursion of Sec. 2 eq. 2/3 (dense), eq. 4 (diagonal), the block
   quasi-DEER recursion of Appendix A.3, Picard (J = 0), or the diagonal
-  estimated from one Rademacher probe per step and sweep (Sec. 4 eq. 10),
+  estimated from one Rademacher probe per step and sweep (Sec. 3.4 eq. 10),
   solved by a plain sequential loop;
 * ``probe_sign`` / ``splitmix64``: the counter-based signs of that probe;
 * ``damp_and_clip``: the damped, entrywise- or norm-clipped Jacobian of full
   DEER;
 * ``rotated_provider``: the chain in orthogonally rotated coordinates
-  (Sec. 4 eq. 11), whose quasi-DEER diagonal is diag(Q^T J Q);
+  (Sec. 3.4 eq. 11), whose quasi-DEER diagonal is diag(Q^T J Q);
 * ``bidiagonal_bruteforce``: the Newton linear system written as one block
   lower-bidiagonal matrix and solved by LAPACK (numpy.linalg.solve).
 
@@ -81,6 +82,16 @@ def lib():
         L.orc_hmc_chain.restype = C.c_long
         L.orc_hmc_chain.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_long, dp, dp, dp, bp,
                                     dp, bp, dp, dp, dp]
+        L.orc_hmc_step.restype = C.c_int
+        L.orc_hmc_step.argtypes = [C.c_void_p, C.c_double, C.c_int, dp, dp, dp, C.c_double, C.c_int,
+                                   dp, dp, dp, dp]
+        L.orc_hmc_seq_chain.restype = C.c_long
+        L.orc_hmc_seq_chain.argtypes = [C.c_void_p, C.c_double, C.c_int, dp, C.c_long, dp, dp, dp, bp,
+                                        dp, bp, dp]
+        L.orc_hmc_step_jac.restype = C.c_int
+        L.orc_hmc_step_jac.argtypes = [C.c_void_p, C.c_double, C.c_int, dp, C.c_int, dp, dp, C.c_double,
+                                       C.c_int, dp, dp]
+        L.orc_hmc_smoothed_step.argtypes = [C.c_void_p, C.c_double, C.c_int, dp, dp, dp, C.c_double, dp]
         L.orc_linrec_diag.argtypes = [C.c_long, C.c_int, dp, dp, dp]
         L.orc_linrec_dense.argtypes = [C.c_long, C.c_int, dp, dp, dp]
         L.orc_linrec_block2.argtypes = [C.c_long, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
@@ -254,6 +265,65 @@ def hmc_chain(tg, eps, L, x0, momenta, U, force=None, want_traj=False):
     return dict(chain=chain, accept=acc, logr=logr, s0=s0, traj=traj)
 
 
+# ------------------------------------------ HMC across the sequence (Sec. 3.3)
+
+def _mass(inv_mass):
+    if inv_mass is None:
+        return None, None
+    return _d(inv_mass)
+
+
+def hmc_step(tg, eps, L, x, xi, u, force=-1, inv_mass=None):
+    """One whole HMC transition as a chain step f_t (Sec. 3.3, parallel HMC
+    across the sequence): momentum xi / sqrt(inv_mass), L leapfrog steps,
+    relaxed-gate forward value.  Returns (x_next, accepted, gtilde, H0 - HL, x_L)."""
+    x, px = _d(x)
+    xi, pxi = _d(xi)
+    im, pim = _mass(inv_mass)
+    out, po = _d(np.empty(tg.dim))
+    prop, pp = _d(np.empty(tg.dim))
+    gt, dh = C.c_double(), C.c_double()
+    a = lib().orc_hmc_step(tg.ptr, eps, int(L), pim, px, pxi, float(u), int(force), po, C.byref(gt), C.byref(dh), pp)
+    return out, int(a), gt.value, dh.value, prop
+
+
+def hmc_seq_chain(tg, eps, L, x0, xi, u, force=None, inv_mass=None):
+    """Sequential chain of HMC transitions.  xi [T, D], u [T].  Returns (states, accept, gtilde)."""
+    xi = np.asarray(xi, dtype=np.float64).reshape(-1, tg.dim)
+    T = xi.shape[0]
+    x0, p0 = _d(x0)
+    xi, pxi = _d(xi)
+    u, pu = _d(u)
+    im, pim = _mass(inv_mass)
+    f, pf = _nullable(force, "b")
+    st = np.empty((T, tg.dim))
+    acc = np.empty(T, dtype=np.int8)
+    gt = np.empty(T)
+    lib().orc_hmc_seq_chain(tg.ptr, eps, int(L), pim, T, p0, pxi, pu, pf, _d(st)[1],
+                            acc.ctypes.data_as(C.POINTER(C.c_int8)), _d(gt)[1])
+    return st, acc, gt
+
+
+def hmc_step_jac(tg, eps, L, x, xi, u, gate=0, force=-1, inv_mass=None):
+    """(f_t(x), dense dx_t/dx_{t-1}) of one HMC transition; gate 0 frozen, 1 relaxed."""
+    x, px = _d(x)
+    xi, pxi = _d(xi)
+    im, pim = _mass(inv_mass)
+    F, pF = _d(np.empty(tg.dim))
+    J, pJ = _d(np.empty((tg.dim, tg.dim)))
+    lib().orc_hmc_step_jac(tg.ptr, eps, int(L), pim, int(gate), px, pxi, float(u), int(force), pF, pJ)
+    return F, J
+
+
+def hmc_smoothed_step(tg, eps, L, x, xi, u, inv_mass=None):
+    x, px = _d(x)
+    xi, pxi = _d(xi)
+    im, pim = _mass(inv_mass)
+    out, po = _d(np.empty(tg.dim))
+    lib().orc_hmc_smoothed_step(tg.ptr, eps, int(L), pim, px, pxi, float(u), po)
+    return out
+
+
 # ------------------------------------------------------- linear recursions
 
 def linrec_diag(a, b):
@@ -349,7 +419,7 @@ def probe_sign(seed: int, sweep: int, t: int, d: int) -> float:
 
 
 def hutchinson_diag(J, z):
-    """The one-probe estimate z o (J z) of diag(J) (Sec. 4 eq. 10): its mean over
+    """The one-probe estimate z o (J z) of diag(J) (Sec. 3.4 eq. 10): its mean over
     the Rademacher distribution of z is diag(J)."""
     J = np.asarray(J, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
@@ -372,7 +442,7 @@ def damp_and_clip(J, damping=1.0, clip=0.0, inf_norm=False):
 
 
 def rotated_provider(step_and_jac, Q):
-    """The chain in the coordinates z = Q^T s of an orthogonal Q (Sec. 4
+    """The chain in the coordinates z = Q^T s of an orthogonal Q (Sec. 3.4
     eq. 11): z_t = Q^T f_t(Q z_{t-1}) with Jacobian Q^T J_t Q.  Wraps a
     step_and_jac(t, s_prev) provider of newton_reference; its initial state
     must be given as Q^T s_0."""

@@ -15,6 +15,9 @@
  *   - HMC with leapfrog integration (Sec. 3.3 eq. for the leapfrog step,
  *     Appendix A.2 algorithm "HMC Step with Parallel Leapfrog", with its
  *     accept test read as the standard Metropolis test log U < H0 - HL);
+ *   - one whole HMC transition as the step f_t of a chain (Sec. 3.3,
+ *     parallel HMC across the sequence), optionally with a diagonal mass
+ *     matrix, with its Jacobian under the frozen or the relaxed gate;
  *   - the Jacobians the Newton update needs (Sec. 2 eq. 2; MALA gate via the
  *     stop-gradient relaxation, Sec. 3.2; leapfrog block form, Sec. 3.3 and
  *     Appendix A.3);
@@ -412,6 +415,178 @@ long orc_hmc_chain(const orc_target *tg, double eps, int L, long n_prop, const d
         for (int d = 0; d < D; d++) chain[(p + 1) * D + d] = x[d];
     }
     return nacc;
+}
+
+/* ------------------------------------- HMC across the sequence (Sec. 3.3) */
+
+/*
+ * One whole HMC transition x_t = f_t(x_{t-1}) with its sequential leapfrog
+ * integrator, the map that Sec. 3.3 ("Parallel HMC with Sequential Leapfrog
+ * Integration") parallelises across the steps of the chain.  Momentum
+ * v0 = xi / sqrt(inv_mass) (inv_mass: diagonal of M^-1, NULL = identity), so
+ * xi ~ N(0, I) gives v0 ~ N(0, M); half step v = v0 + eps/2 grad log p(x);
+ * L leapfrog steps x <- x + eps M^-1 v, v <- v + eps grad log p(x); reverse
+ * half step v_f = v - eps/2 grad log p(x_L); energies
+ * H = v.M^-1 v / 2 - log p(x) (Appendix A.2, with the accept test read as
+ * the Metropolis test); log alpha = min(0, H0 - HL); gate
+ * g~ = log alpha - log u; accept iff g~ > 0 (the forward value of the
+ * relaxed gate of Sec. 3.2).  force as in orc_mala_step.
+ * Writes x_next (and the proposal x_L to xprop, and H0 - HL to dh, when not
+ * NULL); returns the decision; *gt = g~.
+ */
+int orc_hmc_step(const orc_target *tg, double eps, int L, const double *inv_mass, const double *x,
+                 const double *xi, double u, int force, double *x_next, double *gt, double *dh,
+                 double *xprop)
+{
+    int D = tg->dim;
+    double g[MAXD], xl[MAXD], v[MAXD], v0[MAXD];
+    double kin0 = 0, kinL = 0;
+    for (int d = 0; d < D; d++) {
+        double im = inv_mass ? inv_mass[d] : 1.0;
+        v0[d] = xi[d] / sqrt(im);
+        kin0 += v0[d] * im * v0[d];
+    }
+    double H0 = 0.5 * kin0 - orc_logp(tg, x);
+    orc_grad(tg, x, g);
+    for (int d = 0; d < D; d++) {
+        xl[d] = x[d];
+        v[d] = v0[d] + 0.5 * eps * g[d];
+    }
+    for (int l = 0; l < L; l++) {
+        for (int d = 0; d < D; d++) xl[d] += eps * (inv_mass ? inv_mass[d] : 1.0) * v[d];
+        orc_grad(tg, xl, g);
+        for (int d = 0; d < D; d++) v[d] += eps * g[d];
+    }
+    for (int d = 0; d < D; d++) {
+        double vf = v[d] - 0.5 * eps * g[d];
+        kinL += vf * (inv_mass ? inv_mass[d] : 1.0) * vf;
+    }
+    double HL = 0.5 * kinL - orc_logp(tg, xl);
+    double diff = H0 - HL;
+    double log_alpha = diff < 0 ? diff : 0;
+    double gg = log_alpha - log(u);
+    int acc = gg > 0;
+    if (force == 0 || force == 1) acc = force;
+    for (int d = 0; d < D; d++) x_next[d] = acc ? xl[d] : x[d];
+    if (xprop)
+        for (int d = 0; d < D; d++) xprop[d] = xl[d];
+    if (gt) *gt = gg;
+    if (dh) *dh = diff;
+    return acc;
+}
+
+/* Sequential chain of HMC transitions (Sec. 2, the recursion evaluated step by
+ * step).  xi: [T*D] standard normal momenta draws, u: [T]; force NULL or [T].
+ * Outputs states [T*D], accept [T], gtilde [T] (the last two may be NULL).
+ * Returns the number of accepted steps. */
+long orc_hmc_seq_chain(const orc_target *tg, double eps, int L, const double *inv_mass, long T,
+                       const double *x0, const double *xi, const double *u, const int8_t *force,
+                       double *states, int8_t *accept, double *gtilde)
+{
+    int D = tg->dim;
+    double x[MAXD];
+    long nacc = 0;
+    for (int d = 0; d < D; d++) x[d] = x0[d];
+    for (long t = 0; t < T; t++) {
+        double gg;
+        int f = force ? force[t] : -1;
+        int a = orc_hmc_step(tg, eps, L, inv_mass, x, xi + t * D, u[t], f, states + t * D, &gg, NULL, NULL);
+        nacc += a;
+        if (accept) accept[t] = (int8_t)a;
+        if (gtilde) gtilde[t] = gg;
+        for (int d = 0; d < D; d++) x[d] = states[t * D + d];
+    }
+    return nacc;
+}
+
+/*
+ * Jacobian J = d x_t / d x_{t-1} of one HMC transition, dense D x D
+ * (row-major), and F = f_t(x), by the chain rule through the integrator
+ * written out in forward mode: with Xd = dx/dx0 and Vd = dv/dx0 (D x D),
+ *   half step:  Xd = I, Vd = eps/2 H(x0);
+ *   each leapfrog step: Xd <- Xd + eps M^-1 Vd, then Vd <- Vd + eps H(x) Xd
+ *   at the new position (the Jacobian blocks of Sec. 3.3 eq. for the leapfrog
+ *   step, with a mass matrix);
+ * frozen gate (gate 0): J = a Xd_L + (1 - a) I;
+ * relaxed gate (gate 1, the stop-gradient construction of Sec. 3.2 applied to
+ * the HMC accept step): J gains sigma(g~)(1 - sigma(g~)) (x_L - x0) (dg~/dx0)^T
+ * with dg~/dx0 = 1(H0 - HL < 0) d(H0 - HL)/dx0, where
+ *   dH0/dx0 = -grad log p(x0),
+ *   dHL/dx0 = Vf^T M^-1 v_f - Xd_L^T grad log p(x_L),
+ *   Vf = Vd_L - eps/2 H(x_L) Xd_L  (the reverse half step).
+ * Returns the decision.
+ */
+int orc_hmc_step_jac(const orc_target *tg, double eps, int L, const double *inv_mass, int gate,
+                     const double *x, const double *xi, double u, int force, double *F, double *J)
+{
+    int D = tg->dim;
+    static double H[MAXD * MAXD], Xd[MAXD * MAXD], Vd[MAXD * MAXD], T1[MAXD * MAXD];
+    double g[MAXD], xl[MAXD], v[MAXD], g0[MAXD], dl[MAXD], vf[MAXD];
+    double gg, diff;
+    int a = orc_hmc_step(tg, eps, L, inv_mass, x, xi, u, force, F, &gg, &diff, NULL);
+    /* forward pass again, carrying the tangents */
+    orc_grad(tg, x, g0);
+    orc_hess(tg, x, H);
+    for (int i = 0; i < D; i++) g[i] = g0[i];
+    for (int i = 0; i < D; i++) {
+        xl[i] = x[i];
+        v[i] = xi[i] / sqrt(inv_mass ? inv_mass[i] : 1.0) + 0.5 * eps * g0[i];
+        for (int j = 0; j < D; j++) {
+            Xd[i * D + j] = i == j ? 1.0 : 0.0;
+            Vd[i * D + j] = 0.5 * eps * H[i * D + j];
+        }
+    }
+    for (int l = 0; l < L; l++) {
+        for (int i = 0; i < D; i++) {
+            double im = inv_mass ? inv_mass[i] : 1.0;
+            xl[i] += eps * im * v[i];
+            for (int j = 0; j < D; j++) Xd[i * D + j] += eps * im * Vd[i * D + j];
+        }
+        orc_grad(tg, xl, g);
+        orc_hess(tg, xl, H);
+        for (int i = 0; i < D; i++) {
+            v[i] += eps * g[i];
+            for (int j = 0; j < D; j++) {
+                double s = 0;
+                for (int k = 0; k < D; k++) s += H[i * D + k] * Xd[k * D + j];
+                T1[i * D + j] = s;
+            }
+        }
+        for (int i = 0; i < D * D; i++) Vd[i] += eps * T1[i];
+    }
+    for (int i = 0; i < D; i++)
+        for (int j = 0; j < D; j++) J[i * D + j] = a ? Xd[i * D + j] : (i == j ? 1.0 : 0.0);
+    if (gate == 0 || !(diff < 0)) return a;
+    /* relaxed gate: dg~/dx0 = d(H0 - HL)/dx0 where H0 - HL < 0 */
+    for (int i = 0; i < D; i++) vf[i] = v[i] - 0.5 * eps * g[i];
+    /* H = Hess at x_L (from the last leapfrog step; for L = 0 at x0) */
+    for (int j = 0; j < D; j++) {
+        double dHL = 0;
+        for (int i = 0; i < D; i++) {
+            double hx = 0;
+            for (int k = 0; k < D; k++) hx += H[i * D + k] * Xd[k * D + j];
+            double vfd = Vd[i * D + j] - 0.5 * eps * hx;
+            dHL += vfd * (inv_mass ? inv_mass[i] : 1.0) * vf[i] - Xd[i * D + j] * g[i];
+        }
+        dl[j] = -g0[j] - dHL;
+    }
+    double sg = 1.0 / (1.0 + exp(-gg));
+    double c = sg * (1 - sg);
+    for (int i = 0; i < D; i++)
+        for (int j = 0; j < D; j++) J[i * D + j] += c * (xl[i] - x[i]) * dl[j];
+    return a;
+}
+
+/* The sigma-smoothed HMC transition (gate sigma(g~) in the forward pass too):
+ * used only to pin the relaxed-gate Jacobian by finite differences. */
+void orc_hmc_smoothed_step(const orc_target *tg, double eps, int L, const double *inv_mass, const double *x,
+                           const double *xi, double u, double *out)
+{
+    int D = tg->dim;
+    double xl[MAXD], xn[MAXD], gg;
+    orc_hmc_step(tg, eps, L, inv_mass, x, xi, u, -1, xn, &gg, NULL, xl);
+    double s = 1.0 / (1.0 + exp(-gg));
+    for (int d = 0; d < D; d++) out[d] = s * xl[d] + (1 - s) * x[d];
 }
 
 /* --------------------------------------------- linear recursions (eq. 3) */
