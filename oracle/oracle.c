@@ -220,7 +220,8 @@ int orc_mala_step(const orc_target *tg, double eps, int ula, const double *x, co
     double l = orc_logp(tg, xt) - orc_logp(tg, x) + log_q(D, x, xt, gt_, eps) - log_q(D, xt, x, g, eps);
     double log_alpha = l < 0 ? l : 0;
     double gg = log_alpha - log(u);
-    int acc = gg > 0;
+    /* a NaN log ratio (a diverged proposal, inf - inf) rejects */
+    int acc = gg > 0 && l == l;
     if (force == 0 || force == 1) acc = force;
     for (int d = 0; d < D; d++) x_next[d] = acc ? xt[d] : x[d];
     if (gt) *gt = gg;
@@ -465,7 +466,8 @@ int orc_hmc_step(const orc_target *tg, double eps, int L, const double *inv_mass
     double diff = H0 - HL;
     double log_alpha = diff < 0 ? diff : 0;
     double gg = log_alpha - log(u);
-    int acc = gg > 0;
+    /* a NaN energy difference (a diverged trajectory, inf - inf) rejects */
+    int acc = gg > 0 && diff == diff;
     if (force == 0 || force == 1) acc = force;
     for (int d = 0; d < D; d++) x_next[d] = acc ? xl[d] : x[d];
     if (xprop)

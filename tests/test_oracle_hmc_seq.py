@@ -187,3 +187,17 @@ def test_newton_causal_exactness_hmc(orc, kind, variant):
         assert np.array_equal(trace[i][:i], ref[:i]), (variant, i)
     np.testing.assert_array_equal(S, ref)
     assert sweeps <= T + 1
+
+
+def test_diverged_trajectory_rejects(orc):
+    """A trajectory that overflows (banana from a far-out start) gives a NaN
+    energy difference, and the transition rejects it (the reading for a NaN
+    Metropolis ratio); an infinite energy error rejects by the ratio itself."""
+    tg = orc.Target(orc.BANANA, 2)
+    x = np.array([1e120, 0.0])
+    xn, a, gt, dh, xl = orc.hmc_step(tg, 0.5, 8, x, np.array([0.3, -0.2]), 0.5)
+    assert not np.isfinite(dh) and a == 0
+    np.testing.assert_array_equal(xn, x)
+    for force in (-1,):
+        F, J = orc.hmc_step_jac(tg, 0.5, 8, x, np.array([0.3, -0.2]), 0.5, gate=1, force=force)
+        np.testing.assert_array_equal(J, np.eye(2))
