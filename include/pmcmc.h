@@ -19,8 +19,9 @@
  *  - Each call returns a pmc_status and, on failure, sets a thread-local
  *    message readable with pmc_last_error().  PMC_NOT_CONVERGED is a soft
  *    status: all outputs are written and valid (the last Newton iterate).
- *    pmc_solve returns PMC_OK when every chain met the tolerance or stopped at
- *    its rounding floor (pmc_result.n_floor counts the latter).
+ *    pmc_solve returns PMC_OK only when every chain met the tolerance; a
+ *    chain stopped early at its rounding floor (floor_stall) counts as not
+ *    converged (pmc_result.n_floor counts such chains).
  *  - Floating-point types: PMC_F32 arrays are float, PMC_F64 arrays double.
  *  - Calls on one context are not thread-safe; use one context per thread.
  */
@@ -40,15 +41,24 @@ typedef enum {
     PMC_ERR_UNSUPPORTED = 2, /* valid request that the library does not implement   */
     PMC_ERR_OOM = 3,         /* device allocation failed or workspace too small      */
     PMC_ERR_HIP = 4,         /* HIP runtime error (no device, launch failure, ...)   */
-    PMC_NOT_CONVERGED = 5,   /* soft: max_iter reached; outputs hold the last iterate */
-    PMC_ERR_NONFINITE = 6    /* non-finite value in an input array                    */
+    PMC_NOT_CONVERGED = 5,   /* soft: some chain did not meet the tolerance; outputs
+                                hold the last iterate                                 */
+    PMC_ERR_NONFINITE = 6    /* a non-finite value in an input array (initial states,
+                                noise, momenta, initial guess) or a uniform outside
+                                (0, 1); checked on the device before any sweep        */
 } pmc_status;
 
 typedef enum { PMC_F32 = 0, PMC_F64 = 1 } pmc_dtype;
 
 /* Transition f_t.  MALA: the MALA function of Sec. 3.2 with noise xi_t and
- * uniform u_t; ULA: the same proposal, always kept. */
-typedef enum { PMC_SAMPLER_MALA = 0, PMC_SAMPLER_ULA = 1 } pmc_sampler;
+ * uniform u_t; ULA: the same proposal, always kept.  HMC: one whole HMC step
+ * (Sec. 3.3, parallel HMC across the sequence): momentum v0 = xi_t / sqrt(m)
+ * for the diagonal mass matrix diag(m) (identity by default), a half step,
+ * n_leapfrog sequential leapfrog steps of size step_size, the reverse half
+ * step, and the accept gate g~ = min(0, H0 - HL) - log u_t with
+ * H = v.M^-1 v / 2 - log p(x); its relaxed form (PMC_GATE_SURROGATE) enters
+ * the Jacobian as for MALA. */
+typedef enum { PMC_SAMPLER_MALA = 0, PMC_SAMPLER_ULA = 1, PMC_SAMPLER_HMC = 2 } pmc_sampler;
 
 typedef enum {
     PMC_TARGET_GAUSSIAN = 0, /* log p = -(x-mu)^T P (x-mu) / 2                          */
@@ -120,7 +130,9 @@ typedef struct {
                                  s0 broadcast over its steps (the paper's choice)            */
     void *out_states;         /* DEVICE [n_steps, D] written: the trajectory                */
     uint8_t *out_accept;      /* DEVICE [n_steps] or NULL: accept decision of each step     */
-    float *out_gtilde;        /* DEVICE [n_steps] or NULL: g~ = log alpha - log u (MALA)     */
+    float *out_gtilde;        /* DEVICE [n_steps] or NULL: g~ = log alpha - log u (MALA, HMC) */
+    int n_leapfrog;           /* HMC: leapfrog steps L per transition (1..1024)              */
+    const void *inv_mass;     /* HMC: DEVICE [D] diagonal of M^-1 (positive), or NULL = identity */
 } pmc_problem;
 
 typedef struct {
@@ -146,11 +158,12 @@ typedef struct {
     size_t trace_bytes;       /* size of trace_out                                           */
     int floor_stall;          /* > 0: stop a chain at its rounding floor after this many sweeps
                                  without progress (no 2x drop of its best ratio and no advance
-                                 of its converged front) while its ratio is <= 100; 0: never */
+                                 of its converged front) while its ratio is <= 2 (the last
+                                 change within twice the tolerance); 0: never                */
     int profile_kernels;      /* != 0 (graph_sweeps = 0 only): time every eval and scan launch
                                  with HIP events on the context's stream (pmc_result.*_ms)    */
     int jac_probes;           /* PMC_QDEER_DIAG.  0 (default): the exact diagonal of J_t.
-                                 1: the stochastic estimate z o (J_t z) (Sec. 4 eq. 10; its
+                                 1: the stochastic estimate z o (J_t z) (Sec. 3.4 eq. 10; its
                                  mean over Rademacher z is diag J_t), one probe per step and
                                  sweep; the fixed point is unchanged, the sweep count is not.
                                  LOGREG forms J_t z on BF16 matrix cores (D <= 32)            */
@@ -160,11 +173,17 @@ typedef struct {
                                  output function of x + 0x9E3779B97F4A7C15)                   */
     const void *basis;        /* NULL (default), or DEVICE [D, D] row-major orthogonal Q in the
                                  state dtype: quasi-DEER (or Picard) iterates z = Q^T s and
-                                 takes diag(Q^T J_t Q) (Sec. 4 eq. 11); the states, trace and
+                                 takes diag(Q^T J_t Q) (Sec. 3.4 eq. 11); the states, trace and
                                  initial guess stay in s.  Per-step targets: no probes.
                                  LOGREG: solved as the rotated model (design X Q, noise
                                  Q^T xi) with any variant it supports, allocating the rotated
                                  copies for the call.  Q must outlive the call              */
+    double tie_band;          /* >= 0: an accept decision whose gate |g~| is below this keeps the
+                                 decision of the chain's previous sweep (from its second sweep
+                                 on), so that rounding-level changes of the iterate cannot flip
+                                 a decision the arithmetic cannot resolve back and forth between
+                                 sweeps; 0 disables.  Default 2e-5 for F32 (the FP32 error
+                                 bound of g~ on the logistic posterior), 0 for F64            */
 } pmc_options;
 
 typedef struct {
@@ -181,6 +200,8 @@ typedef struct {
     float eval_ms;            /* with profile_kernels: summed duration of the eval launches   */
     float scan_ms;            /* with profile_kernels: summed duration of the scan launches   */
     int64_t eval_steps;       /* with profile_kernels: steps evaluated over all sweeps        */
+    int8_t *chain_state;      /* HOST [n_chains] or NULL: per chain 0 = met the tolerance,
+                                 1 = stopped at its rounding floor, 2 = reached max_iter     */
 } pmc_result;
 
 /* ---- context ------------------------------------------------------------ */
@@ -232,12 +253,14 @@ pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *prob, pmc_
  * L-step leapfrog recursion on s = [x, v] in R^{2D} by Newton iterations with
  * opts->variant (PMC_QDEER_BLOCK2, PMC_QDEER_DIAG or PMC_PICARD) and tolerance;
  * 0 integrates sequentially.  out_chain: DEVICE [n_prop+1, D] (row 0 = x0);
- * accept: DEVICE [n_prop] or NULL; sweeps: HOST [n_prop] or NULL (Newton
- * sweeps per proposal). */
+ * accept: DEVICE [n_prop] or NULL; logr: DEVICE [n_prop] or NULL, the test's
+ * margin (H0 - HL) - log U, assembled in FP64 from FP32 terms and rounded to
+ * float (accept iff > 0); sweeps: HOST [n_prop] or NULL (Newton sweeps per
+ * proposal). */
 pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target, double step_size, int L,
                           int n_prop, const void *x0, const void *momenta, const void *unif,
                           const pmc_options *opts, int parallel_leapfrog, void *out_chain,
-                          uint8_t *accept, int32_t *sweeps, pmc_result *res);
+                          uint8_t *accept, float *logr, int32_t *sweeps, pmc_result *res);
 
 /* ---- derivatives through a converged chain ---------------------------------- */
 /* Reverse (adjoint) scan lambda_t = dF/ds_t + J_{t+1}^T lambda_{t+1} over the

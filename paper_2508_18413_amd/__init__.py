@@ -153,11 +153,18 @@ class Result:
     eval_ms: float = 0.0
     scan_ms: float = 0.0
     eval_steps: int = 0
+    chain_state: list = None  # per chain: 0 converged, 1 at its rounding floor, 2 max_iter
 
 
-def _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out, acc, gt):
+SAMPLERS = {"mala": B.PMC_SAMPLER_MALA, "ula": B.PMC_SAMPLER_ULA, "hmc": B.PMC_SAMPLER_HMC}
+
+
+def _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out, acc, gt, n_leapfrog=0,
+             inv_mass=None):
     p = B.pmc_problem()
-    p.sampler = B.PMC_SAMPLER_ULA if sampler == "ula" else B.PMC_SAMPLER_MALA
+    p.sampler = SAMPLERS[sampler]
+    p.n_leapfrog = int(n_leapfrog)
+    p.inv_mass = _ptr(inv_mass)
     p.target = target.h
     p.step_size = float(eps)
     n_chains = s0.shape[0] if s0.dim() == 2 else 1
@@ -176,7 +183,7 @@ def _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out
 def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rtol=None,
              max_iter=0, damping=1.0, clip=0.0, clip_inf_norm=False, skip_converged_prefix=True,
              graph_sweeps=0, trace=None, floor_stall=None, profile_kernels=False, jac_probes=0,
-             probe_seed=0, basis=None):
+             probe_seed=0, basis=None, tie_band=None):
     o = B.pmc_options()
     B.check(B.lib().pmc_default_options(C.byref(o), _dtype_code(dtype)))
     o.variant = VARIANTS[variant]
@@ -191,6 +198,8 @@ def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rt
     o.graph_sweeps = int(graph_sweeps)
     if floor_stall is not None:
         o.floor_stall = int(floor_stall)
+    if tie_band is not None:
+        o.tie_band = float(tie_band)
     o.profile_kernels = int(bool(profile_kernels))
     o.jac_probes, o.probe_seed = int(jac_probes), int(probe_seed)
     if basis is not None:
@@ -203,9 +212,12 @@ def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rt
 
 
 def solve(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="mala",
-          offsets=None, init_guess=None, want_trace=False, max_iter=0, **opts) -> Result:
+          offsets=None, init_guess=None, want_trace=False, max_iter=0, n_leapfrog=0, inv_mass=None,
+          **opts) -> Result:
     """pmc_solve: parallel Newton solve of one or more chains.  s0: [B, D] (or [D]);
-    noise: [n_steps, D]; uniforms: [n_steps]; offsets: host list [B+1] or None."""
+    noise: [n_steps, D]; uniforms: [n_steps]; offsets: host list [B+1] or None.
+    sampler "hmc": whole HMC transitions with n_leapfrog leapfrog steps and the
+    optional inverse diagonal mass matrix inv_mass [D] (device tensor)."""
     torch = _torch()
     s0 = s0.reshape(-1, target.dim).contiguous()
     n, D = noise.shape
@@ -213,7 +225,8 @@ def solve(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="
     out = torch.empty((n, D), dtype=noise.dtype, device=dev)
     acc = torch.empty(n, dtype=torch.uint8, device=dev)
     gt = torch.empty(n, dtype=torch.float32, device=dev)
-    p, keep = _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out, acc, gt)
+    p, keep = _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out, acc, gt,
+                       n_leapfrog, inv_mass)
     trace = None
     if want_trace:
         if max_iter <= 0:
@@ -221,18 +234,20 @@ def solve(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="
         trace = torch.full((max_iter, n, D), float("nan"), dtype=noise.dtype, device=dev)
     o = _options(noise.dtype, trace=trace, max_iter=max_iter, **opts)
     spc = (C.c_int32 * p.n_chains)()
+    cst = (C.c_int8 * p.n_chains)()
     r = B.pmc_result()
     r.sweeps_per_chain = C.cast(spc, C.POINTER(C.c_int32))
+    r.chain_state = C.cast(cst, C.POINTER(C.c_int8))
     st = B.check(B.lib().pmc_solve(ctx.h, C.byref(p), C.byref(o), None, 0, C.byref(r)),
                  allow=(B.PMC_NOT_CONVERGED,))
     del keep
     return Result(out, acc, gt, st, r.sweeps_total, list(spc), r.n_converged, r.n_accept,
                   r.resid_inf, r.resid_l2, r.max_ratio, r.nonfinite, r.elapsed_ms, trace,
-                  r.n_floor, r.eval_ms, r.scan_ms, r.eval_steps)
+                  r.n_floor, r.eval_ms, r.scan_ms, r.eval_steps, list(cst))
 
 
 def sample_sequential(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="mala",
-                      offsets=None) -> Result:
+                      offsets=None, n_leapfrog=0, inv_mass=None) -> Result:
     """pmc_sample_sequential: the same chains evaluated step by step on the GPU."""
     torch = _torch()
     s0 = s0.reshape(-1, target.dim).contiguous()
@@ -241,7 +256,8 @@ def sample_sequential(ctx: Context, target: Target, eps, s0, noise, uniforms=Non
     out = torch.empty((n, D), dtype=noise.dtype, device=dev)
     acc = torch.empty(n, dtype=torch.uint8, device=dev)
     gt = torch.empty(n, dtype=torch.float32, device=dev)
-    p, keep = _problem(target, sampler, eps, s0, noise, uniforms, offsets, None, out, acc, gt)
+    p, keep = _problem(target, sampler, eps, s0, noise, uniforms, offsets, None, out, acc, gt, n_leapfrog,
+                       inv_mass)
     r = B.pmc_result()
     B.check(B.lib().pmc_sample_sequential(ctx.h, C.byref(p), C.byref(r)))
     del keep
@@ -284,16 +300,17 @@ def hmc_sample(ctx: Context, target: Target, eps, L, x0, momenta, unif, parallel
     dev = momenta.device
     chain = torch.empty((n_prop + 1, D), dtype=torch.float32, device=dev)
     acc = torch.empty(n_prop, dtype=torch.uint8, device=dev)
+    logr = torch.empty(n_prop, dtype=torch.float32, device=dev)
     sweeps = (C.c_int32 * max(n_prop, 1))()
     opts.setdefault("variant", "block2")
     o = _options(torch.float32, **opts)
     r = B.pmc_result()
     st = B.check(B.lib().pmc_hmc_sample(ctx.h, target.h, float(eps), int(L), int(n_prop), _ptr(x0),
                                         _ptr(momenta), _ptr(unif), C.byref(o),
-                                        int(bool(parallel_leapfrog)), _ptr(chain), _ptr(acc),
+                                        int(bool(parallel_leapfrog)), _ptr(chain), _ptr(acc), _ptr(logr),
                                         C.cast(sweeps, C.POINTER(C.c_int32)), C.byref(r)),
                  allow=(B.PMC_NOT_CONVERGED,))
-    return dict(chain=chain, accept=acc, sweeps=list(sweeps)[:n_prop], status=st,
+    return dict(chain=chain, accept=acc, logr=logr, sweeps=list(sweeps)[:n_prop], status=st,
                 elapsed_ms=r.elapsed_ms, n_accept=r.n_accept)
 
 

@@ -15,7 +15,7 @@ PMC_OK, PMC_ERR_INVALID, PMC_ERR_UNSUPPORTED, PMC_ERR_OOM, PMC_ERR_HIP, PMC_NOT_
 STATUS_NAMES = {0: "PMC_OK", 1: "PMC_ERR_INVALID", 2: "PMC_ERR_UNSUPPORTED", 3: "PMC_ERR_OOM",
                 4: "PMC_ERR_HIP", 5: "PMC_NOT_CONVERGED", 6: "PMC_ERR_NONFINITE"}
 PMC_F32, PMC_F64 = 0, 1
-PMC_SAMPLER_MALA, PMC_SAMPLER_ULA = 0, 1
+PMC_SAMPLER_MALA, PMC_SAMPLER_ULA, PMC_SAMPLER_HMC = 0, 1, 2
 PMC_TARGET_GAUSSIAN, PMC_TARGET_BANANA, PMC_TARGET_LOGREG, PMC_TARGET_FUNNEL = 0, 1, 2, 3
 PMC_DEER_DENSE, PMC_QDEER_DIAG, PMC_QDEER_BLOCK2, PMC_PICARD = 0, 1, 2, 3
 PMC_JAC_F32, PMC_JAC_BF16 = 0, 1
@@ -34,7 +34,8 @@ class pmc_problem(C.Structure):
                 ("n_chains", C.c_int), ("offsets", C.POINTER(C.c_int64)), ("n_steps", C.c_int64),
                 ("s0", C.c_void_p), ("noise", C.c_void_p), ("uniforms", C.c_void_p),
                 ("init_guess", C.c_void_p), ("out_states", C.c_void_p),
-                ("out_accept", C.c_void_p), ("out_gtilde", C.c_void_p)]
+                ("out_accept", C.c_void_p), ("out_gtilde", C.c_void_p), ("n_leapfrog", C.c_int),
+                ("inv_mass", C.c_void_p)]
 
 
 class pmc_options(C.Structure):
@@ -44,7 +45,7 @@ class pmc_options(C.Structure):
                 ("skip_converged_prefix", C.c_int), ("graph_sweeps", C.c_int),
                 ("trace_out", C.c_void_p), ("trace_bytes", C.c_size_t), ("floor_stall", C.c_int),
                 ("profile_kernels", C.c_int), ("jac_probes", C.c_int), ("probe_seed", C.c_uint64),
-                ("basis", C.c_void_p)]
+                ("basis", C.c_void_p), ("tie_band", C.c_double)]
 
 
 class pmc_result(C.Structure):
@@ -52,7 +53,7 @@ class pmc_result(C.Structure):
                 ("sweeps_total", C.c_int), ("n_floor", C.c_int), ("n_accept", C.c_int64), ("resid_inf", C.c_double),
                 ("resid_l2", C.c_double), ("max_ratio", C.c_double), ("nonfinite", C.c_int64),
                 ("elapsed_ms", C.c_float), ("eval_ms", C.c_float), ("scan_ms", C.c_float),
-                ("eval_steps", C.c_int64)]
+                ("eval_steps", C.c_int64), ("chain_state", C.POINTER(C.c_int8))]
 
 
 _lib = None
@@ -79,7 +80,7 @@ def lib():
                           C.POINTER(pmc_result)],
             "pmc_sample_sequential": [vp, C.POINTER(pmc_problem), C.POINTER(pmc_result)],
             "pmc_hmc_sample": [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, vp,
-                               C.POINTER(pmc_options), C.c_int, vp, vp, C.POINTER(C.c_int32),
+                               C.POINTER(pmc_options), C.c_int, vp, vp, vp, C.POINTER(C.c_int32),
                                C.POINTER(pmc_result)],
             "pmc_adjoint": [vp, C.POINTER(pmc_problem), vp, vp, vp, C.POINTER(C.c_double),
                             C.POINTER(C.c_double)],

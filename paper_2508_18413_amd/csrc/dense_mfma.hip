@@ -222,6 +222,8 @@ struct Lvl0In {  // Newton level 0: b_t = F_t - S_t from planes (FP32)
     const float *F, *S;
     int64_t ld;
     int D;
+    const ChainStatus *chain;  // window start of the (single) chain, or nullptr
+    __device__ int64_t first() const { return chain ? chain->win_start : 0; }
     __device__ float b(int64_t t, int i) const
     {
         if (i >= D) return 0.f;
@@ -232,10 +234,12 @@ struct Lvl0In {  // Newton level 0: b_t = F_t - S_t from planes (FP32)
 struct RowIn {  // standalone level 0: b_t rows [T, D]
     const float *B;
     int D;
+    __device__ int64_t first() const { return 0; }
     __device__ float b(int64_t t, int i) const { return i < D ? B[(size_t)t * D + i] : 0.f; }
 };
 struct MapIn {  // levels >= 1: B vectors [n, 32]
     const float *B;
+    __device__ int64_t first() const { return 0; }
     __device__ float b(int64_t t, int i) const { return B[(size_t)t * 32 + i]; }
 };
 
@@ -254,12 +258,18 @@ k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout, cons
     const int cnt = (int)min((int64_t)unit, n - t0);
     Chain P;
     P.identity(i, h);
+    // steps before the sliding window are the identity map with b = 0: the
+    // carry entering the window is exactly zero whatever their stale J holds
     f32x16 c;
+#pragma unroll
+    for (int r = 0; r < 16; r++) c[r] = crow(r, h) == i ? 1.f : 0.f;
     float *v = s_v[w];
     if (h == 0) v[i] = 0.f;
     wave_lds_sync();
     bool first = true;
-    for (int e = 0; e < cnt; e++) {
+    const int64_t ws = in.first();
+    const int e0 = ws > t0 ? (int)min((int64_t)cnt, ws - t0) : 0;
+    for (int e = e0; e < cnt; e++) {
         Frag A;
         if constexpr (sizeof(Frag) == sizeof(FragB))
             A.load((const uint4 *)Jv, t0 + e, lane);
@@ -316,7 +326,7 @@ template <class Frag>
 __global__ void __launch_bounds__(64 * kWPB)
 k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int64_t n,
                const float *carry_in, TilePartial *partials, double atol, double rtol, float *trace,
-               const GlobalStatus *glob)
+               const GlobalStatus *glob, const ChainStatus *chain)
 {
     // Once the status fold has stopped the chain, the sweeps still queued
     // behind it must leave S alone: F and J are no longer refreshed, and
@@ -329,11 +339,15 @@ k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int6
     const int64_t t0 = u * kU;
     const int cnt = (int)min((int64_t)kU, n - t0);
     float *v = s_v[w];
-    if (h == 0) v[i] = carry_in ? carry_in[(size_t)u * 32 + i] : 0.f;
+    // steps before the chain's sliding window are frozen: S keeps its values,
+    // delta stays zero and they add nothing to the convergence partials
+    const int64_t ws = chain ? chain->win_start : 0;
+    const int e0 = ws > t0 ? (int)min((int64_t)cnt, ws - t0) : 0;
+    if (h == 0) v[i] = (carry_in && e0 == 0) ? carry_in[(size_t)u * 32 + i] : 0.f;
     wave_lds_sync();
     PartW p{0.f, 0u, INT64_MAX, 0.0, 0.0};
     const bool own = h == 0 && i < D;
-    for (int e = 0; e < cnt; e++) {
+    for (int e = e0; e < cnt; e++) {
         const int64_t t = t0 + e;
         Frag A;
         if constexpr (sizeof(Frag) == sizeof(FragB))
@@ -516,18 +530,19 @@ static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0
 
 pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
                                     float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
-                                    double atol, double rtol, float *trace, void *ws, const GlobalStatus *glob)
+                                    double atol, double rtol, float *trace, void *ws, const GlobalStatus *glob,
+                                    const ChainStatus *chain)
 {
     const float *c0 = nullptr;
-    Lvl0In in{F, S, ld, D};
+    Lvl0In in{F, S, ld, D, chain};
     if (bf16) {
         PMC_TRY((dense_hierarchy<FragB, ChainB, Lvl0In>(ctx, J, in, n, (char *)ws, &c0, glob)));
         hipLaunchKernelGGL(k_down0_newton<FragB>, dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream,
-                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob);
+                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob, chain);
     } else {
         PMC_TRY((dense_hierarchy<FragF, ChainF, Lvl0In>(ctx, J, in, n, (char *)ws, &c0, glob)));
         hipLaunchKernelGGL(k_down0_newton<FragF>, dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream,
-                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob);
+                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob, chain);
     }
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
             xi[d] = R(0);
         }
     }
-    // orthogonal reparameterisation (Sec. 4 eq. 11): the planes hold
+    // orthogonal reparameterisation (Sec. 3.4 eq. 11): the planes hold
     // z = Q^T s, so the previous state is s = Q z (the chain's s0 is in s)
     const R *Q = (const R *)a.basis;
     if (Q && !head) {
@@ -107,6 +107,7 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
         gate = la - log(u);
         acc = gate > R(0);
         if (!(ell == ell)) acc = 0;
+        acc = sticky_decision(a, cs, t, (double)gate, acc);
     }
     R *F = (R *)a.F;
     if (Q) {
@@ -302,6 +303,7 @@ int eval_tile_steps(const DevTarget &tg) { return tg.kind == PMC_TARGET_LOGREG ?
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
 {
     if (a.n_tiles == 0) return PMC_OK;
+    if (a.hmc_L > 0) return launch_eval_hmc(ctx, t, a);
     const int D = t.dim;
     switch (t.kind) {
     case PMC_TARGET_BANANA:

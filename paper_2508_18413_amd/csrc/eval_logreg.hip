@@ -164,7 +164,8 @@ template <int MK>
 __device__ __forceinline__ void finish_step(const EvalArgs &a, const float *s_xty, const f32x16 &Gt, double dll_s,
                                             const float (&SB)[MK], const float (&DB)[MK], const float (&gB)[MK],
                                             const float (&gsc)[MK], float pp, int hh, int64_t ld, int64_t t,
-                                            int64_t tt, bool valid, bool want_j, float damp, float clip)
+                                            int64_t tt, bool valid, bool want_j, float damp, float clip,
+                                            const ChainStatus &cs)
 {
     const int D = a.D;
     const float *noise = (const float *)a.noise;
@@ -202,6 +203,7 @@ __device__ __forceinline__ void finish_step(const EvalArgs &a, const float *s_xt
         gate = (float)gd;
         acc = gd > 0.0;
         if (!(ell == ell)) acc = 0;
+        acc = sticky_decision(a, cs, t, gd, acc);
     }
     float jrej = damp;
     if (clip > 0) jrej = fminf(fmaxf(jrej, -clip), clip);
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
         float gsc[MK];
 #pragma unroll
         for (int m = 0; m < MK; m++) gsc[m] = kLn2;
-        finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip);
+        finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip, cs);
     }
 }
 
@@ -836,7 +838,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
         float gsc[MK];
 #pragma unroll
         for (int m = 0; m < MK; m++) gsc[m] = kLn2 * s_csc[2 * m + hh];
-        finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip);
+        finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip, cs);
     }
 }
 
@@ -987,6 +989,7 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
         gate = (float)gd;
         acc = gd > 0.0;
         if (!(ell == ell)) acc = 0;
+        acc = sticky_decision(a, cs, t, gd, acc);
     }
     float *F = (float *)a.F;
     float *J = (float *)a.J;

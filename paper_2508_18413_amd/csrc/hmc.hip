@@ -41,6 +41,7 @@ struct HMCArgs {
     const float *x0, *momenta, *unif;
     float *chain;
     uint8_t *accept;
+    float *logr;    // (H0 - HL) - log U per proposal, or nullptr
     int32_t *sweeps;
     int variant;  // PMC_QDEER_BLOCK2, PMC_QDEER_DIAG, PMC_PICARD
     float atol, rtol;
@@ -57,15 +58,15 @@ constexpr int kMaxLPar = 64;
 
 __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-// Sum / max over the workgroup; every thread gets the result.  `red` holds NW floats.
-template <int NW>
-__device__ float block_sum(float v, float *red)
+// Sum / max over the workgroup; every thread gets the result.  `red` holds NW values.
+template <int NW, typename T>
+__device__ T block_sum(T v, T *red)
 {
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    float s = 0.f;
+    T s = T(0);
 #pragma unroll
     for (int i = 0; i < NW; i++) s += red[i];
     return s;
@@ -92,7 +93,8 @@ __device__ float block_max(float v, float *red)
 template <int CW>
 __global__ void __launch_bounds__(kNT) k_hmc_seq(HMCArgs a)
 {
-    __shared__ float s_xb[2][kMaxD], s_mu[kMaxD], s_red[kNW];
+    __shared__ float s_xb[2][kMaxD], s_mu[kMaxD];
+    __shared__ double s_red[kNW];
     __shared__ int s_flag;
     const int tid = threadIdx.x, row = tid >> 3, c = tid & 7;
     const int D = a.D, L = a.L;
@@ -130,8 +132,8 @@ __global__ void __launch_bounds__(kNT) k_hmc_seq(HMCArgs a)
     int b = 0;  // buffer holding the current state
     for (int p = 0; p < a.n_prop; p++) {
         const float v0 = owner ? a.momenta[(size_t)p * D + row] : 0.f;
-        const float H0 = 0.5f * block_sum<kNW>(owner ? v0 * v0 : 0.f, s_red) -
-                         0.5f * block_sum<kNW>(owner ? (x - mu) * g : 0.f, s_red);
+        // energies: FP32 terms, FP64 sums (log p = -(x - mu).P(x - mu)/2 = (x - mu).g/2)
+        const double H0 = block_sum<kNW>(owner ? 0.5 * ((double)v0 * v0 - (double)(x - mu) * g) : 0.0, s_red);
         float xl = x, v = fmaf(0.5f * eps, g, v0), gl = g;
         int bl = b;
         for (int t = 1; t <= L; t++) {
@@ -143,12 +145,13 @@ __global__ void __launch_bounds__(kNT) k_hmc_seq(HMCArgs a)
             v = fmaf(eps, gl, v);
         }
         const float vf = fmaf(-0.5f * eps, gl, v);
-        const float HL = 0.5f * block_sum<kNW>(owner ? vf * vf : 0.f, s_red) -
-                         0.5f * block_sum<kNW>(owner ? (xl - mu) * gl : 0.f, s_red);
+        const double HL = block_sum<kNW>(owner ? 0.5 * ((double)vf * vf - (double)(xl - mu) * gl) : 0.0, s_red);
         if (tid == 0) {
-            const int acc = logf(a.unif[p]) < H0 - HL;
+            const double lr = (H0 - HL) - log((double)a.unif[p]);
+            const int acc = lr > 0.0;
             s_flag = acc;
             if (a.accept) a.accept[p] = (uint8_t)acc;
+            if (a.logr) a.logr[p] = (float)lr;
             if (a.sweeps) a.sweeps[p] = 0;
         }
         __syncthreads();
@@ -208,6 +211,7 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
     float *s_g = s_x + kMaxD;                     // [kMaxD] gradient at the current state
     float *s_gl = s_g + kMaxD;                    // [kMaxD] gradient at x_L
     float *s_red = s_gl + kMaxD;                  // [kParNW]
+    __shared__ double s_redd[kParNW];
     __shared__ int s_flag;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 31, hh = lane >> 5;
     const float eps = a.eps;
@@ -259,15 +263,14 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
 
     for (int p = 0; p < a.n_prop; p++) {
         const float *v0 = a.momenta + (size_t)p * D;
-        float kin = 0.f, lp = 0.f;
+        double h0 = 0.0;  // energies: FP32 terms, FP64 sums
         for (int d = tid; d < D; d += kParNT) {
             const float v = v0[d];
-            kin += v * v;
-            lp += (s_x[d] - s_mu[d]) * s_g[d];  // log p = (x - mu).g / 2
+            h0 += 0.5 * ((double)v * v - (double)(s_x[d] - s_mu[d]) * s_g[d]);  // log p = (x - mu).g / 2
             S[d] = s_x[d];
             S[D + d] = fmaf(0.5f * eps, s_g[d], v);
         }
-        const float H0 = 0.5f * block_sum<kParNW>(kin, s_red) - 0.5f * block_sum<kParNW>(lp, s_red);
+        const double H0 = block_sum<kParNW>(h0, s_redd);
         // initial guess: every s_t = s_0
         for (int o = tid; o < L * SP; o += kParNT) S[SP + o] = S[o % SP];
         __syncthreads();
@@ -331,25 +334,25 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
                 stall++;
             }
             if (ratio <= 1.f || nsw >= a.max_sweeps ||
-                (a.floor_stall > 0 && stall >= a.floor_stall && ratio <= 100.f))
+                (a.floor_stall > 0 && stall >= a.floor_stall && ratio <= 2.f))
                 break;
         }
         // gradient at x_L, reverse half step, HL, Metropolis test
         const float *sL = S + (size_t)L * SP;
         pmul(sL, 1, [&](int, int row, float v) { s_gl[row] = -v; });
         __syncthreads();
-        kin = 0.f;
-        lp = 0.f;
+        double hl = 0.0;
         for (int d = tid; d < D; d += kParNT) {
             const float v = fmaf(-0.5f * eps, s_gl[d], sL[D + d]);
-            kin += v * v;
-            lp += (sL[d] - s_mu[d]) * s_gl[d];
+            hl += 0.5 * ((double)v * v - (double)(sL[d] - s_mu[d]) * s_gl[d]);
         }
-        const float HL = 0.5f * block_sum<kParNW>(kin, s_red) - 0.5f * block_sum<kParNW>(lp, s_red);
+        const double HL = block_sum<kParNW>(hl, s_redd);
         if (tid == 0) {
-            const int acc = logf(a.unif[p]) < H0 - HL;
+            const double lr = (H0 - HL) - log((double)a.unif[p]);
+            const int acc = lr > 0.0;
             s_flag = acc;
             if (a.accept) a.accept[p] = (uint8_t)acc;
+            if (a.logr) a.logr[p] = (float)lr;
             if (a.sweeps) a.sweeps[p] = nsw;
         }
         __syncthreads();
@@ -387,7 +390,7 @@ extern "C" pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target,
                                      int L, int n_prop, const void *x0, const void *momenta,
                                      const void *unif, const pmc_options *opts,
                                      int parallel_leapfrog, void *out_chain, uint8_t *accept,
-                                     int32_t *sweeps, pmc_result *res)
+                                     float *logr, int32_t *sweeps, pmc_result *res)
 {
     PMC_REQUIRE(ctx && target && opts, "pmc_hmc_sample: NULL argument");
     const DevTarget &t = target->t;
@@ -420,6 +423,10 @@ extern "C" pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target,
                     is_device_ptr(out_chain),
                 "pmc_hmc_sample: x0, momenta, unif, out_chain must be device pointers");
     PMC_TRY_HIP(hipSetDevice(ctx->device));
+    {
+        const InputCheck in[3] = {{x0, (int64_t)D, 0}, {momenta, (int64_t)n_prop * D, 0}, {unif, n_prop, 1}};
+        PMC_TRY(check_inputs(ctx, PMC_F32, in, 3));
+    }
     PMC_TRY(ensure_pool(ctx, sizeof(int32_t) * n_prop + n_prop));
     int32_t *d_sw = (int32_t *)ctx->pool;
     uint8_t *d_acc = accept ? accept : (uint8_t *)ctx->pool + sizeof(int32_t) * n_prop;
@@ -435,6 +442,7 @@ extern "C" pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target,
     a.unif = (const float *)unif;
     a.chain = (float *)out_chain;
     a.accept = d_acc;
+    a.logr = logr;
     a.sweeps = d_sw;
     a.variant = opts->variant;
     a.atol = (float)opts->atol;

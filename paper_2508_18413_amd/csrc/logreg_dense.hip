@@ -26,7 +26,7 @@
 // dense scan reads (BF16, 2 KiB per step, or FP32, 4 KiB per step).
 //
 // k_logreg_probe_diag: quasi-DEER with the one-probe diagonal z o (J z) of
-// Sec. 4 eq. 10.  For 32 steps per wavefront, M^T = X S^T and V^T = X Z^T
+// Sec. 3.4 eq. 10.  For 32 steps per wavefront, M^T = X S^T and V^T = X Z^T
 // (Z the probe signs), U = w o V in the accumulator, then X^T U, whose
 // B operand is again the accumulator (the table xt orders X^T's K slots the
 // same way), gives (X^T W X z)_d; the diagonal planes receive

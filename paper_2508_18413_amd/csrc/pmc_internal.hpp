@@ -161,6 +161,8 @@ struct pmc_context {
     void *pool = nullptr;            // workspace pool
     size_t pool_bytes = 0;
     pmc::GlobalStatus *h_status = nullptr;  // pinned host mirror
+    uint32_t *d_bad = nullptr;       // count of invalid input values (device word)
+    uint32_t *h_bad = nullptr;       // its pinned host mirror
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t kev[3 * pmc::kSweepBatch] = {};  // per-kernel timing of one batch of sweeps
     // tuning: items per thread of the diagonal scan (0 = default)
@@ -176,6 +178,7 @@ namespace pmc {
 // bytes helper
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+
 // Layout helpers: row-major [n, D] <-> dimension-major planes [D, ld].
 pmc_status rows_to_planes(pmc_context *ctx, pmc_dtype dt, const void *rows, void *planes, int64_t n,
                           int D, int64_t ld);
@@ -188,6 +191,18 @@ pmc_status planes_to_rows(pmc_context *ctx, pmc_dtype dt, const void *planes, vo
 pmc_status broadcast_s0(pmc_context *ctx, pmc_dtype dt, const void *s0, const int64_t *d_offsets,
                         int n_chains, void *planes, int64_t n, int D, int64_t ld);
 bool is_device_ptr(const void *p);
+
+// One input array for check_inputs: n elements of the call's dtype; unit = 1
+// also requires every value to lie in (0, 1) (the accept uniforms), unit = 2
+// to be positive (inverse masses).
+struct InputCheck {
+    const void *p;
+    int64_t n;
+    int unit;
+};
+// PMC_ERR_NONFINITE if any listed array holds a non-finite value (or a
+// uniform outside (0, 1)); synchronises the context's stream.
+pmc_status check_inputs(pmc_context *ctx, pmc_dtype dt, const InputCheck *in, int n_in);  // n_in <= 5
 
 // Ensures ctx->lb_desc holds at least `bytes` (zero filled on growth).
 pmc_status ensure_lb_desc(pmc_context *ctx, size_t bytes);
@@ -270,8 +285,21 @@ struct EvalArgs {
     int probes = 0;           // 1: probed diagonal z o (J z) instead of diag(J) (JM_DIAG)
     const void *basis = nullptr;  // [D, D] orthogonal Q: iterates are z = Q^T s (per-lane targets)
     uint64_t probe_seed = 0;
+    float tie_band = 0.f;         // |g~| below this (from a chain's second sweep on): keep the
+                                  // previous sweep's decision, read from accept[t]
+    int hmc_L = 0;                // > 0: f_t is a whole HMC step with this many leapfrog steps
+    const void *inv_mass = nullptr;  // HMC: [D] diagonal of M^-1, or nullptr = identity
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
+
+// A decision whose gate lies within the tie band keeps the previous sweep's
+// value (stored in accept[t]) once the chain has run a sweep.
+__device__ __forceinline__ int sticky_decision(const EvalArgs &a, const ChainStatus &cs, int64_t t, double gate,
+                                               int acc)
+{
+    if (a.tie_band > 0.f && cs.sweeps >= 1 && fabs(gate) < (double)a.tie_band && a.accept) return a.accept[t];
+    return acc;
+}
 
 // SplitMix64 (Steele, Lea & Flood 2014): the output function applied to
 // x + 0x9E3779B97F4A7C15, modulo 2^64.  The probe sign of coordinate d at
@@ -291,7 +319,7 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
 // (BF16 or FP32) from the evaluation's accept decisions.
 pmc_status logreg_dense_tables(pmc_context *ctx, DevTarget &t);
 int logreg_dense_pair_cols(int D);  // row stride of H (D <= 32)
-// One-probe diagonal z o (J z) on the logistic posterior (Sec. 4 eq. 10):
+// One-probe diagonal z o (J z) on the logistic posterior (Sec. 3.4 eq. 10):
 // J z through X^T (w o X z) on BF16 matrix cores; writes the diagonal planes.
 pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n,
                                     int n_chains);
@@ -312,8 +340,14 @@ struct SeqArgs {
     float *gtilde;
     double eps;
     int ula;
+    int hmc_L = 0;                   // > 0: HMC transitions with this many leapfrog steps
+    const void *inv_mass = nullptr;  // HMC: [D] diagonal of M^-1, or nullptr
 };
 pmc_status launch_sequential(pmc_context *ctx, const DevTarget &tg, const SeqArgs &a);
+// HMC transitions as chain steps (Sec. 3.3): evaluation (per-lane targets and
+// the logistic posterior) and the same-GPU sequential sampler.
+pmc_status launch_eval_hmc(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
+pmc_status launch_sequential_hmc(pmc_context *ctx, const DevTarget &t, const SeqArgs &a);
 
 // Dense DEER scan on matrix cores (D <= 32, F32 states; J in the BF16 or F32
 // fragment layout written by the eval kernels).  Single sequence of n steps.
@@ -322,7 +356,8 @@ int dense_mfma_unit();
 pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
                                     float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
                                     double atol, double rtol, float *trace, void *ws,
-                                    const GlobalStatus *glob);  // n_active == 0 at launch: no-op
+                                    const GlobalStatus *glob,    // n_active == 0 at launch: no-op
+                                    const ChainStatus *chain);   // its window start, or nullptr
 pmc_status launch_linrec_dense_mfma(pmc_context *ctx, int bf16, int D, int64_t T, const float *A,
                                     const float *b, float *out);
 // Same on J already in the fragment layout; ws: dense_mfma_ws_bytes(T) bytes.

@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "pmc_internal.hpp"
@@ -175,6 +176,67 @@ pmc_status broadcast_s0(pmc_context *ctx, pmc_dtype dt, const void *s0, const in
     return PMC_OK;
 }
 
+namespace {
+// Counts the entries of up to four input arrays that are not finite (and, for
+// arrays flagged `unit`, that lie outside the open interval (0, 1)).
+struct BadScan {
+    const void *p[5];
+    int64_t n[5];
+    int unit[5];  // 0: finite; 1: in (0, 1); 2: positive and finite
+};
+template <typename R>
+__global__ void __launch_bounds__(256) k_count_bad(BadScan s, uint32_t *out)
+{
+    uint32_t c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        const R *a = (const R *)s.p[k];
+        if (!a) continue;
+        const int kind = s.unit[k];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n[k]; i += stride) {
+            const R v = a[i];
+            const bool bad = !isfinite(v) || (kind == 1 && !(v > R(0) && v < R(1))) || (kind == 2 && !(v > R(0)));
+            c += bad ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+}  // namespace
+
+pmc_status check_inputs(pmc_context *ctx, pmc_dtype dt, const InputCheck *in, int n_in)
+{
+    PMC_REQUIRE(n_in >= 0 && n_in <= 5, "check_inputs: at most 5 arrays");
+    BadScan s;
+    int64_t most = 0;
+    for (int k = 0; k < 5; k++) {
+        s.p[k] = k < n_in && in[k].n > 0 ? in[k].p : nullptr;
+        s.n[k] = k < n_in ? in[k].n : 0;
+        s.unit[k] = k < n_in ? in[k].unit : 0;
+        if (s.p[k]) most = std::max(most, s.n[k]);
+    }
+    if (most == 0) return PMC_OK;
+    hipStream_t st = ctx->stream;
+    *ctx->h_bad = 0;
+    PMC_TRY_HIP(hipMemcpyAsync(ctx->d_bad, ctx->h_bad, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    const unsigned blocks = (unsigned)std::min<int64_t>((most + 255) / 256, 2048);
+    if (dt == PMC_F64)
+        hipLaunchKernelGGL(k_count_bad<double>, dim3(blocks), dim3(256), 0, st, s, ctx->d_bad);
+    else
+        hipLaunchKernelGGL(k_count_bad<float>, dim3(blocks), dim3(256), 0, st, s, ctx->d_bad);
+    PMC_TRY_HIP(hipGetLastError());
+    PMC_TRY_HIP(hipMemcpyAsync(ctx->h_bad, ctx->d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PMC_TRY_HIP(hipStreamSynchronize(st));
+    if (*ctx->h_bad) {
+        set_error("%u input values are not finite (or uniforms outside (0, 1), or inverse masses not positive)",
+                  *ctx->h_bad);
+        return PMC_ERR_NONFINITE;
+    }
+    return PMC_OK;
+}
+
 bool is_device_ptr(const void *p)
 {
     if (!p) return false;
@@ -224,6 +286,8 @@ pmc_status pmc_create(pmc_context **out, int device, void *hip_stream)
     if (hipMalloc((void **)&ctx->sync, sizeof(ScanSync) * kMaxSyncSlots) != hipSuccess ||
         hipMemset(ctx->sync, 0, sizeof(ScanSync) * kMaxSyncSlots) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_status, sizeof(GlobalStatus)) != hipSuccess ||
+        hipMalloc((void **)&ctx->d_bad, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_bad, sizeof(uint32_t)) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
         set_error("pmc_create: device initialisation failed");
         pmc_destroy(ctx);
@@ -251,6 +315,8 @@ pmc_status pmc_destroy(pmc_context *ctx)
     if (ctx->lb_desc) (void)hipFree(ctx->lb_desc);
     if (ctx->pool) (void)hipFree(ctx->pool);
     if (ctx->h_status) (void)hipHostFree(ctx->h_status);
+    if (ctx->d_bad) (void)hipFree(ctx->d_bad);
+    if (ctx->h_bad) (void)hipHostFree(ctx->h_bad);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->kev)

@@ -1546,8 +1546,10 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
                 cs.active = 0;
             } else if (cs.sweeps >= a.max_iter) {
                 cs.active = 0;
-            } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 100.f) {
-                // rounding floor: no progress for floor_stall sweeps within 100x of the tolerance
+            } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f) {
+                // rounding floor: no progress for floor_stall sweeps with the last change within
+                // twice the tolerance (the state error of a change-based stop is a few times the
+                // last change, so this keeps it near the converged chains' error)
                 cs.at_floor = 1;
                 cs.active = 0;
             } else if (a.skip_prefix && fb != INT64_MAX) {

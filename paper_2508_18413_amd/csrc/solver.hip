@@ -45,7 +45,8 @@ struct Plan {
         o_global, total;
     int max_iter;
     bool logreg_dense = false;  // dense J of the logistic posterior (pair sums in o_hpair)
-    bool logreg_probe = false;  // probed diagonal of the logistic posterior
+    bool logreg_probe = false;  // probed diagonal of the logistic posterior (MALA)
+    bool hmc = false;           // f_t is a whole HMC transition (Sec. 3.3)
     const void *basis = nullptr;  // orthogonal reparameterisation (iterates z = Q^T s)
     size_t o_rot = 0;             // rotation scratch planes [D, ld]
     size_t o_hpair = 0;
@@ -79,8 +80,10 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     pl.dt = t.dtype;
     pl.es = t.dtype == PMC_F64 ? 8 : 4;
     pl.D = t.dim;
-    PMC_REQUIRE(p->sampler == PMC_SAMPLER_MALA || p->sampler == PMC_SAMPLER_ULA,
-                "pmc_solve: sampler must be MALA or ULA");
+    PMC_REQUIRE(p->sampler == PMC_SAMPLER_MALA || p->sampler == PMC_SAMPLER_ULA || p->sampler == PMC_SAMPLER_HMC,
+                "pmc_solve: sampler must be MALA, ULA or HMC");
+    pl.hmc = p->sampler == PMC_SAMPLER_HMC;
+    if (pl.hmc) PMC_REQUIRE(p->n_leapfrog >= 1 && p->n_leapfrog <= 1024, "pmc_solve: HMC needs 1 <= n_leapfrog <= 1024");
     PMC_REQUIRE(p->n_chains >= 1, "pmc_solve: n_chains >= 1 (got %d)", p->n_chains);
     PMC_REQUIRE(p->step_size > 0 && isfinite(p->step_size), "pmc_solve: step_size > 0");
     PMC_REQUIRE(o->atol >= 0 && o->rtol >= 0 && (o->atol > 0 || o->rtol > 0),
@@ -108,8 +111,10 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         PMC_REQUIRE(is_device_ptr(p->s0), "pmc_solve: s0 must be a device pointer");
         PMC_REQUIRE(is_device_ptr(p->noise), "pmc_solve: noise must be a device pointer");
         PMC_REQUIRE(is_device_ptr(p->out_states), "pmc_solve: out_states must be a device pointer");
-        if (p->sampler == PMC_SAMPLER_MALA)
-            PMC_REQUIRE(is_device_ptr(p->uniforms), "pmc_solve: MALA needs device uniforms");
+        if (p->sampler != PMC_SAMPLER_ULA)
+            PMC_REQUIRE(is_device_ptr(p->uniforms), "pmc_solve: MALA and HMC need device uniforms");
+        if (pl.hmc && p->inv_mass)
+            PMC_REQUIRE(is_device_ptr(p->inv_mass), "pmc_solve: inv_mass must be a device pointer");
         if (p->init_guess)
             PMC_REQUIRE(is_device_ptr(p->init_guess), "pmc_solve: init_guess must be a device pointer");
     }
@@ -119,6 +124,23 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     }
     pl.variant = o->variant;
     pl.n_lanes = pl.D;
+    if (pl.hmc) {
+        // HMC transitions (Sec. 3.3): dense J for D <= 4 on the vector scan;
+        // the logistic posterior takes the one-probe diagonal (its exact
+        // diagonal would need one tangent integration per coordinate)
+        if (o->variant == PMC_DEER_DENSE && (t.kind == PMC_TARGET_LOGREG || pl.D > 4)) {
+            set_error("pmc_solve: HMC with dense DEER supports per-lane targets with D <= 4");
+            return PMC_ERR_UNSUPPORTED;
+        }
+        if (t.kind == PMC_TARGET_LOGREG && o->variant == PMC_QDEER_DIAG && o->jac_probes != 1) {
+            set_error("pmc_solve: HMC on logistic regression takes the one-probe diagonal (jac_probes = 1)");
+            return PMC_ERR_UNSUPPORTED;
+        }
+        if (o->basis) {
+            set_error("pmc_solve: basis is not supported with HMC transitions");
+            return PMC_ERR_UNSUPPORTED;
+        }
+    }
     switch (o->variant) {
     case PMC_QDEER_DIAG: pl.jmode = JM_DIAG; break;
     case PMC_PICARD: pl.jmode = JM_NONE; break;
@@ -138,7 +160,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
             pl.logreg_dense = true;
             break;
         }
-        if (pl.dt == PMC_F64 || (pl.D <= 4 && o->jac_prec == PMC_JAC_F32)) {
+        if (pl.dt == PMC_F64 || (pl.D <= 4 && o->jac_prec == PMC_JAC_F32) || pl.hmc) {
             if (pl.D > 4) {
                 set_error("pmc_solve: FP64 dense DEER supports D <= 4 (got %d)", pl.D);
                 return PMC_ERR_UNSUPPORTED;
@@ -165,6 +187,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     }
     PMC_REQUIRE(o->gate == PMC_GATE_FROZEN || o->gate == PMC_GATE_SURROGATE, "pmc_solve: bad gate");
     PMC_REQUIRE(o->damping > 0 && isfinite(o->damping), "pmc_solve: damping must be > 0");
+    PMC_REQUIRE(o->tie_band >= 0 && isfinite(o->tie_band), "pmc_solve: tie_band must be >= 0");
     if (t.kind == PMC_TARGET_LOGREG && o->gate == PMC_GATE_SURROGATE && p->sampler == PMC_SAMPLER_MALA) {
         set_error("pmc_solve: logistic regression supports the frozen gate only");
         return PMC_ERR_UNSUPPORTED;
@@ -173,7 +196,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     PMC_REQUIRE(o->jac_probes == 0 || o->jac_probes == 1, "pmc_solve: jac_probes is 0 or 1");
     if (o->jac_probes) {
         PMC_REQUIRE(o->variant == PMC_QDEER_DIAG, "pmc_solve: jac_probes needs the diagonal variant");
-        if (t.kind == PMC_TARGET_LOGREG) {
+        if (t.kind == PMC_TARGET_LOGREG && !pl.hmc) {
             // J z through the matrix-core kernel of logreg_dense.hip
             if (pl.D > 32) {
                 set_error("pmc_solve: probed diagonals on logistic regression support D <= 32 (got %d)", pl.D);
@@ -282,7 +305,8 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
                                          (float *)sw.sa.S, sw.sa.ld, pl.D, pl.n, sw.sa.partials,
-                                         sw.sa.atol, sw.sa.rtol, nullptr, sw.hier, sw.ea.glob));
+                                         sw.sa.atol, sw.sa.rtol, nullptr, sw.hier, sw.ea.glob,
+                                         sw.sa.chains));
     else if (pl.jmode == JM_DENSE_ROW)
         PMC_TRY(launch_newton_scan_dense_small(ctx, pl.dt, pl.D, sw.sa));
     else
@@ -318,7 +342,7 @@ pmc_status rotate_rows(pmc_context *ctx, const void *in, int64_t rows, int ld_in
     return PMC_OK;
 }
 
-// The logistic posterior in the coordinates z = Q^T s (Sec. 4 eq. 11) is the
+// The logistic posterior in the coordinates z = Q^T s (Sec. 3.4 eq. 11) is the
 // same model with design X Q (the prior N(0, prior_var I) is unchanged by a
 // rotation) and MALA noise Q^T xi, so quasi-DEER's diag(Q^T J Q) is the
 // rotated model's exact Jacobian diagonal.  The rotated target, noise, s0
@@ -421,6 +445,7 @@ pmc_status pmc_default_options(pmc_options *o, pmc_dtype dtype)
     o->clip = 0.0;
     o->skip_converged_prefix = 1;
     o->floor_stall = 16;
+    o->tie_band = dtype == PMC_F64 ? 0.0 : 2e-5;
     return PMC_OK;
 }
 
@@ -434,8 +459,14 @@ pmc_status pmc_workspace_size(pmc_context *ctx, const pmc_problem *prob, const p
     return PMC_OK;
 }
 
-pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
-                     void *workspace, size_t ws_bytes, pmc_result *res)
+}  // extern "C"
+
+namespace pmc {
+namespace {
+// pmc_solve's body.  scratch_ws: the workspace is the static scratch array
+// (its address is not a runtime allocation, so it is not checked as one).
+pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts, void *workspace,
+                      size_t ws_bytes, pmc_result *res, bool scratch_ws)
 {
     Plan pl;
     PMC_TRY(make_plan(ctx, prob, opts, pl));
@@ -444,21 +475,32 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     if (res) {
         int32_t *spc = res->sweeps_per_chain;
+        int8_t *cst = res->chain_state;
         memset(res, 0, sizeof(*res));
         res->sweeps_per_chain = spc;
+        res->chain_state = cst;
     }
     if (pl.n == 0) {
         if (res) {
             res->n_converged = pl.n_chains;
             if (res->sweeps_per_chain) memset(res->sweeps_per_chain, 0, 4 * pl.n_chains);
+            if (res->chain_state) memset(res->chain_state, 0, pl.n_chains);
         }
         return PMC_OK;
+    }
+    {
+        const InputCheck in[5] = {{prob->s0, (int64_t)pl.n_chains * pl.D, 0},
+                                  {prob->noise, pl.n * pl.D, 0},
+                                  {prob->sampler != PMC_SAMPLER_ULA ? prob->uniforms : nullptr, pl.n, 1},
+                                  {prob->init_guess, prob->init_guess ? pl.n * pl.D : 0, 0},
+                                  {pl.hmc ? prob->inv_mass : nullptr, pl.D, 2}};
+        PMC_TRY(check_inputs(ctx, pl.dt, in, 5));
     }
     char *ws;
     if (workspace) {
         PMC_REQUIRE(ws_bytes >= pl.total, "pmc_solve: workspace of %zu bytes < %zu needed", ws_bytes,
                     pl.total);
-        PMC_REQUIRE(is_device_ptr(workspace), "pmc_solve: workspace must be a device pointer");
+        PMC_REQUIRE(scratch_ws || is_device_ptr(workspace), "pmc_solve: workspace must be a device pointer");
         ws = (char *)workspace;
     } else {
         PMC_TRY(ensure_pool(ctx, pl.total));
@@ -549,6 +591,8 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     ea.gtilde = gt;
     ea.eps = prob->step_size;
     ea.ula = prob->sampler == PMC_SAMPLER_ULA;
+    ea.hmc_L = pl.hmc ? prob->n_leapfrog : 0;
+    ea.inv_mass = pl.hmc ? prob->inv_mass : nullptr;
     ea.gate = opts->gate;
     ea.damping = opts->damping;
     ea.clip = opts->clip;
@@ -557,6 +601,7 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
     ea.probes = opts->jac_probes;
     ea.basis = pl.basis;
     ea.probe_seed = opts->probe_seed;
+    ea.tie_band = (float)opts->tie_band;
     ea.tg = pl.tg;
     ea.glob = d_glob;
     NewtonScanArgs &sa = sw.sa;
@@ -707,22 +752,43 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
         res->eval_steps = opts->profile_kernels ? hs->eval_steps : 0;
         if (res->sweeps_per_chain)
             for (int c = 0; c < pl.n_chains; c++) res->sweeps_per_chain[c] = hc[c].sweeps;
+        if (res->chain_state)
+            for (int c = 0; c < pl.n_chains; c++)
+                res->chain_state[c] = (int8_t)(hc[c].converged ? 0 : hc[c].at_floor ? 1 : 2);
     }
     if (res) res->n_floor = hs->n_floor;
-    if (hs->n_converged + hs->n_floor < pl.n_chains) {
-        set_error("pmc_solve: %d of %d chains not converged after %d sweeps (max ratio %g)",
-                  pl.n_chains - hs->n_converged, pl.n_chains, hs->sweeps, (double)hs->max_ratio);
+    // a chain stopped at its rounding floor has not met the tolerance: its
+    // outputs are valid but the call reports the soft status
+    if (hs->n_converged < pl.n_chains) {
+        set_error("pmc_solve: %d of %d chains not converged after %d sweeps (%d stopped at their rounding "
+                  "floor; max ratio %g)",
+                  pl.n_chains - hs->n_converged, pl.n_chains, hs->sweeps, hs->n_floor, (double)hs->max_ratio);
         return PMC_NOT_CONVERGED;
     }
     return PMC_OK;
+}
+
+}  // namespace
+}  // namespace pmc
+
+extern "C" {
+
+pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                     void *workspace, size_t ws_bytes, pmc_result *res)
+{
+    return solve_impl(ctx, prob, opts, workspace, ws_bytes, res, false);
 }
 
 pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_result *res)
 {
     PMC_REQUIRE(ctx && p && p->target, "pmc_sample_sequential: NULL argument");
     const DevTarget &t = p->target->t;
-    PMC_REQUIRE(p->sampler == PMC_SAMPLER_MALA || p->sampler == PMC_SAMPLER_ULA,
-                "pmc_sample_sequential: sampler must be MALA or ULA");
+    PMC_REQUIRE(p->sampler == PMC_SAMPLER_MALA || p->sampler == PMC_SAMPLER_ULA || p->sampler == PMC_SAMPLER_HMC,
+                "pmc_sample_sequential: sampler must be MALA, ULA or HMC");
+    const bool hmc = p->sampler == PMC_SAMPLER_HMC;
+    if (hmc)
+        PMC_REQUIRE(p->n_leapfrog >= 1 && p->n_leapfrog <= 1024,
+                    "pmc_sample_sequential: HMC needs 1 <= n_leapfrog <= 1024");
     PMC_REQUIRE(p->n_chains >= 1, "pmc_sample_sequential: n_chains >= 1");
     std::vector<int64_t> offs(p->n_chains + 1, 0);
     if (p->offsets) {
@@ -738,15 +804,26 @@ pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_res
     }
     if (res) {
         int32_t *spc = res->sweeps_per_chain;
+        int8_t *cst = res->chain_state;
         memset(res, 0, sizeof(*res));
         res->sweeps_per_chain = spc;
+        res->chain_state = cst;
     }
     if (p->n_steps == 0) return PMC_OK;
     PMC_REQUIRE(is_device_ptr(p->s0) && is_device_ptr(p->noise) && is_device_ptr(p->out_states),
                 "pmc_sample_sequential: s0, noise and out_states must be device pointers");
-    if (p->sampler == PMC_SAMPLER_MALA)
-        PMC_REQUIRE(is_device_ptr(p->uniforms), "pmc_sample_sequential: MALA needs device uniforms");
+    if (p->sampler != PMC_SAMPLER_ULA)
+        PMC_REQUIRE(is_device_ptr(p->uniforms), "pmc_sample_sequential: MALA and HMC need device uniforms");
+    if (hmc && p->inv_mass)
+        PMC_REQUIRE(is_device_ptr(p->inv_mass), "pmc_sample_sequential: inv_mass must be a device pointer");
     PMC_TRY_HIP(hipSetDevice(ctx->device));
+    {
+        const InputCheck in[4] = {{p->s0, (int64_t)p->n_chains * t.dim, 0},
+                                  {p->noise, p->n_steps * t.dim, 0},
+                                  {p->sampler != PMC_SAMPLER_ULA ? p->uniforms : nullptr, p->n_steps, 1},
+                                  {hmc ? p->inv_mass : nullptr, t.dim, 2}};
+        PMC_TRY(check_inputs(ctx, t.dtype, in, 4));
+    }
     PMC_TRY(ensure_pool(ctx, sizeof(int64_t) * offs.size()));
     int64_t *d_offs = (int64_t *)ctx->pool;
     hipStream_t st = ctx->stream;
@@ -758,14 +835,19 @@ pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_res
     a.D = t.dim;
     a.s0 = p->s0;
     a.noise = p->noise;
-    a.unif = p->sampler == PMC_SAMPLER_MALA ? p->uniforms : nullptr;
+    a.unif = p->sampler != PMC_SAMPLER_ULA ? p->uniforms : nullptr;
     a.out = p->out_states;
     a.accept = p->out_accept;
     a.gtilde = p->out_gtilde;
     a.eps = p->step_size;
     a.ula = p->sampler == PMC_SAMPLER_ULA;
+    a.hmc_L = hmc ? p->n_leapfrog : 0;
+    a.inv_mass = hmc ? p->inv_mass : nullptr;
     PMC_TRY_HIP(hipEventRecord(ctx->ev0, st));
-    PMC_TRY(launch_sequential(ctx, t, a));
+    if (hmc)
+        PMC_TRY(launch_sequential_hmc(ctx, t, a));
+    else
+        PMC_TRY(launch_sequential(ctx, t, a));
     PMC_TRY_HIP(hipEventRecord(ctx->ev1, st));
     PMC_TRY_HIP(hipStreamSynchronize(st));
     float ms = 0;

@@ -185,8 +185,9 @@ class Batch:
     x0: np.ndarray          # [B, D]
     xi: np.ndarray          # [sum T, D]
     u: np.ndarray           # [sum T]
-    burn_xi: np.ndarray     # [B, 3, D]
-    burn_u: np.ndarray      # [B, 3]
+    burn_xi: np.ndarray     # [B, n_burn, D] (3 MALA steps, or 5 HMC steps)
+    burn_u: np.ndarray      # [B, n_burn]
+    L: int = 0              # HMC transitions: leapfrog steps per transition
 
     @property
     def n_chains(self):
@@ -221,3 +222,28 @@ def logreg_batch(seed: int = 0, n_chains: int = 512, lo: int = 4096, hi: int = 1
         xi[off[c]:off[c + 1]] = normals(_rng(seed, 3 + 16 * c), (T, dim), np.float32)
         u[off[c]:off[c + 1]] = uniforms(_rng(seed, 4 + 16 * c), T, np.float32)
     return Batch(target=tg, eps=eps, offsets=off, x0=x0, xi=xi, u=u, burn_xi=bxi, burn_u=bu)
+
+
+def logreg_hmc_batch(seed: int = 0, n_chains: int = 4, T: int = 1000, eps: float = 0.04, L: int = 4,
+                     n_data: int = 1000, dim: int = 25, n_burn: int = 5) -> Batch:
+    """HMC across the sequence on the logistic posterior with the settings of
+    App. B.4: n_chains chains of T whole HMC transitions (L leapfrog steps of
+    size eps), momentum draws xi_t ~ N(0, I) and uniforms u_t per transition,
+    each chain started after n_burn sequential transitions from x0 ~ N(0, I)
+    (their draws in burn_xi / burn_u; the consumer runs them)."""
+    tg = logreg_target(seed, n_data, dim)
+    off = np.arange(n_chains + 1, dtype=np.int64) * T
+    xi = np.empty((off[-1], dim), dtype=np.float32)
+    u = np.empty(off[-1], dtype=np.float32)
+    x0 = np.empty((n_chains, dim), dtype=np.float32)
+    bxi = np.empty((n_chains, n_burn, dim), dtype=np.float32)
+    bu = np.empty((n_chains, n_burn), dtype=np.float32)
+    for c in range(n_chains):
+        r1 = _rng(seed, 1 + 16 * c)
+        r2 = _rng(seed, 2 + 16 * c)
+        x0[c] = normals(r1, dim, np.float32)
+        bxi[c] = normals(r2, (n_burn, dim), np.float32)
+        bu[c] = uniforms(r2, n_burn, np.float32)
+        xi[off[c]:off[c + 1]] = normals(_rng(seed, 3 + 16 * c), (T, dim), np.float32)
+        u[off[c]:off[c + 1]] = uniforms(_rng(seed, 4 + 16 * c), T, np.float32)
+    return Batch(target=tg, eps=eps, offsets=off, x0=x0, xi=xi, u=u, burn_xi=bxi, burn_u=bu, L=L)

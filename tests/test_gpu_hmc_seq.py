@@ -1,0 +1,257 @@
+"""GPU parity of parallel HMC across the sequence (Sec. 3.3, "Parallel HMC with
+Sequential Leapfrog Integration"; settings of App. B.4): every chain step f_t
+is a whole HMC transition, solved for all t at once by Newton sweeps, against
+the FP64 oracle's sequential chain of the same transitions on the same
+momentum draws and uniforms.
+
+Bars as for MALA (tests/parity.py): FP64 state error <= 1e-10 with accept
+patterns identical up to near-ties; FP32 state error <= 1e-5 with the
+FP32-floor tie class bounded by HMC_SEQ_FP32_GATE_ERR, the pinned FP32 error
+of the gate on these targets (test_hmc_seq_gate_precision)."""
+import numpy as np
+import pytest
+
+from conftest import oracle_target
+from parity import compare_with_resync, floor_cap, record, state_error
+from paper_2508_18413_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+# Pinned bound on |g~ - g~*| of one FP32 HMC transition evaluated from given
+# states (test_hmc_seq_gate_precision): the energy difference is assembled from
+# FP32 leapfrog states, so it carries their rounding.
+HMC_SEQ_FP32_GATE_ERR = 1e-4
+
+
+def _t(x, dtype=None):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_2508_18413_amd as pm
+    return pm
+
+
+@pytest.fixture(scope="module")
+def ctx(pm):
+    c = pm.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _check(orc, tg, ch, L, x0, got_states, got_acc, fp32, label, inv_mass=None, tol=None):
+    st, acc, rep = compare_with_resync(
+        lambda f: orc.hmc_seq_chain(tg, ch.eps, L, np.asarray(x0, np.float64), ch.xi, ch.u, force=f,
+                                    inv_mass=inv_mass), got_acc,
+        floor_band=HMC_SEQ_FP32_GATE_ERR if fp32 else None)
+    err = state_error(got_states, st)
+    n = len(got_acc)
+    n_tie, n_floor = record(label, n, err, rep)
+    _say(f"  state_error={err:.3e} near-ties={n_tie} fp32-floor={n_floor} acceptance={np.mean(got_acc):.3f} {rep}")
+    assert not [x for x in rep if x[2] == "failure"], rep
+    assert n_floor <= floor_cap(n)
+    assert err <= (tol if tol is not None else (1e-5 if fp32 else 1e-10))
+    return err
+
+
+# Fig. 1 analogue: the banana with L = 8 leapfrog steps of 0.5; full DEER
+# damped by 0.5 and clipped to [-1, 1] (App. B.4), and the other updates
+@pytest.mark.parametrize("variant,kw", [("dense", dict(damping=0.5, clip=1.0)), ("dense", {}),
+                                        ("diag", {}), ("diag", dict(jac_probes=1, probe_seed=3)),
+                                        ("picard", {})])
+@pytest.mark.parametrize("gate", ["surrogate", "frozen"])
+def test_hmc_seq_banana_fp64(ctx, pm, orc, variant, kw, gate):
+    _say(f"hmc across the sequence: banana fp64 {variant} {kw} gate={gate}")
+    ch = W.banana_chain(T=1024, seed=4, eps=0.5)
+    L = 8
+    tg = orc.Target(orc.BANANA, 2)
+    g = pm.Target(ctx, ch.target, dtype=torch.float64)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), sampler="hmc", n_leapfrog=L, variant=variant,
+                 gate=gate, max_iter=ch.T + 1, **kw)
+    _say(f"  sweeps={r.sweeps} status={r.status}")
+    assert r.status == 0
+    _check(orc, tg, ch, L, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy(), False,
+           f"hmc-seq banana {variant} {gate}")
+
+
+def test_hmc_seq_sequential_sampler(ctx, pm, orc):
+    """The same-GPU sequential sampler of the same transitions (FP64 banana,
+    FP32 funnel with a diagonal mass matrix)."""
+    _say("hmc across the sequence: sequential sampler")
+    ch = W.banana_chain(T=1024, seed=4, eps=0.5)
+    g = pm.Target(ctx, ch.target, dtype=torch.float64)
+    r = pm.sample_sequential(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), sampler="hmc", n_leapfrog=8)
+    _check(orc, orc.Target(orc.BANANA, 2), ch, 8, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy(), False,
+           "hmc-seq banana sequential")
+    fc = W.funnel_chain(T=2048, seed=2, eps=0.08, dim=8)
+    im = np.linspace(0.5, 1.5, 8)
+    gf = pm.Target(ctx, fc.target)
+    r = pm.sample_sequential(ctx, gf, fc.eps, _t(fc.x0), _t(fc.xi), _t(fc.u), sampler="hmc", n_leapfrog=5,
+                             inv_mass=_t(im, torch.float32))
+    _check(orc, oracle_target(fc.target), fc, 5, fc.x0, r.states.cpu().numpy(), r.accept.cpu().numpy(), True,
+           "hmc-seq funnel fp32 sequential", inv_mass=im.astype(np.float32).astype(np.float64))
+
+
+def _gate_at(orc, tg, eps, L, s0, xi, u, states, inv_mass=None):
+    prev = np.concatenate([np.asarray(s0, np.float64)[None, :], np.asarray(states, np.float64)[:-1]])
+    return np.array([orc.hmc_step(tg, eps, L, prev[t], xi[t], u[t], inv_mass=inv_mass)[2]
+                     for t in range(prev.shape[0])])
+
+
+def test_hmc_seq_gate_precision(ctx, pm, orc):
+    """One FP32 evaluation sweep at the oracle's trajectory (rounded to FP32):
+    each step's gate against the oracle's from the same FP32 states.  Pins
+    HMC_SEQ_FP32_GATE_ERR; decisions with a margin beyond it must agree."""
+    _say("hmc across the sequence: FP32 gate precision")
+    fc = W.funnel_chain(T=2048, seed=5, eps=0.08, dim=8)
+    tg = oracle_target(fc.target)
+    L = 5
+    st, _, _ = orc.hmc_seq_chain(tg, fc.eps, L, fc.x0.astype(np.float64), fc.xi, fc.u)
+    init = st.astype(np.float32)
+    ref = _gate_at(orc, tg, fc.eps, L, fc.x0, fc.xi, fc.u, init)
+    g = pm.Target(ctx, fc.target)
+    r = pm.solve(ctx, g, fc.eps, _t(fc.x0), _t(fc.xi), _t(fc.u), sampler="hmc", n_leapfrog=L, variant="diag",
+                 max_iter=1, init_guess=_t(init))
+    got = r.gtilde.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(ref) & (np.abs(ref) < 1e3)
+    err = np.abs(got - ref)[fin]
+    _say(f"  max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() <= HMC_SEQ_FP32_GATE_ERR
+    clear = np.abs(ref) > HMC_SEQ_FP32_GATE_ERR
+    assert np.array_equal(r.accept.cpu().numpy()[clear].astype(bool), ref[clear] > 0)
+
+
+# A damped update converges linearly, so a stop on the change between sweeps
+# leaves a larger multiple of the tolerance as state error: damped runs stop
+# at 1e-7 instead of the default 5e-7.
+DAMPED_TOL = dict(atol=1e-7, rtol=1e-7)
+
+
+@pytest.mark.parametrize("variant,kw", [("diag", {}), ("diag", dict(jac_probes=1, probe_seed=9)),
+                                        ("diag", dict(damping=0.4, clip=1.0, **DAMPED_TOL)), ("picard", {})])
+def test_hmc_seq_funnel_fp32_mass(ctx, pm, orc, variant, kw):
+    _say(f"hmc across the sequence: funnel fp32 D=8, diagonal mass, {variant} {kw}")
+    fc = W.funnel_chain(T=2048, seed=2, eps=0.08, dim=8)
+    im = np.linspace(0.5, 1.5, 8).astype(np.float32)
+    g = pm.Target(ctx, fc.target)
+    r = pm.solve(ctx, g, fc.eps, _t(fc.x0), _t(fc.xi), _t(fc.u), sampler="hmc", n_leapfrog=5, variant=variant,
+                 gate="surrogate", inv_mass=_t(im), max_iter=fc.T + 1, **kw)
+    _say(f"  sweeps={r.sweeps} status={r.status}")
+    assert r.status == 0
+    _check(orc, oracle_target(fc.target), fc, 5, fc.x0, r.states.cpu().numpy(), r.accept.cpu().numpy(), True,
+           f"hmc-seq funnel fp32 {variant} {kw}", inv_mass=im.astype(np.float64))
+
+
+def test_hmc_seq_batched_uneven(ctx, pm, orc):
+    """Several banana chains of uneven length in one solve."""
+    _say("hmc across the sequence: batched uneven chains")
+    lens = [1, 37, 256, 700]
+    chs = [W.banana_chain(T=n, seed=20 + i, eps=0.5) for i, n in enumerate(lens)]
+    off = np.concatenate([[0], np.cumsum(lens)])
+    x0 = np.stack([c.x0 for c in chs])
+    xi = np.concatenate([c.xi for c in chs])
+    u = np.concatenate([c.u for c in chs])
+    g = pm.Target(ctx, chs[0].target, dtype=torch.float64)
+    r = pm.solve(ctx, g, 0.5, _t(x0), _t(xi), _t(u), offsets=list(off), sampler="hmc", n_leapfrog=8,
+                 variant="dense", damping=0.5, clip=1.0, max_iter=int(max(lens)) + 1)
+    assert r.status == 0
+    st, acc = r.states.cpu().numpy(), r.accept.cpu().numpy()
+    for i, c in enumerate(chs):
+        _check(orc, orc.Target(orc.BANANA, 2), c, 8, c.x0, st[off[i]:off[i + 1]], acc[off[i]:off[i + 1]], False,
+               f"hmc-seq banana batch chain {i}")
+
+
+def test_hmc_seq_refusals(ctx, pm):
+    from paper_2508_18413_amd import _binding as B
+    fc = W.funnel_chain(T=64, seed=2, eps=0.08, dim=8)
+    g = pm.Target(ctx, fc.target)
+    args = (ctx, g, fc.eps, _t(fc.x0), _t(fc.xi), _t(fc.u))
+    with pytest.raises(B.PMCError) as e:  # dense HMC needs D <= 4
+        pm.solve(*args, sampler="hmc", n_leapfrog=3, variant="dense")
+    assert e.value.status == B.PMC_ERR_UNSUPPORTED
+    with pytest.raises(B.PMCError) as e:
+        pm.solve(*args, sampler="hmc", n_leapfrog=0, variant="diag")
+    assert e.value.status == B.PMC_ERR_INVALID
+    with pytest.raises(B.PMCError) as e:  # inverse masses must be positive
+        pm.solve(*args, sampler="hmc", n_leapfrog=3, variant="diag", inv_mass=_t(np.zeros(8, np.float32)))
+    assert e.value.status == B.PMC_ERR_NONFINITE
+    bad = fc.xi.copy()
+    bad[3, 2] = np.nan
+    with pytest.raises(B.PMCError) as e:
+        pm.solve(ctx, g, fc.eps, _t(fc.x0), _t(bad), _t(fc.u), sampler="hmc", n_leapfrog=3, variant="diag")
+    assert e.value.status == B.PMC_ERR_NONFINITE
+
+
+# ------------------------------------------------- logistic posterior (App. B.4)
+
+def _logreg_hmc(orc, n_chains=4, T=1000, seed=0):
+    b = W.logreg_hmc_batch(seed=seed, n_chains=n_chains, T=T)
+    tg = oracle_target(b.target)
+    # 5 sequential burn-in transitions per chain (App. B.4) by the oracle, rounded to FP32
+    s0 = np.stack([orc.hmc_seq_chain(tg, b.eps, b.L, b.x0[c].astype(np.float64), b.burn_xi[c], b.burn_u[c])[0][-1]
+                   for c in range(b.n_chains)]).astype(np.float32)
+    return b, tg, s0
+
+
+def test_hmc_seq_logreg_gate_precision(ctx, pm, orc):
+    """One evaluation sweep at the oracle's trajectory (rounded to FP32) of
+    the logistic posterior: the gate of each transition against the oracle's
+    from the same FP32 states, and the decisions beyond the pinned bound."""
+    _say("hmc across the sequence: logistic posterior, FP32 gate precision")
+    b, tg, s0 = _logreg_hmc(orc, n_chains=1, T=512, seed=1)
+    st, _, _ = orc.hmc_seq_chain(tg, b.eps, b.L, s0[0].astype(np.float64), b.xi, b.u)
+    init = st.astype(np.float32)
+    ref = _gate_at(orc, tg, b.eps, b.L, s0[0], b.xi, b.u, init)
+    g = pm.Target(ctx, b.target)
+    r = pm.solve(ctx, g, b.eps, _t(s0[0]), _t(b.xi), _t(b.u), sampler="hmc", n_leapfrog=b.L, variant="diag",
+                 jac_probes=1, max_iter=1, init_guess=_t(init))
+    got = r.gtilde.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(ref) & (np.abs(ref) < 1e3)
+    err = np.abs(got - ref)[fin]
+    _say(f"  max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}, acceptance {np.mean(ref > 0):.3f}")
+    assert err.max() <= HMC_SEQ_FP32_GATE_ERR
+    clear = np.abs(ref) > HMC_SEQ_FP32_GATE_ERR
+    assert np.array_equal(r.accept.cpu().numpy()[clear].astype(bool), ref[clear] > 0)
+
+
+@pytest.mark.parametrize("gate,kw", [("surrogate", dict(damping=0.4, clip=1.0, **DAMPED_TOL)),
+                                     ("frozen", dict(damping=0.4, clip=1.0, **DAMPED_TOL)), ("surrogate", {})])
+def test_hmc_seq_logreg_batch(ctx, pm, orc, gate, kw):
+    """App. B.4: 4 chains x 1000 transitions, L = 4, eps = 0.04, the one-probe
+    diagonal, damping 0.4 and |J_ii| <= 1, in one batched solve."""
+    _say(f"hmc across the sequence: logistic posterior 4 x 1000, gate={gate} {kw}")
+    b, tg, s0 = _logreg_hmc(orc)
+    g = pm.Target(ctx, b.target)
+    r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), sampler="hmc",
+                 n_leapfrog=b.L, variant="diag", jac_probes=1, probe_seed=11, gate=gate, max_iter=1001, **kw)
+    _say(f"  sweeps per chain={r.sweeps_per_chain} status={r.status} chain_state={r.chain_state}")
+    assert r.status == 0
+    st, acc = r.states.cpu().numpy(), r.accept.cpu().numpy()
+    for c in range(b.n_chains):
+        o0, o1 = int(b.offsets[c]), int(b.offsets[c + 1])
+        ch = W.Chain(target=b.target, eps=b.eps, x0=s0[c], xi=b.xi[o0:o1], u=b.u[o0:o1])
+        _check(orc, tg, ch, b.L, s0[c], st[o0:o1], acc[o0:o1], True, f"hmc-seq logreg chain {c} {gate} {kw}")
+
+
+def test_hmc_seq_logreg_sequential_and_picard(ctx, pm, orc):
+    _say("hmc across the sequence: logistic posterior, sequential sampler and Picard")
+    b, tg, s0 = _logreg_hmc(orc, n_chains=2, T=400, seed=2)
+    g = pm.Target(ctx, b.target)
+    rs = pm.sample_sequential(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), sampler="hmc",
+                              n_leapfrog=b.L)
+    rp = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), sampler="hmc",
+                  n_leapfrog=b.L, variant="picard", max_iter=401)
+    assert rp.status == 0
+    for r, name in ((rs, "sequential"), (rp, "picard")):
+        st, acc = r.states.cpu().numpy(), r.accept.cpu().numpy()
+        for c in range(b.n_chains):
+            o0, o1 = int(b.offsets[c]), int(b.offsets[c + 1])
+            ch = W.Chain(target=b.target, eps=b.eps, x0=s0[c], xi=b.xi[o0:o1], u=b.u[o0:o1])
+            _check(orc, tg, ch, b.L, s0[c], st[o0:o1], acc[o0:o1], True, f"hmc-seq logreg {name} chain {c}")

@@ -134,7 +134,7 @@ def test_leapfrog_gaussian_one_solve_full_deer(orc):
     assert it2 >= it
 
 
-# ------------------------------------------- stochastic diagonal (Sec. 4 eq. 10)
+# ------------------------------------------- stochastic diagonal (Sec. 3.4 eq. 10)
 
 @pytest.mark.parametrize("D", [1, 2, 5, 10])
 def test_hutchinson_identity_bruteforce(orc, D):
