@@ -473,8 +473,26 @@ def _structure(J, variant, D):
     raise ValueError(variant)
 
 
+def block2_probe_jacobian(J, eps, z):
+    """Block quasi-DEER Jacobian of a leapfrog step (App. A.3) with the
+    Hessian diagonal estimated from one Hessian-vector product: the step's
+    Jacobian is [[I, eps I], [eps H, I + eps^2 H]] (s = [x, v], 2D x 2D), so
+    H = J[D:, :D] / eps, and h = z o (H z) replaces diag(H) in
+    [[I, eps I], [eps diag(h), I + eps^2 diag(h)]]."""
+    J = np.asarray(J, dtype=np.float64)
+    D = J.shape[0] // 2
+    H = J[D:, :D] / eps
+    h = np.asarray(z, dtype=np.float64) * (H @ np.asarray(z, dtype=np.float64))
+    out = np.zeros_like(J)
+    out[:D, :D] = np.eye(D)
+    out[:D, D:] = eps * np.eye(D)
+    out[D:, :D] = eps * np.diag(h)
+    out[D:, D:] = np.eye(D) + eps * eps * np.diag(h)
+    return out
+
+
 def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=None, tol=0.0,
-                     full_trace=True, probe_seed=0, step0=0):
+                     full_trace=True, probe_seed=0, step0=0, jac_transform=None):
     """Algorithm 1 (Appendix A.1) with the update of Sec. 2 eq. 2, in FP64.
 
     step_and_jac(t, s_prev) -> (f_t(s_prev), df_t/ds(s_prev)) for t = 0..T-1.
@@ -483,8 +501,10 @@ def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=N
     variant "hutchinson" takes J_t = diag(z o (J z)) with z the probe signs
     of (probe_seed, sweep, step0 + t): step0 is the chain's first global step
     when the chain is one of a batch laid end to end.  Stops when max_t |s^{new}_t - s_t|_inf <= tol,
-    or after max_iter sweeps (default T + 1).  Returns (final trajectory,
-    list of iterates, sweeps).
+    or after max_iter sweeps (default T + 1).  jac_transform(J, t, sweep), when
+    given, replaces the variant's structure with its own approximate Jacobian
+    (e.g. block2_probe_jacobian).  Returns (final trajectory, list of
+    iterates, sweeps).
     """
     s0 = np.asarray(s0, dtype=np.float64)
     D = s0.shape[0]
@@ -498,7 +518,9 @@ def newton_reference(step_and_jac, s0, T, variant="dense", init=None, max_iter=N
         for t in range(T):
             prev = s0 if t == 0 else S[t - 1]
             F[t], J = step_and_jac(t, prev)
-            if variant == "hutchinson":
+            if jac_transform is not None:
+                Js[t] = jac_transform(J, t, it)
+            elif variant == "hutchinson":
                 z = np.array([probe_sign(probe_seed, it, step0 + t, d) for d in range(D)])
                 Js[t] = np.diag(hutchinson_diag(J, z))
             else:

@@ -264,3 +264,52 @@ def test_rotated_quasi_deer_reaches_the_chain(orc, case):
     for i, Zi in enumerate(trace):
         np.testing.assert_allclose(Zi[:i] @ Q.T, ref[:i], atol=1e-10)
     np.testing.assert_allclose(Z @ Q.T, ref, atol=1e-10)
+
+
+# ------------------------------ one-HVP block quasi-DEER (App. A.3, last identity)
+
+def test_block2_probe_jacobian_mean_is_block_quasi_deer(orc):
+    """Averaged over all 2^D Rademacher vectors, the one-HVP estimate gives
+    exactly the block quasi-DEER Jacobian (diagonal of each block)."""
+    import itertools
+    gt = W.gaussian_target(3, dim=5, lam_lo=0.2, lam_hi=1.0, dtype=np.float64)
+    tg = oracle_target(gt)
+    eps = 0.3
+    s = np.random.default_rng(4).normal(size=10)
+    _, J = orc.leapfrog_step(tg, eps, s, with_jac=True)
+    acc = np.zeros_like(J)
+    signs = list(itertools.product((-1.0, 1.0), repeat=5))
+    for z in signs:
+        acc += orc.block2_probe_jacobian(J, eps, np.array(z))
+    acc /= len(signs)
+    D = 5
+    want = np.zeros_like(J)
+    for bi in range(2):
+        for bj in range(2):
+            want[bi * D:(bi + 1) * D, bj * D:(bj + 1) * D] = np.diag(np.diag(J[bi * D:(bi + 1) * D, bj * D:(bj + 1) * D]))
+    np.testing.assert_allclose(acc, want, atol=1e-13)
+    # one probe differs from the exact block form (the off-diagonal Hessian enters)
+    assert np.max(np.abs(orc.block2_probe_jacobian(J, eps, np.ones(5)) - want)) > 1e-3
+
+
+def test_block2_probe_newton_causal_exactness(orc):
+    """Leapfrog on a non-Gaussian target (funnel) solved with the one-HVP block
+    Jacobian: bitwise causal exactness and the sequential fixed point."""
+    tg = oracle_target(W.funnel_target(seed=2, dim=4, theta=0.2))
+    eps, T = 0.1, 14
+    s0 = np.concatenate([np.array([0.3, -0.2, 0.5, 0.1]), np.array([0.4, 0.2, -0.3, 0.6])])
+    ref = [s0]
+    for t in range(T):
+        ref.append(orc.leapfrog_step(tg, eps, ref[-1]))
+    ref = np.array(ref[1:])
+
+    def sj(t, s):
+        return orc.leapfrog_step(tg, eps, s, with_jac=True)
+
+    def tr(J, t, sweep):
+        z = np.array([orc.probe_sign(7, sweep, t, d) for d in range(4)])
+        return orc.block2_probe_jacobian(J, eps, z)
+    S, trace, sweeps = orc.newton_reference(sj, s0, T, jac_transform=tr)
+    for i in range(1, len(trace)):
+        assert np.array_equal(trace[i][:i], ref[:i])
+    np.testing.assert_allclose(S, ref, rtol=0, atol=1e-13)
