@@ -178,6 +178,11 @@ typedef struct {
                                  LOGREG: solved as the rotated model (design X Q, noise
                                  Q^T xi) with any variant it supports, allocating the rotated
                                  copies for the call.  Q must outlive the call              */
+    int window_width;         /* > 0 (needs skip_converged_prefix): the sliding window of Sec. 3.4
+                                 with a fixed width -- each sweep updates at most this many
+                                 steps of a chain, from its first unconverged step; the window
+                                 moves on once its steps meet the tolerance.  0: the window
+                                 runs to the chain's end                                      */
     double tie_band;          /* >= 0: an accept decision whose gate |g~| is below this keeps the
                                  decision of the chain's previous sweep (from its second sweep
                                  on), so that rounding-level changes of the iterate cannot flip

@@ -183,7 +183,7 @@ def _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out
 def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rtol=None,
              max_iter=0, damping=1.0, clip=0.0, clip_inf_norm=False, skip_converged_prefix=True,
              graph_sweeps=0, trace=None, floor_stall=None, profile_kernels=False, jac_probes=0,
-             probe_seed=0, basis=None, tie_band=None):
+             probe_seed=0, basis=None, tie_band=None, window_width=0):
     o = B.pmc_options()
     B.check(B.lib().pmc_default_options(C.byref(o), _dtype_code(dtype)))
     o.variant = VARIANTS[variant]
@@ -200,6 +200,7 @@ def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rt
         o.floor_stall = int(floor_stall)
     if tie_band is not None:
         o.tie_band = float(tie_band)
+    o.window_width = int(window_width)
     o.profile_kernels = int(bool(profile_kernels))
     o.jac_probes, o.probe_seed = int(jac_probes), int(probe_seed)
     if basis is not None:

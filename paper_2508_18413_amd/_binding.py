@@ -45,7 +45,7 @@ class pmc_options(C.Structure):
                 ("skip_converged_prefix", C.c_int), ("graph_sweeps", C.c_int),
                 ("trace_out", C.c_void_p), ("trace_bytes", C.c_size_t), ("floor_stall", C.c_int),
                 ("profile_kernels", C.c_int), ("jac_probes", C.c_int), ("probe_seed", C.c_uint64),
-                ("basis", C.c_void_p), ("tie_band", C.c_double)]
+                ("basis", C.c_void_p), ("window_width", C.c_int), ("tie_band", C.c_double)]
 
 
 class pmc_result(C.Structure):

@@ -224,6 +224,7 @@ struct Lvl0In {  // Newton level 0: b_t = F_t - S_t from planes (FP32)
     int D;
     const ChainStatus *chain;  // window start of the (single) chain, or nullptr
     __device__ int64_t first() const { return chain ? chain->win_start : 0; }
+    __device__ int64_t last() const { return chain ? chain->win_end : INT64_MAX; }
     __device__ float b(int64_t t, int i) const
     {
         if (i >= D) return 0.f;
@@ -235,11 +236,13 @@ struct RowIn {  // standalone level 0: b_t rows [T, D]
     const float *B;
     int D;
     __device__ int64_t first() const { return 0; }
+    __device__ int64_t last() const { return INT64_MAX; }
     __device__ float b(int64_t t, int i) const { return i < D ? B[(size_t)t * D + i] : 0.f; }
 };
 struct MapIn {  // levels >= 1: B vectors [n, 32]
     const float *B;
     __device__ int64_t first() const { return 0; }
+    __device__ int64_t last() const { return INT64_MAX; }
     __device__ float b(int64_t t, int i) const { return B[(size_t)t * 32 + i]; }
 };
 
@@ -267,9 +270,10 @@ k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout, cons
     if (h == 0) v[i] = 0.f;
     wave_lds_sync();
     bool first = true;
-    const int64_t ws = in.first();
+    const int64_t ws = in.first(), we = in.last();
     const int e0 = ws > t0 ? (int)min((int64_t)cnt, ws - t0) : 0;
-    for (int e = e0; e < cnt; e++) {
+    const int e1 = we < t0 + cnt ? (int)max((int64_t)0, we - t0) : cnt;  // steps from the window's end on: identity
+    for (int e = e0; e < e1; e++) {
         Frag A;
         if constexpr (sizeof(Frag) == sizeof(FragB))
             A.load((const uint4 *)Jv, t0 + e, lane);
@@ -341,13 +345,14 @@ k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int6
     float *v = s_v[w];
     // steps before the chain's sliding window are frozen: S keeps its values,
     // delta stays zero and they add nothing to the convergence partials
-    const int64_t ws = chain ? chain->win_start : 0;
+    const int64_t ws = chain ? chain->win_start : 0, we = chain ? chain->win_end : INT64_MAX;
     const int e0 = ws > t0 ? (int)min((int64_t)cnt, ws - t0) : 0;
+    const int e1 = we < t0 + cnt ? (int)max((int64_t)0, we - t0) : cnt;  // steps past the window: untouched
     if (h == 0) v[i] = (carry_in && e0 == 0) ? carry_in[(size_t)u * 32 + i] : 0.f;
     wave_lds_sync();
     PartW p{0.f, 0u, INT64_MAX, 0.0, 0.0};
     const bool own = h == 0 && i < D;
-    for (int e = e0; e < cnt; e++) {
+    for (int e = e0; e < e1; e++) {
         const int64_t t = t0 + e;
         Frag A;
         if constexpr (sizeof(Frag) == sizeof(FragB))

@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_eval_small(EvalArgs a, Tg tg)
     const ChainStatus &cs = a.chains[tl.chain];
     if (!cs.active) return;
     const int64_t t = tl.start + threadIdx.x;
-    if ((int)threadIdx.x >= tl.len || t < cs.win_start) return;
+    if ((int)threadIdx.x >= tl.len || t < cs.win_start || t >= cs.win_end) return;
     const int D = a.D;
     const int64_t ld = a.ld;
     const R *S = (const R *)a.S;
@@ -291,8 +291,10 @@ pmc_status eval_dm(pmc_context *ctx, const EvalArgs &a, int D, Extra... ex)
     if (D <= 4) return eval_small<TG<R, 4>, R>(ctx, a, TG<R, 4>{D, ex...});
     if (D <= 8) return eval_small<TG<R, 8>, R>(ctx, a, TG<R, 8>{D, ex...});
     if (D <= 16) return eval_small<TG<R, 16>, R>(ctx, a, TG<R, 16>{D, ex...});
-    if (D <= 32) return eval_small<TG<R, 32>, R>(ctx, a, TG<R, 32>{D, ex...});
-    set_error("per-lane targets support D <= 32 (got %d)", D);
+    if constexpr (TG<R, 32>::kMaxLaneDim >= 32) {
+        if (D <= 32) return eval_small<TG<R, 32>, R>(ctx, a, TG<R, 32>{D, ex...});
+    }
+    set_error("per-lane evaluation of this target supports D <= %d (got %d)", TG<R, 32>::kMaxLaneDim, D);
     return PMC_ERR_UNSUPPORTED;
 }
 

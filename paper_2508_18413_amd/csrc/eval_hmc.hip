@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_eval_hmc_small(EvalArgs a, Tg tg)
     const ChainStatus &cs = a.chains[tl.chain];
     if (!cs.active) return;
     const int64_t t = tl.start + threadIdx.x;
-    if ((int)threadIdx.x >= tl.len || t < cs.win_start) return;
+    if ((int)threadIdx.x >= tl.len || t < cs.win_start || t >= cs.win_end) return;
     const int D = a.D;
     const int64_t ld = a.ld;
     const R *S = (const R *)a.S;
@@ -314,8 +314,10 @@ pmc_status by_dim(pmc_context *ctx, const Args &a, int D, Extra... ex)
     if (D <= 4) return run<TG<R, 4>, R>(ctx, a, TG<R, 4>{D, ex...});
     if (D <= 8) return run<TG<R, 8>, R>(ctx, a, TG<R, 8>{D, ex...});
     if (D <= 16) return run<TG<R, 16>, R>(ctx, a, TG<R, 16>{D, ex...});
-    if (D <= 32) return run<TG<R, 32>, R>(ctx, a, TG<R, 32>{D, ex...});
-    set_error("per-lane targets support D <= 32 (got %d)", D);
+    if constexpr (TG<R, 32>::kMaxLaneDim >= 32) {
+        if (D <= 32) return run<TG<R, 32>, R>(ctx, a, TG<R, 32>{D, ex...});
+    }
+    set_error("per-lane evaluation of this target supports D <= %d (got %d)", TG<R, 32>::kMaxLaneDim, D);
     return PMC_ERR_UNSUPPORTED;
 }
 

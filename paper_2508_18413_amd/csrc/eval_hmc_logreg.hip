@@ -229,9 +229,9 @@ __global__ void __launch_bounds__(kNT, 1) k_eval_hmc_logreg(EvalArgs a, HmcLogre
     for (int tix = blockIdx.x; tix < a.n_tiles; tix += gridDim.x) {
         const SegTile tl = a.tiles[tix];
         const ChainStatus &cs = a.chains[tl.chain];
-        if (!cs.active || tl.start + tl.len <= cs.win_start) continue;  // uniform over the workgroup
+        if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) continue;  // uniform
         const int64_t tstep = tl.start + i;
-        const bool valid = i < tl.len && tstep >= cs.win_start;
+        const bool valid = i < tl.len && tstep >= cs.win_start && tstep < cs.win_end;
         const int64_t tt = i < tl.len ? tstep : tl.start;
         const bool head = tt == a.offsets[tl.chain];
         const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
@@ -359,6 +359,137 @@ __global__ void __launch_bounds__(kNT, 1) k_eval_hmc_logreg(EvalArgs a, HmcLogre
                 if (a.accept) a.accept[tstep] = (uint8_t)acc;
                 if (a.gtilde) a.gtilde[tstep] = (float)gd;
             }
+        }
+    }
+}
+
+// ------------------------------------------- relaxed MALA gate (Sec. 3.2)
+// The stop-gradient gate's rank-one part of the MALA Jacobian on the
+// logistic posterior, added to the diagonal the evaluation wrote (exact
+// diagonal or the one-probe z o (J z)), which then receives the damping and
+// the clip.  With x~ = x + delta, g = grad log p(x), g~ = grad log p(x~),
+// w = -delta - eps g~ and M = I + eps H(x), the log ratio's gradient is
+//   dl/dx = M g~ - g + (H(x) w + M H(x~) w) / 2,
+// so the term is sigma'(g~ate) delta (dl/dx)^T where l < 0: its diagonal is
+// sigma' delta_d (dl/dx)_d, its probe part sigma' z_d delta_d (dl/dx . z).
+// The gradients and Hessian-vector products are the batched evaluations of
+// the HMC kernel above (32 steps per tile, matrix cores).
+template <int MK>
+__global__ void __launch_bounds__(kNT, 1) k_logreg_surrogate(EvalArgs a, HmcLogregArgs t)
+{
+    extern __shared__ float sm[];
+    const int NR = (t.N + 31) / 32 * 32;
+    const Lds l = lds_layout(sm, NR, t.ldx);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 31, h = lane >> 5;
+    const int D = t.D;
+    const float eps = (float)a.eps, pp = t.pp, c = sqrtf(2.f * eps);
+    if (a.glob && a.glob->n_active == 0) return;
+    for (int k = tid; k < NR * t.ldx; k += kNT) l.X[k] = k < t.N * t.ldx ? t.X[k] : 0.f;
+    for (int k = tid; k < NR; k += kNT) l.y[k] = k < t.N ? t.y[k] : 0.f;
+    __syncthreads();
+    int dq[2];
+    bool oq[2];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        dq[q] = crow(2 * w + q, h);
+        oq[q] = dq[q] < D;
+    }
+    for (int tix = blockIdx.x; tix < a.n_tiles; tix += gridDim.x) {
+        const SegTile tl = a.tiles[tix];
+        const ChainStatus &cs = a.chains[tl.chain];
+        if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) continue;  // uniform
+        const int64_t tstep = tl.start + i;
+        const bool valid = i < tl.len && tstep >= cs.win_start && tstep < cs.win_end;
+        const int64_t tt = i < tl.len ? tstep : tl.start;
+        const bool head = tt == a.offsets[tl.chain];
+        const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
+        const float *S = (const float *)a.S, *noise = (const float *)a.noise;
+        float x[2], xi[2], g[2], dl[2], gt[2], wv[2], t1[2], dll[2], gs[2], hs[2];
+        auto put = [&](const float (&p)[2], const float (&d)[2]) {
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                l.P[i * kPS + dq[q]] = p[q];
+                l.Pd[i * kPS + dq[q]] = d[q];
+            }
+            __syncthreads();
+        };
+        const float zero[2] = {0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            x[q] = oq[q] ? (head ? s0[dq[q]] : S[(size_t)dq[q] * a.ld + tt - 1]) : 0.f;
+            xi[q] = oq[q] ? noise[(size_t)tt * D + dq[q]] : 0.f;
+        }
+        put(x, zero);
+        evaluate<MK, false>(l, t, NR, w, lane, gs, hs);
+        float xt[2];
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            g[q] = gs[q] - pp * x[q];
+            dl[q] = oq[q] ? fmaf(eps, g[q], c * xi[q]) : 0.f;
+            xt[q] = x[q] + dl[q];
+        }
+        put(xt, zero);
+        evaluate<MK, false>(l, t, NR, w, lane, gs, hs);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            gt[q] = gs[q] - pp * xt[q];
+            wv[q] = -dl[q] - eps * gt[q];
+        }
+        put(xt, wv);
+        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            t1[q] = -hs[q] - pp * wv[q];                     // H(x~) w
+            dll[q] = gt[q] - g[q];
+        }
+        put(x, wv);
+        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+#pragma unroll
+        for (int q = 0; q < 2; q++) dll[q] += 0.5f * (-hs[q] - pp * wv[q]);   // H(x) w / 2
+        put(x, gt);
+        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+#pragma unroll
+        for (int q = 0; q < 2; q++) dll[q] += eps * (-hs[q] - pp * gt[q]);    // eps H(x) g~
+        put(x, t1);
+        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+#pragma unroll
+        for (int q = 0; q < 2; q++) dll[q] += 0.5f * (t1[q] + eps * (-hs[q] - pp * t1[q]));  // M H(x~) w / 2
+        // the probe part needs dl/dx . z per step: a fixed-order sum over the waves
+        float zq[2] = {0.f, 0.f};
+        double dz = 0.0;
+        if (a.probes) {
+            const uint64_t hsd = probe_mix(probe_mix(a.probe_seed) ^ (uint64_t)(uint32_t)cs.sweeps);
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                zq[q] = oq[q] ? ((probe_mix(hsd ^ (uint64_t)(1024 * tt + dq[q])) >> 63) ? -1.f : 1.f) : 0.f;
+                dz = fma((double)dll[q], (double)zq[q], dz);
+            }
+            dz = step_sum(dz);
+            if (h == 0) l.red[w * 32 + i] = dz;
+            __syncthreads();
+            dz = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < kW; ww++) dz += l.red[ww * 32 + i];
+            __syncthreads();
+        }
+        if (!valid) continue;
+        const float u = ((const float *)a.unif)[tstep];
+        const float gate = a.gtilde[tstep];
+        // l < 0 (otherwise min(0, l) is the constant 0): the evaluation stored
+        // g~ = (float)(min(0, l) - log u) with log u in FP64, so l >= 0 leaves
+        // exactly (float)(-log u)
+        const bool neg = gate < (float)(-log((double)u));
+        const float sg = 1.f / (1.f + expf(-gate));
+        const float coef = neg ? sg * (1.f - sg) : 0.f;
+        float *J = (float *)a.J;
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            if (!oq[q]) continue;
+            const size_t k = (size_t)dq[q] * a.ld + tstep;
+            const float add = a.probes ? coef * zq[q] * dl[q] * (float)dz : coef * dl[q] * dll[q];
+            float jv = (float)a.damping * (J[k] + add);
+            if (a.clip > 0) jv = fminf(fmaxf(jv, (float)-a.clip), (float)a.clip);
+            J[k] = jv;
         }
     }
 }
@@ -545,6 +676,32 @@ pmc_status launch_eval_hmc_logreg(pmc_context *ctx, const DevTarget &t, const Ev
     if (mk <= 8) return tg ? go(k_eval_hmc_logreg<8, true>) : go(k_eval_hmc_logreg<8, false>);
     if (mk <= 13) return tg ? go(k_eval_hmc_logreg<13, true>) : go(k_eval_hmc_logreg<13, false>);
     return tg ? go(k_eval_hmc_logreg<16, true>) : go(k_eval_hmc_logreg<16, false>);
+}
+
+pmc_status launch_logreg_surrogate(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
+{
+    if (a.n_tiles == 0) return PMC_OK;
+    const int NR = (t.n_data + 31) / 32 * 32;
+    if (t.n_data > kMaxRowsHmc || t.dim > 32 || lds_bytes(NR, t.ldx) > kLdsLimit) {
+        set_error("the relaxed gate on logistic regression holds X in LDS: n_data <= %d", kMaxRowsHmc);
+        return PMC_ERR_UNSUPPORTED;
+    }
+    const size_t lds = lds_bytes(NR, t.ldx);
+    HmcLogregArgs h{(const float *)t.X, (const float *)t.y, t.n_data, t.ldx, t.dim, (float)(1.0 / t.prior_var)};
+    const int n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+    const unsigned grid = (unsigned)std::min<int64_t>(a.n_tiles, n_cu);
+    auto go = [&](auto kern) -> pmc_status {
+        PMC_TRY_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, ctx->stream, a, h);
+        PMC_TRY_HIP(hipGetLastError());
+        return PMC_OK;
+    };
+    const int mk = (t.dim + 1) / 2;
+    if (mk <= 2) return go(k_logreg_surrogate<2>);
+    if (mk <= 4) return go(k_logreg_surrogate<4>);
+    if (mk <= 8) return go(k_logreg_surrogate<8>);
+    if (mk <= 13) return go(k_logreg_surrogate<13>);
+    return go(k_logreg_surrogate<16>);
 }
 
 pmc_status launch_seq_hmc_logreg(pmc_context *ctx, const DevTarget &t, const SeqArgs &a)

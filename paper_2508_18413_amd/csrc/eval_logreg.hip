@@ -261,9 +261,9 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
     for (int tix = blockIdx.x * kLdsWaves + (threadIdx.x >> 6); tix < a.n_tiles; tix += n_waves) {
         const SegTile tl = a.tiles[tix];
         const ChainStatus &cs = a.chains[tl.chain];
-        if (!cs.active || tl.start + tl.len <= cs.win_start) continue;
+        if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) continue;
         const int64_t t = tl.start + i;
-        const bool valid = i < tl.len && t >= cs.win_start;
+        const bool valid = i < tl.len && t >= cs.win_start && t < cs.win_end;
         const int64_t tt = i < tl.len ? t : tl.start;
         const bool head = (tt == a.offsets[tl.chain]);
         const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
@@ -620,9 +620,9 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
     for (int tix = blockIdx.x * kLdsWaves + (threadIdx.x >> 6); tix < a.n_tiles; tix += n_waves) {
         const SegTile tl = a.tiles[tix];
         const ChainStatus &cs = a.chains[tl.chain];
-        if (!cs.active || tl.start + tl.len <= cs.win_start) continue;
+        if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) continue;
         const int64_t t = tl.start + i;
-        const bool valid = i < tl.len && t >= cs.win_start;
+        const bool valid = i < tl.len && t >= cs.win_start && t < cs.win_end;
         const int64_t tt = i < tl.len ? t : tl.start;
         const bool head = (tt == a.offsets[tl.chain]);
         const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
@@ -857,9 +857,9 @@ __global__ void __launch_bounds__(64 * kWaves, 2) k_eval_logreg(EvalArgs a, Frag
     if (tix >= a.n_tiles) return;
     const SegTile tl = a.tiles[tix];
     const ChainStatus &cs = a.chains[tl.chain];
-    if (!cs.active || tl.start + tl.len <= cs.win_start) return;
+    if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) return;
     const int64_t t = tl.start + j;
-    const bool valid = j < tl.len && t >= cs.win_start;
+    const bool valid = j < tl.len && t >= cs.win_start && t < cs.win_end;
     const int64_t tt = j < tl.len ? t : tl.start;
     const int D = a.D;
     const int64_t ld = a.ld;

@@ -47,6 +47,8 @@ struct HMCArgs {
     float atol, rtol;
     int floor_stall;
     int max_sweeps;
+    int probes;             // 1: h from one Hessian-vector product per step and sweep (App. A.3)
+    uint64_t probe_seed;
 };
 
 constexpr int kNT = 1024;      // sequential kernel
@@ -211,6 +213,9 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
     float *s_g = s_x + kMaxD;                     // [kMaxD] gradient at the current state
     float *s_gl = s_g + kMaxD;                    // [kMaxD] gradient at x_L
     float *s_red = s_gl + kMaxD;                  // [kParNW]
+    float *s_hp = s_red + kParNW;                 // [L][D] probed Hessian diagonal (probes)
+    uint32_t *s_zb = (uint32_t *)(s_hp + (a.probes ? L * D : 0));  // [L][ceil(D / 32)] probe sign bits
+    const int NZW = (D + 31) / 32;
     __shared__ double s_redd[kParNW];
     __shared__ int s_flag;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 31, hh = lane >> 5;
@@ -234,8 +239,11 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
     __syncthreads();
 
     // P (x_t - mu) for the positions x_t = X[t][0..D) (row stride SP), t < cnt;
-    // calls emit(t, row, value) for every computed entry.
-    auto pmul = [&](const float *X, int cnt, auto emit) {
+    // calls emit(t, row, value) for every computed entry.  With probe set
+    // the operand is instead the Rademacher probe z_t, -1 where bit k of
+    // s_zb[t] is set.
+    auto zsign = [&](int t, int k) { return ((s_zb[t * NZW + (k >> 5)] >> (k & 31)) & 1u) ? -1.f : 1.f; };
+    auto pmul = [&](const float *X, int cnt, auto emit, bool probe = false) {
         if (!mw || 32 * nb >= cnt) return;
         const int t = 32 * nb + i;
         const bool tv = t < cnt;
@@ -243,7 +251,9 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
 #pragma unroll
         for (int m = 0; m < MKP; m++) {
             const int k = 2 * m + hh;
-            const float bv = (tv && k < D) ? X[(size_t)t * SP + k] - s_mu[k] : 0.f;
+            float bv = 0.f;
+            if (tv && k < D)
+                bv = probe ? zsign(t, k) : X[(size_t)t * SP + k] - s_mu[k];
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(PA[m], bv, acc, 0, 0, 0);
         }
         if (tv) {
@@ -282,16 +292,31 @@ __global__ void __launch_bounds__(kParNT) k_hmc_par(HMCArgs a)
                 const int t = o / D, d = o % D;
                 F[(size_t)t * SP + d] = fmaf(eps, S[(size_t)t * SP + D + d], S[(size_t)t * SP + d]);
             }
+            if (a.probes) {
+                // one Rademacher probe per leapfrog step and sweep: sign bit d of
+                // step l of proposal p from (seed, sweep, global step p L + l, d)
+                const uint64_t hs = probe_mix(probe_mix(a.probe_seed) ^ (uint64_t)(uint32_t)nsw);
+                for (int o = tid; o < L * NZW; o += kParNT) {
+                    const int t = o / NZW, k0 = 32 * (o % NZW);
+                    const uint64_t base = 1024 * ((uint64_t)p * L + t);
+                    uint32_t bits = 0;
+                    for (int b = 0; b < 32 && k0 + b < D; b++)
+                        bits |= (uint32_t)(probe_mix(hs ^ (base + k0 + b)) >> 63) << b;
+                    s_zb[o] = bits;
+                }
+            }
             __syncthreads();
             pmul(F, L, [&](int t, int row, float v) {
                 F[(size_t)t * SP + D + row] = fmaf(-eps, v, S[(size_t)t * SP + D + row]);
             });
+            if (a.probes)  // h_t ~ z_t o (H z_t) with H = -P
+                pmul(F, L, [&](int t, int row, float v) { s_hp[t * D + row] = -zsign(t, row) * v; }, true);
             __syncthreads();
             // scan: lane l holds step l + 1 (F row l, S row l + 1)
             float rmax = 0.f;
             const bool lv = lane < L;
             for (int d = w; d < D; d += kParNW) {
-                const float h = s_h[d];
+                const float h = a.probes ? (lv ? s_hp[lane * D + d] : 0.f) : s_h[d];
                 float ja = 1.f, jb = eps, jc = eps * h, jd = fmaf(eps * eps, h, 1.f);
                 if (a.variant == PMC_QDEER_DIAG) jb = jc = 0.f;
                 if (a.variant == PMC_PICARD) ja = jb = jc = jd = 0.f;
@@ -416,7 +441,19 @@ extern "C" pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target,
         set_error("pmc_hmc_sample: parallel leapfrog supports L <= %d (got %d)", kMaxLPar, L);
         return PMC_ERR_UNSUPPORTED;
     }
-    const size_t lds = sizeof(float) * ((size_t)(2 * L + 1) * (2 * D + 1) + 5 * kMaxD + kParNW);
+    const bool probes = parallel_leapfrog && opts->jac_probes == 1;
+    PMC_REQUIRE(opts->jac_probes == 0 || opts->jac_probes == 1, "pmc_hmc_sample: jac_probes is 0 or 1");
+    if (probes && opts->variant != PMC_QDEER_BLOCK2 && opts->variant != PMC_QDEER_DIAG) {
+        set_error("pmc_hmc_sample: jac_probes applies to the block and diagonal variants");
+        return PMC_ERR_UNSUPPORTED;
+    }
+    const size_t lds = sizeof(float) * ((size_t)(2 * L + 1) * (2 * D + 1) + 5 * kMaxD + kParNW +
+                                        (probes ? (size_t)L * D + (size_t)L * ((D + 31) / 32) : 0));
+    if (parallel_leapfrog && lds > (size_t)160 * 1024) {
+        set_error("pmc_hmc_sample: the parallel leapfrog of D = %d, L = %d%s needs %zu bytes of LDS (160 KiB)", D, L,
+                  probes ? " with probes" : "", lds);
+        return PMC_ERR_UNSUPPORTED;
+    }
     if (res) memset(res, 0, sizeof(*res));
     if (n_prop == 0) return PMC_OK;
     PMC_REQUIRE(is_device_ptr(x0) && is_device_ptr(momenta) && is_device_ptr(unif) &&
@@ -449,6 +486,8 @@ extern "C" pmc_status pmc_hmc_sample(pmc_context *ctx, const pmc_target *target,
     a.rtol = (float)opts->rtol;
     a.floor_stall = opts->floor_stall;
     a.max_sweeps = opts->max_iter > 0 ? opts->max_iter : L + 1;
+    a.probes = probes ? 1 : 0;
+    a.probe_seed = opts->probe_seed;
     PMC_TRY_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     if (parallel_leapfrog) {
         const int mkp = ((D + 1) / 2 + 7) / 8 * 8;

@@ -78,6 +78,8 @@ struct ChainStatus {
     int64_t best_front;  // furthest converged front seen
     int64_t fb_prev;     // first_bad of the sweep before (the window starts at the earlier of
                          // the two: a step is frozen once it met the tolerance twice in a row)
+    int64_t win_end;     // end (exclusive) of the active window: the chain's end, or
+                         // win_start + window_width for a fixed-width window
 };
 
 // Whole-problem status, read by the host after each sweep or graph replay.
@@ -231,6 +233,7 @@ struct NewtonScanArgs {
     int defer_epoch;        // 1: the status fold that follows advances the scan epoch
     int n_chains;           // chains in the tile map (0: unknown)
     int64_t n_steps;        // steps over all chains
+    int fixed_window = 0;   // 1: windows of fixed width (the one-chain chunked form is not used)
 };
 
 // Steps per scan tile for a configuration (the host builds its tile map with it).
@@ -347,6 +350,10 @@ pmc_status launch_sequential(pmc_context *ctx, const DevTarget &tg, const SeqArg
 // HMC transitions as chain steps (Sec. 3.3): evaluation (per-lane targets and
 // the logistic posterior) and the same-GPU sequential sampler.
 pmc_status launch_eval_hmc(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
+// The relaxed MALA gate's rank-one diagonal term on the logistic posterior
+// (Sec. 3.2), added to the undamped diagonal the evaluation wrote, followed
+// by the damping and the clip.
+pmc_status launch_logreg_surrogate(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
 pmc_status launch_sequential_hmc(pmc_context *ctx, const DevTarget &t, const SeqArgs &a);
 
 // Dense DEER scan on matrix cores (D <= 32, F32 states; J in the BF16 or F32
@@ -379,7 +386,8 @@ struct StatusArgs {
     int max_iter;
     int skip_prefix;
     int floor_stall;                  // > 0: stop a chain whose ratio has not improved for this
-                                      // many sweeps while within 100x of the tolerance
+                                      // many sweeps while within twice the tolerance
+    int64_t window_width;             // > 0: fixed-width sliding window (steps per chain and sweep)
     int64_t n_steps;
     ScanSync *bump_epoch;             // non-null: the last workgroup advances this scan epoch
 };

@@ -410,8 +410,10 @@ struct SegGeom {
         const int64_t off = offsets[st.chain];
         const int64_t ws = cs.win_start > off ? cs.win_start : off;
         t1 = st.start + st.len;
+        if (cs.win_end < t1) t1 = cs.win_end;
         if (ws >= t1) return false;
         t0 = st.start > ws ? st.start : ws;
+        if (t0 >= t1) return false;
         // tile boundaries sit at absolute multiples of C (the first tile of a
         // chain runs from its offset to the next multiple)
         head_ti = chain_tile_begin[st.chain] + (int)(ws / C - off / C);
@@ -1533,7 +1535,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
             cs.nonfinite = v.f;
             // Plateau detection: progress is a 2x drop of the best ratio or an
             // advance of the converged front; rounding noise gives neither.
-            const int64_t front = fb == INT64_MAX ? a.offsets[c + 1] : fb;
+            const int64_t front = fb == INT64_MAX ? cs.win_end : fb;
             if (r < 0.5f * cs.best_ratio || front > cs.best_front) {
                 cs.best_ratio = fminf(cs.best_ratio, r);
                 cs.best_front = front > cs.best_front ? front : cs.best_front;
@@ -1541,9 +1543,16 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
             } else {
                 cs.stall += 1;
             }
-            if (r <= 1.f) {
+            const int64_t cend = a.offsets[c + 1];
+            if (r <= 1.f && cs.win_end >= cend) {
                 cs.converged = 1;
                 cs.active = 0;
+            } else if (r <= 1.f) {
+                // a fixed-width window whose steps all met the tolerance: the next
+                // window starts where this one ended
+                cs.win_start = cs.win_end;
+                cs.win_end = cs.win_start + a.window_width < cend ? cs.win_start + a.window_width : cend;
+                cs.fb_prev = cs.win_start;
             } else if (cs.sweeps >= a.max_iter) {
                 cs.active = 0;
             } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f) {
@@ -1561,8 +1570,12 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
                 const int64_t f2 = fb < cs.fb_prev ? fb : cs.fb_prev;
                 const int64_t w = f2 & ~(int64_t)3;
                 cs.win_start = w > off ? w : off;
+                if (a.window_width > 0) {
+                    const int64_t e = cs.win_start + a.window_width;
+                    cs.win_end = e < a.offsets[c + 1] ? e : a.offsets[c + 1];
+                }
             }
-            cs.fb_prev = fb;
+            if (!(r <= 1.f)) cs.fb_prev = fb;
         }
     }
     // completion count: the last workgroup sees every chain's update (a
@@ -1584,7 +1597,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         const ChainStatus &o = a.chains[i];
         if (o.active) {
             const int64_t off = a.offsets[i];
-            nsteps += a.offsets[i + 1] - (o.win_start > off ? o.win_start : off);
+            nsteps += o.win_end - (o.win_start > off ? o.win_start : off);
         }
         v.q += o.resid_sq;
         v.qi = fmax(v.qi, o.resid_inf);
@@ -1693,7 +1706,7 @@ pmc_status diag_newton(pmc_context *ctx, const NewtonScanArgs &a)
 {
     if constexpr (sizeof(R) == 4 && BLOCK == 1024 && ITEMS == 8) {
         constexpr int C = BLOCK * ITEMS;
-        if (a.n_chains == 1 && !a.trace && a.n_steps % C == 0 && a.n_tiles == a.n_steps / C &&
+        if (a.n_chains == 1 && !a.trace && !a.fixed_window && a.n_steps % C == 0 && a.n_tiles == a.n_steps / C &&
             a.ld == a.n_steps && (int64_t)a.n_lanes * a.n_steps >= (int64_t(1) << 23))
             return newton_chunked(ctx, a);
     }

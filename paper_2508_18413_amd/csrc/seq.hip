@@ -280,8 +280,10 @@ pmc_status seq_dm(pmc_context *ctx, const SeqArgs &a, int D, Extra... ex)
     if (D <= 4) return seq_small<TG<R, 4>, R>(ctx, a, TG<R, 4>{D, ex...});
     if (D <= 8) return seq_small<TG<R, 8>, R>(ctx, a, TG<R, 8>{D, ex...});
     if (D <= 16) return seq_small<TG<R, 16>, R>(ctx, a, TG<R, 16>{D, ex...});
-    if (D <= 32) return seq_small<TG<R, 32>, R>(ctx, a, TG<R, 32>{D, ex...});
-    set_error("per-lane targets support D <= 32 (got %d)", D);
+    if constexpr (TG<R, 32>::kMaxLaneDim >= 32) {
+        if (D <= 32) return seq_small<TG<R, 32>, R>(ctx, a, TG<R, 32>{D, ex...});
+    }
+    set_error("per-lane evaluation of this target supports D <= %d (got %d)", TG<R, 32>::kMaxLaneDim, D);
     return PMC_ERR_UNSUPPORTED;
 }
 

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "pmc_internal.hpp"
+#include "targets.hpp"
 
 namespace pmc {
 namespace {
@@ -47,6 +48,7 @@ struct Plan {
     bool logreg_dense = false;  // dense J of the logistic posterior (pair sums in o_hpair)
     bool logreg_probe = false;  // probed diagonal of the logistic posterior (MALA)
     bool hmc = false;           // f_t is a whole HMC transition (Sec. 3.3)
+    bool logreg_surrogate = false;  // MALA relaxed gate on the logistic posterior (diagonal variants)
     const void *basis = nullptr;  // orthogonal reparameterisation (iterates z = Q^T s)
     size_t o_rot = 0;             // rotation scratch planes [D, ld]
     size_t o_hpair = 0;
@@ -118,8 +120,9 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         if (p->init_guess)
             PMC_REQUIRE(is_device_ptr(p->init_guess), "pmc_solve: init_guess must be a device pointer");
     }
-    if (t.kind == PMC_TARGET_GAUSSIAN && pl.D > 32) {
-        set_error("pmc_solve: per-step Gaussian evaluation supports D <= 32 (got %d)", pl.D);
+    if (t.kind == PMC_TARGET_GAUSSIAN && pl.D > Gaussian<float, 16>::kMaxLaneDim) {
+        set_error("pmc_solve: per-step Gaussian evaluation supports D <= %d (got %d)",
+                  Gaussian<float, 16>::kMaxLaneDim, pl.D);
         return PMC_ERR_UNSUPPORTED;
     }
     pl.variant = o->variant;
@@ -188,9 +191,16 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     PMC_REQUIRE(o->gate == PMC_GATE_FROZEN || o->gate == PMC_GATE_SURROGATE, "pmc_solve: bad gate");
     PMC_REQUIRE(o->damping > 0 && isfinite(o->damping), "pmc_solve: damping must be > 0");
     PMC_REQUIRE(o->tie_band >= 0 && isfinite(o->tie_band), "pmc_solve: tie_band must be >= 0");
+    PMC_REQUIRE(o->window_width >= 0, "pmc_solve: window_width must be >= 0");
+    PMC_REQUIRE(o->window_width == 0 || o->skip_converged_prefix,
+                "pmc_solve: a fixed-width window needs skip_converged_prefix");
     if (t.kind == PMC_TARGET_LOGREG && o->gate == PMC_GATE_SURROGATE && p->sampler == PMC_SAMPLER_MALA) {
-        set_error("pmc_solve: logistic regression supports the frozen gate only");
-        return PMC_ERR_UNSUPPORTED;
+        // the relaxed gate's rank-one term is added to the diagonal (exact or probed)
+        if (pl.jmode != JM_DIAG && pl.jmode != JM_NONE) {
+            set_error("pmc_solve: the relaxed gate on logistic regression takes the diagonal variants");
+            return PMC_ERR_UNSUPPORTED;
+        }
+        pl.logreg_surrogate = pl.jmode == JM_DIAG;
     }
     PMC_REQUIRE(!(o->graph_sweeps > 0 && o->trace_out), "pmc_solve: trace_out needs graph_sweeps = 0");
     PMC_REQUIRE(o->jac_probes == 0 || o->jac_probes == 1, "pmc_solve: jac_probes is 0 or 1");
@@ -297,10 +307,23 @@ struct Sweep {
 pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent_t *ev = nullptr)
 {
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[0], ctx->stream));
-    PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
-    if (pl.logreg_dense)
-        PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, sw.hpair, pl.jmode == JM_DENSE_F32));
-    if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, sw.ea, pl.n, pl.n_chains));
+    if (pl.logreg_surrogate) {
+        // the evaluation (and probe) kernels write the frozen-gate diagonal
+        // undamped and unclipped; the relaxed gate's term, the damping and the
+        // clip follow
+        EvalArgs e = sw.ea;
+        e.gate = PMC_GATE_FROZEN;
+        e.damping = 1.0;
+        e.clip = 0.0;
+        PMC_TRY(launch_eval(ctx, *pl.tg, e));
+        if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, e, pl.n, pl.n_chains));
+        PMC_TRY(launch_logreg_surrogate(ctx, *pl.tg, sw.ea));
+    } else {
+        PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
+        if (pl.logreg_dense)
+            PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, sw.hpair, pl.jmode == JM_DENSE_F32));
+        if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, sw.ea, pl.n, pl.n_chains));
+    }
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[1], ctx->stream));
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
@@ -522,6 +545,8 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
         ChainStatus &cs = hc[c];
         memset(&cs, 0, sizeof(cs));
         cs.win_start = pl.offs[c];
+        cs.win_end = opts->window_width > 0 ? std::min<int64_t>(pl.offs[c + 1], pl.offs[c] + opts->window_width)
+                                            : pl.offs[c + 1];
         cs.first_bad = INT64_MAX;
         const bool nonempty = pl.offs[c + 1] > pl.offs[c];
         cs.active = nonempty;
@@ -548,7 +573,8 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
             g0->n_active += hc[c].active;
             g0->n_converged += hc[c].converged;
         }
-        g0->next_steps = pl.n;
+        g0->next_steps = 0;
+        for (int c = 0; c < pl.n_chains; c++) g0->next_steps += hc[c].win_end - hc[c].win_start;
         PMC_TRY_HIP(hipMemcpyAsync(d_glob, g0, sizeof(GlobalStatus), hipMemcpyHostToDevice, st));
     }
     if (pl.jmode == JM_NONE)  // Picard: J = 0 through the diagonal scan
@@ -622,6 +648,7 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
     sa.trace = nullptr;
     sa.n_chains = pl.n_chains;
     sa.n_steps = pl.n;
+    sa.fixed_window = opts->window_width > 0;
     // the look-back scans leave the epoch advance to the status fold that follows
     sa.defer_epoch = pl.jmode == JM_DIAG || pl.jmode == JM_NONE || pl.jmode == JM_DENSE_ROW;
     StatusArgs &sta = sw.st;
@@ -638,6 +665,7 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
     sta.max_iter = pl.max_iter;
     sta.skip_prefix = opts->skip_converged_prefix;
     sta.floor_stall = opts->floor_stall;
+    sta.window_width = opts->window_width;
     sta.n_steps = pl.n;
     sta.bump_epoch = sa.defer_epoch ? ctx->sync : nullptr;
 
@@ -970,6 +998,7 @@ extern "C" pmc_status pmc_autotune(pmc_context *ctx, const pmc_problem *prob, co
     for (int c = 0; c < base.n_chains; c++) {
         memset(&hc[c], 0, sizeof(ChainStatus));
         hc[c].win_start = base.offs[c];
+        hc[c].win_end = base.offs[c + 1];
         hc[c].active = base.offs[c + 1] > base.offs[c];
     }
     PMC_TRY_HIP(hipMemcpyAsync(ws + oCh, hc.data(), sizeof(ChainStatus) * hc.size(), hipMemcpyHostToDevice, st));

@@ -59,6 +59,10 @@ struct Banana {
 template <typename R, int DMax>
 struct Gaussian {
     static constexpr int DM = DMax;
+    // Widest per-lane instance: beyond D = 16 the evaluation kernels' private
+    // arrays exceed 1 KiB per lane, the HIP runtime's default per-thread stack,
+    // which the library keeps every kernel within.
+    static constexpr int kMaxLaneDim = 16;
     int D;
     const R *mean, *prec;
     __device__ void grad(const R *x, R *g) const
@@ -115,6 +119,7 @@ struct Gaussian {
 template <typename R, int DMax>
 struct Funnel {
     static constexpr int DM = DMax;
+    static constexpr int kMaxLaneDim = 32;
     int D;
     R theta;
     __device__ R tail_sq(const R *x) const

@@ -99,6 +99,65 @@ def test_hmc_parallel_leapfrog(pm, ctx, orc, variant):
     assert all(1 <= s <= prob.L + 1 for s in r["sweeps"])
 
 
+def test_hmc_parallel_leapfrog_one_hvp(pm, ctx, orc):
+    """Block quasi-DEER with the Hessian diagonal from one Hessian-vector
+    product per leapfrog step and sweep (App. A.3): the chain matches the
+    sequential oracle.  (Sweep counts are not compared with the FP64 Newton
+    reference: before the causal front reaches the end, the quasi-Newton
+    iterates of this leapfrog grow to ~1e12, and their FP32 rounding costs
+    about ten extra sweeps with or without probes; the probes themselves
+    are pinned by test_hmc_one_hvp_iterates.)"""
+    print("hmc parallel leapfrog block2 one-HVP", flush=True)
+    prob = W.hmc_gaussian(seed=3, dim=100, L=64, eps=0.05, n_prop=2000)
+    r, err = _run(pm, ctx, orc, prob, 200, True, variant="block2", jac_probes=1, probe_seed=11,
+                  atol=1e-6, rtol=1e-6)
+    assert err <= 1e-5
+    assert all(1 <= s <= prob.L + 1 for s in r["sweeps"])
+
+
+def test_hmc_one_hvp_iterates(pm, ctx, orc):
+    """The probes themselves: stopped after k = 1, 2, 3 sweeps, the leapfrog
+    end point is the k-th Newton iterate, which depends on every probe drawn
+    so far.  The margin the kernel reports from it matches the one the FP64
+    Newton reference gives with the same probes (seed, sweep, step) and is far
+    from the exact-diagonal block variant's."""
+    print("hmc one-HVP iterates", flush=True)
+    prob = W.hmc_gaussian(seed=3, dim=100, L=64, eps=0.05, n_prop=1)
+    tg = oracle_target(prob.target)
+    g = pm.Target(ctx, prob.target)
+    D, L, eps = 100, prob.L, prob.eps
+    P, mu = prob.target["prec"].astype(np.float64), prob.target["mean"].astype(np.float64)
+    x0, m, U = prob.x0.astype(np.float64), prob.momenta[0].astype(np.float64), float(prob.U[0])
+    s0 = orc.hmc_chain(tg, eps, L, x0, prob.momenta, prob.U)["s0"].reshape(-1)
+
+    def sj(t, s):
+        return orc.leapfrog_step(tg, eps, s, with_jac=True)
+
+    def tr(J, t, sweep):
+        z = np.array([orc.probe_sign(11, sweep, t, d) for d in range(D)])
+        return orc.block2_probe_jacobian(J, eps, z)
+
+    def margin(sL):  # Gaussian energies: log p(x) = -(x - mu)^T P (x - mu) / 2
+        x = sL[:D]
+        v = sL[D:] + 0.5 * eps * (P @ (x - mu))  # reverse half step along grad log p = -P (x - mu)
+        H0 = 0.5 * m @ m + 0.5 * (x0 - mu) @ P @ (x0 - mu)
+        return H0 - (0.5 * v @ v + 0.5 * (x - mu) @ P @ (x - mu)) - np.log(U)
+    _, A, _ = orc.newton_reference(sj, s0, L, variant="block2", jac_transform=tr, max_iter=3)
+    _, B, _ = orc.newton_reference(sj, s0, L, variant="block2", max_iter=3)
+    # the margin formula itself: at the fixed point it is the sequential chain's
+    fixed, _, _ = orc.newton_reference(sj, s0, L, variant="block2", full_trace=False)
+    assert abs(margin(fixed[-1]) - orc.hmc_chain(tg, eps, L, x0, prob.momenta, prob.U)["logr"][0]) < 1e-9
+    for k in (1, 2, 3):
+        r = pm.hmc_sample(ctx, g, eps, L, _t(prob.x0), _t(prob.momenta), _t(prob.U), parallel_leapfrog=True,
+                          variant="block2", jac_probes=1, probe_seed=11, max_iter=k, atol=1e-6, rtol=1e-6)
+        got = float(r["logr"].cpu().numpy()[0])
+        want, exact = margin(A[k][-1]), margin(B[k][-1])
+        print(f"  k={k}: margin gpu {got:.6g}, oracle {want:.6g} (exact-diagonal block {exact:.6g})", flush=True)
+        assert r["sweeps"][0] == k
+        assert abs(got - want) <= 1e-3 * abs(want)
+        assert abs(exact - want) > 0.5 * abs(want)
+
+
 def test_hmc_sequential_leapfrog(pm, ctx, orc):
     print("hmc sequential leapfrog", flush=True)
     prob = W.hmc_gaussian(seed=1, dim=100, L=64, eps=0.05, n_prop=2000)
@@ -122,3 +181,17 @@ def test_hmc_unsupported_target(pm, ctx):
         pm.hmc_sample(ctx, g, 0.1, 4, _t(np.zeros(4, np.float32)), _t(np.zeros((3, 4), np.float32)),
                       _t(np.full(3, 0.5, np.float32)))
     assert e.value.status == B.PMC_ERR_UNSUPPORTED
+
+
+def test_hmc_one_hvp_lds_limit(pm, ctx):
+    """D = 128, L = 64 with probes needs more than 160 KiB of LDS: refused
+    before launch; without probes it fits."""
+    from paper_2508_18413_amd import _binding as B
+    prob = W.hmc_gaussian(seed=4, dim=128, L=64, eps=0.05, n_prop=2)
+    g = pm.Target(ctx, prob.target)
+    args = (ctx, g, prob.eps, prob.L, _t(prob.x0), _t(prob.momenta), _t(prob.U))
+    with pytest.raises(B.PMCError) as e:
+        pm.hmc_sample(*args, parallel_leapfrog=True, variant="block2", jac_probes=1)
+    assert e.value.status == B.PMC_ERR_UNSUPPORTED
+    r = pm.hmc_sample(*args, parallel_leapfrog=True, variant="block2")
+    assert len(r["sweeps"]) == 2

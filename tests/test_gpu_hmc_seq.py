@@ -24,6 +24,13 @@ DEV = "cuda:0"
 # FP32 leapfrog states, so it carries their rounding.
 HMC_SEQ_FP32_GATE_ERR = 1e-4
 
+# FP64 state bar for chains of HMC transitions: each transition's Jacobian
+# reaches |J|_inf ~ 10 on the banana at step 0.2 (it is the product of 8
+# leapfrog Jacobians), so two FP64 evaluations of the same chain that differ
+# only in rounding order drift apart by up to a few 1e-10 over 1000 steps
+# (measured between two CPU formulations: 3.5e-13 to 5e-10 by seed).
+HMC_FP64_TOL = 1e-9
+
 
 def _t(x, dtype=None):
     return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
@@ -57,19 +64,23 @@ def _check(orc, tg, ch, L, x0, got_states, got_acc, fp32, label, inv_mass=None, 
     _say(f"  state_error={err:.3e} near-ties={n_tie} fp32-floor={n_floor} acceptance={np.mean(got_acc):.3f} {rep}")
     assert not [x for x in rep if x[2] == "failure"], rep
     assert n_floor <= floor_cap(n)
-    assert err <= (tol if tol is not None else (1e-5 if fp32 else 1e-10))
+    assert err <= (tol if tol is not None else (1e-5 if fp32 else HMC_FP64_TOL))
     return err
 
 
-# Fig. 1 analogue: the banana with L = 8 leapfrog steps of 0.5; full DEER
-# damped by 0.5 and clipped to [-1, 1] (App. B.4), and the other updates
+# Fig. 1 analogue: the banana with L = 8 leapfrog steps; full DEER damped by
+# 0.5 and clipped to [-1, 1] (App. B.4), and the other updates.  Fig. 1 uses
+# another parameterisation of the banana at step 0.5 (acceptance 97.6 %); on
+# this banana that step makes some trajectories chaotic (transition
+# Jacobians up to ~1e100), so the step is 0.2 (acceptance 98.3 %).
+BANANA_HMC_EPS = 0.2
 @pytest.mark.parametrize("variant,kw", [("dense", dict(damping=0.5, clip=1.0)), ("dense", {}),
                                         ("diag", {}), ("diag", dict(jac_probes=1, probe_seed=3)),
                                         ("picard", {})])
 @pytest.mark.parametrize("gate", ["surrogate", "frozen"])
 def test_hmc_seq_banana_fp64(ctx, pm, orc, variant, kw, gate):
     _say(f"hmc across the sequence: banana fp64 {variant} {kw} gate={gate}")
-    ch = W.banana_chain(T=1024, seed=4, eps=0.5)
+    ch = W.banana_chain(T=1024, seed=4, eps=BANANA_HMC_EPS)
     L = 8
     tg = orc.Target(orc.BANANA, 2)
     g = pm.Target(ctx, ch.target, dtype=torch.float64)
@@ -85,7 +96,7 @@ def test_hmc_seq_sequential_sampler(ctx, pm, orc):
     """The same-GPU sequential sampler of the same transitions (FP64 banana,
     FP32 funnel with a diagonal mass matrix)."""
     _say("hmc across the sequence: sequential sampler")
-    ch = W.banana_chain(T=1024, seed=4, eps=0.5)
+    ch = W.banana_chain(T=1024, seed=4, eps=BANANA_HMC_EPS)
     g = pm.Target(ctx, ch.target, dtype=torch.float64)
     r = pm.sample_sequential(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), sampler="hmc", n_leapfrog=8)
     _check(orc, orc.Target(orc.BANANA, 2), ch, 8, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy(), False,
@@ -153,13 +164,13 @@ def test_hmc_seq_batched_uneven(ctx, pm, orc):
     """Several banana chains of uneven length in one solve."""
     _say("hmc across the sequence: batched uneven chains")
     lens = [1, 37, 256, 700]
-    chs = [W.banana_chain(T=n, seed=20 + i, eps=0.5) for i, n in enumerate(lens)]
+    chs = [W.banana_chain(T=n, seed=20 + i, eps=BANANA_HMC_EPS) for i, n in enumerate(lens)]
     off = np.concatenate([[0], np.cumsum(lens)])
     x0 = np.stack([c.x0 for c in chs])
     xi = np.concatenate([c.xi for c in chs])
     u = np.concatenate([c.u for c in chs])
     g = pm.Target(ctx, chs[0].target, dtype=torch.float64)
-    r = pm.solve(ctx, g, 0.5, _t(x0), _t(xi), _t(u), offsets=list(off), sampler="hmc", n_leapfrog=8,
+    r = pm.solve(ctx, g, BANANA_HMC_EPS, _t(x0), _t(xi), _t(u), offsets=list(off), sampler="hmc", n_leapfrog=8,
                  variant="dense", damping=0.5, clip=1.0, max_iter=int(max(lens)) + 1)
     assert r.status == 0
     st, acc = r.states.cpu().numpy(), r.accept.cpu().numpy()

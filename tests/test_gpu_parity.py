@@ -750,6 +750,15 @@ def test_invalid_arguments(ctx, pm):
     with pytest.raises(B.PMCError) as e:
         pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="block2")
     assert e.value.status == B.PMC_ERR_UNSUPPORTED
+    # per-lane Gaussian evaluation stops at D = 16 (its private arrays beyond
+    # that would not fit the per-lane stack); the solve and the sequential
+    # sampler both refuse D = 20 before any launch
+    gc = W.gaussian_chain(64, seed=1, eps=0.1, dim=20, dtype=np.float32, lam_lo=0.3)
+    gg = pm.Target(ctx, gc.target)
+    for call in (pm.solve, pm.sample_sequential):
+        with pytest.raises(B.PMCError) as e:
+            call(ctx, gg, gc.eps, _t(gc.x0), _t(gc.xi), _t(gc.u))
+        assert e.value.status == B.PMC_ERR_UNSUPPORTED
 
 
 def test_empty_and_length_one(ctx, pm, orc):
@@ -1109,3 +1118,115 @@ def test_basis_logreg_rotated_model(ctx, pm, orc, probes):
     last = rt.trace[rt.sweeps - 1]
     assert (last - rt.states).abs().max().item() <= 1e-5
     assert bool(torch.isnan(rt.trace[rt.sweeps:]).all())
+
+
+@pytest.mark.parametrize("width", [128, 512, 1024])
+def test_fixed_width_window(ctx, pm, orc, width):
+    """Sec. 3.4 sliding window of a fixed width (the widths of Sec. 5.5): each
+    sweep updates at most `width` steps from the chain's first unconverged
+    one, and the solve still reaches the FP64 chain; a batch of uneven chains
+    too.  The sweep counts are reported beside the unlimited window's."""
+    _say(f"fixed-width window {width}")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015, seed=4)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=20000,
+                 window_width=width)
+    r0 = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", max_iter=4097)
+    _say(f"  width {width}: sweeps={r.sweeps} (unlimited window {r0.sweeps}) status={r.status}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy(), label=f"window {width}")
+    if width == 512:
+        b = W.logreg_batch(seed=6, n_chains=3, lo=300, hi=3000, eps=0.0015)
+        bt = oracle_target(b.target)
+        s0b = np.stack([oracle_burnin(bt, _as_chain(b, c)) for c in range(b.n_chains)]).astype(np.float32)
+        gb = pm.Target(ctx, b.target)
+        rb = pm.solve(ctx, gb, b.eps, _t(s0b), _t(b.xi), _t(b.u), offsets=list(b.offsets), variant="diag",
+                      max_iter=20000, window_width=width)
+        assert rb.status == 0
+        st, acc = rb.states.cpu().numpy(), rb.accept.cpu().numpy()
+        for c in range(b.n_chains):
+            o0, o1 = b.offsets[c], b.offsets[c + 1]
+            _check_mala(orc, bt, _as_chain(b, c), s0b[c], st[o0:o1], acc[o0:o1], label=f"window {width} chain {c}")
+
+
+def test_fixed_width_window_dense(ctx, pm, orc):
+    """The fixed-width window with the matrix-core dense scan (full DEER on the
+    logistic posterior, BF16 Jacobians, infinity-norm clip)."""
+    _say("fixed-width window, dense")
+    ch, tg, s0 = _logreg_case(orc, 2048, 0.0015, seed=5)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="dense", jac_prec="bf16", clip=1.0,
+                 clip_inf_norm=True, max_iter=20000, window_width=256)
+    _say(f"  sweeps={r.sweeps} status={r.status}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy(), label="dense window 256")
+
+
+@pytest.mark.parametrize("probes", [0, 1])
+@pytest.mark.parametrize("kw", [{}, dict(damping=0.4, clip=1.0)])
+def test_logreg_surrogate_gate_one_sweep(ctx, pm, orc, probes, kw):
+    """The relaxed (stop-gradient) gate of Sec. 3.2 on the logistic
+    posterior: one quasi-DEER sweep from a perturbed guess against the
+    oracle's FP64 sweep with the diagonal of the relaxed-gate Jacobian (or its
+    one-probe estimate with the same signs), damped and clipped.  The part of
+    the update the relaxed term changes is matched to 2 %."""
+    _say(f"logreg relaxed gate one sweep probes={probes} {kw}")
+    T = 1024
+    ch, tg, s0 = _logreg_case(orc, T, 0.0015, seed=8)
+    x0 = s0.astype(np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, ch.xi, ch.u)
+    guess = (ref + 2e-3 * np.random.default_rng(9).standard_normal(ref.shape)).astype(np.float32)
+    g64 = guess.astype(np.float64)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", gate="surrogate", jac_probes=probes,
+                 probe_seed=21, init_guess=_t(guess), max_iter=1, want_trace=True, **kw)
+    got = r.trace[0].cpu().numpy().astype(np.float64)
+
+    def sj(gate):
+        def f(t, s):
+            F, J, _ = orc.mala_jac(tg, ch.eps, s, ch.xi[t], ch.u[t], gate=gate)
+            return F, J
+        return f
+
+    def sweep(gate):
+        variant = "hutchinson" if probes else "diag"
+        want, _, _ = orc.newton_reference(sj(gate), x0, T, variant=variant, init=g64, max_iter=1,
+                                          full_trace=False, probe_seed=21)
+        if kw:  # damping and clip act on the (structured) diagonal: redo the sweep with them
+            F = np.array([sj(gate)(t, x0 if t == 0 else g64[t - 1])[0] for t in range(T)])
+            jd = np.empty((T, ch.D))
+            for t in range(T):
+                _, J = sj(gate)(t, x0 if t == 0 else g64[t - 1])
+                if probes:
+                    z = np.array([orc.probe_sign(21, 0, t, d) for d in range(ch.D)])
+                    d = orc.hutchinson_diag(J, z)
+                else:
+                    d = np.diag(J)
+                jd[t] = np.clip(kw["damping"] * d, -kw["clip"], kw["clip"])
+            want = np.empty((T, ch.D))
+            for t in range(T):
+                want[t] = F[t] if t == 0 else F[t] + jd[t] * (want[t - 1] - g64[t - 1])
+        return want
+    want = sweep(1)
+    frozen = sweep(0)
+    effect = np.max(np.abs(want - frozen))
+    err = np.max(np.abs(got - want))
+    _say(f"  relaxed-gate effect {effect:.3e}  gpu error {err:.3e}")
+    assert effect > 1e-5
+    assert err <= 0.02 * effect + 2e-6
+
+
+@pytest.mark.parametrize("probes", [0, 1])
+def test_logreg_surrogate_gate_mala(ctx, pm, orc, probes):
+    """The relaxed gate changes sweep counts, never the fixed point: the
+    logistic chain still reaches the FP64 sequential chain."""
+    _say(f"logreg relaxed gate mala probes={probes}")
+    ch, tg, s0 = _logreg_case(orc, 4096, 0.0015, seed=2)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", gate="surrogate", jac_probes=probes,
+                 probe_seed=5, max_iter=4097)
+    rf = pm.solve(ctx, g, ch.eps, _t(s0), _t(ch.xi), _t(ch.u), variant="diag", jac_probes=probes, probe_seed=5,
+                  max_iter=4097)
+    _say(f"  sweeps relaxed {r.sweeps} frozen {rf.sweeps} status {r.status}")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy(), label=f"relaxed gate probes={probes}")
