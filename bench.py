@@ -98,7 +98,7 @@ def main():
                          "FP32 matrix instructions (default) or split-FP16 terms on the FP16 matrix "
                          "cores (the other one is reported as a variant row)")
     ap.add_argument("--workload", default="logreg",
-                    choices=["logreg", "banana", "hmc", "funnel", "batched"],
+                    choices=["logreg", "banana", "hmc", "funnel", "batched", "hmc_seq", "batchcurve", "window"],
                     help="logreg (default) is the benchmark line; the others print "
                          "measurements of the remaining configurations")
     args = ap.parse_args()
@@ -553,6 +553,86 @@ def other_workload(args, pm, W, np, torch):
                          "sweeps_median": float(np.median(spc)), "sweeps_p90": float(np.percentile(spc, 90)),
                          "sweeps_max": int(spc.max()),
                          "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+    elif args.workload == "hmc_seq":
+        # HMC across the sequence (Sec. 3.3): the logistic posterior at the
+        # settings of App. B.4 (4 chains x 1000 transitions, L = 4, eps = 0.04,
+        # one-probe diagonal, damping 0.4, |J_ii| <= 1) and the banana analogue
+        # of Fig. 1 (L = 8, full DEER damped by 0.5 and clipped to [-1, 1])
+        b = W.logreg_hmc_batch(seed=0, n_chains=4, T=1000)
+        g = pm.Target(ctx, b.target)
+        D = b.x0.shape[1]
+        bx = pm.sample_sequential(ctx, g, b.eps, t(b.x0), t(b.burn_xi.reshape(-1, D)), t(b.burn_u.reshape(-1)),
+                                  offsets=list(range(0, 5 * b.n_chains + 1, 5)), sampler="hmc", n_leapfrog=b.L)
+        s0 = bx.states.reshape(b.n_chains, 5, D)[:, -1].contiguous()
+        xi, u = t(b.xi), t(b.u)
+        off = [int(v) for v in b.offsets]
+        n = off[-1]
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, g, b.eps, s0, xi, u, offsets=off, sampler="hmc",
+                                                     n_leapfrog=b.L), reps, torch, "hmc-seq logreg sequential")
+        res["logreg"] = {"chains": b.n_chains, "T": 1000, "L": b.L, "eps": b.eps, "sequential_ms": 1e3 * ts,
+                         "acceptance": rs.accept.float().mean().item()}
+        for name, kw in [("probe_damped", dict(variant="diag", jac_probes=1, probe_seed=1, damping=0.4, clip=1.0,
+                                               gate="surrogate", atol=1e-7, rtol=1e-7)),
+                         ("probe", dict(variant="diag", jac_probes=1, probe_seed=1, gate="surrogate")),
+                         ("picard", dict(variant="picard"))]:
+            r, tp = _timed(lambda: pm.solve(ctx, g, b.eps, s0, xi, u, offsets=off, sampler="hmc", n_leapfrog=b.L,
+                                            max_iter=1001, **kw), reps, torch, name)
+            res["logreg"][name] = {"ms": 1e3 * tp, "chain_steps_per_s": n / tp, "vs_sequential": ts / tp,
+                                   "sweeps_per_chain": r.sweeps_per_chain, "status": r.status,
+                                   "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+        ch = W.banana_chain(T=100000, seed=0, eps=0.2)
+        gb = pm.Target(ctx, ch.target, dtype=torch.float64)
+        x0, xib, ub = t(ch.x0), t(ch.xi), t(ch.u)
+        rsb, tsb = _timed(lambda: pm.sample_sequential(ctx, gb, ch.eps, x0, xib, ub, sampler="hmc", n_leapfrog=8),
+                          reps, torch, "hmc-seq banana sequential")
+        res["banana"] = {"T": ch.T, "L": 8, "eps": ch.eps, "sequential_ms": 1e3 * tsb,
+                         "acceptance": rsb.accept.float().mean().item()}
+        for name, kw in [("dense_damped_clipped", dict(variant="dense", damping=0.5, clip=1.0, gate="surrogate")),
+                         ("diag", dict(variant="diag"))]:
+            r, tp = _timed(lambda: pm.solve(ctx, gb, ch.eps, x0, xib, ub, sampler="hmc", n_leapfrog=8,
+                                            max_iter=ch.T + 1, **kw), 1, torch, name)
+            res["banana"][name] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status, "vs_sequential": tsb / tp,
+                                   "max_abs_vs_sequential": (r.states - rsb.states).abs().max().item()}
+    elif args.workload == "batchcurve":
+        # Sec. 5.2: B equal chains of T = 65536 steps on the logistic posterior
+        # (quasi-DEER, FP32 products) against the same-GPU sequential sampler
+        # running the B chains at once (one workgroup per chain)
+        T = args.T
+        res["T"] = T
+        for B in (1, 2, 4, 8, 16, 32):
+            chs = [W.logreg_chain(T=T, seed=0, eps=args.eps, chain=c) for c in range(B)]
+            tg = pm.Target(ctx, dict(chs[0].target, products="f32"))
+            D = chs[0].D
+            bx = pm.sample_sequential(ctx, tg, args.eps, t(np.stack([c.x0 for c in chs])),
+                                      t(np.concatenate([c.burn_xi for c in chs])),
+                                      t(np.concatenate([c.burn_u for c in chs])), offsets=list(range(0, 3 * B + 1, 3)))
+            s0 = bx.states.reshape(B, 3, D)[:, -1].contiguous()
+            xi = t(np.concatenate([c.xi for c in chs]))
+            u = t(np.concatenate([c.u for c in chs]))
+            off = [c * T for c in range(B + 1)]
+            rs, ts = _timed(lambda: pm.sample_sequential(ctx, tg, args.eps, s0, xi, u, offsets=off), reps, torch,
+                            f"B={B} sequential")
+            r, tp = _timed(lambda: pm.solve(ctx, tg, args.eps, s0, xi, u, offsets=off, variant="diag",
+                                            max_iter=T + 1, atol=TOL, rtol=TOL), reps, torch, f"B={B} parallel")
+            res[f"B{B}"] = {"parallel_ms": 1e3 * tp, "sequential_ms": 1e3 * ts, "speedup": ts / tp,
+                            "chain_steps_per_s": B * T / tp, "sweeps_max": max(r.sweeps_per_chain),
+                            "status": r.status,
+                            "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+            del tg, xi, u, r, rs
+            torch.cuda.empty_cache()
+    elif args.workload == "window":
+        # Sec. 3.4 / Sec. 5.5: fixed-width sliding windows of 128 to 1024 steps
+        # on the logistic chain of the benchmark line (T = 65536)
+        ch = W.logreg_chain(T=args.T, seed=0, eps=args.eps)
+        tg = pm.Target(ctx, dict(ch.target, products="f32"))
+        b = pm.sample_sequential(ctx, tg, args.eps, t(ch.x0), t(ch.burn_xi), t(ch.burn_u))
+        s0 = b.states[-1].clone()
+        xi, u = t(ch.xi), t(ch.u)
+        for w in (0, 128, 256, 512, 1024, 4096):
+            r, tp = _timed(lambda: pm.solve(ctx, tg, args.eps, s0, xi, u, variant="diag", max_iter=200000,
+                                            atol=TOL, rtol=TOL, window_width=w), reps, torch, f"window {w}")
+            res[f"w{w}"] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status,
+                            "chain_steps_per_s": args.T / tp}
     return res
 
 
