@@ -245,6 +245,26 @@ pmc_status pmc_default_options(pmc_options *opts, pmc_dtype dtype);
 pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
                      void *workspace, size_t ws_bytes, pmc_result *res);
 
+/* ---- allocation-free solve -------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): pmc_solve
+ * with its workspace and the scans' look-back descriptors taken from a
+ * per-device static scratch array of 64 MiB (PMC_SCRATCH_BYTES), loaded with
+ * the library and held until the process ends.  Calls no hipMalloc, hipFree
+ * or allocating library routine.  The caller passes inputs and outputs as
+ * for pmc_solve.  A problem whose workspace plus descriptors exceed the
+ * scratch is PMC_ERR_INVALID (quasi-DEER F32 fits up to about 5e6 steps x
+ * coordinates); graph_sweeps > 0, the rotated logistic model (basis on
+ * LOGREG) and the logistic posterior's dense or probed Jacobians before one
+ * pmc_solve has built the target's operand tables are PMC_ERR_UNSUPPORTED.
+ * Every call on a device shares that device's scratch and leaves its
+ * contents behind (the descriptors are cleared at each call, the workspace
+ * is fully rewritten), so calls that overlap on one device -- from several
+ * threads, contexts or streams -- race. */
+#define PMC_SCRATCH_BYTES (64u << 20)
+pmc_status pmc_solve_noalloc(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                             pmc_result *res);
+
 /* ---- same-GPU sequential sampler ------------------------------------------ */
 /* Evaluates s_t = f_t(s_{t-1}) step by step on the device (one workgroup per
  * chain): the baseline the parallel solve is measured against (Sec. 2). */

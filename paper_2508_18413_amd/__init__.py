@@ -13,7 +13,7 @@ from dataclasses import dataclass
 
 from . import _binding as B
 
-__all__ = ["Context", "Target", "solve", "sample_sequential", "linrec_diag", "linrec_block2",
+__all__ = ["Context", "Target", "solve", "solve_noalloc", "sample_sequential", "linrec_diag", "linrec_block2",
            "linrec_dense", "hmc_sample", "adjoint", "autotune", "ParallelMALA", "B"]
 
 VARIANTS = {"dense": B.PMC_DEER_DENSE, "diag": B.PMC_QDEER_DIAG, "block2": B.PMC_QDEER_BLOCK2,
@@ -212,9 +212,18 @@ def _options(dtype, variant="diag", jac_prec="f32", gate="frozen", atol=None, rt
     return o
 
 
+def solve_noalloc(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="mala",
+                  offsets=None, init_guess=None, want_trace=False, max_iter=0, out=None, **opts) -> Result:
+    """pmc_solve_noalloc: pmc_solve with its workspace in the library's static
+    per-device scratch array (no device allocation inside the call).  Output
+    tensors are allocated here unless passed in `out` = (states, accept, gtilde)."""
+    return solve(ctx, target, eps, s0, noise, uniforms, sampler, offsets, init_guess, want_trace, max_iter,
+                 _noalloc=True, _out=out, **opts)
+
+
 def solve(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="mala",
-          offsets=None, init_guess=None, want_trace=False, max_iter=0, n_leapfrog=0, inv_mass=None,
-          **opts) -> Result:
+          offsets=None, init_guess=None, want_trace=False, max_iter=0, _noalloc=False, _out=None,
+          n_leapfrog=0, inv_mass=None, **opts) -> Result:
     """pmc_solve: parallel Newton solve of one or more chains.  s0: [B, D] (or [D]);
     noise: [n_steps, D]; uniforms: [n_steps]; offsets: host list [B+1] or None.
     sampler "hmc": whole HMC transitions with n_leapfrog leapfrog steps and the
@@ -223,9 +232,12 @@ def solve(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="
     s0 = s0.reshape(-1, target.dim).contiguous()
     n, D = noise.shape
     dev = noise.device
-    out = torch.empty((n, D), dtype=noise.dtype, device=dev)
-    acc = torch.empty(n, dtype=torch.uint8, device=dev)
-    gt = torch.empty(n, dtype=torch.float32, device=dev)
+    if _out is not None:
+        out, acc, gt = _out
+    else:
+        out = torch.empty((n, D), dtype=noise.dtype, device=dev)
+        acc = torch.empty(n, dtype=torch.uint8, device=dev)
+        gt = torch.empty(n, dtype=torch.float32, device=dev)
     p, keep = _problem(target, sampler, eps, s0, noise, uniforms, offsets, init_guess, out, acc, gt,
                        n_leapfrog, inv_mass)
     trace = None
@@ -239,8 +251,12 @@ def solve(ctx: Context, target: Target, eps, s0, noise, uniforms=None, sampler="
     r = B.pmc_result()
     r.sweeps_per_chain = C.cast(spc, C.POINTER(C.c_int32))
     r.chain_state = C.cast(cst, C.POINTER(C.c_int8))
-    st = B.check(B.lib().pmc_solve(ctx.h, C.byref(p), C.byref(o), None, 0, C.byref(r)),
-                 allow=(B.PMC_NOT_CONVERGED,))
+    if _noalloc:
+        st = B.check(B.lib().pmc_solve_noalloc(ctx.h, C.byref(p), C.byref(o), C.byref(r)),
+                     allow=(B.PMC_NOT_CONVERGED,))
+    else:
+        st = B.check(B.lib().pmc_solve(ctx.h, C.byref(p), C.byref(o), None, 0, C.byref(r)),
+                     allow=(B.PMC_NOT_CONVERGED,))
     del keep
     return Result(out, acc, gt, st, r.sweeps_total, list(spc), r.n_converged, r.n_accept,
                   r.resid_inf, r.resid_l2, r.max_ratio, r.nonfinite, r.elapsed_ms, trace,

@@ -78,6 +78,7 @@ def lib():
             "pmc_default_options": [C.POINTER(pmc_options), C.c_int],
             "pmc_solve": [vp, C.POINTER(pmc_problem), C.POINTER(pmc_options), vp, C.c_size_t,
                           C.POINTER(pmc_result)],
+            "pmc_solve_noalloc": [vp, C.POINTER(pmc_problem), C.POINTER(pmc_options), C.POINTER(pmc_result)],
             "pmc_sample_sequential": [vp, C.POINTER(pmc_problem), C.POINTER(pmc_result)],
             "pmc_hmc_sample": [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, vp,
                                C.POINTER(pmc_options), C.c_int, vp, vp, vp, C.POINTER(C.c_int32),

@@ -162,6 +162,7 @@ struct pmc_context {
     size_t lb_desc_bytes = 0;
     void *pool = nullptr;            // workspace pool
     size_t pool_bytes = 0;
+    bool no_alloc = false;           // inside pmc_solve_noalloc: growing lb_desc or pool is an error
     pmc::GlobalStatus *h_status = nullptr;  // pinned host mirror
     uint32_t *d_bad = nullptr;       // count of invalid input values (device word)
     uint32_t *h_bad = nullptr;       // its pinned host mirror
@@ -180,6 +181,12 @@ namespace pmc {
 // bytes helper
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Allocation-free entry point: size of the per-device static scratch array,
+// its one-time address lookup (pmc_create, with the device current) and the
+// address for a device (nullptr before scratch_init on that device).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+pmc_status scratch_init(int device);
+void *scratch_ptr(int device);
 
 // Layout helpers: row-major [n, D] <-> dimension-major planes [D, ld].
 pmc_status rows_to_planes(pmc_context *ctx, pmc_dtype dt, const void *rows, void *planes, int64_t n,

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "pmc_internal.hpp"
@@ -11,6 +12,39 @@
 namespace pmc {
 
 static thread_local char g_err[1024] = "";
+
+// ---------------------------------------------------- allocation-free scratch
+// Device memory of pmc_solve_noalloc: one statically sized array per device,
+// loaded with the library's code object and held until the process ends.
+// Host code never uses the array's name as an address: its per-device
+// address comes from hipGetSymbolAddress, taken once per device (with that
+// device current) by pmc_create.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+pmc_status scratch_init(int device)
+{
+    PMC_REQUIRE(device >= 0 && device < kMaxDevices, "scratch: device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return PMC_OK;
+    void *ptr = nullptr;
+    PMC_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    PMC_REQUIRE(ptr != nullptr, "scratch: no device address for device %d", device);
+    g_scratch[device] = ptr;
+    return PMC_OK;
+}
+
+void *scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
 
 void set_error(const char *fmt, ...)
 {
@@ -24,6 +58,11 @@ const char *last_error() { return g_err; }
 pmc_status ensure_lb_desc(pmc_context *ctx, size_t bytes)
 {
     if (bytes <= ctx->lb_desc_bytes) return PMC_OK;
+    if (ctx->no_alloc) {
+        set_error("pmc_solve_noalloc: %zu bytes of look-back descriptors exceed the %zu reserved in scratch", bytes,
+                  ctx->lb_desc_bytes);
+        return PMC_ERR_UNSUPPORTED;
+    }
     size_t nb = align_up(bytes + bytes / 4, 1 << 20);
     if (ctx->lb_desc) {
         PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
@@ -44,6 +83,10 @@ pmc_status ensure_lb_desc(pmc_context *ctx, size_t bytes)
 pmc_status ensure_pool(pmc_context *ctx, size_t bytes)
 {
     if (bytes <= ctx->pool_bytes) return PMC_OK;
+    if (ctx->no_alloc) {
+        set_error("pmc_solve_noalloc: a %zu-byte workspace pool would have to be allocated", bytes);
+        return PMC_ERR_UNSUPPORTED;
+    }
     if (ctx->pool) {
         PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
         PMC_TRY_HIP(hipFree(ctx->pool));
@@ -290,6 +333,11 @@ pmc_status pmc_create(pmc_context **out, int device, void *hip_stream)
         hipHostMalloc((void **)&ctx->h_bad, sizeof(uint32_t)) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
         set_error("pmc_create: device initialisation failed");
+        pmc_destroy(ctx);
+        return PMC_ERR_HIP;
+    }
+    // per-device address of the allocation-free entry point's scratch array
+    if (scratch_init(device) != PMC_OK) {
         pmc_destroy(ctx);
         return PMC_ERR_HIP;
     }

@@ -796,6 +796,11 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
     return PMC_OK;
 }
 
+__global__ void k_zero_words(uint64_t *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
 }  // namespace
 }  // namespace pmc
 
@@ -805,6 +810,58 @@ pmc_status pmc_solve(pmc_context *ctx, const pmc_problem *prob, const pmc_option
                      void *workspace, size_t ws_bytes, pmc_result *res)
 {
     return solve_impl(ctx, prob, opts, workspace, ws_bytes, res, false);
+}
+
+// The workspace and the look-back descriptors of the scans come from the
+// per-device static scratch array: look-back descriptors first (cleared by a
+// fill kernel at every call), then the solve's workspace.  Rejects what would
+// allocate: graph capture, the rotated logistic model, and the logistic
+// posterior's dense or probed Jacobians before their operand tables exist.
+pmc_status pmc_solve_noalloc(pmc_context *ctx, const pmc_problem *prob, const pmc_options *opts,
+                             pmc_result *res)
+{
+    Plan pl;
+    PMC_TRY(make_plan(ctx, prob, opts, pl));
+    const DevTarget &t = *pl.tg;
+    if (opts->graph_sweeps > 0) {
+        set_error("pmc_solve_noalloc: graph_sweeps must be 0 (graph instantiation allocates)");
+        return PMC_ERR_UNSUPPORTED;
+    }
+    if (opts->basis && t.kind == PMC_TARGET_LOGREG) {
+        set_error("pmc_solve_noalloc: the rotated logistic model allocates its rotated copies");
+        return PMC_ERR_UNSUPPORTED;
+    }
+    if ((pl.logreg_dense || pl.logreg_probe) && !t.dxa) {
+        set_error("pmc_solve_noalloc: this target's dense/probe operand tables are not built yet "
+                  "(one pmc_solve with this variant builds them)");
+        return PMC_ERR_UNSUPPORTED;
+    }
+    char *base = (char *)scratch_ptr(ctx->device);
+    if (!base) {
+        set_error("pmc_solve_noalloc: no scratch address for device %d", ctx->device);
+        return PMC_ERR_HIP;
+    }
+    // one descriptor of at most 48 words per lane and scan tile (every scan of the solve fits)
+    const size_t desc = align_up((size_t)48 * 8 * pl.n_lanes * std::max<size_t>(pl.stiles.size(), 1), 256);
+    if (desc + pl.total > kScratchBytes) {
+        set_error("pmc_solve_noalloc: problem needs %zu bytes of scratch, more than its %zu", desc + pl.total,
+                  kScratchBytes);
+        return PMC_ERR_INVALID;
+    }
+    PMC_TRY_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>((desc / 8 + 255) / 256, 1024)), dim3(256), 0,
+                       ctx->stream, (uint64_t *)base, desc / 8);
+    PMC_TRY_HIP(hipGetLastError());
+    void *saved = ctx->lb_desc;
+    const size_t saved_bytes = ctx->lb_desc_bytes;
+    ctx->lb_desc = base;
+    ctx->lb_desc_bytes = desc;
+    ctx->no_alloc = true;
+    const pmc_status st = solve_impl(ctx, prob, opts, base + desc, pl.total, res, true);
+    ctx->no_alloc = false;
+    ctx->lb_desc = saved;
+    ctx->lb_desc_bytes = saved_bytes;
+    return st;
 }
 
 pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_result *res)
