@@ -272,6 +272,7 @@ def main():
         "roofline_scan_in_solve": {"bound": "hbm", "achieved": scan_bytes / (scan_avg_ms * 1e-3) / 1e9,
                                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                    "frac": scan_bytes / (scan_avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                   "traffic": _traffic("k_scan_diag_newton"),
                                    "avg_launch_ms": scan_avg_ms, "kernel": "k_scan<DiagNewtonIO>"},
     }
 

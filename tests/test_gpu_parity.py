@@ -803,6 +803,22 @@ def test_funnel_dense_deer(ctx, pm, orc, jac):
     _check_mala(orc, tg, ch, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy())
 
 
+@pytest.mark.parametrize("jac", ["bf16", "f32"])
+def test_funnel_dense_deer_full_length(ctx, pm, orc, jac):
+    """The funnel at its full length, D = 32, T = 16384: full DEER on the
+    matrix-core dense scan against the FP64 chain."""
+    _say(f"funnel dense DEER T=16384 {jac}")
+    ch = W.funnel_chain(T=16384, seed=4)
+    tg = oracle_target(ch.target)
+    g = pm.Target(ctx, ch.target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0), _t(ch.xi), _t(ch.u), variant="dense", jac_prec=jac,
+                 max_iter=ch.T + 1)
+    _say(f"  dense sweeps={r.sweeps} status={r.status} floor={r.n_floor} {r.elapsed_ms:.1f} ms")
+    assert r.status == 0
+    _check_mala(orc, tg, ch, ch.x0, r.states.cpu().numpy(), r.accept.cpu().numpy(),
+                label=f"funnel dense {jac} T=16384")
+
+
 def test_ula_gaussian_one_solve_mfma(ctx, pm, orc):
     """Affine f: the first matrix-core (F32) dense solve already gives the chain."""
     _say("ula gaussian one solve mfma D=16")
