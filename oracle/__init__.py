@@ -126,8 +126,12 @@ class _TargetStruct(C.Structure):
 class Target:
     """A target density for the oracle.  Arrays are promoted exactly to FP64."""
 
+    MAX_DIM = 1024  # capacity of oracle.c's per-call arrays
+
     def __init__(self, kind, dim, mean=None, prec=None, X=None, y=None, prior_var=1.0, theta=0.0):
         self.kind, self.dim = int(kind), int(dim)
+        if not 1 <= self.dim <= self.MAX_DIM:
+            raise ValueError(f"oracle targets have 1 <= dim <= {self.MAX_DIM} (got {self.dim})")
         self._keep = []
         s = _TargetStruct()
         s.kind, s.dim, s.prior_var, s.theta = self.kind, self.dim, float(prior_var), float(theta)

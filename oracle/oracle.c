@@ -45,7 +45,7 @@ typedef struct {
     double theta;       /* funnel:   neck log-scale */
 } orc_target;
 
-#define MAXD 512
+#define MAXD 1024
 
 static double softplus(double z) { return z > 0 ? z + log1p(exp(-z)) : log1p(exp(z)); }
 static double sigmoid(double z) { return z >= 0 ? 1.0 / (1.0 + exp(-z)) : exp(z) / (1.0 + exp(z)); }

@@ -135,6 +135,48 @@ def logreg_chain(T: int = 65536, seed: int = 0, eps: float = 0.02, n_data: int =
                  meta=dict(workload=f"mala-logreg-d{dim}-n{n_data}", T=T, seed=seed, chain=chain))
 
 
+def embedding_logreg_target(seed: int = 0, n_data: int = 1024, dim: int = 768, decay: float = 0.75,
+                            dtype=np.float32) -> dict:
+    """Synthetic stand-in for a logistic regression on sentence embeddings
+    (Sec. 5.5 uses 768-D text embeddings of 1024 reviews, which are not
+    available here): rows are unit vectors whose covariance has a power-law
+    spectrum (the k-th principal direction carries weight (1 + k)^-decay
+    before normalisation, in a random orthogonal basis V), labels follow a
+    logistic model on w* ~ N(0, I), prior N(0, I).  Also returns the
+    orthogonal basis the paper uses for this model: the left singular
+    vectors of the feature covariance X^T X / N (computed in FP64), as
+    `basis` [D, D] with columns ordered by decreasing singular value."""
+    r = _rng(seed, 0)
+    G = r.standard_normal((dim, dim))
+    V, R = np.linalg.qr(G)
+    V = V * np.sign(np.diag(R))[None, :]
+    scale = (1.0 + np.arange(dim)) ** (-decay)
+    Z = normals(r, (n_data, dim), np.float64)
+    X = (Z * scale[None, :]) @ V.T
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    w = r.standard_normal(dim)
+    p = 1.0 / (1.0 + np.exp(-(X @ w)))
+    y = (r.random(n_data) < p).astype(np.float64)
+    Xr = X.astype(dtype).astype(np.float64)
+    U, _, _ = np.linalg.svd(Xr.T @ Xr / n_data)
+    return dict(kind="logreg", dim=dim, X=X.astype(dtype), y=y.astype(dtype), prior_var=1.0, w_true=w,
+                basis=np.ascontiguousarray(U.astype(dtype)))
+
+
+def embedding_logreg_batch(seed: int = 0, n_chains: int = 4, T: int = 4096, eps: float = 0.015,
+                           n_data: int = 1024, dim: int = 768) -> "Batch":
+    """B chains of MALA on the embedding stand-in (Sec. 5.5: B = 4, 4096
+    samples, step size 0.015), x0 = 0, laid end to end (CSR offsets).  No
+    burn-in steps (burn_xi and burn_u are empty)."""
+    tg = embedding_logreg_target(seed, n_data, dim)
+    offsets = np.arange(n_chains + 1, dtype=np.int64) * T
+    return Batch(target=tg, eps=eps, offsets=offsets, x0=np.zeros((n_chains, dim), dtype=np.float32),
+                 xi=normals(_rng(seed, 3), (n_chains * T, dim), np.float32),
+                 u=uniforms(_rng(seed, 4), n_chains * T, np.float32),
+                 burn_xi=np.zeros((n_chains, 0, dim), dtype=np.float32),
+                 burn_u=np.zeros((n_chains, 0), dtype=np.float32))
+
+
 def funnel_chain(T: int = 16384, seed: int = 0, eps: float = 0.05, theta: float | None = None,
                  dim: int = 32) -> Chain:
     """MALA on the funnel, FP32, x0 = 0."""
