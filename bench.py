@@ -98,7 +98,8 @@ def main():
                          "FP32 matrix instructions (default) or split-FP16 terms on the FP16 matrix "
                          "cores (the other one is reported as a variant row)")
     ap.add_argument("--workload", default="logreg",
-                    choices=["logreg", "banana", "hmc", "funnel", "batched", "hmc_seq", "batchcurve", "window"],
+                    choices=["logreg", "banana", "hmc", "funnel", "batched", "hmc_seq", "batchcurve", "window",
+                             "wide"],
                     help="logreg (default) is the benchmark line; the others print "
                          "measurements of the remaining configurations")
     args = ap.parse_args()
@@ -634,6 +635,38 @@ def other_workload(args, pm, W, np, torch):
                                             atol=TOL, rtol=TOL, window_width=w), reps, torch, f"window {w}")
             res[f"w{w}"] = {"ms": 1e3 * tp, "sweeps": r.sweeps, "status": r.status,
                             "chain_steps_per_s": args.T / tp}
+    elif args.workload == "wide":
+        # Sec. 5.5: MALA on the 768-dimensional embedding regression stand-in,
+        # B = 4 chains x 4096 steps, step size 0.015, with the orthogonal basis
+        # (left singular vectors of the feature covariance) and fixed-width
+        # windows, against the same-GPU sequential sampler
+        b = W.embedding_logreg_batch(seed=0, n_chains=4, T=4096, eps=0.015)
+        tg = pm.Target(ctx, b.target)
+        x0, xi, u, Q = t(b.x0), t(b.xi), t(b.u), t(b.target["basis"])
+        offs = list(b.offsets)
+        n = int(b.offsets[-1])
+        N, D = b.target["X"].shape
+        rs, ts = _timed(lambda: pm.sample_sequential(ctx, tg, b.eps, x0, xi, u, offsets=offs), reps, torch,
+                        "wide sequential")
+        res.update({"chains": 4, "T": 4096, "D": D, "n_data": N, "eps": b.eps,
+                    "sequential_ms": 1e3 * ts, "acceptance": float(rs.accept.float().mean())})
+        seq_states = rs.states
+        flop_step = 10.0 * N * D
+        for basis in (True, False):
+            for w in ((0, 128, 256, 512, 1024) if basis else (0,)):
+                kw = dict(variant="diag", max_iter=200000, window_width=w, offsets=offs)
+                if basis:
+                    kw["basis"] = Q
+                r, tp = _timed(lambda: pm.solve(ctx, tg, b.eps, x0, xi, u, **kw), reps, torch,
+                               f"wide basis={basis} window {w}")
+                pr = pm.solve(ctx, tg, b.eps, x0, xi, u, profile_kernels=True, **kw)
+                ach = flop_step * pr.eval_steps / (pr.eval_ms * 1e-3) / 1e12 if pr.eval_ms > 0 else None
+                res[f"{'basis' if basis else 'plain'}_w{w}"] = {
+                    "ms": 1e3 * tp, "sweeps_per_chain": list(r.sweeps_per_chain), "status": r.status,
+                    "chain_steps_per_s": n / tp, "vs_sequential": ts / tp,
+                    "max_abs_vs_sequential": float((r.states - seq_states).abs().max()),
+                    "eval_tflops": ach, "eval_frac_of_fp32_peak": ach / PEAK_FP32_TFLOPS if ach else None,
+                    "eval_ms_per_sweep": pr.eval_ms / max(1, pr.sweeps), "scan_ms_per_sweep": pr.scan_ms / max(1, pr.sweeps)}
     return res
 
 

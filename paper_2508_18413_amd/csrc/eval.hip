@@ -300,7 +300,11 @@ pmc_status eval_dm(pmc_context *ctx, const EvalArgs &a, int D, Extra... ex)
 
 }  // namespace
 
-int eval_tile_steps(const DevTarget &tg) { return tg.kind == PMC_TARGET_LOGREG ? 32 : 256; }
+int eval_tile_steps(const DevTarget &tg)
+{
+    if (tg.kind == PMC_TARGET_LOGREG) return tg.dim >= kWideMinDim ? wide_tile_steps() : 32;
+    return 256;
+}
 
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
 {
@@ -321,6 +325,10 @@ pmc_status launch_eval(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
     case PMC_TARGET_LOGREG:
         if (t.dtype != PMC_F32) {
             set_error("logistic regression runs in F32");
+            return PMC_ERR_UNSUPPORTED;
+        }
+        if (t.dim >= kWideMinDim) {
+            set_error("logistic regression with D > 32 is evaluated by the solve's GEMM path only");
             return PMC_ERR_UNSUPPORTED;
         }
         // dense modes: the kernel writes f_t and the decisions only; the

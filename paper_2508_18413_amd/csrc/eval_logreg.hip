@@ -1117,6 +1117,7 @@ hipError_t allow_lds()
 
 pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
 {
+    if (t.dim >= kWideMinDim) return logreg_wide_tables(ctx, t);
     const int nr = (t.n_data + 31) / 32, mk = (t.dim + 1) / 2;
     t.nr = nr;
     t.mk = mk <= 2 ? 2 : mk <= 4 ? 4 : mk <= 8 ? 8 : mk <= 13 ? 13 : 16;

@@ -142,6 +142,9 @@ struct DevTarget {
     // pair products x_d x_e in BF16 matrix-core order
     void *dxa = nullptr, *dpb = nullptr, *dxt = nullptr;
     int dnb = 0, dnpt = 0, dgrp = 0;
+    // logistic regression with D > 32: X is [Np][ldx] (both padded to 128,
+    // zero filled, y zero past n_data), with X^T and (X o X)^T [ldx][Np]
+    void *xwt = nullptr, *x2wt = nullptr;
 };
 
 }  // namespace pmc
@@ -324,6 +327,22 @@ __device__ __forceinline__ uint64_t probe_mix(uint64_t x)
 }
 pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);
 pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
+// Logistic regression with 32 < D <= 1024 (logreg_wide.hip): the MALA
+// evaluation as five FP32 matrix-core GEMMs over the steps of the active
+// windows, with fused epilogues.  Workspace per solve (wide_workspace_bytes)
+// holds the predictor and residual planes, the gradient and increment
+// planes, the noise in planes (filled once per solve by wide_rows_to_planes
+// at wide_xi_planes) and the per-step row-tile sums.
+constexpr int kWideMinDim = 33, kWideMaxDim = 1024;
+int wide_pad(int n);          // rows and columns padded to the GEMM tile (128)
+int wide_tile_steps();        // evaluation tile (steps)
+size_t wide_workspace_bytes(const DevTarget &t, int64_t ld);
+float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld);
+pmc_status logreg_wide_tables(pmc_context *ctx, DevTarget &t);
+pmc_status wide_rotate_rows(pmc_context *ctx, const float *in, int64_t rows, int64_t ld_in, const float *Q, int D,
+                            bool transpose, float *out, int64_t ld_out);
+pmc_status wide_rows_to_planes(pmc_context *ctx, const float *in, int64_t n, int D, int64_t ld, float *out);
+pmc_status launch_eval_logreg_wide(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, void *ws);
 // Full-DEER Jacobians on the logistic posterior: operand tables (once per
 // target), then per sweep the pair sums H [n, 32 dnpt] and the dense J image
 // (BF16 or FP32) from the evaluation's accept decisions.
@@ -352,8 +371,16 @@ struct SeqArgs {
     int ula;
     int hmc_L = 0;                   // > 0: HMC transitions with this many leapfrog steps
     const void *inv_mass = nullptr;  // HMC: [D] diagonal of M^-1, or nullptr
+    void *scratch = nullptr;         // device scratch of seq_scratch_bytes bytes
+    const int64_t *host_offsets = nullptr;  // [n_chains + 1], host copy of offsets
 };
 pmc_status launch_sequential(pmc_context *ctx, const DevTarget &tg, const SeqArgs &a);
+// Device scratch the sequential sampler needs for this target (the D > 32
+// logistic sampler's grid-barrier words and partial sums), else 0.
+size_t seq_scratch_bytes(const DevTarget &tg, int n_chains);
+// The same-GPU sequential MALA sampler for logistic regression with D > 32:
+// one cooperative launch per group of up to four chains (logreg_wide.hip).
+pmc_status launch_sequential_logreg_wide(pmc_context *ctx, const DevTarget &t, const SeqArgs &a);
 // HMC transitions as chain steps (Sec. 3.3): evaluation (per-lane targets and
 // the logistic posterior) and the same-GPU sequential sampler.
 pmc_status launch_eval_hmc(pmc_context *ctx, const DevTarget &t, const EvalArgs &a);

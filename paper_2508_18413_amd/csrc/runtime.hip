@@ -429,18 +429,28 @@ pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *d, pmc_tar
                 ldx = c;
                 break;
             }
-        if (!ldx) {
-            set_error("logreg target: dim <= 32 (got %d)", d->dim);
-            return PMC_ERR_UNSUPPORTED;
+        const bool wide = d->dim >= kWideMinDim;
+        if (wide) {
+            // the matrix-core GEMM path: rows and columns padded to its tile
+            if (d->dim > kWideMaxDim) {
+                set_error("logreg target: dim <= %d (got %d)", kWideMaxDim, d->dim);
+                return PMC_ERR_UNSUPPORTED;
+            }
+            PMC_REQUIRE(d->products != PMC_PRODUCTS_SPLIT16,
+                        "logreg target: dim > 32 evaluates with FP32 matrix products only");
+            PMC_REQUIRE(d->n_data <= (1 << 24), "logreg target: n_data <= 2^24 (got %d)", d->n_data);
+            ldx = wide_pad(d->dim);
         }
         PMC_REQUIRE(d->products >= PMC_PRODUCTS_AUTO && d->products <= PMC_PRODUCTS_SPLIT16,
                     "logreg target: unknown products mode %d", (int)d->products);
         t.ldx = ldx;
         t.n_data = d->n_data;
-        t.products = d->products;
-        PMC_TRY_HIP(hipMalloc(&t.X, 4 * (size_t)ldx * d->n_data));
-        PMC_TRY_HIP(hipMalloc(&t.y, 4 * (size_t)d->n_data));
-        PMC_TRY_HIP(hipMemsetAsync(t.X, 0, 4 * (size_t)ldx * d->n_data, ctx->stream));
+        t.products = wide ? PMC_PRODUCTS_F32 : d->products;
+        const size_t rows = wide ? (size_t)wide_pad(d->n_data) : (size_t)d->n_data;
+        PMC_TRY_HIP(hipMalloc(&t.X, 4 * (size_t)ldx * rows));
+        PMC_TRY_HIP(hipMalloc(&t.y, 4 * rows));
+        PMC_TRY_HIP(hipMemsetAsync(t.X, 0, 4 * (size_t)ldx * rows, ctx->stream));
+        PMC_TRY_HIP(hipMemsetAsync(t.y, 0, 4 * rows, ctx->stream));
         PMC_TRY_HIP(hipMemcpy2DAsync(t.X, 4 * ldx, d->X, 4 * d->dim, 4 * d->dim, d->n_data,
                                      hipMemcpyDeviceToDevice, ctx->stream));
         PMC_TRY_HIP(hipMemcpyAsync(t.y, d->y, 4 * (size_t)d->n_data, hipMemcpyDeviceToDevice,
@@ -468,7 +478,8 @@ pmc_status pmc_target_destroy(pmc_target *tgt)
     if (tgt->t.prec) (void)hipFree(tgt->t.prec);
     if (tgt->t.X) (void)hipFree(tgt->t.X);
     if (tgt->t.y) (void)hipFree(tgt->t.y);
-    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl, tgt->t.xh, tgt->t.dxa, tgt->t.dpb, tgt->t.dxt})
+    for (void *q : {tgt->t.xa, tgt->t.xta, tgt->t.x2ta, tgt->t.ypad, tgt->t.xl, tgt->t.xh, tgt->t.dxa, tgt->t.dpb, tgt->t.dxt,
+                    tgt->t.xwt, tgt->t.x2wt})
         if (q) (void)hipFree(q);
     delete tgt;
     return PMC_OK;

@@ -304,6 +304,7 @@ pmc_status launch_sequential(pmc_context *ctx, const DevTarget &t, const SeqArgs
         if (t.dtype == PMC_F64) return seq_dm<double, Funnel>(ctx, a, D, (double)t.theta);
         return seq_dm<float, Funnel>(ctx, a, D, (float)t.theta);
     case PMC_TARGET_LOGREG: {
+        if (t.dim >= kWideMinDim) return launch_sequential_logreg_wide(ctx, t, a);
         // 256 threads x 4 rows up to 1024 data points, 512 x 4 up to 2048
         if (t.n_data > 4 * 512) {
             set_error("sequential logreg sampler supports n_data <= 2048");

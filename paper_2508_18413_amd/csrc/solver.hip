@@ -52,6 +52,8 @@ struct Plan {
     const void *basis = nullptr;  // orthogonal reparameterisation (iterates z = Q^T s)
     size_t o_rot = 0;             // rotation scratch planes [D, ld]
     size_t o_hpair = 0;
+    bool logreg_wide = false;     // logistic regression with D > 32 (matrix-core GEMM evaluation)
+    size_t o_wide = 0;
 };
 
 void build_tiles(const std::vector<int64_t> &offs, int C, std::vector<SegTile> &tiles,
@@ -123,6 +125,14 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     if (t.kind == PMC_TARGET_GAUSSIAN && pl.D > Gaussian<float, 16>::kMaxLaneDim) {
         set_error("pmc_solve: per-step Gaussian evaluation supports D <= %d (got %d)",
                   Gaussian<float, 16>::kMaxLaneDim, pl.D);
+        return PMC_ERR_UNSUPPORTED;
+    }
+    pl.logreg_wide = t.kind == PMC_TARGET_LOGREG && pl.D >= kWideMinDim;
+    if (pl.logreg_wide &&
+        (pl.hmc || (o->variant != PMC_QDEER_DIAG && o->variant != PMC_PICARD) || o->jac_probes ||
+         (o->gate == PMC_GATE_SURROGATE && p->sampler == PMC_SAMPLER_MALA))) {
+        set_error("pmc_solve: logistic regression with D > 32 runs MALA or ULA, frozen gate, with quasi-DEER "
+                  "(exact diagonal) or Picard");
         return PMC_ERR_UNSUPPORTED;
     }
     pl.variant = o->variant;
@@ -281,6 +291,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
                                                                          : 256);
     if (pl.logreg_dense) pl.o_hpair = take(sizeof(float) * (size_t)pl.n * logreg_dense_pair_cols(pl.D));
     if (pl.basis) pl.o_rot = take(plane * pl.D);
+    if (pl.logreg_wide) pl.o_wide = take(wide_workspace_bytes(t, pl.ld));
     pl.o_acc = take(std::max<int64_t>(pl.n, 1));
     pl.o_gt = take(4 * std::max<int64_t>(pl.n, 1));
     pl.o_etiles = take(sizeof(SegTile) * std::max<size_t>(pl.etiles.size(), 1));
@@ -300,6 +311,7 @@ struct Sweep {
     StatusArgs st;
     void *hier;  // matrix-core scan hierarchy workspace
     float *hpair = nullptr;  // pair sums of the logistic Hessian (dense DEER)
+    void *wide = nullptr;    // workspace of the D > 32 logistic evaluation
 };
 
 // One Newton sweep: evaluation, scan, status fold.  ev (optional) receives
@@ -318,6 +330,8 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
         PMC_TRY(launch_eval(ctx, *pl.tg, e));
         if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, e, pl.n, pl.n_chains));
         PMC_TRY(launch_logreg_surrogate(ctx, *pl.tg, sw.ea));
+    } else if (pl.logreg_wide) {
+        PMC_TRY(launch_eval_logreg_wide(ctx, *pl.tg, sw.ea, sw.wide));
     } else {
         PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
         if (pl.logreg_dense)
@@ -358,6 +372,9 @@ pmc_status rotate_rows(pmc_context *ctx, const void *in, int64_t rows, int ld_in
                        bool transpose, void *out, int ld_out)
 {
     if (rows <= 0) return PMC_OK;
+    if (D >= kWideMinDim)
+        return wide_rotate_rows(ctx, (const float *)in, rows, ld_in, (const float *)Q, D, transpose, (float *)out,
+                                ld_out);
     PMC_REQUIRE(D >= 1 && D <= 32 && (rows + 255) / 256 <= 0x7fffffff, "rotate_rows: bad shape");
     hipLaunchKernelGGL(k_rotate_rows, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, ctx->stream,
                        (const float *)in, rows, ld_in, (const float *)Q, D, transpose ? 1 : 0, (float *)out, ld_out);
@@ -379,7 +396,7 @@ pmc_status solve_logreg_rotated(pmc_context *ctx, const pmc_problem *prob, const
     const int D = t.dim, nc = prob->n_chains;
     const int64_t n = prob->n_steps;
     PMC_REQUIRE(is_device_ptr(opts->basis), "pmc_solve: basis must be a device pointer");
-    PMC_REQUIRE(nc >= 1 && n >= 0 && D <= 32, "pmc_solve: bad rotated logistic problem");
+    PMC_REQUIRE(nc >= 1 && n >= 0 && D <= kWideMaxDim, "pmc_solve: bad rotated logistic problem");
     PMC_TRY_HIP(hipSetDevice(ctx->device));
     pmc_target rt;
     rt.device = prob->target->device;
@@ -396,12 +413,14 @@ pmc_status solve_logreg_rotated(pmc_context *ctx, const pmc_problem *prob, const
     auto release = [&]() {
         (void)hipStreamSynchronize(ctx->stream);
         for (void *q : {(void *)rt.t.X, rt.t.xa, rt.t.xta, rt.t.x2ta, rt.t.ypad, rt.t.xl, rt.t.xh, rt.t.dxa,
-                        rt.t.dpb, rt.t.dxt, (void *)xi, (void *)s0, (void *)guess, (void *)zout, (void *)ztrace})
+                        rt.t.dpb, rt.t.dxt, rt.t.xwt, rt.t.x2wt, (void *)xi, (void *)s0, (void *)guess, (void *)zout,
+                        (void *)ztrace})
             if (q) (void)hipFree(q);
     };
     pmc_status st = PMC_OK;
     auto run = [&]() -> pmc_status {
-        const size_t xb = 4 * (size_t)t.ldx * t.n_data, rb = 4 * (size_t)std::max<int64_t>(n, 1) * D;
+        const size_t xrows = D >= kWideMinDim ? (size_t)wide_pad(t.n_data) : (size_t)t.n_data;
+        const size_t xb = 4 * (size_t)t.ldx * xrows, rb = 4 * (size_t)std::max<int64_t>(n, 1) * D;
         PMC_TRY_HIP(hipMalloc(&rt.t.X, xb));
         PMC_TRY_HIP(hipMemsetAsync(rt.t.X, 0, xb, ctx->stream));
         PMC_TRY(rotate_rows(ctx, t.X, t.n_data, t.ldx, opts->basis, D, false, rt.t.X, t.ldx));  // X Q
@@ -594,6 +613,12 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
 
     Sweep sw;
     sw.hier = ws + pl.o_hier;
+    if (pl.logreg_wide) {
+        // the noise as planes, once per solve
+        sw.wide = ws + pl.o_wide;
+        PMC_TRY(wide_rows_to_planes(ctx, (const float *)prob->noise, pl.n, pl.D, pl.ld,
+                                    wide_xi_planes(sw.wide, *pl.tg, pl.ld)));
+    }
     if (pl.logreg_dense || pl.logreg_probe) {
         // operand tables: derived data of the target, built by its first
         // dense or probed solve
@@ -909,7 +934,8 @@ pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_res
                                   {hmc ? p->inv_mass : nullptr, t.dim, 2}};
         PMC_TRY(check_inputs(ctx, t.dtype, in, 4));
     }
-    PMC_TRY(ensure_pool(ctx, sizeof(int64_t) * offs.size()));
+    const size_t offs_bytes = align_up(sizeof(int64_t) * offs.size(), 256);
+    PMC_TRY(ensure_pool(ctx, offs_bytes + (hmc ? 0 : seq_scratch_bytes(t, p->n_chains))));
     int64_t *d_offs = (int64_t *)ctx->pool;
     hipStream_t st = ctx->stream;
     PMC_TRY_HIP(hipMemcpyAsync(d_offs, offs.data(), sizeof(int64_t) * offs.size(),
@@ -928,6 +954,8 @@ pmc_status pmc_sample_sequential(pmc_context *ctx, const pmc_problem *p, pmc_res
     a.ula = p->sampler == PMC_SAMPLER_ULA;
     a.hmc_L = hmc ? p->n_leapfrog : 0;
     a.inv_mass = hmc ? p->inv_mass : nullptr;
+    a.scratch = (char *)ctx->pool + offs_bytes;
+    a.host_offsets = offs.data();
     PMC_TRY_HIP(hipEventRecord(ctx->ev0, st));
     if (hmc)
         PMC_TRY(launch_sequential_hmc(ctx, t, a));
