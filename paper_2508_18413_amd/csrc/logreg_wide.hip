@@ -213,44 +213,46 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
             prow[q] = g.P + (size_t)i * g.ldp;
         }
     }
-    float pv[16], qv[16];
-    auto load_stage = [&](int k0) {
+    // two register sets: the loads of stage kt + 2 are issued before the
+    // products of stage kt and stored to LDS after those of stage kt + 1
+    float pv[2][16], qv[2][16];
+    auto load_stage = [&](int r, int k0) {
         if (kPadP) {
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const float4 v = *(const float4 *)(prow[q] + k0);
-                pv[4 * q] = v.x;
-                pv[4 * q + 1] = v.y;
-                pv[4 * q + 2] = v.z;
-                pv[4 * q + 3] = v.w;
+                pv[r][4 * q] = v.x;
+                pv[r][4 * q + 1] = v.y;
+                pv[r][4 * q + 2] = v.z;
+                pv[r][4 * q + 3] = v.w;
             }
         } else {
             const int k = min(k0 + pk, g.K - 1);
 #pragma unroll
-            for (int q = 0; q < 16; q++) pv[q] = prow[q][k];
+            for (int q = 0; q < 16; q++) pv[r][q] = prow[q][k];
         }
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const int kk = k0 + qr0 + 2 * q;
-            qv[q] = qbase[(kk < g.K ? kk : 0) * qstride];
+            qv[r][q] = qbase[(kk < g.K ? kk : 0) * qstride];
         }
     };
-    auto store_stage = [&](int s, int k0) {
+    auto store_stage = [&](int r, int s, int k0) {
         float *Ps = lds + s * kStageFloats, *Qs = Ps + kBI * kPS;
         if (kPadP) {
 #pragma unroll
             for (int q = 0; q < 4; q++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) Ps[(pr4 + 32 * q) * kPS + pk4 + e] = pv[4 * q + e];
+                for (int e = 0; e < 4; e++) Ps[(pr4 + 32 * q) * kPS + pk4 + e] = pv[r][4 * q + e];
         } else {
             const bool kv = k0 + pk < g.K;
 #pragma unroll
             for (int q = 0; q < 16; q++)
-                Ps[(pr0 + 8 * q) * kPS + pk] = (kv && i0 + pr0 + 8 * q < g.I) ? pv[q] : 0.f;
+                Ps[(pr0 + 8 * q) * kPS + pk] = (kv && i0 + pr0 + 8 * q < g.I) ? pv[r][q] : 0.f;
         }
 #pragma unroll
         for (int q = 0; q < 16; q++)
-            Qs[(qr0 + 2 * q) * kQS + qj] = (qval && k0 + qr0 + 2 * q < g.K) ? qv[q] : 0.f;
+            Qs[(qr0 + 2 * q) * kQS + qj] = (qval && k0 + qr0 + 2 * q < g.K) ? qv[r][q] : 0.f;
     };
 
     f32x16 acc[2][2];
@@ -260,15 +262,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
         for (int b = 0; b < 2; b++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
-
-    const int nk = (g.K + kBK - 1) / kBK;
-    load_stage(0);
-    store_stage(0, 0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; kt++) {
-        const bool more = kt + 1 < nk;
-        if (more) load_stage((kt + 1) * kBK);
-        const float *Ps = lds + (kt & 1) * kStageFloats, *Qs = Ps + kBI * kPS;
+    auto compute = [&](int s) {
+        const float *Ps = lds + s * kStageFloats, *Qs = Ps + kBI * kPS;
 #pragma unroll
         for (int kp = 0; kp < kBK / 2; kp++) {
             const int kk = 2 * kp + h;
@@ -283,8 +278,25 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
                 for (int b = 0; b < 2; b++)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-        if (more) store_stage((kt + 1) & 1, (kt + 1) * kBK);
+    };
+
+    const int nk = (g.K + kBK - 1) / kBK;
+    load_stage(0, 0);
+    store_stage(0, 0, 0);
+    if (nk > 1) load_stage(1, kBK);
+    __syncthreads();
+    // stage kt lives in LDS buffer kt & 1 and arrives through register set kt & 1
+    for (int kt = 0; kt < nk; kt += 2) {
+        if (kt + 2 < nk) load_stage(0, (kt + 2) * kBK);
+        compute(0);
+        if (kt + 1 < nk) store_stage(1, 1, (kt + 1) * kBK);
         __syncthreads();
+        if (kt + 1 < nk) {
+            if (kt + 3 < nk) load_stage(1, (kt + 3) * kBK);
+            compute(1);
+            if (kt + 2 < nk) store_stage(0, 0, (kt + 2) * kBK);
+            __syncthreads();
+        }
     }
 
     // ---- epilogue: lane (jl, h) of block (a, b) holds C[i][jj] with
@@ -686,17 +698,28 @@ pmc_status launch_eval_logreg_wide(pmc_context *ctx, const DevTarget &t, const E
 // The same-GPU sequential sampler for D > 32: the chain's steps in order,
 // each step spread over the whole GPU.  nb workgroups (one cooperative
 // launch, all resident) each own rpw data rows, whose slice of X stays in
-// LDS.  Per step and chain, workgroup w computes for its rows the predictor
-// increments dA = X Delta, the residuals at the proposal and its share of
-// X^T R~ and of the log-likelihood difference, and publishes them; one grid
-// barrier; then every workgroup sums all shares in the same fixed order, so
-// each one takes the same decision and holds the same state (x, g, Delta)
-// without a second barrier.  Partial sums are double-buffered by step
-// parity.  Up to kSeqChains chains run in one launch.
+// LDS, and a slice of the coordinates.  Every workgroup keeps the whole
+// state (x, grad log p(x), Delta) of each chain; per step and chain:
+//   A. all: Delta = eps g + sqrt(2 eps) xi, the predictor increments of own
+//      rows, residuals at the proposal; publish own share of X^T r~ (every
+//      coordinate) and of the log-likelihood difference;
+//   B. coordinate owners: sum the shares of own coordinates -> g~ there,
+//      and own slice's sums for the proposal-density and prior terms;
+//      publish them;
+//   C. all: read g~ and the slice sums, take the decision (the same values
+//      in the same order everywhere, so every workgroup decides alike) and
+//      update the state.
+// Shared words carry the step's tag in their upper half (agent-scope
+// atomic 64-bit stores and loads); a reader waits until the tag matches,
+// so no grid barrier and no cache flush is needed.  Words are
+// double-buffered by tag parity: a workgroup cannot publish step k + 2
+// before every workgroup has consumed step k.  Up to kSeqChains chains run
+// in one launch.
 namespace {
 
-constexpr int kSeqThreads = 256, kSeqChains = 4;
+constexpr int kSeqThreads = 512, kSeqChains = 4;
 constexpr size_t kSeqLdsLimit = 150 * 1024;
+constexpr int kSeqQ = 6;  // slice sums: |g + g~|^2, xi.(g + g~), Delta.(x~ + x), each as two words
 
 struct SeqWide {
     SeqArgs a;
@@ -704,13 +727,47 @@ struct SeqWide {
     const float *y;     // [Np]
     int N, ldx, D;
     float pp;
-    int nb, rpw;        // workgroups, rows per workgroup
+    int nb, rpw, dpw;   // workgroups, rows and coordinates per workgroup
     int c0, nc;         // chains c0 .. c0 + nc - 1
     int64_t steps;      // longest chain of the group
-    float *part;        // [2][kSeqChains][D + 1][nb]: workgroup w's share last
-    uint32_t *ctr;      // grid barrier counter (zero at launch)
-    uint32_t *abort_;   // set when a barrier wait times out
+    uint64_t *p1;       // [2][nb][kSeqChains][D + 1] shares of X^T r~ and of the log-likelihood difference
+    uint64_t *p2;       // [2][kSeqChains][D] g~
+    uint64_t *p3;       // [2][nb][kSeqChains][kSeqQ] slice sums
+    uint32_t *abort_;   // set when a wait times out
 };
+
+__device__ __forceinline__ uint64_t tagw(uint32_t tag, uint32_t bits) { return ((uint64_t)tag << 32) | bits; }
+__device__ __forceinline__ void put(uint64_t *w, uint32_t tag, float v)
+{
+    __hip_atomic_store(w, tagw(tag, __float_as_uint(v)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads n tagged words (n <= 16) into v once all carry `tag`; false on a
+// timeout or when another workgroup gave up.
+template <int NMAX>
+__device__ bool take(const SeqWide &q, const uint64_t *const *w, int n, uint32_t tag, float *v)
+{
+    uint32_t ready = 0;
+    const uint32_t all = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+    for (uint32_t spin = 0;; spin++) {
+#pragma unroll
+        for (int i = 0; i < NMAX; i++) {
+            if (i < n && !(ready >> i & 1u)) {
+                const uint64_t x = __hip_atomic_load(w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)(x >> 32) == tag) {
+                    v[i] = __uint_as_float((uint32_t)x);
+                    ready |= 1u << i;
+                }
+            }
+        }
+        if (ready == all) return true;
+        if (spin > (1u << 22) || __hip_atomic_load(q.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(q.abort_, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
 
 __device__ __forceinline__ double block_sum_d(double v, double *red)
 {
@@ -724,98 +781,197 @@ __device__ __forceinline__ double block_sum_d(double v, double *red)
     return s;
 }
 
-// Grid barrier number b (1-based); false if it timed out or another
-// workgroup gave up.
-__device__ bool grid_barrier(const SeqWide &q, uint32_t b)
+// the workgroup-wide AND of per-thread flags
+__device__ __forceinline__ bool block_all(bool ok)
 {
-    __shared__ int s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(q.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = b * (uint32_t)q.nb;
-        int ok = 1;
-        for (uint32_t spin = 0;; spin++) {
-            if (__hip_atomic_load(q.ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-            if (__hip_atomic_load(q.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spin > (1u << 24)) {
-                __hip_atomic_store(q.abort_, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
+    return __syncthreads_and(ok ? 1 : 0) != 0;
+}
+
+__device__ __forceinline__ void put_d(uint64_t *w, uint32_t tag, double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    __hip_atomic_store(w, tagw(tag, (uint32_t)u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, tagw(tag, (uint32_t)(u >> 32)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void __launch_bounds__(kSeqThreads) k_seq_logreg_wide(SeqWide q)
 {
     extern __shared__ float sm[];
     __shared__ double s_red[kSeqThreads / 64];
+    __shared__ double s_sum[kSeqChains][4];
     __shared__ int s_acc[kSeqChains];
-    const int D = q.D, ldx = q.ldx, rpw = q.rpw, nc = q.nc, tid = threadIdx.x;
+    __shared__ int64_t s_t0[kSeqChains], s_t1[kSeqChains];
+    __shared__ float s_y[32];
+    const int D = q.D, ldx = q.ldx, rpw = q.rpw, nc = q.nc, nb = q.nb, tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int r0 = blockIdx.x * rpw;
+    const int d0 = min(D, (int)blockIdx.x * q.dpw), d1 = min(D, d0 + q.dpw);
     float *sX = sm;                                  // [rpw][ldx]
-    float *sx = sX + (size_t)rpw * ldx;              // [nc][D] x
-    float *sg = sx + (size_t)kSeqChains * D;         // [nc][D] gradient at x
-    float *sdl = sg + (size_t)kSeqChains * D;        // [nc][D] Delta
-    float *sgt = sdl + (size_t)kSeqChains * D;       // [nc][D] gradient at the proposal
-    float *sa = sgt + (size_t)kSeqChains * D;        // [nc][rpw] predictors of own rows at x
-    float *sat = sa + kSeqChains * rpw;              // [nc][rpw] at the proposal
-    float *sr = sat + kSeqChains * rpw;              // [nc][rpw] residuals
+    float *sx = sX + (size_t)rpw * ldx;              // [kSeqChains][D] x
+    float *sg = sx + (size_t)kSeqChains * D;         // [kSeqChains][D] gradient at x
+    float *sdl = sg + (size_t)kSeqChains * D;        // [kSeqChains][D] Delta
+    float *sgt = sdl + (size_t)kSeqChains * D;       // [kSeqChains][D] gradient at the proposal
+    float *sa = sgt + (size_t)kSeqChains * D;        // [kSeqChains][rpw] predictors of own rows at x
+    float *sat = sa + kSeqChains * rpw;              // [kSeqChains][rpw] at the proposal
+    float *sr = sat + kSeqChains * rpw;              // [kSeqChains][rpw] residuals
     const float eps = (float)q.a.eps, cc = sqrtf(2.f * eps);
     const float *noise = (const float *)q.a.noise, *unif = (const float *)q.a.unif;
     const int64_t *offs = q.a.offsets;
     float *out = (float *)q.a.out;
-    const int nb = q.nb;
-    // share of workgroup w in value v (0..D-1: X^T r, D: log-likelihood difference) of chain c
-    auto pidx = [&](int buf, int c, int v, int w) {
-        return (((size_t)buf * kSeqChains + c) * ((size_t)D + 1) + v) * nb + w;
+    // word addresses (32-bit index arithmetic: every buffer holds < 2^31 words)
+    uint64_t *const p1 = q.p1, *const p2 = q.p2, *const p3 = q.p3;
+    const uint32_t D1 = (uint32_t)D + 1, ud = (uint32_t)D, unb = (uint32_t)nb;
+    auto P1 = [=](uint32_t tag, int w, int c, int v) {
+        return p1 + ((((tag & 1u) * unb + (uint32_t)w) * kSeqChains + (uint32_t)c) * D1 + (uint32_t)v);
+    };
+    auto P2 = [=](uint32_t tag, int c, int d) { return p2 + (((tag & 1u) * kSeqChains + (uint32_t)c) * ud + (uint32_t)d); };
+    auto P3 = [=](uint32_t tag, int w, int c) {
+        return p3 + ((((tag & 1u) * unb + (uint32_t)w) * kSeqChains + (uint32_t)c) * kSeqQ);
     };
 
     for (int o = tid; o < rpw * ldx; o += kSeqThreads) sX[o] = q.X[(size_t)r0 * ldx + o];
     for (int c = 0; c < nc; c++)
         for (int d = tid; d < D; d += kSeqThreads) sx[c * D + d] = ((const float *)q.a.s0)[(size_t)(q.c0 + c) * D + d];
+    if (tid < nc) {
+        s_t0[tid] = offs[q.c0 + tid];
+        s_t1[tid] = offs[q.c0 + tid + 1];
+    }
+    if (tid < rpw) s_y[tid] = r0 + tid < q.N ? q.y[r0 + tid] : 0.f;
     __syncthreads();
-
-    // predictors of own rows for the rows' share of a product with X
-    auto row_dots = [&](const float *vec, float *dst) {
-        for (int pr = wv; pr < nc * rpw; pr += kSeqThreads / 64) {
-            const int c = pr / rpw, r = pr % rpw;
-            float acc = 0.f;
-            for (int d = lane; d < D; d += 64) acc = fmaf(sX[(size_t)r * ldx + d], vec[c * D + d], acc);
-            for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-            if (lane == 0) dst[c * rpw + r] = acc;
-        }
-    };
-    // this workgroup's share of X^T r
-    auto share_xtr = [&](int buf, const float *rr) {
-        for (int c = 0; c < nc; c++)
-            for (int d = tid; d < D; d += kSeqThreads) {
-                float acc = 0.f;
-                for (int r = 0; r < rpw; r++) acc = fmaf(sX[(size_t)r * ldx + d], rr[c * rpw + r], acc);
-                q.part[pidx(buf, c, d, blockIdx.x)] = acc;
+    // the noise of the next step, in registers: xin at coordinates tid + 256 j,
+    // xown at the own coordinate d0 + tid; the uniform in thread c
+    float xin[kSeqChains][4], xown[kSeqChains], un = 0.f;
+    auto load_xi = [&](int64_t k) {
+#pragma unroll
+        for (int c = 0; c < kSeqChains; c++) {
+            const int64_t t = s_t0[c < nc ? c : 0] + k;
+            const bool live = c < nc && t < s_t1[c < nc ? c : 0];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int d = tid + kSeqThreads * j;
+                xin[c][j] = (live && d < D) ? noise[(size_t)t * D + d] : 0.f;
             }
-    };
-    // sum of all workgroups' shares of one value, in workgroup order
-    // (nb is a multiple of 4: the shares are read as float4)
-    auto gather = [&](int buf, int c, int v) {
-        const float4 *pb = (const float4 *)(q.part + pidx(buf, c, v, 0));
-        float s = 0.f;
-        for (int w = 0; w < nb / 4; w++) {
-            const float4 u = pb[w];
-            s += u.x;
-            s += u.y;
-            s += u.z;
-            s += u.w;
+            xown[c] = (live && tid < 64 && d0 + tid < d1) ? noise[(size_t)t * D + d0 + tid] : 0.f;
+            if (tid == c && live && !q.a.ula) un = unif[t];
         }
-        return s;
     };
 
-    // ---- gradient at s0
-    uint32_t bar = 0;
+    // dst[c][r] = X_r . vec_c for own rows r: each wave takes eight (chain,
+    // row) pairs at a time, lanes over the coordinates, eight independent
+    // accumulators
+    auto row_dots = [&](const float *vec, float *dst) {
+        const int npairs = nc * rpw;
+        for (int p0 = wv * 8; p0 < npairs; p0 += (kSeqThreads / 64) * 8) {
+            float acc[8];
+            int pc[8], pr[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int pi = min(p0 + i, npairs - 1);
+                pc[i] = pi / rpw;
+                pr[i] = pi % rpw;
+                acc[i] = 0.f;
+            }
+#pragma unroll 4
+            for (int d = lane; d < D; d += 64) {
+#pragma unroll
+                for (int i = 0; i < 8; i++) acc[i] = fmaf(sX[(size_t)pr[i] * ldx + d], vec[pc[i] * D + d], acc[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                float v = acc[i];
+                for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+                if (lane == 0 && p0 + i < npairs) dst[pc[i] * rpw + pr[i]] = v;
+            }
+        }
+    };
+    // A: publish this workgroup's share of X^T r (every coordinate): thread
+    // tid sums over own rows for coordinates tid + 256 j and every chain
+    auto publish_share = [&](uint32_t tag, const float *rr) {
+        float acc[kSeqChains][4];
+#pragma unroll
+        for (int c = 0; c < kSeqChains; c++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[c][j] = 0.f;
+        // branch-free: chains past nc and coordinates past D read valid
+        // elements, and their sums are never stored
+        int cofs[kSeqChains], dcl[4];
+#pragma unroll
+        for (int c = 0; c < kSeqChains; c++) cofs[c] = min(c, nc - 1) * rpw;
+#pragma unroll
+        for (int j = 0; j < 4; j++) dcl[j] = min(tid + kSeqThreads * j, D - 1);
+#pragma unroll 4
+        for (int r = 0; r < rpw; r++) {
+            float rv[kSeqChains];
+#pragma unroll
+            for (int c = 0; c < kSeqChains; c++) rv[c] = rr[cofs[c] + r];
+            const float *xr = sX + (size_t)r * ldx;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float xv = xr[dcl[j]];
+#pragma unroll
+                for (int c = 0; c < kSeqChains; c++) acc[c][j] = fmaf(xv, rv[c], acc[c][j]);
+            }
+        }
+        uint64_t *const base = P1(tag, blockIdx.x, 0, 0);  // chain c at base + c (D + 1)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int d = tid + kSeqThreads * j;
+            if (d < D) {
+                uint64_t *w = base + d;
+#pragma unroll
+                for (int c = 0; c < kSeqChains; c++) {
+                    if (c < nc) put(w, tag, acc[c][j]);
+                    w += D1;
+                }
+            }
+        }
+    };
+    // B: sums of own coordinates' shares (in workgroup order) into sgt
+    auto reduce_own = [&](uint32_t tag) -> bool {
+        bool ok = true;
+        const int n_own = (d1 - d0) * nc;
+        for (int o = tid; o < n_own; o += kSeqThreads) {
+            const int c = o / (d1 - d0), d = d0 + o % (d1 - d0);
+            float s = 0.f;
+            for (int w0 = 0; w0 < nb && ok; w0 += 16) {
+                const int n = min(16, nb - w0);
+                const uint64_t *ws[16];
+                float v[16];
+#pragma unroll
+                for (int i = 0; i < 16; i++) ws[i] = P1(tag, w0 + (i < n ? i : 0), c, d);
+                ok = take<16>(q, ws, n, tag, v);
+#pragma unroll
+                for (int i = 0; i < 16; i++)
+                    if (i < n) s += v[i];
+            }
+            sgt[c * D + d] = s;
+        }
+        return block_all(ok);
+    };
+    // C: every coordinate's reduced value from its owner, into dst
+    auto gather_all = [&](uint32_t tag, float *dst) -> bool {
+        bool ok = true;
+        for (int o0 = 0; o0 < nc * D && ok; o0 += 16 * kSeqThreads) {
+            const uint64_t *ws[16];
+            float v[16];
+            int n = 0;
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                const int o = o0 + i * kSeqThreads + tid;
+                ws[i] = o < nc * D ? P2(tag, o / D, o % D) : P2(tag, 0, 0);
+                if (o < nc * D) n = i + 1;
+            }
+            ok = take<16>(q, ws, n, tag, v);
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                const int o = o0 + i * kSeqThreads + tid;
+                if (i < n && o < nc * D) dst[o] = v[i];
+            }
+        }
+        return block_all(ok);
+    };
+
+    // ---- gradient at s0 (tag 1)
     row_dots(sx, sa);
     __syncthreads();
     for (int o = tid; o < nc * rpw; o += kSeqThreads) {
@@ -823,100 +979,152 @@ __global__ void __launch_bounds__(kSeqThreads) k_seq_logreg_wide(SeqWide q)
         sr[o] = n < q.N ? q.y[n] - 1.f / (1.f + __expf(-sa[o])) : 0.f;
     }
     __syncthreads();
-    share_xtr(0, sr);
-    if (!grid_barrier(q, ++bar)) return;
-    for (int c = 0; c < nc; c++)
-        for (int d = tid; d < D; d += kSeqThreads) sg[c * D + d] = fmaf(-q.pp, sx[c * D + d], gather(0, c, d));
-    __syncthreads();
+    publish_share(1, sr);
+    if (!reduce_own(1)) return;
+    for (int o = tid; o < (d1 - d0) * nc; o += kSeqThreads) {
+        const int c = o / (d1 - d0), d = d0 + o % (d1 - d0);
+        put(P2(1, c, d), 1, fmaf(-q.pp, sx[c * D + d], sgt[c * D + d]));
+    }
+    if (!gather_all(1, sg)) return;
 
+    load_xi(0);
     for (int64_t k = 0; k < q.steps; k++) {
-        const int buf = (int)((k + 1) & 1);
-        // Delta for every chain that has step k
+        const uint32_t tag = (uint32_t)(k + 2);
+        // ---- A
         for (int c = 0; c < nc; c++) {
-            const int64_t t = offs[q.c0 + c] + k;
-            const bool live = t < offs[q.c0 + c + 1];
-            for (int d = tid; d < D; d += kSeqThreads)
-                sdl[c * D + d] = live ? fmaf(eps, sg[c * D + d], cc * noise[(size_t)t * D + d]) : 0.f;
-        }
-        __syncthreads();
-        row_dots(sdl, sat);  // dA of own rows
-        __syncthreads();
-        for (int c = 0; c < nc; c++) {
-            double dl = 0.0;
-            for (int r = tid; r < rpw; r += kSeqThreads) {
-                const int n = r0 + r, o = c * rpw + r;
-                const float a0 = sa[o], da = sat[o];
-                if (n < q.N) {
-                    sr[o] = q.y[n] - 1.f / (1.f + __expf(-(a0 + da)));
-                    dl += (double)q.y[n] * (double)da - softplus_inc(a0, da);
-                } else {
-                    sr[o] = 0.f;
-                }
-                sat[o] = a0 + da;
+            const bool live = s_t0[c] + k < s_t1[c];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int d = tid + kSeqThreads * j;
+                if (d < D) sdl[c * D + d] = live ? fmaf(eps, sg[c * D + d], cc * xin[c][j]) : 0.f;
             }
-            dl = block_sum_d(dl, s_red);
-            if (tid == 0) q.part[pidx(buf, c, D, blockIdx.x)] = (float)dl;
         }
         __syncthreads();
-        share_xtr(buf, sr);
-        if (!grid_barrier(q, ++bar)) return;
-        // every workgroup: the ratio and decision of each chain, identically
+        row_dots(sdl, sat);
+        __syncthreads();
+        if (wv == 0) {
+            // own rows (rpw <= 32): lanes 0..31 take chain c, lanes 32..63 chain c + 1
+            for (int c2 = 0; c2 < nc; c2 += 2) {
+                const int c = c2 + (lane >> 5), r = lane & 31;
+                double dl = 0.0;
+                if (r < rpw && c < nc) {
+                    const int n = r0 + r, o = c * rpw + r;
+                    const float a0 = sa[o], da = sat[o];
+                    if (n < q.N) {
+                        sr[o] = s_y[r] - 1.f / (1.f + __expf(-(a0 + da)));
+                        dl = (double)s_y[r] * (double)da - softplus_inc(a0, da);
+                    } else {
+                        sr[o] = 0.f;
+                    }
+                    sat[o] = a0 + da;
+                }
+                for (int m = 16; m >= 1; m >>= 1) dl += __shfl_xor(dl, m, 64);
+                if (r == 0 && c < nc) put(P1(tag, blockIdx.x, c, D), tag, (float)dl);
+            }
+        }
+        __syncthreads();
+        publish_share(tag, sr);
+        // ---- B
+        if (!reduce_own(tag)) return;
+        if (wv == 0) {
+            // own coordinates (at most 64) in lanes of wave 0
+            for (int c = 0; c < nc; c++) {
+                double sn = 0.0, sxi = 0.0, dpr = 0.0;
+                const int d = d0 + lane;
+                if (d < d1) {
+                    const float x = sx[c * D + d], dl = sdl[c * D + d], xt = x + dl;
+                    const float gt = fmaf(-q.pp, xt, sgt[c * D + d]);
+                    put(P2(tag, c, d), tag, gt);
+                    const double sgv = (double)sg[c * D + d] + (double)gt;
+                    sn = sgv * sgv;
+                    sxi = (double)xown[c] * sgv;
+                    dpr = (double)dl * ((double)xt + (double)x);
+                }
+                for (int m = 32; m >= 1; m >>= 1) {
+                    sn += __shfl_xor(sn, m, 64);
+                    sxi += __shfl_xor(sxi, m, 64);
+                    dpr += __shfl_xor(dpr, m, 64);
+                }
+                if (lane == 0) {
+                    uint64_t *w = P3(tag, blockIdx.x, c);
+                    put_d(w, tag, sn);
+                    put_d(w + 2, tag, sxi);
+                    put_d(w + 4, tag, dpr);
+                }
+            }
+        }
+        // ---- C: g~ everywhere; the slice sums and the log-likelihood shares
+        // of every workgroup, summed in the same order in each workgroup.
+        // The uniform of this step is kept; the next step's noise loads
+        // while this workgroup waits.
+        const float u_now = un;
+        load_xi(k + 1);
+        if (!gather_all(tag, sgt)) return;
+        bool ok = true;
+        double tot[4] = {0.0, 0.0, 0.0, 0.0};
+        if (wv < nc) {
+            const int c = wv;
+            for (int w0 = lane; w0 < nb && ok; w0 += 64) {
+                const uint64_t *ws[7];
+                float v[7];
+#pragma unroll
+                for (int i = 0; i < kSeqQ; i++) ws[i] = P3(tag, w0, c) + i;
+                ws[6] = P1(tag, w0, c, D);
+                ok = take<7>(q, ws, 7, tag, v);
+                auto dbl = [&](int i) {
+                    return __longlong_as_double((long long)((uint64_t)__float_as_uint(v[i]) |
+                                                            ((uint64_t)__float_as_uint(v[i + 1]) << 32)));
+                };
+                tot[0] += dbl(0);
+                tot[1] += dbl(2);
+                tot[2] += dbl(4);
+                tot[3] += (double)v[6];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                for (int m = 32; m >= 1; m >>= 1) tot[i] += __shfl_xor(tot[i], m, 64);
+            if (lane == 0)
+#pragma unroll
+                for (int i = 0; i < 4; i++) s_sum[c][i] = tot[i];
+        }
+        if (!block_all(ok)) return;
+        if (tid < nc) {
+            const int c = tid;
+            const int64_t t = s_t0[c] + k;
+            const bool live = t < s_t1[c];
+            const double sn = s_sum[c][0], sxi = s_sum[c][1], dpr = s_sum[c][2], dll = s_sum[c][3];
+            int acc = 1;
+            float gate = INFINITY;
+            if (!q.a.ula) {
+                const double ell = dll - 0.5 * (double)q.pp * dpr - 0.25 * q.a.eps * sn - sqrt(0.5 * q.a.eps) * sxi;
+                const double la = ell < 0.0 ? ell : 0.0;
+                const double gd = live ? la - log((double)u_now) : -1.0;
+                gate = (float)gd;
+                acc = gd > 0.0 && ell == ell;
+            }
+            if (!live) acc = 0;
+            s_acc[c] = acc;
+            if (live && blockIdx.x == 0) {
+                if (q.a.accept) q.a.accept[t] = (uint8_t)acc;
+                if (q.a.gtilde) q.a.gtilde[t] = gate;
+            }
+        }
+        __syncthreads();
+        // state update (every workgroup) and the step's output (own coordinates)
         for (int c = 0; c < nc; c++) {
-            const int64_t t = offs[q.c0 + c] + k;
-            const bool live = t < offs[q.c0 + c + 1];
-            double sn = 0.0, sxi = 0.0, dpr = 0.0;
+            if (!s_acc[c]) continue;
             for (int d = tid; d < D; d += kSeqThreads) {
-                const float x = sx[c * D + d], dl = sdl[c * D + d], xt = x + dl;
-                const float gt = fmaf(-q.pp, xt, gather(buf, c, d));
-                const double sgv = (double)sg[c * D + d] + (double)gt;
-                sn = fma(sgv, sgv, sn);
-                if (live) sxi = fma((double)noise[(size_t)t * D + d], sgv, sxi);
-                dpr = fma((double)dl, (double)xt + (double)x, dpr);
-                sgt[c * D + d] = gt;
+                sx[c * D + d] = sx[c * D + d] + sdl[c * D + d];
+                sg[c * D + d] = sgt[c * D + d];
             }
-            sn = block_sum_d(sn, s_red);
-            sxi = block_sum_d(sxi, s_red);
-            dpr = block_sum_d(dpr, s_red);
-            if (tid == 0) {
-                double dll = 0.0;
-                for (int w = 0; w < nb; w++) dll += (double)q.part[pidx(buf, c, D, w)];
-                int acc = 1;
-                float gate = INFINITY;
-                if (!q.a.ula) {
-                    const double ell = dll - 0.5 * (double)q.pp * dpr - 0.25 * q.a.eps * sn - sqrt(0.5 * q.a.eps) * sxi;
-                    const double la = ell < 0.0 ? ell : 0.0;
-                    const double gd = live ? la - log((double)unif[t]) : -1.0;
-                    gate = (float)gd;
-                    acc = gd > 0.0 && ell == ell;
-                }
-                if (!live) acc = 0;
-                s_acc[c] = acc;
-                if (live && blockIdx.x == 0) {
-                    if (q.a.accept) q.a.accept[t] = (uint8_t)acc;
-                    if (q.a.gtilde) q.a.gtilde[t] = gate;
-                }
-            }
-            __syncthreads();
+            for (int r = tid; r < rpw; r += kSeqThreads) sa[c * rpw + r] = sat[c * rpw + r];
         }
-        // state update (every workgroup) and the step's output (coordinates
-        // spread over the workgroups)
-        const int dpw = (D + q.nb - 1) / q.nb, d0 = blockIdx.x * dpw, d1 = min(D, d0 + dpw);
+        __syncthreads();
         for (int c = 0; c < nc; c++) {
-            const int64_t t = offs[q.c0 + c] + k;
-            const bool live = t < offs[q.c0 + c + 1];
-            const int acc = s_acc[c];
-            if (acc) {
-                for (int d = tid; d < D; d += kSeqThreads) {
-                    sx[c * D + d] = sx[c * D + d] + sdl[c * D + d];
-                    sg[c * D + d] = sgt[c * D + d];
-                }
-                for (int r = tid; r < rpw; r += kSeqThreads) sa[c * rpw + r] = sat[c * rpw + r];
-            }
-            __syncthreads();
-            if (live)
+            const int64_t t = s_t0[c] + k;
+            if (t < s_t1[c])
                 for (int d = d0 + tid; d < d1; d += kSeqThreads) out[(size_t)t * D + d] = sx[c * D + d];
         }
-        __syncthreads();
     }
 }
 
@@ -932,7 +1140,8 @@ SeqPlan seq_plan(const DevTarget &t)
     for (int r : {32, 16, 8, 4}) {
         const int nb = Np / r;
         const size_t lds = sizeof(float) * ((size_t)r * t.ldx + 4 * (size_t)kSeqChains * t.dim + 3 * kSeqChains * r);
-        if (Np % r == 0 && nb % 4 == 0 && nb <= 256 && lds <= kSeqLdsLimit) {
+        // own coordinates are handled by one wave: at most 64 per workgroup
+        if (Np % r == 0 && nb % 4 == 0 && nb <= 256 && (t.dim + nb - 1) / nb <= 64 && lds <= kSeqLdsLimit) {
             p.rpw = r;
             p.nb = nb;
             p.lds = lds;
@@ -940,6 +1149,12 @@ SeqPlan seq_plan(const DevTarget &t)
         }
     }
     return p;
+}
+
+size_t seq_words(const SeqPlan &p, int D)
+{
+    return 2 * (size_t)p.nb * kSeqChains * ((size_t)D + 1) + 2 * (size_t)kSeqChains * D +
+           2 * (size_t)p.nb * kSeqChains * kSeqQ;
 }
 
 }  // namespace
@@ -950,7 +1165,7 @@ size_t seq_scratch_bytes(const DevTarget &t, int n_chains)
     if (t.kind != PMC_TARGET_LOGREG || t.dim < kWideMinDim) return 0;
     const SeqPlan p = seq_plan(t);
     if (!p.nb) return 0;
-    return 256 + sizeof(float) * 2 * kSeqChains * ((size_t)t.dim + 1) * p.nb;
+    return 256 + sizeof(uint64_t) * seq_words(p, t.dim);
 }
 
 pmc_status launch_sequential_logreg_wide(pmc_context *ctx, const DevTarget &t, const SeqArgs &a)
@@ -968,8 +1183,11 @@ pmc_status launch_sequential_logreg_wide(pmc_context *ctx, const DevTarget &t, c
         set_error("sequential logistic sampler (D > 32) needs cooperative launches");
         return PMC_ERR_UNSUPPORTED;
     }
-    uint32_t *ctr = (uint32_t *)a.scratch, *abort_ = ctr + 1;
-    float *part = (float *)((char *)a.scratch + 256);
+    uint32_t *abort_ = (uint32_t *)a.scratch;
+    uint64_t *words = (uint64_t *)((char *)a.scratch + 256);
+    const size_t nw = seq_words(p, t.dim);
+    uint64_t *p1 = words, *p2 = p1 + 2 * (size_t)p.nb * kSeqChains * ((size_t)t.dim + 1);
+    uint64_t *p3 = p2 + 2 * (size_t)kSeqChains * t.dim;
     PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_seq_logreg_wide, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)p.lds));
     PMC_TRY_HIP(hipMemsetAsync(abort_, 0, sizeof(uint32_t), ctx->stream));
@@ -984,16 +1202,19 @@ pmc_status launch_sequential_logreg_wide(pmc_context *ctx, const DevTarget &t, c
         q.pp = (float)(1.0 / t.prior_var);
         q.nb = p.nb;
         q.rpw = p.rpw;
+        q.dpw = (t.dim + p.nb - 1) / p.nb;
         q.c0 = c0;
         q.nc = std::min(kSeqChains, a.n_chains - c0);
         q.steps = 0;
         for (int c = c0; c < c0 + q.nc; c++)
             q.steps = std::max<int64_t>(q.steps, a.host_offsets[c + 1] - a.host_offsets[c]);
-        q.part = part;
-        q.ctr = ctr;
+        q.p1 = p1;
+        q.p2 = p2;
+        q.p3 = p3;
         q.abort_ = abort_;
         if (q.steps == 0) continue;
-        PMC_TRY_HIP(hipMemsetAsync(ctr, 0, sizeof(uint32_t), ctx->stream));
+        // tags restart at 1 in every launch: clear the words of the previous one
+        PMC_TRY_HIP(hipMemsetAsync(words, 0, sizeof(uint64_t) * nw, ctx->stream));
         void *args[] = {&q};
         PMC_TRY_HIP(hipLaunchCooperativeKernel((const void *)k_seq_logreg_wide, dim3(p.nb), dim3(kSeqThreads), args,
                                                (unsigned)p.lds, ctx->stream));
@@ -1002,7 +1223,7 @@ pmc_status launch_sequential_logreg_wide(pmc_context *ctx, const DevTarget &t, c
     PMC_TRY_HIP(hipMemcpyAsync(&h_abort, abort_, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
     PMC_TRY_HIP(hipStreamSynchronize(ctx->stream));
     if (h_abort) {
-        set_error("sequential logistic sampler: a grid barrier timed out");
+        set_error("sequential logistic sampler: a wait for another workgroup's words timed out");
         return PMC_ERR_HIP;
     }
     return PMC_OK;
