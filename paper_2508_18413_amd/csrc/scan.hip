@@ -6,7 +6,7 @@
 // consecutive steps reduces to one map.  One kernel launch does the whole
 // scan:
 //   1. each thread composes ITEMS consecutive steps held in registers;
-//   2. a wavefront inclusive scan of the thread aggregates (cross-lane shuffles);
+//   2. a wavefront inclusive scan of the thread aggregates (DPP lane moves);
 //   3. wave aggregates combine through LDS into the tile aggregate;
 //   4. decoupled look-back: the tile publishes its aggregate, then wave 0 reads
 //      up to 64 predecessor descriptors at once and folds aggregates back to the
@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include "pmc_internal.hpp"
+#include "wave.hpp"
 
 namespace pmc {
 namespace {
@@ -100,28 +101,45 @@ __device__ __forceinline__ void apply(const Aff<R, M> &e, const R (&x)[M], R (&y
     for (int i = 0; i < M; i++) y[i] = t[i];
 }
 
-template <typename R, int M>
-__device__ __forceinline__ Aff<R, M> shfl_up_aff(const Aff<R, M> &e, int off)
-{
-    Aff<R, M> o;
+// Moves every register of a map with one DPP pattern (wave.hpp).
+struct AffMover {
+    template <int CTRL, int ROWS, typename R, int M>
+    __device__ __forceinline__ Aff<R, M> move(const Aff<R, M> &old, const Aff<R, M> &v) const
+    {
+        Aff<R, M> o;
 #pragma unroll
-    for (int i = 0; i < M; i++) {
+        for (int i = 0; i < M; i++) {
 #pragma unroll
-        for (int j = 0; j < M; j++) o.a[i][j] = __shfl_up(e.a[i][j], off, kWave);
-        o.b[i] = __shfl_up(e.b[i], off, kWave);
+            for (int j = 0; j < M; j++) o.a[i][j] = wave::dpp<CTRL, ROWS>(old.a[i][j], v.a[i][j]);
+            o.b[i] = wave::dpp<CTRL, ROWS>(old.b[i], v.b[i]);
+        }
+        return o;
     }
-    return o;
+};
+
+// Inclusive scan of the lanes' maps in lane order (lane 0 earliest): lane l
+// ends with e_l o ... o e_0; `excl` gets e_{l-1} o ... o e_0 (identity in
+// lane 0).  All 64 lanes must be active.
+template <typename R, int M>
+__device__ __forceinline__ Aff<R, M> wave_scan_aff(const Aff<R, M> &e, Aff<R, M> &excl)
+{
+    const Aff<R, M> id = aff_identity<R, M>();
+    const Aff<R, M> inc = wave::scan_incl(e, id, AffMover{},
+                                          [](const Aff<R, M> &L, const Aff<R, M> &E) { return compose(L, E); });
+    excl = wave::shift_up1(inc, id, AffMover{});
+    return inc;
 }
 
+// Map of lane l in every lane.
 template <typename R, int M>
-__device__ __forceinline__ Aff<R, M> shfl_down_aff(const Aff<R, M> &e, int off)
+__device__ __forceinline__ Aff<R, M> aff_lane(const Aff<R, M> &e, int l)
 {
     Aff<R, M> o;
 #pragma unroll
     for (int i = 0; i < M; i++) {
 #pragma unroll
-        for (int j = 0; j < M; j++) o.a[i][j] = __shfl_down(e.a[i][j], off, kWave);
-        o.b[i] = __shfl_down(e.b[i], off, kWave);
+        for (int j = 0; j < M; j++) o.a[i][j] = wave::lane_value(e.a[i][j], l);
+        o.b[i] = wave::lane_value(e.b[i], l);
     }
     return o;
 }
@@ -300,20 +318,13 @@ __device__ void lookback(uint64_t *desc, int64_t self, int64_t head, uint32_t ep
         }
         const uint64_t incmask = __ballot(st == 2);
         const int first_inc = incmask ? __ffsll((unsigned long long)incmask) - 1 : kWave;
-        // ordered fold m_0 o m_1 o ... o m_first_inc (lane 0 is the nearest tile)
+        // ordered fold m_0 o m_1 o ... o m_first_inc (lane 0 is the nearest
+        // tile, so a lower lane's map applies after a higher lane's); lane 63
+        // ends with the whole fold
         if (lid > first_inc || st == 3) m = aff_identity<R, M>();
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            Aff<R, M> o = shfl_down_aff(m, off);
-            if ((lid & (2 * off - 1)) == 0 && lid + off < kWave) m = compose(m, o);
-        }
-        // lane 0 holds the fold; broadcast it
-#pragma unroll
-        for (int i = 0; i < M; i++) {
-#pragma unroll
-            for (int j = 0; j < M; j++) m.a[i][j] = __shfl(m.a[i][j], 0, kWave);
-            m.b[i] = __shfl(m.b[i], 0, kWave);
-        }
+        m = wave::scan_incl(m, aff_identity<R, M>(), AffMover{},
+                            [](const Aff<R, M> &higher, const Aff<R, M> &lower) { return compose(lower, higher); });
+        m = aff_lane(m, kWave - 1);
         acc = compose(acc, m);
         if (first_inc < kWave) break;
         p -= kWave;
@@ -351,14 +362,33 @@ __device__ __forceinline__ void part_merge(Part &a, const Part &b)
     a.rinf = fmax(a.rinf, b.rinf);
 }
 
-__device__ __forceinline__ Part part_shfl_xor(const Part &p, int m)
+struct PartMover {
+    template <int CTRL, int ROWS>
+    __device__ __forceinline__ Part move(const Part &old, const Part &v) const
+    {
+        Part o;
+        o.ratio = wave::dpp<CTRL, ROWS>(old.ratio, v.ratio);
+        o.nonfinite = wave::dpp<CTRL, ROWS>(old.nonfinite, v.nonfinite);
+        o.first_bad = wave::dpp<CTRL, ROWS>(old.first_bad, v.first_bad);
+        o.rsq = wave::dpp<CTRL, ROWS>(old.rsq, v.rsq);
+        o.rinf = wave::dpp<CTRL, ROWS>(old.rinf, v.rinf);
+        return o;
+    }
+};
+
+// The wave's partials folded into one, in every lane (all lanes active).
+__device__ __forceinline__ Part wave_fold_part(const Part &p)
 {
+    Part f = wave::scan_incl(p, part_neutral(), PartMover{}, [](Part a, const Part &b) {
+        part_merge(a, b);
+        return a;
+    });
     Part o;
-    o.ratio = __shfl_xor(p.ratio, m, kWave);
-    o.nonfinite = __shfl_xor(p.nonfinite, m, kWave);
-    o.first_bad = __shfl_xor(p.first_bad, m, kWave);
-    o.rsq = __shfl_xor(p.rsq, m, kWave);
-    o.rinf = __shfl_xor(p.rinf, m, kWave);
+    o.ratio = wave::lane_value(f.ratio, kWave - 1);
+    o.nonfinite = wave::lane_value(f.nonfinite, kWave - 1);
+    o.first_bad = wave::lane_value(f.first_bad, kWave - 1);
+    o.rsq = wave::lane_value(f.rsq, kWave - 1);
+    o.rinf = wave::lane_value(f.rinf, kWave - 1);
     return o;
 }
 
@@ -400,10 +430,27 @@ struct SegGeom {
     const int64_t *offsets;
     const ChainStatus *chains;
     const int32_t *chain_tile_begin;
+    // > 0: the map holds one chain of this many steps from step 0, so tile ti
+    // is [ti C, (ti + 1) C) and only the chain's status is loaded (one
+    // dependent load before the tile's data instead of two)
+    int64_t single_len;
 
     // [t0, t1) of the tile, its sequence head tile, false if the tile is idle.
     __device__ bool range(int ti, int C, int64_t &t0, int64_t &t1, int &head_ti) const
     {
+        if (single_len > 0) {
+            const ChainStatus &cs = chains[0];
+            if (!cs.active) return false;
+            const int64_t ws = cs.win_start > 0 ? cs.win_start : 0;
+            t0 = (int64_t)ti * C;
+            t1 = t0 + C < single_len ? t0 + C : single_len;
+            if (cs.win_end < t1) t1 = cs.win_end;
+            if (ws >= t1) return false;
+            if (t0 < ws) t0 = ws;
+            if (t0 >= t1) return false;
+            head_ti = (int)(ws / C);
+            return true;
+        }
         const SegTile st = tiles[ti];
         const ChainStatus &cs = chains[st.chain];
         if (!cs.active) return false;
@@ -830,9 +877,15 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         typename IO::Extra x[ITEMS];
         const int64_t base = t0 + (int64_t)tid * ITEMS;
         bool vec = false;
+        // every item of this thread inside the tile: the vector loads and
+        // updates run without per-item bounds (the common case)
+        const bool whole = base + ITEMS <= t1;
         if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) vec = io.vec_ok(t0);
         if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) {
-            if (vec) {
+            if (vec && whole) {
+#pragma unroll
+                for (int i = 0; i < ITEMS; i += 4) io.load4(lane, base + i, &e[i], &x[i]);
+            } else if (vec) {
 #pragma unroll
                 for (int i = 0; i < ITEMS; i += 4) {
                     if (base + i + 3 < t1) {
@@ -861,14 +914,8 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         A agg = e[0];
 #pragma unroll
         for (int i = 1; i < ITEMS; i++) agg = compose(e[i], agg);
-        A inc = agg;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            A o = shfl_up_aff(inc, off);
-            if (lid >= off) inc = compose(inc, o);
-        }
-        A excl = shfl_up_aff(inc, 1);
-        if (lid == 0) excl = aff_identity<R, M>();
+        A excl;
+        const A inc = wave_scan_aff(agg, excl);
         if (lid == kWave - 1) s_wagg[wid] = inc;
         lds_barrier();
         A wpre = aff_identity<R, M>();
@@ -899,7 +946,10 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         apply(wpre, d, d);
         apply(excl, d, d);
         if constexpr (HasVec<IO>::value && ITEMS % 4 == 0) {
-            if (vec) {
+            if (vec && whole) {
+#pragma unroll
+                for (int i = 0; i < ITEMS; i += 4) io.update4(lane, base + i, 4, &e[i], &x[i], d, part);
+            } else if (vec) {
 #pragma unroll
                 for (int i = 0; i < ITEMS; i += 4) {
                     const int64_t left = t1 - (base + i);
@@ -926,8 +976,7 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
         // Each wave folds its partial and leaves it in LDS; the wave that
         // arrives last (LDS counter) folds the NW of them across its lanes
         // and writes the tile's partial, so no wave waits for the others.
-#pragma unroll
-        for (int m = 1; m < kWave; m <<= 1) part_merge(part, part_shfl_xor(part, m));
+        part = wave_fold_part(part);
         TilePartial &tp = partials[(size_t)lane * n_tiles + ti];
         bool write = false;
         if (!active) {
@@ -938,12 +987,10 @@ k_scan(IO io, ScanSync *sync, uint64_t *desc, int n_tiles, TilePartial *partials
                 s_part[wid] = part;
                 arrived = __hip_atomic_fetch_add(&s_cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            arrived = __shfl(arrived, 0, kWave);
+            arrived = wave::lane_value(arrived, 0);
             if (arrived == NW - 1) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                part = lid < NW ? s_part[lid] : part_neutral();
-#pragma unroll
-                for (int m = 1; m < NW; m <<= 1) part_merge(part, part_shfl_xor(part, m));
+                part = wave_fold_part(lid < NW ? s_part[lid] : part_neutral());
                 write = true;
             }
         }
@@ -1013,14 +1060,8 @@ k_scan_chunked(IO io, ScanSync *sync, uint64_t *desc, int n_chunks, int64_t chun
         A agg = e[0];
 #pragma unroll
         for (int i = 1; i < ITEMS; i++) agg = compose(e[i], agg);
-        A inc = agg;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            A o = shfl_up_aff(inc, off);
-            if (lid >= off) inc = compose(inc, o);
-        }
-        A excl = shfl_up_aff(inc, 1);
-        if (lid == 0) excl = aff_identity<R, M>();
+        A excl;
+        const A inc = wave_scan_aff(agg, excl);
         if (lid == kWave - 1) s_wagg[par][wid] = inc;
         lds_barrier();
         A wpre = aff_identity<R, M>();
@@ -1218,14 +1259,8 @@ k_scan_newton_chunked(NewtonChunkArgs a, ScanSync *sync, uint64_t *desc, int n_c
         A agg = map_of(0);
 #pragma unroll
         for (int i = 1; i < ITEMS; i++) agg = compose(map_of(i), agg);
-        A inc = agg;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            A o = shfl_up_aff(inc, off);
-            if (lid >= off) inc = compose(inc, o);
-        }
-        A excl = shfl_up_aff(inc, 1);
-        if (lid == 0) excl = aff_identity<float, 1>();
+        A excl;
+        const A inc = wave_scan_aff(agg, excl);
         if (lid == kWave - 1) s_wagg[par][wid] = inc;
         lds_barrier();
         A wpre = aff_identity<float, 1>();
@@ -1237,15 +1272,11 @@ k_scan_newton_chunked(NewtonChunkArgs a, ScanSync *sync, uint64_t *desc, int n_c
     // each wave leaves its folded partial in s_part[par]; after the next
     // barrier wave 0 folds the NW of them
     auto leave_part = [&](Part p, int par) {
-#pragma unroll
-        for (int m = 1; m < kWave; m <<= 1) part_merge(p, part_shfl_xor(p, m));
+        p = wave_fold_part(p);
         if (lid == 0) s_part[par][wid] = p;
     };
     auto fold_prev = [&](int par) {
-        Part p = lid < NW ? s_part[par][lid] : part_neutral();
-#pragma unroll
-        for (int m = 1; m < NW; m <<= 1) part_merge(p, part_shfl_xor(p, m));
-        return p;
+        return wave_fold_part(lid < NW ? s_part[par][lid] : part_neutral());
     };
 
     // ---- 1: the chunk from a zero carry.  A step's map is (J, F - S) and
@@ -1469,32 +1500,44 @@ struct Fold {
     int64_t fb;
 };
 
+__device__ __forceinline__ void fold_merge(Fold &v, const Fold &o)
+{
+    v.q += o.q;
+    v.qi = fmax(v.qi, o.qi);
+    v.r = fmaxf(v.r, o.r);
+    v.f += o.f;
+    v.fb = o.fb < v.fb ? o.fb : v.fb;
+}
+
+struct FoldMover {
+    template <int CTRL, int ROWS>
+    __device__ __forceinline__ Fold move(const Fold &old, const Fold &v) const
+    {
+        Fold o;
+        o.q = wave::dpp<CTRL, ROWS>(old.q, v.q);
+        o.qi = wave::dpp<CTRL, ROWS>(old.qi, v.qi);
+        o.r = wave::dpp<CTRL, ROWS>(old.r, v.r);
+        o.f = wave::dpp<CTRL, ROWS>(old.f, v.f);
+        o.fb = wave::dpp<CTRL, ROWS>(old.fb, v.fb);
+        return o;
+    }
+};
+
 // Block-wide fold of per-thread values; the result is valid in thread 0.
 // Fixed tree order, so the FP64 sums are deterministic.
 __device__ Fold block_fold(Fold v)
 {
     __shared__ Fold s_w[kStatusThreads / 64];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        v.q += __shfl_xor(v.q, m);
-        v.qi = fmax(v.qi, __shfl_xor(v.qi, m));
-        v.r = fmaxf(v.r, __shfl_xor(v.r, m));
-        v.f += __shfl_xor(v.f, m);
-        const int64_t o = __shfl_xor(v.fb, m);
-        v.fb = o < v.fb ? o : v.fb;
-    }
+    v = wave::scan_incl(v, Fold{0.0, 0.0, 0.f, 0u, INT64_MAX}, FoldMover{}, [](Fold a, const Fold &o) {
+        fold_merge(a, o);
+        return a;
+    });
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) s_w[w] = v;
+    if ((threadIdx.x & 63) == 63) s_w[w] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < kStatusThreads / 64; i++) {
-            const Fold &o = s_w[i];
-            v.q += o.q;
-            v.qi = fmax(v.qi, o.qi);
-            v.r = fmaxf(v.r, o.r);
-            v.f += o.f;
-            v.fb = o.fb < v.fb ? o.fb : v.fb;
-        }
+        v = s_w[0];
+        for (int i = 1; i < kStatusThreads / 64; i++) fold_merge(v, s_w[i]);
     }
     __syncthreads();
     return v;
@@ -1506,6 +1549,61 @@ __device__ Fold block_fold(Fold v)
 // updates its Newton state; the last workgroup to finish folds every chain
 // into the global status and re-arms the completion counter, so the kernel
 // can be replayed inside a captured graph.
+// One chain's Newton state after a sweep, from the fold of its tile partials
+// (off and cend are the chain's first and one-past-last step).
+__device__ void chain_update(ChainStatus &cs, const Fold &v, const StatusArgs &a, int64_t off, int64_t cend)
+{
+    const float r = v.r;
+    const int64_t fb = v.fb;
+    cs.sweeps += 1;
+    cs.max_ratio = r;
+    cs.first_bad = fb;
+    cs.resid_sq = v.q;
+    cs.resid_inf = v.qi;
+    cs.nonfinite = v.f;
+    // Plateau detection: progress is a 2x drop of the best ratio or an
+    // advance of the converged front; rounding noise gives neither.
+    const int64_t front = fb == INT64_MAX ? cs.win_end : fb;
+    if (r < 0.5f * cs.best_ratio || front > cs.best_front) {
+        cs.best_ratio = fminf(cs.best_ratio, r);
+        cs.best_front = front > cs.best_front ? front : cs.best_front;
+        cs.stall = 0;
+    } else {
+        cs.stall += 1;
+    }
+    if (r <= 1.f && cs.win_end >= cend) {
+        cs.converged = 1;
+        cs.active = 0;
+    } else if (r <= 1.f) {
+        // a fixed-width window whose steps all met the tolerance: the next
+        // window starts where this one ended
+        cs.win_start = cs.win_end;
+        cs.win_end = cs.win_start + a.window_width < cend ? cs.win_start + a.window_width : cend;
+        cs.fb_prev = cs.win_start;
+    } else if (cs.sweeps >= a.max_iter) {
+        cs.active = 0;
+    } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f) {
+        // rounding floor: no progress for floor_stall sweeps with the last change within
+        // twice the tolerance (the state error of a change-based stop is a few times the
+        // last change, so this keeps it near the converged chains' error)
+        cs.at_floor = 1;
+        cs.active = 0;
+    } else if (a.skip_prefix && fb != INT64_MAX) {
+        // the window starts at the first step that has not met the
+        // tolerance in both of the last two sweeps (its frozen
+        // residual is then the second, smaller change), rounded down
+        // to a multiple of 4 (aligned vector loads)
+        const int64_t f2 = fb < cs.fb_prev ? fb : cs.fb_prev;
+        const int64_t w = f2 & ~(int64_t)3;
+        cs.win_start = w > off ? w : off;
+        if (a.window_width > 0) {
+            const int64_t e = cs.win_start + a.window_width;
+            cs.win_end = e < cend ? e : cend;
+        }
+    }
+    if (!(r <= 1.f)) cs.fb_prev = fb;
+}
+
 __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
 {
     const int c = blockIdx.x, tid = threadIdx.x;
@@ -1525,57 +1623,9 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         }
         v = block_fold(v);
         if (tid == 0) {
-            const float r = v.r;
-            const int64_t fb = v.fb;
-            cs.sweeps += 1;
-            cs.max_ratio = r;
-            cs.first_bad = fb;
-            cs.resid_sq = v.q;
-            cs.resid_inf = v.qi;
-            cs.nonfinite = v.f;
-            // Plateau detection: progress is a 2x drop of the best ratio or an
-            // advance of the converged front; rounding noise gives neither.
-            const int64_t front = fb == INT64_MAX ? cs.win_end : fb;
-            if (r < 0.5f * cs.best_ratio || front > cs.best_front) {
-                cs.best_ratio = fminf(cs.best_ratio, r);
-                cs.best_front = front > cs.best_front ? front : cs.best_front;
-                cs.stall = 0;
-            } else {
-                cs.stall += 1;
-            }
-            const int64_t cend = a.offsets[c + 1];
-            if (r <= 1.f && cs.win_end >= cend) {
-                cs.converged = 1;
-                cs.active = 0;
-            } else if (r <= 1.f) {
-                // a fixed-width window whose steps all met the tolerance: the next
-                // window starts where this one ended
-                cs.win_start = cs.win_end;
-                cs.win_end = cs.win_start + a.window_width < cend ? cs.win_start + a.window_width : cend;
-                cs.fb_prev = cs.win_start;
-            } else if (cs.sweeps >= a.max_iter) {
-                cs.active = 0;
-            } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f) {
-                // rounding floor: no progress for floor_stall sweeps with the last change within
-                // twice the tolerance (the state error of a change-based stop is a few times the
-                // last change, so this keeps it near the converged chains' error)
-                cs.at_floor = 1;
-                cs.active = 0;
-            } else if (a.skip_prefix && fb != INT64_MAX) {
-                // the window starts at the first step that has not met the
-                // tolerance in both of the last two sweeps (its frozen
-                // residual is then the second, smaller change), rounded down
-                // to a multiple of 4 (aligned vector loads)
-                const int64_t off = a.offsets[c];
-                const int64_t f2 = fb < cs.fb_prev ? fb : cs.fb_prev;
-                const int64_t w = f2 & ~(int64_t)3;
-                cs.win_start = w > off ? w : off;
-                if (a.window_width > 0) {
-                    const int64_t e = cs.win_start + a.window_width;
-                    cs.win_end = e < a.offsets[c + 1] ? e : a.offsets[c + 1];
-                }
-            }
-            if (!(r <= 1.f)) cs.fb_prev = fb;
+            ChainStatus x = cs;
+            chain_update(x, v, a, a.offsets[c], a.offsets[c + 1]);
+            cs = x;
         }
     }
     // completion count: the last workgroup sees every chain's update (a
@@ -1608,14 +1658,11 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         nfloor += o.at_floor;
         sweeps = max(sweeps, o.sweeps);
     }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        nact += __shfl_xor(nact, m);
-        nconv += __shfl_xor(nconv, m);
-        nfloor += __shfl_xor(nfloor, m);
-        sweeps = max(sweeps, __shfl_xor(sweeps, m));
-        nsteps += __shfl_xor(nsteps, m);
-    }
+    nact = wave::reduce_sum(nact);
+    nconv = wave::reduce_sum(nconv);
+    nfloor = wave::reduce_sum(nfloor);
+    sweeps = wave::reduce_max(sweeps, INT32_MIN);
+    nsteps = wave::reduce_sum(nsteps);
     __shared__ int64_t s_steps[kStatusThreads / 64];
     if ((tid & 63) == 0) {
         s_cnt[tid >> 6][0] = nact;
@@ -1654,6 +1701,58 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
     }
 }
 
+// The status fold of a problem with one chain, in one workgroup: every load
+// the fold needs (the chain's state, its tile partials, which are all the
+// map's tiles, the global counters and the scan epoch) is issued at the
+// start, and the global status is written from the updated chain state held
+// in registers, so the launch waits for one round of loads instead of a
+// chain of dependent ones.  Same results as k_status with one workgroup.
+__global__ void __launch_bounds__(kStatusThreads) k_status_one(StatusArgs a)
+{
+    const int tid = threadIdx.x;
+    ChainStatus cs;
+    int64_t cend = 0, eval_steps = 0, next_steps = 0;
+    uint32_t epoch = 0;
+    if (tid == 0) {
+        cs = a.chains[0];
+        cend = a.offsets[1];
+        eval_steps = a.global->eval_steps;
+        next_steps = a.global->next_steps;
+        if (a.bump_epoch) epoch = __hip_atomic_load(&a.bump_epoch->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
+    const int64_t cnt = (int64_t)a.n_lanes * a.n_tiles;
+    for (int64_t i = tid; i < cnt; i += kStatusThreads) {
+        const TilePartial &p = a.partials[i];
+        v.r = fmaxf(v.r, p.max_ratio);
+        v.fb = p.first_bad < v.fb ? p.first_bad : v.fb;
+        v.q += p.resid_sq;
+        v.qi = fmax(v.qi, p.resid_inf);
+        v.f += p.nonfinite;
+    }
+    v = block_fold(v);
+    if (tid != 0) return;
+    if (cs.active) {
+        chain_update(cs, v, a, 0, cend);
+        a.chains[0] = cs;
+    }
+    GlobalStatus *g = a.global;
+    g->n_active = cs.active;
+    g->n_converged = cs.converged;
+    g->n_floor = cs.at_floor;
+    g->sweeps = cs.sweeps;
+    g->resid_sq = cs.resid_sq;
+    g->resid_inf = cs.resid_inf;
+    g->max_ratio = cs.max_ratio;
+    g->nonfinite = cs.nonfinite;
+    g->n_accept = 0;
+    g->eval_steps = eval_steps + next_steps;  // what this sweep evaluated
+    g->next_steps = cs.active ? cs.win_end - (cs.win_start > 0 ? cs.win_start : 0) : 0;
+    if (a.bump_epoch)
+        __hip_atomic_store(&a.bump_epoch->epoch, (epoch + 1) & 0x3fffffffu, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Number of accepted proposals: a grid-stride byte count added into the
 // global status (which the preceding status fold has set to zero).
 __global__ void __launch_bounds__(256) k_count_accept(const uint8_t *__restrict__ acc, int64_t n,
@@ -1663,8 +1762,7 @@ __global__ void __launch_bounds__(256) k_count_accept(const uint8_t *__restrict_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         s += acc[i];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    s = wave::reduce_sum(s);
     __shared__ uint32_t s_w[4];
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -1701,6 +1799,14 @@ pmc_status newton_chunked(pmc_context *ctx, const NewtonScanArgs &a)
     return PMC_OK;
 }
 
+// Steps of the one chain of a tile map that holds a single chain cut at
+// multiples of C (the chain starts at step 0), else 0.
+int64_t single_chain_len(const NewtonScanArgs &a, int C)
+{
+    if (a.n_chains != 1 || a.n_steps <= 0 || a.n_tiles != (a.n_steps + C - 1) / C) return 0;
+    return a.n_steps;
+}
+
 template <typename R, int BLOCK, int ITEMS>
 pmc_status diag_newton(pmc_context *ctx, const NewtonScanArgs &a)
 {
@@ -1710,14 +1816,14 @@ pmc_status diag_newton(pmc_context *ctx, const NewtonScanArgs &a)
             a.ld == a.n_steps && (int64_t)a.n_lanes * a.n_steps >= (int64_t(1) << 23))
             return newton_chunked(ctx, a);
     }
-    SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
+    SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin, single_chain_len(a, BLOCK * ITEMS)};
     DiagNewtonIO<R> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol, a.rtol};
     return run_scan<DiagNewtonIO<R>, BLOCK, ITEMS>(ctx, io, a.n_lanes, a.n_tiles, a.partials, !a.defer_epoch);
 }
 template <typename R, int MM, int BLOCK, int ITEMS>
 pmc_status dense_newton(pmc_context *ctx, const NewtonScanArgs &a)
 {
-    SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin};
+    SegGeom g{a.tiles, a.n_tiles, a.offsets, a.chains, a.chain_tile_begin, single_chain_len(a, BLOCK * ITEMS)};
     DenseNewtonIO<R, MM> io{g, a.ld, (const R *)a.J, (const R *)a.F, (R *)a.S, (R *)a.trace, a.atol,
                             a.rtol};
     return run_scan<DenseNewtonIO<R, MM>, BLOCK, ITEMS>(ctx, io, 1, a.n_tiles, a.partials, !a.defer_epoch);
@@ -1862,7 +1968,10 @@ pmc_status check_scan_health(pmc_context *ctx)
 pmc_status launch_status(pmc_context *ctx, const StatusArgs &a)
 {
     if (a.n_chains <= 0) return PMC_OK;
-    hipLaunchKernelGGL(k_status, dim3(a.n_chains), dim3(kStatusThreads), 0, ctx->stream, a);
+    if (a.n_chains == 1)
+        hipLaunchKernelGGL(k_status_one, dim3(1), dim3(kStatusThreads), 0, ctx->stream, a);
+    else
+        hipLaunchKernelGGL(k_status, dim3(a.n_chains), dim3(kStatusThreads), 0, ctx->stream, a);
     PMC_TRY_HIP(hipGetLastError());
     if (a.accept && a.n_steps > 0) {
         const int64_t per = 256 * 16;

@@ -58,14 +58,23 @@ def test_noalloc_matches_solve_two_calls(pm):
         n, D = xi.shape
         outs = (torch.empty((n, D), dtype=xi.dtype, device=DEV), torch.empty(n, dtype=torch.uint8, device=DEV),
                 torch.empty(n, dtype=torch.float32, device=DEV))
-        torch.cuda.synchronize()
-        free0 = torch.cuda.mem_get_info()[0]
-        rn = pm.solve_noalloc(ctx, tg, ch.eps, s0, xi, u, variant="diag", max_iter=n + 1, out=outs)
-        torch.cuda.synchronize()
-        free1 = torch.cuda.mem_get_info()[0]
+        # An allocation shows as free memory shrinking across the call.  The
+        # HIP runtime may hand scratch backing that earlier kernels of the
+        # process used back to the device at any moment, which shows as free
+        # memory growing; such a call is repeated (at most three times) until
+        # one leaves the free memory exactly unchanged, and no call may shrink it.
+        used = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            rn = pm.solve_noalloc(ctx, tg, ch.eps, s0, xi, u, variant="diag", max_iter=n + 1, out=outs)
+            torch.cuda.synchronize()
+            used.append(free0 - torch.cuda.mem_get_info()[0])
+            if used[-1] == 0:
+                break
         r = pm.solve(ctx, tg, ch.eps, s0, xi, u, variant="diag", max_iter=n + 1)
-        print(f"  T={n}: sweeps {rn.sweeps} / {r.sweeps}, free memory change {free0 - free1} bytes", flush=True)
-        assert free1 == free0, "the allocation-free call changed the device's free memory"
+        print(f"  T={n}: sweeps {rn.sweeps} / {r.sweeps}, device memory taken per call {used} bytes", flush=True)
+        assert max(used) <= 0 and used[-1] == 0, "the allocation-free call changed the device's free memory"
         assert rn.status == 0
         _same(rn, r)
     ctx.close()
