@@ -2,19 +2,22 @@
 // J_t a full D x D matrix (D <= 32, padded to 32), the linearised recursion of
 // Sec. 2 eq. 3.
 //
-// Hierarchical reduce-then-scan over units of 32 elements, one wavefront per
-// unit:
-//   up:   each unit composes its 32 affine maps into one (P, B):
-//         P = J_32 ... J_1 by matrix-core products with the running product in
-//         the B-operand role (J_t streams in as the A operand straight from
-//         memory; the accumulator returns to the B layout by a swap of half
-//         its registers between lanes l and l + 32), B = the unit applied to a
-//         zero carry, by FP32 matrix-vector products;
-//         levels repeat on the (P, B) arrays until at most 32 maps remain;
-//   down: from a zero carry at the top, each unit applies its maps in order to
-//         produce the carries of the level below; at level 0 the apply is the
-//         Newton update S_t <- F_t + J_t delta_{t-1} in FP32 with fused
-//         convergence partials.
+// Hierarchical reduce-then-scan, one wavefront per unit, every chain of a
+// batch with a hierarchy of its own (chains laid end to end; a chain's
+// level-0 units are its scan tiles of at most 32 steps):
+//   up:   each level-0 unit composes its steps' affine maps into one (P, B):
+//         P = J_last ... J_first by matrix-core products with the running
+//         product in the B-operand role (J_t streams in as the A operand
+//         straight from memory; the accumulator returns to the B layout by a
+//         swap of half its registers between lanes l and l + 32), B = the
+//         unit applied to a zero carry, by FP32 matrix-vector products;
+//         levels above compose groups of 8 maps the same way, until a chain
+//         has at most 8 maps left (its top level);
+//   down: from a zero carry at each chain's top, each group applies its maps
+//         in order to produce the carries of the level below; at level 0 the
+//         apply is the Newton update S_t <- F_t + J_t delta_{t-1} in FP32 with
+//         fused convergence partials.
+// One launch per level and direction covers every chain that has the level.
 // Level-0 J is BF16 (v_mfma_f32_32x32x16_bf16, FP32 accumulation; the exact
 // FP32 residual makes the Newton iteration a refinement, so BF16 products cost
 // sweeps, not accuracy) or FP32 (v_mfma_f32_32x32x2_f32).  Levels >= 1 are FP32.
@@ -27,7 +30,9 @@
 //   accumulator (C/D) of a 32 x 32 product: register r holds
 //     C[8 (r / 4) + 4 h + r % 4][i].
 #include <math.h>
+#include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "pmc_internal.hpp"
@@ -217,14 +222,40 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ----------------------------------------------------------- level inputs
+// ----------------------------------------------------------- level-0 units
+// A level-0 unit is one scan tile (at most 32 steps of one chain).  In the
+// Newton update the tile map and the chains' windows give its steps; the
+// standalone recursion cuts its one sequence every 32 steps.
+struct Unit {
+    int64_t t0;  // first step
+    int cnt;     // steps
+    int e0, e1;  // steps [e0, e1) of the unit lie in the chain's window
+    int chain;
+};
+
 struct Lvl0In {  // Newton level 0: b_t = F_t - S_t from planes (FP32)
     const float *F, *S;
     int64_t ld;
     int D;
-    const ChainStatus *chain;  // window start of the (single) chain, or nullptr
-    __device__ int64_t first() const { return chain ? chain->win_start : 0; }
-    __device__ int64_t last() const { return chain ? chain->win_end : INT64_MAX; }
+    const SegTile *tiles;
+    const ChainStatus *chains;
+    // false if the unit's chain has stopped (nothing to do)
+    __device__ bool unit(int64_t u, Unit &g) const
+    {
+        const SegTile st = tiles[u];
+        const ChainStatus &cs = chains[st.chain];
+        if (!cs.active) return false;
+        g.t0 = st.start;
+        g.cnt = st.len;
+        g.chain = st.chain;
+        // steps before the window are the identity map with b = 0 (the carry
+        // entering the window is exactly zero whatever their stale J holds);
+        // steps from the window's end on are the identity too
+        const int64_t ws = cs.win_start, we = cs.win_end;
+        g.e0 = ws > g.t0 ? (int)min((int64_t)g.cnt, ws - g.t0) : 0;
+        g.e1 = we < g.t0 + g.cnt ? (int)max((int64_t)0, we - g.t0) : g.cnt;
+        return true;
+    }
     __device__ float b(int64_t t, int i) const
     {
         if (i >= D) return 0.f;
@@ -235,34 +266,36 @@ struct Lvl0In {  // Newton level 0: b_t = F_t - S_t from planes (FP32)
 struct RowIn {  // standalone level 0: b_t rows [T, D]
     const float *B;
     int D;
-    __device__ int64_t first() const { return 0; }
-    __device__ int64_t last() const { return INT64_MAX; }
+    int64_t n;
+    __device__ bool unit(int64_t u, Unit &g) const
+    {
+        g.t0 = u * kU;
+        g.cnt = (int)min((int64_t)kU, n - g.t0);
+        g.e0 = 0;
+        g.e1 = g.cnt;
+        g.chain = 0;
+        return true;
+    }
     __device__ float b(int64_t t, int i) const { return i < D ? B[(size_t)t * D + i] : 0.f; }
 };
-struct MapIn {  // levels >= 1: B vectors [n, 32]
-    const float *B;
-    __device__ int64_t first() const { return 0; }
-    __device__ int64_t last() const { return INT64_MAX; }
-    __device__ float b(int64_t t, int i) const { return B[(size_t)t * 32 + i]; }
-};
 
-// ---------------------------------------------------------------- up pass
+// ---------------------------------------------------------- level-0 up pass
+// Each unit composes its steps into one map (P, B): P = J_last ... J_first by
+// matrix-core products, B = the unit applied to a zero carry.
 template <class Frag, class Chain, class In>
 __global__ void __launch_bounds__(64 * kWPB)
-k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout, const GlobalStatus *glob)
+k_up0(const void *Jv, In in, int64_t n_units, float4 *Pout, float *Bout, const GlobalStatus *glob)
 {
-    if (glob && glob->n_active == 0) return;  // Newton: the chain has stopped
+    if (glob && glob->n_active == 0) return;  // Newton: every chain has stopped
     __shared__ float s_t[kWPB][32 * 33];
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
-    if (u * unit >= n) return;
-    const int64_t t0 = u * unit;
-    const int cnt = (int)min((int64_t)unit, n - t0);
+    if (u >= n_units) return;
+    Unit g;
+    if (!in.unit(u, g)) return;
     Chain P;
     P.identity(i, h);
-    // steps before the sliding window are the identity map with b = 0: the
-    // carry entering the window is exactly zero whatever their stale J holds
     f32x16 c;
 #pragma unroll
     for (int r = 0; r < 16; r++) c[r] = crow(r, h) == i ? 1.f : 0.f;
@@ -270,19 +303,22 @@ k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout, cons
     if (h == 0) v[i] = 0.f;
     wave_lds_sync();
     bool first = true;
-    const int64_t ws = in.first(), we = in.last();
-    const int e0 = ws > t0 ? (int)min((int64_t)cnt, ws - t0) : 0;
-    const int e1 = we < t0 + cnt ? (int)max((int64_t)0, we - t0) : cnt;  // steps from the window's end on: identity
-    for (int e = e0; e < e1; e++) {
-        Frag A;
+    // J of the next step is requested before this step's products
+    auto load_j = [&](int e, Frag &A) {
         if constexpr (sizeof(Frag) == sizeof(FragB))
-            A.load((const uint4 *)Jv, t0 + e, lane);
+            A.load((const uint4 *)Jv, g.t0 + e, lane);
         else
-            A.load((const float4 *)Jv, t0 + e, lane);
+            A.load((const float4 *)Jv, g.t0 + e, lane);
+    };
+    Frag An;
+    if (g.e0 < g.e1) load_j(g.e0, An);
+    for (int e = g.e0; e < g.e1; e++) {
+        const Frag A = An;
+        if (e + 1 < g.e1) load_j(e + 1, An);
         if (!first) P.from_acc(c, h);
         c = P.mul(A);
         first = false;
-        const float y = matvec(A, v, h) + in.b(t0 + e, i);
+        const float y = matvec(A, v, h) + in.b(g.t0 + e, i);
         wave_lds_sync();
         if (h == 0) v[i] = y;
         wave_lds_sync();
@@ -291,33 +327,134 @@ k_up(const void *Jv, In in, int64_t n, int unit, float4 *Pout, float *Bout, cons
     if (h == 0) Bout[(size_t)u * 32 + i] = v[i];
 }
 
-// ------------------------------------------------------------- down pass
-// Level >= 1: carries of the children.  carry_in == nullptr means zero.
-__global__ void __launch_bounds__(64 * kWPB)
-k_down_maps(const float4 *P, const float *B, int64_t n, int unit, const float *carry_in, float *carry_out,
-            const GlobalStatus *glob)
+// ------------------------------------------------------------ upper levels
+// Level k >= 1 holds, per chain, one map per group of 8 maps of level k - 1
+// (its last group may be shorter), up to the chain's top level of at most 8
+// maps.  One launch per level and direction, over the units of every chain
+// that has that level: up, a unit composes its group into the level's map;
+// down, a unit applies the maps of its group in order from the carry entering
+// the group (zero for a chain's top level) and writes the carry entering each
+// map.  Level-0 maps and carries are indexed by scan tile; the maps of levels
+// >= 1 of all chains share one array (DenseChainGeom::ubase).
+struct LevelArgs {
+    int k;                       // level
+    const int32_t *units;        // [n_units][2] (chain, group), or nullptr: one chain, group = unit
+    int64_t n_units;
+    const DenseChainGeom *geom;  // [n_chains]
+    const float4 *P0;            // level-0 maps [n_tiles][256] float4 (F32 fragment layout)
+    const float *B0;             // [n_tiles][32]
+    float *C0;                   // carries entering each level-0 map [n_tiles][32]
+    float4 *UP;                  // upper-level maps [n_up][256] float4
+    float *UB, *UC;              // [n_up][32]
+    const ChainStatus *chains;   // nullptr: standalone (the chain is active)
+    const GlobalStatus *glob;
+};
+
+// Map e of a group at level k of chain G: level 0 by tile, levels >= 1 from
+// the shared array.
+struct MapSrc {
+    const float4 *P;
+    const float *B;
+    __device__ void load(int64_t x, int lane, FragF &A, float &b) const
+    {
+        A.load(P, x, lane);
+        b = B[(size_t)x * 32 + (lane & 31)];
+    }
+};
+
+__device__ __forceinline__ bool level_unit(const LevelArgs &a, int64_t u, int &c, int64_t &grp)
 {
-    if (glob && glob->n_active == 0) return;
+    if (a.units) {
+        c = a.units[2 * u];
+        grp = a.units[2 * u + 1];
+    } else {
+        c = 0;
+        grp = u;
+    }
+    return !a.chains || a.chains[c].active;
+}
+
+__global__ void __launch_bounds__(64 * kWPB) k_up_level(LevelArgs a)
+{
+    if (a.glob && a.glob->n_active == 0) return;
+    __shared__ float s_t[kWPB][32 * 33];
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
-    if (u * unit >= n) return;
-    const int64_t t0 = u * unit;
-    const int cnt = (int)min((int64_t)unit, n - t0);
+    if (u >= a.n_units) return;
+    int c;
+    int64_t p;
+    if (!level_unit(a, u, c, p)) return;
+    const DenseChainGeom &G = a.geom[c];
+    const int k = a.k;
+    const int cnt = (int)min((int64_t)8, G.m[k - 1] - 8 * p);
+    const int64_t x0 = (k == 1 ? G.tile0 : G.ubase[k - 1]) + 8 * p;
+    const MapSrc src{k == 1 ? a.P0 : (const float4 *)a.UP, k == 1 ? a.B0 : (const float *)a.UB};
     float *v = s_v[w];
-    if (h == 0) v[i] = carry_in ? carry_in[(size_t)u * 32 + i] : 0.f;
+    ChainF P;
+    P.identity(i, h);
+    f32x16 acc;
+    if (h == 0) v[i] = 0.f;
     wave_lds_sync();
+    // the next map is requested before this one's products
+    FragF An;
+    float bn;
+    src.load(x0, lane, An, bn);
     for (int e = 0; e < cnt; e++) {
-        FragF A;
-        A.load(P, t0 + e, lane);
-        if (h == 0) carry_out[(size_t)(t0 + e) * 32 + i] = v[i];
-        const float y = matvec(A, v, h) + B[(size_t)(t0 + e) * 32 + i];
+        const FragF A = An;
+        const float b = bn;
+        if (e + 1 < cnt) src.load(x0 + e + 1, lane, An, bn);
+        if (e > 0) P.from_acc(acc, h);
+        acc = P.mul(A);
+        const float y = matvec(A, v, h) + b;
+        wave_lds_sync();
+        if (h == 0) v[i] = y;
+        wave_lds_sync();
+    }
+    const int64_t xo = G.ubase[k] + p;
+    store_acc_as_fragf(acc, s_t[w], a.UP + (size_t)xo * 256, lane);
+    if (h == 0) a.UB[(size_t)xo * 32 + i] = v[i];
+}
+
+__global__ void __launch_bounds__(64 * kWPB) k_down_level(LevelArgs a)
+{
+    if (a.glob && a.glob->n_active == 0) return;
+    __shared__ float s_v[kWPB][32];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+    const int64_t u = (int64_t)blockIdx.x * kWPB + w;
+    if (u >= a.n_units) return;
+    int c;
+    int64_t q;
+    if (!level_unit(a, u, c, q)) return;
+    const DenseChainGeom &G = a.geom[c];
+    const int k = a.k;
+    const bool top = k == G.L - 1;  // the top level starts from a zero carry
+    const int64_t first = top ? 0 : 8 * q;
+    const int cnt = top ? (int)G.m[k] : (int)min((int64_t)8, G.m[k] - first);
+    const int64_t x0 = (k == 0 ? G.tile0 : G.ubase[k]) + first;
+    const MapSrc src{k == 0 ? a.P0 : (const float4 *)a.UP, k == 0 ? a.B0 : (const float *)a.UB};
+    float *out = k == 0 ? a.C0 : a.UC;
+    float *v = s_v[w];
+    if (h == 0) v[i] = top ? 0.f : a.UC[(size_t)(G.ubase[k + 1] + q) * 32 + i];
+    wave_lds_sync();
+    FragF An;
+    float bn;
+    src.load(x0, lane, An, bn);
+    for (int e = 0; e < cnt; e++) {
+        const FragF A = An;
+        const float b = bn;
+        if (e + 1 < cnt) src.load(x0 + e + 1, lane, An, bn);
+        if (h == 0) out[(size_t)(x0 + e) * 32 + i] = v[i];
+        const float y = matvec(A, v, h) + b;
         wave_lds_sync();
         if (h == 0) v[i] = y;
         wave_lds_sync();
     }
 }
 
+__global__ void k_store_geom(DenseChainGeom g, DenseChainGeom *out) { *out = g; }
+
+// ------------------------------------------------------------- down pass
 struct PartW {
     float ratio;
     uint32_t nonfinite;
@@ -325,62 +462,65 @@ struct PartW {
     double rsq, rinf;
 };
 
-// Level 0, Newton: S_t <- F_t + J_t delta_{t-1}, delta_t = J_t delta_{t-1} + b_t.
+// Level 0, Newton: S_t <- F_t + J_t delta_{t-1}, delta_t = J_t delta_{t-1} + b_t
+// from the unit's carry, with the tile's convergence partials.
 template <class Frag>
 __global__ void __launch_bounds__(64 * kWPB)
-k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int64_t n,
-               const float *carry_in, TilePartial *partials, double atol, double rtol, float *trace,
-               const GlobalStatus *glob, const ChainStatus *chain)
+k_down0_newton(const void *Jv, Lvl0In in, int64_t n_units, const float *carry, TilePartial *partials,
+               double atol, double rtol, float *trace, const GlobalStatus *glob)
 {
-    // Once the status fold has stopped the chain, the sweeps still queued
+    // Once the status fold has stopped every chain, the sweeps still queued
     // behind it must leave S alone: F and J are no longer refreshed, and
     // re-applying S <- F + J delta with them need not stay bounded.
     if (glob && glob->n_active == 0) return;
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
     const int64_t u = (int64_t)blockIdx.x * kWPB + w;
-    if (u * kU >= n) return;
-    const int64_t t0 = u * kU;
-    const int cnt = (int)min((int64_t)kU, n - t0);
-    float *v = s_v[w];
-    // steps before the chain's sliding window are frozen: S keeps its values,
-    // delta stays zero and they add nothing to the convergence partials
-    const int64_t ws = chain ? chain->win_start : 0, we = chain ? chain->win_end : INT64_MAX;
-    const int e0 = ws > t0 ? (int)min((int64_t)cnt, ws - t0) : 0;
-    const int e1 = we < t0 + cnt ? (int)max((int64_t)0, we - t0) : cnt;  // steps past the window: untouched
-    if (h == 0) v[i] = (carry_in && e0 == 0) ? carry_in[(size_t)u * 32 + i] : 0.f;
-    wave_lds_sync();
+    if (u >= n_units) return;
     PartW p{0.f, 0u, INT64_MAX, 0.0, 0.0};
-    const bool own = h == 0 && i < D;
-    for (int e = e0; e < e1; e++) {
-        const int64_t t = t0 + e;
-        Frag A;
-        if constexpr (sizeof(Frag) == sizeof(FragB))
-            A.load((const uint4 *)Jv, t, lane);
-        else
-            A.load((const float4 *)Jv, t, lane);
-        const float jv = matvec(A, v, h);
-        float y = 0.f;
-        if (own) {
-            const size_t k = (size_t)i * ld + t;
-            const float f = F[k], so = S[k];
-            const float b = f - so;
-            y = jv + b;
-            const float sn = f + jv;
-            S[k] = sn;
-            if (trace) trace[k] = sn;
-            float r = (float)(fabs((double)y) / (atol + rtol * fabs((double)sn)));
-            if (!(r == r)) r = INFINITY;
-            if (!isfinite(sn)) p.nonfinite++;
-            if (r > kFreezeRatio && t < p.first_bad) p.first_bad = t;
-            p.ratio = fmaxf(p.ratio, r);
-            p.rsq += (double)b * b;
-            double ab = fabs((double)b);
-            p.rinf = (ab == ab) ? fmax(p.rinf, ab) : INFINITY;
+    Unit g;
+    if (in.unit(u, g)) {
+        float *v = s_v[w];
+        // steps before the chain's window are frozen: S keeps its values,
+        // delta stays zero and they add nothing to the convergence partials
+        if (h == 0) v[i] = g.e0 == 0 ? carry[(size_t)u * 32 + i] : 0.f;
+        wave_lds_sync();
+        const bool own = h == 0 && i < in.D;
+        auto load_j = [&](int64_t t, Frag &A) {
+            if constexpr (sizeof(Frag) == sizeof(FragB))
+                A.load((const uint4 *)Jv, t, lane);
+            else
+                A.load((const float4 *)Jv, t, lane);
+        };
+        Frag An;
+        if (g.e0 < g.e1) load_j(g.t0 + g.e0, An);
+        for (int e = g.e0; e < g.e1; e++) {
+            const int64_t t = g.t0 + e;
+            const Frag A = An;
+            if (e + 1 < g.e1) load_j(t + 1, An);
+            const float jv = matvec(A, v, h);
+            float y = 0.f;
+            if (own) {
+                const size_t k = (size_t)i * in.ld + t;
+                const float f = in.F[k], so = in.S[k];
+                const float b = f - so;
+                y = jv + b;
+                const float sn = f + jv;
+                ((float *)in.S)[k] = sn;
+                if (trace) trace[k] = sn;
+                float r = (float)(fabs((double)y) / (atol + rtol * fabs((double)sn)));
+                if (!(r == r)) r = INFINITY;
+                if (!isfinite(sn)) p.nonfinite++;
+                if (r > kFreezeRatio && t < p.first_bad) p.first_bad = t;
+                p.ratio = fmaxf(p.ratio, r);
+                p.rsq += (double)b * b;
+                double ab = fabs((double)b);
+                p.rinf = (ab == ab) ? fmax(p.rinf, ab) : INFINITY;
+            }
+            wave_lds_sync();
+            if (h == 0) v[i] = y;
+            wave_lds_sync();
         }
-        wave_lds_sync();
-        if (h == 0) v[i] = y;
-        wave_lds_sync();
     }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
@@ -403,7 +543,7 @@ k_down0_newton(const void *Jv, const float *F, float *S, int64_t ld, int D, int6
 // Level 0, standalone recursion: out_t = delta_t, rows [T, D].
 template <class Frag>
 __global__ void __launch_bounds__(64 * kWPB)
-k_down0_plain(const void *Jv, const float *Bv, float *out, int D, int64_t n, const float *carry_in)
+k_down0_plain(const void *Jv, const float *Bv, float *out, int D, int64_t n, const float *carry)
 {
     __shared__ float s_v[kWPB][32];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
@@ -412,7 +552,7 @@ k_down0_plain(const void *Jv, const float *Bv, float *out, int D, int64_t n, con
     const int64_t t0 = u * kU;
     const int cnt = (int)min((int64_t)kU, n - t0);
     float *v = s_v[w];
-    if (h == 0) v[i] = carry_in ? carry_in[(size_t)u * 32 + i] : 0.f;
+    if (h == 0) v[i] = carry[(size_t)u * 32 + i];
     wave_lds_sync();
     for (int e = 0; e < cnt; e++) {
         const int64_t t = t0 + e;
@@ -460,115 +600,209 @@ __global__ void k_pack(const float *A, int D, int64_t T, void *out, int bf16)
     }
 }
 
-inline unsigned blocks_for(int64_t n, int unit = kU) { return (unsigned)(((n + unit - 1) / unit + kWPB - 1) / kWPB); }
+inline unsigned blocks_for_units(int64_t n_units) { return (unsigned)((n_units + kWPB - 1) / kWPB); }
+
+// Levels of one chain of m0 tile maps; returns the number of upper-level
+// maps it adds (their first index is ubase0).
+int64_t chain_geom(int64_t m0, int64_t tile0, int64_t ubase0, DenseChainGeom &g)
+{
+    memset(&g, 0, sizeof(g));
+    g.tile0 = tile0;
+    if (m0 <= 0) return 0;
+    g.m[0] = m0;
+    g.L = 1;
+    while (g.m[g.L - 1] > 8) {
+        g.m[g.L] = (g.m[g.L - 1] + 7) / 8;
+        g.L++;
+    }
+    int64_t add = 0;
+    for (int k = 1; k < g.L; k++) {
+        g.ubase[k] = ubase0 + add;
+        add += g.m[k];
+    }
+    return add;
+}
+
+void hier_layout(DenseHier &h)
+{
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(b, 1), 256);
+        return o;
+    };
+    h.o_P0 = take((size_t)h.n_tiles * 4096);
+    h.o_B0 = take((size_t)h.n_tiles * 128);
+    h.o_C0 = take((size_t)h.n_tiles * 128);
+    h.o_UP = take((size_t)h.n_up * 4096);
+    h.o_UB = take((size_t)h.n_up * 128);
+    h.o_UC = take((size_t)h.n_up * 128);
+    h.o_geom = take(sizeof(DenseChainGeom) * std::max(h.n_chains, 1));
+    h.o_units = take(sizeof(int32_t) * h.units.size());
+    h.bytes = off;
+}
+
+LevelArgs level_args(const DenseHier &h, char *ws, int k, bool up, const ChainStatus *chains,
+                     const GlobalStatus *glob)
+{
+    LevelArgs a;
+    memset(&a, 0, sizeof(a));
+    a.k = k;
+    if (h.n_chains > 1) {
+        const int64_t off = up ? h.up_off[k] : h.down_off[k];
+        a.units = (const int32_t *)(ws + h.o_units) + 2 * off;
+        a.n_units = up ? h.up_cnt[k] : h.down_cnt[k];
+    } else {
+        const DenseChainGeom &g = h.geom[0];
+        a.units = nullptr;
+        a.n_units = up ? g.m[k] : (k == g.L - 1 ? 1 : g.m[k + 1]);
+    }
+    a.geom = (const DenseChainGeom *)(ws + h.o_geom);
+    a.P0 = (const float4 *)(ws + h.o_P0);
+    a.B0 = (const float *)(ws + h.o_B0);
+    a.C0 = (float *)(ws + h.o_C0);
+    a.UP = (float4 *)(ws + h.o_UP);
+    a.UB = (float *)(ws + h.o_UB);
+    a.UC = (float *)(ws + h.o_UC);
+    a.chains = chains;
+    a.glob = glob;
+    return a;
+}
+
+// The levels >= 1 (up, then down to the carries of the level-0 maps).
+pmc_status run_levels(pmc_context *ctx, const DenseHier &h, char *ws, const ChainStatus *chains,
+                      const GlobalStatus *glob)
+{
+    for (int k = 1; k < h.L_max; k++) {
+        const LevelArgs a = level_args(h, ws, k, true, chains, glob);
+        if (a.n_units > 0)
+            hipLaunchKernelGGL(k_up_level, dim3(blocks_for_units(a.n_units)), dim3(64 * kWPB), 0, ctx->stream, a);
+    }
+    for (int k = h.L_max - 1; k >= 0; k--) {
+        const LevelArgs a = level_args(h, ws, k, false, chains, glob);
+        if (a.n_units > 0)
+            hipLaunchKernelGGL(k_down_level, dim3(blocks_for_units(a.n_units)), dim3(64 * kWPB), 0, ctx->stream, a);
+    }
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
 
 }  // namespace
 
-// Workspace of the hierarchy for n level-0 elements.
+void dense_hier_plan(const std::vector<int32_t> &ctb, int n_chains, DenseHier &h)
+{
+    h = DenseHier();
+    h.n_chains = n_chains;
+    h.n_tiles = n_chains > 0 ? ctb[n_chains] : 0;
+    h.geom.resize(std::max(n_chains, 1));
+    int64_t ub = 0;
+    for (int c = 0; c < n_chains; c++) {
+        ub += chain_geom(ctb[c + 1] - ctb[c], ctb[c], ub, h.geom[c]);
+        h.L_max = std::max(h.L_max, h.geom[c].L);
+    }
+    h.n_up = ub;
+    if (n_chains > 1) {
+        // units per level: up level k composes groups of level k - 1 into
+        // the chain's level-k maps; down level k applies groups of level k
+        // (a chain's top level is one group)
+        for (int k = 0; k < h.L_max; k++) {
+            h.up_off[k] = (int64_t)h.units.size() / 2;
+            for (int c = 0; c < n_chains && k >= 1; c++)
+                for (int64_t p = 0; k < h.geom[c].L && p < h.geom[c].m[k]; p++) h.units.insert(h.units.end(), {c, (int32_t)p});
+            h.up_cnt[k] = (int64_t)h.units.size() / 2 - h.up_off[k];
+        }
+        for (int k = 0; k < h.L_max; k++) {
+            h.down_off[k] = (int64_t)h.units.size() / 2;
+            for (int c = 0; c < n_chains; c++) {
+                const DenseChainGeom &g = h.geom[c];
+                if (k == g.L - 1)
+                    h.units.insert(h.units.end(), {c, 0});
+                else if (k < g.L - 1)
+                    for (int64_t q = 0; q < g.m[k + 1]; q++) h.units.insert(h.units.end(), {c, (int32_t)q});
+            }
+            h.down_cnt[k] = (int64_t)h.units.size() / 2 - h.down_off[k];
+        }
+    }
+    hier_layout(h);
+}
+
+pmc_status dense_hier_setup(pmc_context *ctx, const DenseHier &h, void *ws)
+{
+    char *p = (char *)ws;
+    if (h.n_chains <= 1) {
+        // one chain: its geometry travels as a kernel argument (the host
+        // copy may be gone before an asynchronous copy would run)
+        hipLaunchKernelGGL(k_store_geom, dim3(1), dim3(1), 0, ctx->stream, h.geom[0], (DenseChainGeom *)(p + h.o_geom));
+        PMC_TRY_HIP(hipGetLastError());
+    } else {
+        PMC_TRY_HIP(hipMemcpyAsync(p + h.o_geom, h.geom.data(), sizeof(DenseChainGeom) * h.n_chains,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        PMC_TRY_HIP(hipMemcpyAsync(p + h.o_units, h.units.data(), sizeof(int32_t) * h.units.size(),
+                                   hipMemcpyHostToDevice, ctx->stream));
+    }
+    return PMC_OK;
+}
+
+// Workspace of the hierarchy of one sequence of n steps.
 size_t dense_mfma_ws_bytes(int64_t n)
 {
-    size_t b = 0;
-    int64_t m = n;
-    int unit = kU;
-    while (m > unit) {
-        const int64_t u = (m + unit - 1) / unit;
-        b += align_up((size_t)u * 1024 * 4, 256) + 2 * align_up((size_t)u * 32 * 4, 256);
-        m = u;
-        unit = kU1;
-    }
-    return b + 256;
-}
-
-// Shared driver: runs the up levels, the top and the down levels >= 1, and
-// returns the carries for the level-0 units (nullptr if T <= 32).
-template <class Frag, class Chain, class In>
-static pmc_status dense_hierarchy(pmc_context *ctx, const void *J, const In &in0, int64_t n, char *ws,
-                                  const float **carry0, const GlobalStatus *glob = nullptr)
-{
-    struct Lv {
-        int64_t n;      // elements of this level (maps of the level below)
-        float4 *P;      // [n] maps (level >= 1)
-        float *B;       // [n][32]
-        float *carry;   // [n][32] carries entering each element
-    };
-    std::vector<Lv> lv;
-    int64_t m = n;
-    char *p = ws;
-    int unit = kU;  // level 0 groups 32 steps, the levels above kU1 maps
-    while (m > unit) {
-        const int64_t u = (m + unit - 1) / unit;
-        unit = kU1;
-        Lv L;
-        L.n = u;
-        L.P = (float4 *)p;
-        p += align_up((size_t)u * 1024 * 4, 256);
-        L.B = (float *)p;
-        p += align_up((size_t)u * 32 * 4, 256);
-        L.carry = (float *)p;
-        p += align_up((size_t)u * 32 * 4, 256);
-        lv.push_back(L);
-        m = u;
-    }
-    if (lv.empty()) {
-        *carry0 = nullptr;
-        return PMC_OK;
-    }
-    // up
-    hipLaunchKernelGGL((k_up<Frag, Chain, In>), dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream, J,
-                       in0, n, kU, lv[0].P, lv[0].B, glob);
-    for (size_t k = 1; k < lv.size(); k++)
-        hipLaunchKernelGGL((k_up<FragF, ChainF, MapIn>), dim3(blocks_for(lv[k - 1].n, kU1)), dim3(64 * kWPB),
-                           0, ctx->stream, (const void *)lv[k - 1].P, MapIn{lv[k - 1].B}, lv[k - 1].n, kU1,
-                           lv[k].P, lv[k].B, glob);
-    // top: the last level's maps (<= kU1) from a zero carry
-    const Lv &top = lv.back();
-    hipLaunchKernelGGL(k_down_maps, dim3(1), dim3(64 * kWPB), 0, ctx->stream, (const float4 *)top.P,
-                       (const float *)top.B, top.n, kU1, (const float *)nullptr, top.carry, glob);
-    for (int k = (int)lv.size() - 2; k >= 0; k--)
-        hipLaunchKernelGGL(k_down_maps, dim3(blocks_for(lv[k].n, kU1)), dim3(64 * kWPB), 0, ctx->stream,
-                           (const float4 *)lv[k].P, (const float *)lv[k].B, lv[k].n, kU1,
-                           (const float *)lv[k + 1].carry, lv[k].carry, glob);
-    PMC_TRY_HIP(hipGetLastError());
-    *carry0 = lv[0].carry;
-    return PMC_OK;
-}
-
-pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
-                                    float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
-                                    double atol, double rtol, float *trace, void *ws, const GlobalStatus *glob,
-                                    const ChainStatus *chain)
-{
-    const float *c0 = nullptr;
-    Lvl0In in{F, S, ld, D, chain};
-    if (bf16) {
-        PMC_TRY((dense_hierarchy<FragB, ChainB, Lvl0In>(ctx, J, in, n, (char *)ws, &c0, glob)));
-        hipLaunchKernelGGL(k_down0_newton<FragB>, dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream,
-                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob, chain);
-    } else {
-        PMC_TRY((dense_hierarchy<FragF, ChainF, Lvl0In>(ctx, J, in, n, (char *)ws, &c0, glob)));
-        hipLaunchKernelGGL(k_down0_newton<FragF>, dim3(blocks_for(n)), dim3(64 * kWPB), 0, ctx->stream,
-                           J, F, S, ld, D, n, c0, partials, atol, rtol, trace, glob, chain);
-    }
-    PMC_TRY_HIP(hipGetLastError());
-    return PMC_OK;
+    DenseHier h;
+    dense_hier_plan({0, (int32_t)((n + kU - 1) / kU)}, 1, h);
+    return h.bytes;
 }
 
 int dense_mfma_unit() { return kU; }
 
+pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
+                                    float *S, int64_t ld, int D, const SegTile *tiles,
+                                    const ChainStatus *chains, TilePartial *partials, double atol,
+                                    double rtol, float *trace, void *ws, const DenseHier &h,
+                                    const GlobalStatus *glob)
+{
+    if (h.n_tiles == 0) return PMC_OK;
+    char *p = (char *)ws;
+    Lvl0In in{F, S, ld, D, tiles, chains};
+    if (bf16)
+        hipLaunchKernelGGL((k_up0<FragB, ChainB, Lvl0In>), dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
+                           ctx->stream, J, in, h.n_tiles, (float4 *)(p + h.o_P0), (float *)(p + h.o_B0), glob);
+    else
+        hipLaunchKernelGGL((k_up0<FragF, ChainF, Lvl0In>), dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
+                           ctx->stream, J, in, h.n_tiles, (float4 *)(p + h.o_P0), (float *)(p + h.o_B0), glob);
+    PMC_TRY(run_levels(ctx, h, p, chains, glob));
+    if (bf16)
+        hipLaunchKernelGGL(k_down0_newton<FragB>, dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
+                           ctx->stream, J, in, h.n_tiles, (const float *)(p + h.o_C0), partials, atol, rtol, trace,
+                           glob);
+    else
+        hipLaunchKernelGGL(k_down0_newton<FragF>, dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
+                           ctx->stream, J, in, h.n_tiles, (const float *)(p + h.o_C0), partials, atol, rtol, trace,
+                           glob);
+    PMC_TRY_HIP(hipGetLastError());
+    return PMC_OK;
+}
+
 pmc_status launch_linrec_dense_mfma_packed(pmc_context *ctx, int bf16, int D, int64_t T,
                                            const void *Jf, const float *b, float *out, void *ws)
 {
-    const float *c0 = nullptr;
-    RowIn in{b, D};
-    if (bf16) {
-        PMC_TRY((dense_hierarchy<FragB, ChainB, RowIn>(ctx, Jf, in, T, (char *)ws, &c0)));
-        hipLaunchKernelGGL(k_down0_plain<FragB>, dim3(blocks_for(T)), dim3(64 * kWPB), 0, ctx->stream,
-                           Jf, b, out, D, T, c0);
-    } else {
-        PMC_TRY((dense_hierarchy<FragF, ChainF, RowIn>(ctx, Jf, in, T, (char *)ws, &c0)));
-        hipLaunchKernelGGL(k_down0_plain<FragF>, dim3(blocks_for(T)), dim3(64 * kWPB), 0, ctx->stream,
-                           Jf, b, out, D, T, c0);
-    }
+    if (T == 0) return PMC_OK;
+    DenseHier h;
+    dense_hier_plan({0, (int32_t)((T + kU - 1) / kU)}, 1, h);
+    PMC_TRY(dense_hier_setup(ctx, h, ws));
+    char *p = (char *)ws;
+    RowIn in{b, D, T};
+    if (bf16)
+        hipLaunchKernelGGL((k_up0<FragB, ChainB, RowIn>), dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
+                           ctx->stream, Jf, in, h.n_tiles, (float4 *)(p + h.o_P0), (float *)(p + h.o_B0), nullptr);
+    else
+        hipLaunchKernelGGL((k_up0<FragF, ChainF, RowIn>), dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
+                           ctx->stream, Jf, in, h.n_tiles, (float4 *)(p + h.o_P0), (float *)(p + h.o_B0), nullptr);
+    PMC_TRY(run_levels(ctx, h, p, nullptr, nullptr));
+    if (bf16)
+        hipLaunchKernelGGL(k_down0_plain<FragB>, dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0, ctx->stream,
+                           Jf, b, out, D, T, (const float *)(p + h.o_C0));
+    else
+        hipLaunchKernelGGL(k_down0_plain<FragF>, dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0, ctx->stream,
+                           Jf, b, out, D, T, (const float *)(p + h.o_C0));
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;
 }
@@ -581,22 +815,11 @@ pmc_status launch_linrec_dense_mfma(pmc_context *ctx, int bf16, int D, int64_t T
     PMC_TRY(ensure_pool(ctx, need));
     char *ws = (char *)ctx->pool;
     void *Jf = ws;
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)T), dim3(64), 0, ctx->stream, A, D, T, Jf, bf16);
-    PMC_TRY_HIP(hipGetLastError());
-    const float *c0 = nullptr;
-    RowIn in{b, D};
-    char *hw = ws + align_up(jb, 256);
-    if (bf16) {
-        PMC_TRY((dense_hierarchy<FragB, ChainB, RowIn>(ctx, Jf, in, T, hw, &c0)));
-        hipLaunchKernelGGL(k_down0_plain<FragB>, dim3(blocks_for(T)), dim3(64 * kWPB), 0, ctx->stream,
-                           (const void *)Jf, b, out, D, T, c0);
-    } else {
-        PMC_TRY((dense_hierarchy<FragF, ChainF, RowIn>(ctx, Jf, in, T, hw, &c0)));
-        hipLaunchKernelGGL(k_down0_plain<FragF>, dim3(blocks_for(T)), dim3(64 * kWPB), 0, ctx->stream,
-                           (const void *)Jf, b, out, D, T, c0);
+    if (T > 0) {
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)T), dim3(64), 0, ctx->stream, A, D, T, Jf, bf16);
+        PMC_TRY_HIP(hipGetLastError());
     }
-    PMC_TRY_HIP(hipGetLastError());
-    return PMC_OK;
+    return launch_linrec_dense_mfma_packed(ctx, bf16, D, T, Jf, b, out, ws + align_up(jb, 256));
 }
 
 }  // namespace pmc

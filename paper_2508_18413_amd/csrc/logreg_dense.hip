@@ -121,12 +121,26 @@ struct DenseHArgs {
     const uint4 *xa, *pb;
     int nb_count, npt;  // data tiles, pair tiles (a multiple of the group)
     const float *S;     // [D, ld]
-    const float *s0;    // [D]
+    const float *s0;    // [n_chains, D]
+    const int64_t *offsets;  // [n_chains + 1] first step of each chain
+    int n_chains;
     int64_t ld, n;
     int D;
     float *H;           // [n, 32 npt] pair sums
     const GlobalStatus *glob;  // n_active == 0 at launch: nothing to do
 };
+
+// chain of global step t (offsets ascending, offsets[0] = 0 <= t < offsets[n_chains])
+__device__ __forceinline__ int chain_of(const int64_t *offsets, int n_chains, int64_t t)
+{
+    int lo = 0, hi = n_chains - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // grid.x: 32-step tiles / kDenseWaves, grid.y: groups of G pair tiles
 template <int G>
@@ -138,6 +152,13 @@ __global__ void __launch_bounds__(64 * kDenseWaves) k_logreg_dense_h(DenseHArgs 
     if (a.glob && a.glob->n_active == 0) return;
     const int pt0 = blockIdx.y * G;
     const int64_t t = t0 + i;
+    // the state entering step t: s0 of its chain at the chain's first step
+    int c = 0;
+    bool head = t == 0;
+    if (a.n_chains > 1 && t < a.n) {
+        c = chain_of(a.offsets, a.n_chains, t);
+        head = t == a.offsets[c];
+    }
 
     // B operand of M^T = X S^T: lane (i, h) holds s_{t-1}[16 kd + 8 h + j]
     bf16x8 sb[2];
@@ -148,7 +169,7 @@ __global__ void __launch_bounds__(64 * kDenseWaves) k_logreg_dense_h(DenseHArgs 
         for (int j = 0; j < 8; j++) {
             const int d = 16 * kd + 8 * h + j;
             float x = 0.f;
-            if (t < a.n && d < a.D) x = t == 0 ? a.s0[d] : a.S[(size_t)d * a.ld + t - 1];
+            if (t < a.n && d < a.D) x = head ? a.s0[(size_t)c * a.D + d] : a.S[(size_t)d * a.ld + t - 1];
             v[j] = x;
         }
         sb[kd] = pack8(v);
@@ -308,17 +329,6 @@ struct ProbeArgs {
     const GlobalStatus *glob;
 };
 
-// chain of global step t (offsets ascending, offsets[0] = 0 <= t < offsets[n_chains])
-__device__ __forceinline__ int chain_of(const int64_t *offsets, int n_chains, int64_t t)
-{
-    int lo = 0, hi = n_chains - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (offsets[mid] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ float probe_sign(uint64_t hs, int64_t t, int d)
 {
@@ -450,13 +460,13 @@ pmc_status logreg_dense_tables(pmc_context *ctx, DevTarget &t)
     return PMC_OK;
 }
 
-pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n, float *H,
-                                   bool f32)
+pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n,
+                                   int n_chains, float *H, bool f32)
 {
     if (n <= 0) return PMC_OK;
     PMC_REQUIRE(t.dxa && t.dpb, "logreg dense Jacobian: tables not built");
     DenseHArgs ha{(const uint4 *)t.dxa, (const uint4 *)t.dpb, t.dnb, t.dnpt, (const float *)a.S,
-                  (const float *)a.s0, a.ld, n, t.dim, H, a.glob};
+                  (const float *)a.s0, a.offsets, n_chains, a.ld, n, t.dim, H, a.glob};
     const int g = t.dgrp;
     const int64_t tiles = (n + 31) / 32, gx = (tiles + kDenseWaves - 1) / kDenseWaves;
     PMC_REQUIRE(gx <= 0x7fffffff && g >= 1 && g <= kMaxGroup && t.dnpt % g == 0,

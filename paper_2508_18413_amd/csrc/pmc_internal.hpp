@@ -352,8 +352,8 @@ int logreg_dense_pair_cols(int D);  // row stride of H (D <= 32)
 // J z through X^T (w o X z) on BF16 matrix cores; writes the diagonal planes.
 pmc_status launch_logreg_probe_diag(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n,
                                     int n_chains);
-pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n, float *H,
-                                   bool f32);
+pmc_status launch_logreg_dense_jac(pmc_context *ctx, const DevTarget &t, const EvalArgs &a, int64_t n,
+                                   int n_chains, float *H, bool f32);
 // Tile length the eval kernel for this target expects.
 int eval_tile_steps(const DevTarget &tg);
 
@@ -391,14 +391,47 @@ pmc_status launch_logreg_surrogate(pmc_context *ctx, const DevTarget &t, const E
 pmc_status launch_sequential_hmc(pmc_context *ctx, const DevTarget &t, const SeqArgs &a);
 
 // Dense DEER scan on matrix cores (D <= 32, F32 states; J in the BF16 or F32
-// fragment layout written by the eval kernels).  Single sequence of n steps.
+// fragment layout written by the eval kernels).
+//
+// Every chain has a hierarchy of its own: level 0 holds one affine map per
+// scan tile of the chain (at most 32 steps), each level above composes
+// groups of 8 maps of the level below, up to a top level of at most 8 maps.
+constexpr int kDenseMaxLev = 11;  // 2^31 steps: 2^26 tiles, then / 8 per level
+struct DenseChainGeom {
+    int32_t L;                    // levels (0: empty chain; 1: its <= 8 tile maps are the top)
+    int32_t pad;
+    int64_t tile0;                // first scan tile of the chain (index of its level-0 maps)
+    int64_t m[kDenseMaxLev];      // maps per level (m[0]: the chain's tiles)
+    int64_t ubase[kDenseMaxLev];  // k >= 1: index of the level's first map among all upper-level maps
+};
+struct DenseHier {
+    int n_chains = 0;
+    int L_max = 0;
+    int64_t n_tiles = 0, n_up = 0;
+    std::vector<DenseChainGeom> geom;  // per chain
+    // several chains: (chain, group) pairs of each level's up and down launch
+    std::vector<int32_t> units;
+    int64_t up_off[kDenseMaxLev] = {}, up_cnt[kDenseMaxLev] = {};
+    int64_t down_off[kDenseMaxLev] = {}, down_cnt[kDenseMaxLev] = {};
+    size_t o_P0 = 0, o_B0 = 0, o_C0 = 0, o_UP = 0, o_UB = 0, o_UC = 0, o_geom = 0, o_units = 0,
+           bytes = 0;                  // workspace layout
+};
+// Hierarchy of the chains whose scan tiles are [ctb[c], ctb[c + 1]).
+void dense_hier_plan(const std::vector<int32_t> &ctb, int n_chains, DenseHier &h);
+// Copies the chain tables into the workspace (once per solve, before the
+// first sweep).
+pmc_status dense_hier_setup(pmc_context *ctx, const DenseHier &h, void *ws);
+// Workspace of the hierarchy of one sequence of n steps.
 size_t dense_mfma_ws_bytes(int64_t n);
 int dense_mfma_unit();
+// One Newton update of every active chain: the scan tiles are the level-0
+// units; chains[c].active == 0 leaves chain c untouched; glob->n_active == 0
+// at launch makes the whole call a no-op.
 pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, const float *F,
-                                    float *S, int64_t ld, int D, int64_t n, TilePartial *partials,
-                                    double atol, double rtol, float *trace, void *ws,
-                                    const GlobalStatus *glob,    // n_active == 0 at launch: no-op
-                                    const ChainStatus *chain);   // its window start, or nullptr
+                                    float *S, int64_t ld, int D, const SegTile *tiles,
+                                    const ChainStatus *chains, TilePartial *partials, double atol,
+                                    double rtol, float *trace, void *ws, const DenseHier &h,
+                                    const GlobalStatus *glob);
 pmc_status launch_linrec_dense_mfma(pmc_context *ctx, int bf16, int D, int64_t T, const float *A,
                                     const float *b, float *out);
 // Same on J already in the fragment layout; ws: dense_mfma_ws_bytes(T) bytes.

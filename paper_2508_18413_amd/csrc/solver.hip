@@ -39,6 +39,7 @@ struct Plan {
     int jmode;
     int n_lanes;
     int scan_items, scan_block, C_scan, C_eval;
+    DenseHier dh;  // matrix-core dense scan: per-chain hierarchy and its workspace layout
     std::vector<int64_t> offs;
     std::vector<SegTile> etiles, stiles;
     std::vector<int32_t> ctb;
@@ -165,10 +166,6 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
                 set_error("pmc_solve: dense DEER on logistic regression supports D <= 32 (got %d)", pl.D);
                 return PMC_ERR_UNSUPPORTED;
             }
-            if (p->n_chains != 1) {
-                set_error("pmc_solve: matrix-core dense DEER solves one chain per call");
-                return PMC_ERR_UNSUPPORTED;
-            }
             pl.jmode = o->jac_prec == PMC_JAC_BF16 ? JM_DENSE_BF16 : JM_DENSE_F32;
             pl.logreg_dense = true;
             break;
@@ -182,10 +179,6 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         } else {
             if (pl.D > 32) {
                 set_error("pmc_solve: matrix-core dense DEER supports D <= 32 (got %d)", pl.D);
-                return PMC_ERR_UNSUPPORTED;
-            }
-            if (p->n_chains != 1) {
-                set_error("pmc_solve: matrix-core dense DEER solves one chain per call");
                 return PMC_ERR_UNSUPPORTED;
             }
             pl.jmode = o->jac_prec == PMC_JAC_BF16 ? JM_DENSE_BF16 : JM_DENSE_F32;
@@ -287,8 +280,8 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     default: jb = 0;
     }
     pl.o_J = take(std::max<size_t>(jb, 256));
-    pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? dense_mfma_ws_bytes(pl.n)
-                                                                         : 256);
+    if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) dense_hier_plan(pl.ctb, pl.n_chains, pl.dh);
+    pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? pl.dh.bytes : 256);
     if (pl.logreg_dense) pl.o_hpair = take(sizeof(float) * (size_t)pl.n * logreg_dense_pair_cols(pl.D));
     if (pl.basis) pl.o_rot = take(plane * pl.D);
     if (pl.logreg_wide) pl.o_wide = take(wide_workspace_bytes(t, pl.ld));
@@ -335,15 +328,16 @@ pmc_status one_sweep(pmc_context *ctx, const Plan &pl, const Sweep &sw, hipEvent
     } else {
         PMC_TRY(launch_eval(ctx, *pl.tg, sw.ea));
         if (pl.logreg_dense)
-            PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, sw.hpair, pl.jmode == JM_DENSE_F32));
+            PMC_TRY(launch_logreg_dense_jac(ctx, *pl.tg, sw.ea, pl.n, pl.n_chains, sw.hpair,
+                                            pl.jmode == JM_DENSE_F32));
         if (pl.logreg_probe) PMC_TRY(launch_logreg_probe_diag(ctx, *pl.tg, sw.ea, pl.n, pl.n_chains));
     }
     if (ev) PMC_TRY_HIP(hipEventRecord(ev[1], ctx->stream));
     if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32)
         PMC_TRY(launch_dense_mfma_newton(ctx, pl.jmode == JM_DENSE_BF16, sw.sa.J, (const float *)sw.sa.F,
-                                         (float *)sw.sa.S, sw.sa.ld, pl.D, pl.n, sw.sa.partials,
-                                         sw.sa.atol, sw.sa.rtol, nullptr, sw.hier, sw.ea.glob,
-                                         sw.sa.chains));
+                                         (float *)sw.sa.S, sw.sa.ld, pl.D, sw.sa.tiles, sw.sa.chains,
+                                         sw.sa.partials, sw.sa.atol, sw.sa.rtol, nullptr, sw.hier, pl.dh,
+                                         sw.ea.glob));
     else if (pl.jmode == JM_DENSE_ROW)
         PMC_TRY(launch_newton_scan_dense_small(ctx, pl.dt, pl.D, sw.sa));
     else
@@ -613,6 +607,7 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
 
     Sweep sw;
     sw.hier = ws + pl.o_hier;
+    if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) PMC_TRY(dense_hier_setup(ctx, pl.dh, sw.hier));
     if (pl.logreg_wide) {
         // the noise as planes, once per solve
         sw.wide = ws + pl.o_wide;

@@ -819,6 +819,58 @@ def test_funnel_dense_deer_full_length(ctx, pm, orc, jac):
                 label=f"funnel dense {jac} T=16384")
 
 
+@pytest.mark.parametrize("jac", ["bf16", "f32"])
+def test_batched_dense_deer_logreg(ctx, pm, orc, jac):
+    """Full DEER on uneven logistic chains laid end to end in one solve (chain
+    lengths not multiples of the 32-step tile, from 1 step to several levels
+    of the matrix-core hierarchy): each chain against its FP64 sequential
+    chain from its own burned-in start."""
+    _say(f"batched dense DEER logreg {jac}")
+    b = W.logreg_batch(seed=3, n_chains=6, lo=1, hi=9000, eps=0.0015)
+    lens = np.diff(b.offsets)
+    tg = oracle_target(b.target)
+    s0 = np.stack([oracle_burnin(tg, _as_chain(b, c)) for c in range(b.n_chains)]).astype(np.float32)
+    g = pm.Target(ctx, b.target)
+    r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets), variant="dense",
+                 jac_prec=jac, clip=1.0, clip_inf_norm=True, max_iter=int(lens.max()) + 1)
+    _say(f"  lens={lens.tolist()} sweeps/chain={r.sweeps_per_chain} status={r.status}")
+    assert r.status == 0 and r.n_converged == b.n_chains
+    st = r.states.cpu().numpy()
+    acc = r.accept.cpu().numpy()
+    for c in range(b.n_chains):
+        o0, o1 = b.offsets[c], b.offsets[c + 1]
+        _check_mala(orc, tg, _as_chain(b, c), s0[c], st[o0:o1], acc[o0:o1], label=f"batched dense {jac} chain {c}")
+
+
+def test_batched_dense_deer_funnel(ctx, pm, orc):
+    """Full DEER on three funnel chains of one target (D = 32, per-step
+    Jacobians of the evaluation kernel), lengths 300, 2000 and 4097, solved
+    together and each compared with its FP64 chain."""
+    _say("batched dense DEER funnel")
+    lens = (300, 2000, 4097)
+    chs = [W.funnel_chain(T=n, seed=1) for n in lens]
+    # one target: the chains differ in their noise streams
+    chs = [W.Chain(target=chs[0].target, eps=c.eps, x0=c.x0, xi=W.normals(np.random.default_rng(40 + k), (n, 32),
+                                                                           np.float32),
+                   u=W.uniforms(np.random.default_rng(50 + k), n, np.float32))
+           for k, (c, n) in enumerate(zip(chs, lens))]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    tg = oracle_target(chs[0].target)
+    g = pm.Target(ctx, chs[0].target)
+    x0 = np.stack([c.x0 for c in chs])
+    xi = np.concatenate([c.xi for c in chs])
+    u = np.concatenate([c.u for c in chs])
+    r = pm.solve(ctx, g, chs[0].eps, _t(x0), _t(xi), _t(u), offsets=list(offs), variant="dense", jac_prec="bf16",
+                 max_iter=max(lens) + 1)
+    _say(f"  sweeps/chain={r.sweeps_per_chain} status={r.status}")
+    assert r.status == 0
+    st = r.states.cpu().numpy()
+    acc = r.accept.cpu().numpy()
+    for c, ch in enumerate(chs):
+        _check_mala(orc, tg, ch, ch.x0, st[offs[c]:offs[c + 1]], acc[offs[c]:offs[c + 1]],
+                    label=f"batched dense funnel chain {c}")
+
+
 def test_ula_gaussian_one_solve_mfma(ctx, pm, orc):
     """Affine f: the first matrix-core (F32) dense solve already gives the chain."""
     _say("ula gaussian one solve mfma D=16")
