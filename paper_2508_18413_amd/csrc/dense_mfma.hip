@@ -239,15 +239,22 @@ struct Lvl0In {  // Newton level 0: b_t = F_t - S_t from planes (FP32)
     int D;
     const SegTile *tiles;
     const ChainStatus *chains;
+    int64_t single_len;  // > 0: one chain of this many steps, cut every 32 (no tile load)
     // false if the unit's chain has stopped (nothing to do)
     __device__ bool unit(int64_t u, Unit &g) const
     {
-        const SegTile st = tiles[u];
-        const ChainStatus &cs = chains[st.chain];
+        if (single_len > 0) {
+            g.t0 = u * kU;
+            g.cnt = (int)min((int64_t)kU, single_len - g.t0);
+            g.chain = 0;
+        } else {
+            const SegTile st = tiles[u];
+            g.t0 = st.start;
+            g.cnt = st.len;
+            g.chain = st.chain;
+        }
+        const ChainStatus &cs = chains[g.chain];
         if (!cs.active) return false;
-        g.t0 = st.start;
-        g.cnt = st.len;
-        g.chain = st.chain;
         // steps before the window are the identity map with b = 0 (the carry
         // entering the window is exactly zero whatever their stale J holds);
         // steps from the window's end on are the identity too
@@ -689,10 +696,11 @@ pmc_status run_levels(pmc_context *ctx, const DenseHier &h, char *ws, const Chai
 
 }  // namespace
 
-void dense_hier_plan(const std::vector<int32_t> &ctb, int n_chains, DenseHier &h)
+void dense_hier_plan(const std::vector<int32_t> &ctb, int n_chains, int64_t n_steps, DenseHier &h)
 {
     h = DenseHier();
     h.n_chains = n_chains;
+    h.single_len = n_chains == 1 ? n_steps : 0;
     h.n_tiles = n_chains > 0 ? ctb[n_chains] : 0;
     h.geom.resize(std::max(n_chains, 1));
     int64_t ub = 0;
@@ -747,7 +755,7 @@ pmc_status dense_hier_setup(pmc_context *ctx, const DenseHier &h, void *ws)
 size_t dense_mfma_ws_bytes(int64_t n)
 {
     DenseHier h;
-    dense_hier_plan({0, (int32_t)((n + kU - 1) / kU)}, 1, h);
+    dense_hier_plan({0, (int32_t)((n + kU - 1) / kU)}, 1, n, h);
     return h.bytes;
 }
 
@@ -761,7 +769,7 @@ pmc_status launch_dense_mfma_newton(pmc_context *ctx, int bf16, const void *J, c
 {
     if (h.n_tiles == 0) return PMC_OK;
     char *p = (char *)ws;
-    Lvl0In in{F, S, ld, D, tiles, chains};
+    Lvl0In in{F, S, ld, D, tiles, chains, h.single_len};
     if (bf16)
         hipLaunchKernelGGL((k_up0<FragB, ChainB, Lvl0In>), dim3(blocks_for_units(h.n_tiles)), dim3(64 * kWPB), 0,
                            ctx->stream, J, in, h.n_tiles, (float4 *)(p + h.o_P0), (float *)(p + h.o_B0), glob);
@@ -786,7 +794,7 @@ pmc_status launch_linrec_dense_mfma_packed(pmc_context *ctx, int bf16, int D, in
 {
     if (T == 0) return PMC_OK;
     DenseHier h;
-    dense_hier_plan({0, (int32_t)((T + kU - 1) / kU)}, 1, h);
+    dense_hier_plan({0, (int32_t)((T + kU - 1) / kU)}, 1, T, h);
     PMC_TRY(dense_hier_setup(ctx, h, ws));
     char *p = (char *)ws;
     RowIn in{b, D, T};

@@ -408,6 +408,7 @@ struct DenseHier {
     int n_chains = 0;
     int L_max = 0;
     int64_t n_tiles = 0, n_up = 0;
+    int64_t single_len = 0;            // one chain: its steps (its tiles are then every 32 steps)
     std::vector<DenseChainGeom> geom;  // per chain
     // several chains: (chain, group) pairs of each level's up and down launch
     std::vector<int32_t> units;
@@ -416,8 +417,9 @@ struct DenseHier {
     size_t o_P0 = 0, o_B0 = 0, o_C0 = 0, o_UP = 0, o_UB = 0, o_UC = 0, o_geom = 0, o_units = 0,
            bytes = 0;                  // workspace layout
 };
-// Hierarchy of the chains whose scan tiles are [ctb[c], ctb[c + 1]).
-void dense_hier_plan(const std::vector<int32_t> &ctb, int n_chains, DenseHier &h);
+// Hierarchy of the chains whose scan tiles are [ctb[c], ctb[c + 1]) (n_steps
+// steps in all, cut into tiles at multiples of 32).
+void dense_hier_plan(const std::vector<int32_t> &ctb, int n_chains, int64_t n_steps, DenseHier &h);
 // Copies the chain tables into the workspace (once per solve, before the
 // first sweep).
 pmc_status dense_hier_setup(pmc_context *ctx, const DenseHier &h, void *ws);

@@ -280,7 +280,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     default: jb = 0;
     }
     pl.o_J = take(std::max<size_t>(jb, 256));
-    if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) dense_hier_plan(pl.ctb, pl.n_chains, pl.dh);
+    if (pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32) dense_hier_plan(pl.ctb, pl.n_chains, pl.n, pl.dh);
     pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? pl.dh.bytes : 256);
     if (pl.logreg_dense) pl.o_hpair = take(sizeof(float) * (size_t)pl.n * logreg_dense_pair_cols(pl.D));
     if (pl.basis) pl.o_rot = take(plane * pl.D);
