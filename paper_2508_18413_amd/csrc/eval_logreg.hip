@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
     const int D = a.D, nr = f.nr;
     const int64_t ld = a.ld;
     const float *S = (const float *)a.S, *noise = (const float *)a.noise;
-    float *J = (float *)a.J;
+    float *J = (float *)a.J, *F = (float *)a.F;
     const float *s_csc = s_xty + 32;  // c_d
     const float eps = (float)a.eps, c = sqrtf(2.f * eps), pp = f.pp;
     const float damp = (float)a.damping, clip = (float)a.clip;
@@ -627,13 +627,18 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
         const bool head = (tt == a.offsets[tl.chain]);
         const float *s0 = (const float *)a.s0 + (size_t)tl.chain * D;
 
-        float SB[MK], SC[MK];
+        // the iterate s_{t-1} in the B layout; loaded where it is used (after
+        // pass 1 and in the epilogue) rather than held through both passes,
+        // which keeps the kernel within its 256 registers
+        auto sb = [&](int m) -> float {
+            const int d = 2 * m + hh;
+            return d < D ? (head ? s0[d] : S[(size_t)d * ld + tt - 1]) : 0.f;
+        };
+        float SC[MK];
         float smax = 0.f;
 #pragma unroll
         for (int m = 0; m < MK; m++) {
-            const int d = 2 * m + hh;
-            SB[m] = d < D ? (head ? s0[d] : S[(size_t)d * ld + tt - 1]) : 0.f;
-            SC[m] = SB[m] * s_csc[2 * m + hh];
+            SC[m] = sb(m) * s_csc[2 * m + hh];
             smax = fmaxf(smax, fabsf(SC[m]));
         }
         // scaled iterate outside [2^-3, 2^14): taken to [2^13, 2^14) (Z undone by 2^-es)
@@ -726,8 +731,11 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
             for (int m = 0; m < MK; m++) {
                 const int d = 2 * m + hh;
                 const float cd = s_csc[2 * m + hh], gs = kLn2 * cd;
-                gB[m] = fmaf(GB[m], gs, -pp * SB[m]);
+                gB[m] = fmaf(GB[m], gs, -pp * sb(m));
                 DB[m] = d < D ? fmaf(eps, gB[m], c * noise[(size_t)tt * D + d]) : 0.f;
+                // the gradient waits for the epilogue in this step's F slot
+                // (written there at the end), not in registers through pass 2
+                if (valid && d < D) F[(size_t)d * ld + t] = gB[m];
                 DC[m] = DB[m] * cd;
                 dmax = fmaxf(dmax, fabsf(DC[m]));
                 if (want_j && valid && d < D) {
@@ -835,9 +843,18 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
             const int o = (32 * (nr - 1) + 16 * kk) * kHW + goff;
             Gt = mfma3(g_operand(s_hi, o), g_operand(s_lo, o), Th[kk], Tl[kk], Gt);
         }
-        float gsc[MK];
+        // (the compiler must not carry the stashed gradient in registers
+        // through pass 2: an empty asm statement that clobbers memory makes
+        // the loads below real)
+        asm volatile("" ::: "memory");
+        float gsc[MK], SB[MK];
 #pragma unroll
-        for (int m = 0; m < MK; m++) gsc[m] = kLn2 * s_csc[2 * m + hh];
+        for (int m = 0; m < MK; m++) {
+            const int d = 2 * m + hh;
+            gsc[m] = kLn2 * s_csc[2 * m + hh];
+            SB[m] = sb(m);
+            gB[m] = valid && d < D ? F[(size_t)d * ld + t] : 0.f;
+        }
         finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip, cs);
     }
 }
