@@ -854,6 +854,8 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
             gsc[m] = kLn2 * s_csc[2 * m + hh];
             SB[m] = sb(m);
             gB[m] = valid && d < D ? F[(size_t)d * ld + t] : 0.f;
+            // the increment again, from the same operands (bit for bit)
+            DB[m] = d < D ? fmaf(eps, gB[m], c * noise[(size_t)tt * D + d]) : 0.f;
         }
         finish_step<MK>(a, s_xty, Gt, dll_s, SB, DB, gB, gsc, pp, hh, ld, t, tt, valid, want_j, damp, clip, cs);
     }
