@@ -555,6 +555,33 @@ def other_workload(args, pm, W, np, torch):
                          "sweeps_median": float(np.median(spc)), "sweeps_p90": float(np.percentile(spc, 90)),
                          "sweeps_max": int(spc.max()),
                          "max_abs_vs_sequential": (r.states - rs.states).abs().max().item()}
+        # full DEER (BF16 Jacobians, infinity-norm clip 1) on 16 uneven chains
+        # in one solve, against the same chains solved one call each and the
+        # sequential sampler
+        b2 = W.logreg_batch(seed=2, n_chains=16, lo=4096, hi=16384, eps=args.eps)
+        g2 = pm.Target(ctx, b2.target)
+        bx2 = pm.sample_sequential(ctx, g2, b2.eps, t(b2.x0), t(b2.burn_xi.reshape(-1, b2.x0.shape[1])),
+                                   t(b2.burn_u.reshape(-1)), offsets=list(range(0, 3 * 16 + 1, 3)))
+        s02 = bx2.states.reshape(16, 3, -1)[:, -1].contiguous()
+        xi2, u2 = t(b2.xi), t(b2.u)
+        off2 = [int(v) for v in b2.offsets]
+        n2 = off2[-1]
+        dk = dict(variant="dense", jac_prec="bf16", clip=1.0, clip_inf_norm=True, max_iter=max(np.diff(off2)) + 1)
+        rs2, ts2 = _timed(lambda: pm.sample_sequential(ctx, g2, b2.eps, s02, xi2, u2, offsets=off2), 1, torch,
+                          "dense batch sequential")
+        rb2, tb2 = _timed(lambda: pm.solve(ctx, g2, b2.eps, s02, xi2, u2, offsets=off2, **dk), 1, torch,
+                          "dense batch")
+
+        def one_by_one():
+            for c in range(16):
+                pm.solve(ctx, g2, b2.eps, s02[c:c + 1], xi2[off2[c]:off2[c + 1]], u2[off2[c]:off2[c + 1]], **dk)
+
+        _, t12 = _timed(one_by_one, 1, torch, "dense one chain per call")
+        res["dense_batch_16"] = {"n_steps": n2, "sequential_ms": 1e3 * ts2, "batched_ms": 1e3 * tb2,
+                                 "one_call_per_chain_ms": 1e3 * t12, "chain_steps_per_s": n2 / tb2,
+                                 "vs_sequential": ts2 / tb2, "status": rb2.status,
+                                 "sweeps_max": int(max(rb2.sweeps_per_chain)),
+                                 "max_abs_vs_sequential": (rb2.states - rs2.states).abs().max().item()}
     elif args.workload == "hmc_seq":
         # HMC across the sequence (Sec. 3.3): the logistic posterior at the
         # settings of App. B.4 (4 chains x 1000 transitions, L = 4, eps = 0.04,
