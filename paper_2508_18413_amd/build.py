@@ -21,6 +21,11 @@ ARCH = os.environ.get("PMC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
          "-Rpass-analysis=kernel-resource-usage"]
+# Per-source additions.  The wide logistic GEMM's epilogues are fully unrolled
+# loops over a lane's 64 accumulator elements; above the compiler's default
+# size limit for a requested full unroll the loop stays rolled and the
+# accumulators move to private memory.
+FILE_FLAGS = {"logreg_wide.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 # Every kernel's private segment (spills and private arrays) stays within the
 # HIP runtime's default per-thread stack of 1 KiB.
 MAX_PRIVATE_BYTES = 1024
@@ -44,7 +49,7 @@ def _resources(text: str) -> list[dict]:
 
 
 def _compile(src: str, obj: str) -> tuple[str, int, str, list]:
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     text = p.stdout + p.stderr
     res = _resources(text)

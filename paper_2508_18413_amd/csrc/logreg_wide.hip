@@ -83,6 +83,19 @@ struct WideGemm {
     float *F, *Jd;    // planes [D][ld]
     float damp, clip;
     int want_j;
+    // split K (narrow windows, where a launch has few output tiles): the
+    // kernel's phase 1 computes slice blockIdx.y of ksplit slices of K into
+    // kpart planes [ksplit][ipad][ld]; phase 2 sums the slices in order and
+    // runs the epilogue; phase 0 is the whole product in one launch
+    int ksplit;
+    int64_t ipad;
+    float *kpart;
+    // fixed-width windows: with win_tiles > 0 the grid covers only the
+    // win_tiles evaluation tiles of each chain from the one holding its
+    // window start (ctile0[c]: the chain's first tile, [n_chains + 1])
+    const int32_t *ctile0;
+    int win_tiles;
+    int n_chains;
 };
 
 // Per-column context of a tile: global step, chain start, validity.
@@ -119,13 +132,7 @@ __device__ __forceinline__ constexpr int n_parts()
     return MODE == W_DELTA ? 1 : MODE == W_GRADP ? 3 : 0;
 }
 
-// s_{t-1}[d] for the step of column context cc
-__device__ __forceinline__ float prev_state(const WideGemm &g, const ColCtx &cc, int d)
-{
-    return cc.head ? g.s0[(size_t)cc.chain * g.D + d] : g.S[(size_t)d * g.ld + cc.t - 1];
-}
-
-template <int MODE, int QF>
+template <int MODE, int QF, int PH>
 __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
 {
     extern __shared__ float lds[];
@@ -137,11 +144,23 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
     // eight XCDs in turn, so the row tiles of one column tile are given the
     // same XCD and share its L2 copy of the column panel
     const int n_it = (g.I + kBI - 1) / kBI;
-    const int64_t slot = blockIdx.x >> 3;
-    const int xcd = blockIdx.x & 7;
-    const int it = (int)(slot % n_it);
-    const int64_t jt = (slot / n_it) * 8 + xcd;
-    if (jt >= g.n_jtiles) return;
+    int it;
+    int64_t jt;
+    if (g.win_tiles > 0) {
+        // compact grid: workgroup -> (row tile, chain, k-th tile of its window)
+        it = (int)(blockIdx.x % n_it);
+        const int64_t rest = blockIdx.x / n_it;
+        const int c = (int)(rest / g.win_tiles);
+        const ChainStatus &cs = g.chains[c];
+        if (!cs.active) return;
+        jt = g.ctile0[c] + (cs.win_start / kBJ - g.offsets[c] / kBJ) + rest % g.win_tiles;
+        if (jt >= g.ctile0[c + 1]) return;
+    } else {
+        const int64_t slot = blockIdx.x >> 3;
+        it = (int)(slot % n_it);
+        jt = (slot / n_it) * 8 + (blockIdx.x & 7);
+        if (jt >= g.n_jtiles) return;
+    }
     const int i0 = it * kBI;
 
     // ---- columns of this tile
@@ -280,27 +299,87 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
         }
     };
 
-    const int nk = (g.K + kBK - 1) / kBK;
-    load_stage(0, 0);
-    store_stage(0, 0, 0);
-    if (nk > 1) load_stage(1, kBK);
-    __syncthreads();
+    // K tiles [kb, kb + nk) of this launch: all of them, or one slice
+    const int nk_all = (g.K + kBK - 1) / kBK;
+    int kb = 0, nk = nk_all;
+    if (PH == 1) {
+        const int per = (nk_all + g.ksplit - 1) / g.ksplit;
+        kb = min(nk_all, (int)blockIdx.y * per);
+        nk = min(nk_all, kb + per) - kb;
+    } else if (PH == 2) {
+        nk = 0;
+    }
+    if (nk > 0) {
+        load_stage(0, kb * kBK);
+        store_stage(0, 0, kb * kBK);
+        if (nk > 1) load_stage(1, (kb + 1) * kBK);
+        __syncthreads();
+    }
     // stage kt lives in LDS buffer kt & 1 and arrives through register set kt & 1
     for (int kt = 0; kt < nk; kt += 2) {
-        if (kt + 2 < nk) load_stage(0, (kt + 2) * kBK);
+        if (kt + 2 < nk) load_stage(0, (kb + kt + 2) * kBK);
         compute(0);
-        if (kt + 1 < nk) store_stage(1, 1, (kt + 1) * kBK);
+        if (kt + 1 < nk) store_stage(1, 1, (kb + kt + 1) * kBK);
         __syncthreads();
         if (kt + 1 < nk) {
-            if (kt + 3 < nk) load_stage(1, (kt + 3) * kBK);
+            if (kt + 3 < nk) load_stage(1, (kb + kt + 3) * kBK);
             compute(1);
-            if (kt + 2 < nk) store_stage(0, 0, (kt + 2) * kBK);
+            if (kt + 2 < nk) store_stage(0, 0, (kb + kt + 2) * kBK);
             __syncthreads();
+        }
+    }
+    if (PH == 1) {
+        // this slice's partial products, for the valid columns
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const ColCtx cc = s_col[64 * wj + 32 * b + jl];
+            if (!cc.valid) continue;
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    const int i = i0 + 64 * wi + 32 * a + crow(r, h);
+                    if (i < g.I) g.kpart[((size_t)blockIdx.y * g.ipad + i) * g.ld + cc.t] = acc[a][b][r];
+                }
+        }
+        return;
+    }
+    if (PH == 2) {
+        // the slices summed in order.  Every lane loads all 64 of its
+        // elements of a slice unconditionally (a masked column or row reads
+        // an in-range element that is then dropped), so a slice's loads are
+        // in flight together instead of one branch and one round trip each.
+        // (rows past I lie inside the slice planes, which have ipad rows)
+        for (int ks = 0; ks < g.ksplit; ks++) {
+            const float *src = g.kpart + (size_t)ks * g.ipad * g.ld;
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                const ColCtx cc = s_col[64 * wj + 32 * b + jl];
+                const float *col = src + (cc.valid ? cc.t : j0) + (size_t)(i0 + 64 * wi + 4 * h) * g.ld;
+                float v[2][16];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int r = 0; r < 16; r++) v[a][r] = col[(size_t)(32 * a + crow(r, 0)) * g.ld];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int r = 0; r < 16; r++) {
+                        const int i = i0 + 64 * wi + 32 * a + crow(r, h);
+                        if (cc.valid && i < g.I) acc[a][b][r] += v[a][r];
+                    }
+                asm volatile("" ::: "memory");
+            }
         }
     }
 
     // ---- epilogue: lane (jl, h) of block (a, b) holds C[i][jj] with
-    // i = i0 + 64 wi + 32 a + crow(r, h), jj = 64 wj + 32 b + jl
+    // i = i0 + 64 wi + 32 a + crow(r, h), jj = 64 wj + 32 b + jl.  Per block
+    // (a, b) the operands of all 16 elements are gathered first, with
+    // in-range addresses for masked elements (column j0, row clamped), and
+    // only then combined and stored: loads placed after a store to a buffer
+    // the compiler cannot prove disjoint would each wait for the previous
+    // element's round trip.
     constexpr int NP = n_parts<MODE>();
     double psum[2][3];
 #pragma unroll
@@ -311,52 +390,87 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
     for (int b = 0; b < 2; b++) {
         const int jj = 64 * wj + 32 * b + jl;
         const ColCtx cc = s_col[jj];
-        if (!cc.valid) continue;
-        const int64_t t = cc.t;
+        const bool cv = cc.valid;
+        const int64_t t = cv ? cc.t : j0;
+        // s_{t-1}: the chain's s0 at its first step, else the previous column of S
+        const bool hd = cv && cc.head;
+        const float *xp = hd ? g.s0 + (size_t)cc.chain * g.D : g.S + (t > 0 ? t - 1 : 0);
+        const int64_t xs = hd ? 1 : g.ld;
+        const int ac = (MODE == W_HESS) ? g.accept[t] : 0;
+        // elements per gather: fewer where the combine step is long (the
+        // log-likelihood increments), so that its temporaries fit in registers
+        constexpr int GS = MODE == W_DELTA || MODE == W_GRADP ? 8 : 16;
 #pragma unroll
-        for (int a = 0; a < 2; a++) {
+        for (int ag = 0; ag < 32 / GS; ag++) {
+            const int a = ag * GS / 16, r0 = ag * GS % 16;
+            const int ib = i0 + 64 * wi + 32 * a;
+            float o0[16], o1[16], o2[16], o3[16];
+            // gather
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                const int i = i0 + 64 * wi + 32 * a + crow(r, h);
+            for (int r = r0; r < r0 + GS; r++) {
+                const int i = ib + crow(r, h);
+                const int ii = min(i, g.I - 1);
+                const int id = min(i, g.D - 1);
+                if (MODE == W_FWD) {
+                    o0[r] = g.y[ii];
+                } else if (MODE == W_GRAD) {
+                    o0[r] = xp[(size_t)id * xs];
+                    o1[r] = g.xi[(size_t)id * g.ld + t];
+                } else if (MODE == W_DELTA) {
+                    o0[r] = g.Abuf[(size_t)ii * g.ld + t];
+                    o1[r] = g.y[ii];
+                } else if (MODE == W_GRADP) {
+                    o0[r] = xp[(size_t)id * xs];
+                    o1[r] = g.Dbuf[(size_t)id * g.ld + t];
+                    o2[r] = g.Gbuf[(size_t)id * g.ld + t];
+                    o3[r] = g.xi[(size_t)id * g.ld + t];
+                } else if (MODE == W_HESS) {
+                    o0[r] = xp[(size_t)id * xs];
+                    o1[r] = g.Dbuf[(size_t)id * g.ld + t];
+                }
+            }
+            if (!cv) continue;
+            // combine and store
+#pragma unroll
+            for (int r = r0; r < r0 + GS; r++) {
+                const int i = ib + crow(r, h);
                 const float v = acc[a][b][r];
                 if (MODE == W_ROT) {
                     if (i < g.I) g.out[(size_t)i * g.ldo + t] = v;
                 } else if (MODE == W_FWD) {
                     if (i < g.I) {
-                        const float s = sigmoidf_(v);
+                        const float sg = sigmoidf_(v);
                         g.Abuf[(size_t)i * g.ld + t] = v;
-                        g.Rbuf[(size_t)i * g.ld + t] = g.y[i] - s;
-                        g.Wbuf[(size_t)i * g.ld + t] = s * (1.f - s);
+                        g.Rbuf[(size_t)i * g.ld + t] = o0[r] - sg;
+                        g.Wbuf[(size_t)i * g.ld + t] = sg * (1.f - sg);
                     }
                 } else if (MODE == W_GRAD) {
                     if (i < g.D) {
-                        const float x = prev_state(g, cc, i);
-                        const float gr = fmaf(-g.pp, x, v);
+                        const float gr = fmaf(-g.pp, o0[r], v);
                         g.Gbuf[(size_t)i * g.ld + t] = gr;
-                        g.Dbuf[(size_t)i * g.ld + t] = fmaf(g.eps, gr, g.c * g.xi[(size_t)i * g.ld + t]);
+                        g.Dbuf[(size_t)i * g.ld + t] = fmaf(g.eps, gr, g.c * o1[r]);
                     }
                 } else if (MODE == W_DELTA) {
                     if (i < g.I) {
-                        const float a0 = g.Abuf[(size_t)i * g.ld + t];
-                        g.Rbuf[(size_t)i * g.ld + t] = g.y[i] - sigmoidf_(a0 + v);
-                        if (i < g.N) psum[b][0] += (double)g.y[i] * (double)v - softplus_inc(a0, v);
+                        const float a0 = o0[r];
+                        g.Rbuf[(size_t)i * g.ld + t] = o1[r] - sigmoidf_(a0 + v);
+                        if (i < g.N) psum[b][0] += (double)o1[r] * (double)v - softplus_inc(a0, v);
                     }
                 } else if (MODE == W_GRADP) {
                     if (i < g.D) {
-                        const float x = prev_state(g, cc, i);
-                        const float dl = g.Dbuf[(size_t)i * g.ld + t];
+                        const float x = o0[r];
+                        const float dl = o1[r];
                         const float xt = x + dl;
                         const float gt = fmaf(-g.pp, xt, v);
-                        const double sg = (double)g.Gbuf[(size_t)i * g.ld + t] + (double)gt;
+                        const double sg = (double)o2[r] + (double)gt;
                         psum[b][0] = fma(sg, sg, psum[b][0]);
-                        psum[b][1] = fma((double)g.xi[(size_t)i * g.ld + t], sg, psum[b][1]);
+                        psum[b][1] = fma((double)o3[r], sg, psum[b][1]);
                         psum[b][2] = fma((double)dl, (double)xt + (double)x, psum[b][2]);
                     }
                 } else if (MODE == W_HESS) {
                     if (i < g.D) {
-                        const float x = prev_state(g, cc, i);
-                        const int ac = g.accept[t];
-                        const float dl = g.Dbuf[(size_t)i * g.ld + t];
+                        const float x = o0[r];
+                        const float dl = o1[r];
                         g.F[(size_t)i * g.ld + t] = ac ? x + dl : x;
                         if (g.want_j) {
                             float jv = ac ? g.damp * fmaf(g.eps, -v - g.pp, 1.f) : g.damp;
@@ -366,6 +480,8 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
                     }
                 }
             }
+            // the next block's gathers are not hoisted above these stores
+            asm volatile("" ::: "memory");
         }
     }
     if (NP > 0) {
@@ -494,12 +610,25 @@ pmc_status launch_gemm(pmc_context *ctx, WideGemm g, int64_t n_jtiles)
 {
     if (n_jtiles <= 0 || g.I <= 0) return PMC_OK;
     const int64_t n_it = (g.I + kBI - 1) / kBI;
-    const int64_t blocks = (n_jtiles + 7) / 8 * 8 * n_it;
+    const int64_t blocks =
+        g.win_tiles > 0 ? (int64_t)g.n_chains * g.win_tiles * n_it : (n_jtiles + 7) / 8 * 8 * n_it;
     PMC_REQUIRE(blocks <= 0x7fffffff, "wide logistic: %lld workgroups exceed the launch limit", (long long)blocks);
     g.n_jtiles = n_jtiles;
-    PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_wide_gemm<MODE, QF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)gemm_lds()));
-    hipLaunchKernelGGL((k_wide_gemm<MODE, QF>), dim3((unsigned)blocks), dim3(kThreads), gemm_lds(), ctx->stream, g);
+    if (g.ksplit > 1 && g.kpart) {
+        PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_wide_gemm<MODE, QF, 1>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds()));
+        PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_wide_gemm<MODE, QF, 2>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds()));
+        hipLaunchKernelGGL((k_wide_gemm<MODE, QF, 1>), dim3((unsigned)blocks, (unsigned)g.ksplit), dim3(kThreads),
+                           gemm_lds(), ctx->stream, g);
+        hipLaunchKernelGGL((k_wide_gemm<MODE, QF, 2>), dim3((unsigned)blocks), dim3(kThreads), gemm_lds(),
+                           ctx->stream, g);
+    } else {
+        PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_wide_gemm<MODE, QF, 0>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds()));
+        hipLaunchKernelGGL((k_wide_gemm<MODE, QF, 0>), dim3((unsigned)blocks), dim3(kThreads), gemm_lds(),
+                           ctx->stream, g);
+    }
     PMC_TRY_HIP(hipGetLastError());
     return PMC_OK;
 }
@@ -514,9 +643,10 @@ namespace {
 struct WideWs {
     float *A, *R, *W, *G, *Dl, *xi;
     double *part_dll, *part_q;
+    float *kpart;  // split-K slices [ksplit][max(Np, Dp)][ld], or nullptr
     size_t total;
 };
-WideWs wide_layout(void *base, const DevTarget &t, int64_t ld)
+WideWs wide_layout(void *base, const DevTarget &t, int64_t ld, int ksplit)
 {
     const size_t np = (size_t)wide_pad(t.n_data), D = (size_t)t.dim;
     const size_t nid = (size_t)(wide_pad(t.dim) / kBI), nin = np / kBI;
@@ -537,13 +667,33 @@ WideWs wide_layout(void *base, const DevTarget &t, int64_t ld)
     w.xi = (float *)take(4 * D * ld);
     w.part_dll = (double *)take(8 * nin * ld);
     w.part_q = (double *)take(8 * 3 * nid * ld);
+    w.kpart = ksplit > 1 ? (float *)take(4 * (size_t)ksplit * std::max(np, (size_t)t.ldx) * ld) : nullptr;
     w.total = off;
     return w;
 }
 }  // namespace
 
-size_t wide_workspace_bytes(const DevTarget &t, int64_t ld) { return wide_layout(nullptr, t, ld).total; }
-float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld) { return wide_layout(ws, t, ld).xi; }
+size_t wide_workspace_bytes(const DevTarget &t, int64_t ld, int ksplit)
+{
+    return wide_layout(nullptr, t, ld, ksplit).total;
+}
+float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld, int ksplit)
+{
+    return wide_layout(ws, t, ld, ksplit).xi;
+}
+
+int wide_ksplit(const DevTarget &t, int64_t window_width, int n_chains)
+{
+    // enough workgroups (about kSplitTarget) for the chip's 256 CUs
+    constexpr int64_t kSplitTarget = 512, kSplitMax = 8;
+    if (window_width <= 0) return 1;
+    // output tiles of a launch: row tiles x the chains' active column tiles
+    // (a window may straddle one more tile than its width covers)
+    const int64_t n_it = std::max(wide_pad(t.n_data), t.ldx) / kBI;
+    const int64_t cols = (int64_t)n_chains * ((window_width + kBJ - 1) / kBJ + 1);
+    const int64_t ks = kSplitTarget / std::max<int64_t>(1, n_it * cols);
+    return (int)std::min<int64_t>(kSplitMax, std::max<int64_t>(1, ks));
+}
 
 pmc_status logreg_wide_tables(pmc_context *ctx, DevTarget &t)
 {
@@ -596,7 +746,7 @@ pmc_status launch_eval_logreg_wide(pmc_context *ctx, const DevTarget &t, const E
     PMC_REQUIRE(t.xwt && t.x2wt && t.ldx % kBI == 0, "wide logistic: target tables missing");
     const int Np = wide_pad(t.n_data), D = t.dim;
     const int64_t ld = a.ld;
-    const WideWs w = wide_layout(ws, t, ld);
+    const WideWs w = wide_layout(ws, t, ld, a.ksplit);
     float *Abuf = w.A, *Rbuf = w.R, *Wbuf = w.W, *Gbuf = w.G, *Dbuf = w.Dl;
     const float *xi_planes = w.xi;
     const int n_it_n = Np / kBI, n_it_d = t.ldx / kBI;
@@ -628,6 +778,14 @@ pmc_status launch_eval_logreg_wide(pmc_context *ctx, const DevTarget &t, const E
     g.damp = (float)a.damping;
     g.clip = (float)a.clip;
     g.want_j = a.jmode == JM_DIAG;
+    g.ksplit = w.kpart ? a.ksplit : 1;
+    g.kpart = w.kpart;
+    g.ipad = std::max(Np, t.ldx);
+    if (a.window_width > 0 && a.chain_etile_begin) {
+        g.ctile0 = a.chain_etile_begin;
+        g.win_tiles = (int)((a.window_width + kBJ - 1) / kBJ + 1);
+        g.n_chains = a.n_chains;
+    }
     const int64_t nj = a.n_tiles;
 
     // 1. predictors at s_{t-1}

@@ -302,6 +302,12 @@ struct EvalArgs {
                                   // previous sweep's decision, read from accept[t]
     int hmc_L = 0;                // > 0: f_t is a whole HMC step with this many leapfrog steps
     const void *inv_mass = nullptr;  // HMC: [D] diagonal of M^-1, or nullptr = identity
+    int ksplit = 1;               // logistic D > 32: K slices of the GEMMs (wide_ksplit)
+    // fixed-width windows (logistic D > 32): the width, the chain count and
+    // each chain's first eval tile [n_chains + 1]
+    int64_t window_width = 0;
+    int n_chains = 0;
+    const int32_t *chain_etile_begin = nullptr;
 };
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
 
@@ -336,8 +342,10 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
 constexpr int kWideMinDim = 33, kWideMaxDim = 1024;
 int wide_pad(int n);          // rows and columns padded to the GEMM tile (128)
 int wide_tile_steps();        // evaluation tile (steps)
-size_t wide_workspace_bytes(const DevTarget &t, int64_t ld);
-float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld);
+size_t wide_workspace_bytes(const DevTarget &t, int64_t ld, int ksplit);
+// K slices of the wide GEMMs for fixed-width windows of this width (1: none)
+int wide_ksplit(const DevTarget &t, int64_t window_width, int n_chains);
+float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld, int ksplit);
 pmc_status logreg_wide_tables(pmc_context *ctx, DevTarget &t);
 pmc_status wide_rotate_rows(pmc_context *ctx, const float *in, int64_t rows, int64_t ld_in, const float *Q, int D,
                             bool transpose, float *out, int64_t ld_out);

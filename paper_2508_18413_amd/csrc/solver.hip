@@ -54,7 +54,10 @@ struct Plan {
     size_t o_rot = 0;             // rotation scratch planes [D, ld]
     size_t o_hpair = 0;
     bool logreg_wide = false;     // logistic regression with D > 32 (matrix-core GEMM evaluation)
+    int wide_ks = 1;              // K slices of its GEMMs (fixed-width windows)
     size_t o_wide = 0;
+    std::vector<int32_t> ectb;    // each chain's first eval tile (wide, fixed-width windows)
+    size_t o_ectb = 0;
 };
 
 void build_tiles(const std::vector<int64_t> &offs, int C, std::vector<SegTile> &tiles,
@@ -250,7 +253,8 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     }
     pl.C_eval = eval_tile_steps(t);
     build_tiles(pl.offs, pl.C_scan, pl.stiles, &pl.ctb);
-    build_tiles(pl.offs, pl.C_eval, pl.etiles, nullptr);
+    build_tiles(pl.offs, pl.C_eval, pl.etiles,
+                pl.logreg_wide && o->window_width > 0 ? &pl.ectb : nullptr);
 
     pl.max_iter = o->max_iter;
     if (pl.max_iter <= 0)
@@ -284,7 +288,11 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     pl.o_hier = take(pl.jmode == JM_DENSE_BF16 || pl.jmode == JM_DENSE_F32 ? pl.dh.bytes : 256);
     if (pl.logreg_dense) pl.o_hpair = take(sizeof(float) * (size_t)pl.n * logreg_dense_pair_cols(pl.D));
     if (pl.basis) pl.o_rot = take(plane * pl.D);
-    if (pl.logreg_wide) pl.o_wide = take(wide_workspace_bytes(t, pl.ld));
+    if (pl.logreg_wide) {
+        pl.wide_ks = wide_ksplit(t, o->window_width, pl.n_chains);
+        pl.o_wide = take(wide_workspace_bytes(t, pl.ld, pl.wide_ks));
+        if (!pl.ectb.empty()) pl.o_ectb = take(sizeof(int32_t) * pl.ectb.size());
+    }
     pl.o_acc = take(std::max<int64_t>(pl.n, 1));
     pl.o_gt = take(4 * std::max<int64_t>(pl.n, 1));
     pl.o_etiles = take(sizeof(SegTile) * std::max<size_t>(pl.etiles.size(), 1));
@@ -612,7 +620,7 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
         // the noise as planes, once per solve
         sw.wide = ws + pl.o_wide;
         PMC_TRY(wide_rows_to_planes(ctx, (const float *)prob->noise, pl.n, pl.D, pl.ld,
-                                    wide_xi_planes(sw.wide, *pl.tg, pl.ld)));
+                                    wide_xi_planes(sw.wide, *pl.tg, pl.ld, pl.wide_ks)));
     }
     if (pl.logreg_dense || pl.logreg_probe) {
         // operand tables: derived data of the target, built by its first
@@ -650,6 +658,15 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
     ea.tie_band = (float)opts->tie_band;
     ea.tg = pl.tg;
     ea.glob = d_glob;
+    ea.ksplit = pl.wide_ks;
+    if (!pl.ectb.empty()) {
+        int32_t *d_ectb = (int32_t *)(ws + pl.o_ectb);
+        PMC_TRY_HIP(hipMemcpyAsync(d_ectb, pl.ectb.data(), sizeof(int32_t) * pl.ectb.size(), hipMemcpyHostToDevice,
+                                   st));
+        ea.chain_etile_begin = d_ectb;
+        ea.window_width = opts->window_width;
+        ea.n_chains = pl.n_chains;
+    }
     NewtonScanArgs &sa = sw.sa;
     sa.n_lanes = pl.n_lanes;
     sa.ld = pl.ld;
