@@ -84,15 +84,23 @@ typedef enum { PMC_JAC_F32 = 0, PMC_JAC_BF16 = 1 } pmc_jac_prec;
 typedef enum { PMC_GATE_FROZEN = 0, PMC_GATE_SURROGATE = 1 } pmc_gate;
 
 /* How the logistic-regression evaluation forms its matrix products (FP32
- * targets).  SPLIT16 writes each operand as hi + lo, two FP16 numbers, and sums
+ * targets, D <= 32 for SPLIT16 and REFINE).  SPLIT16 writes each operand as hi + lo, two FP16 numbers, and sums
  * lo*hi + hi*lo + hi*hi on the FP16 matrix cores with FP32 accumulation (the
  * error-compensated half-precision product of Markidis et al. 2018 and Ootomo
  * & Yokota 2022: about 2^-22 of each product is dropped, against 2^-24 for
  * FP32; operands are brought to FP16's range by exact power-of-two scalings);
  * it needs n_data <= 1216.  AUTO takes SPLIT16 where that holds and FP32
  * matrix instructions elsewhere; SPLIT16 requested for more data points is
- * PMC_ERR_UNSUPPORTED at pmc_target_create. */
-typedef enum { PMC_PRODUCTS_AUTO = 0, PMC_PRODUCTS_F32 = 1, PMC_PRODUCTS_SPLIT16 = 2 } pmc_products;
+ * PMC_ERR_UNSUPPORTED at pmc_target_create.  REFINE keeps both: in pmc_solve
+ * (MALA or ULA, no fixed-width window) each chain's Newton iteration runs on
+ * SPLIT16 products until it meets the tolerance (or its rounding floor), then
+ * restarts its window at its first step and runs on FP32 products until it
+ * meets the tolerance again, so the result is the FP32-product iteration's
+ * fixed point (Alg. 1 with a cheaper f in its early sweeps; the paper's
+ * convergence test applies unchanged to the final sweeps).  It needs
+ * n_data <= 1152 (PMC_ERR_UNSUPPORTED at pmc_target_create otherwise); with
+ * a fixed-width window, and for HMC, chains use FP32 products throughout. */
+typedef enum { PMC_PRODUCTS_AUTO = 0, PMC_PRODUCTS_F32 = 1, PMC_PRODUCTS_SPLIT16 = 2, PMC_PRODUCTS_REFINE = 3 } pmc_products;
 
 typedef struct pmc_context pmc_context; /* opaque: device, stream, workspace pool, tuning table */
 typedef struct pmc_target pmc_target;   /* opaque: device copy of a target's parameters        */

@@ -18,7 +18,8 @@ __all__ = ["Context", "Target", "solve", "solve_noalloc", "sample_sequential", "
 
 VARIANTS = {"dense": B.PMC_DEER_DENSE, "diag": B.PMC_QDEER_DIAG, "block2": B.PMC_QDEER_BLOCK2,
             "picard": B.PMC_PICARD}
-PRODUCTS = {"auto": B.PMC_PRODUCTS_AUTO, "f32": B.PMC_PRODUCTS_F32, "split16": B.PMC_PRODUCTS_SPLIT16}
+PRODUCTS = {"auto": B.PMC_PRODUCTS_AUTO, "f32": B.PMC_PRODUCTS_F32, "split16": B.PMC_PRODUCTS_SPLIT16,
+            "refine": B.PMC_PRODUCTS_REFINE}
 KINDS = {"gaussian": B.PMC_TARGET_GAUSSIAN, "banana": B.PMC_TARGET_BANANA,
          "logreg": B.PMC_TARGET_LOGREG, "funnel": B.PMC_TARGET_FUNNEL}
 

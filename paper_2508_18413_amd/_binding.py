@@ -20,7 +20,7 @@ PMC_TARGET_GAUSSIAN, PMC_TARGET_BANANA, PMC_TARGET_LOGREG, PMC_TARGET_FUNNEL = 0
 PMC_DEER_DENSE, PMC_QDEER_DIAG, PMC_QDEER_BLOCK2, PMC_PICARD = 0, 1, 2, 3
 PMC_JAC_F32, PMC_JAC_BF16 = 0, 1
 PMC_GATE_FROZEN, PMC_GATE_SURROGATE = 0, 1
-PMC_PRODUCTS_AUTO, PMC_PRODUCTS_F32, PMC_PRODUCTS_SPLIT16 = 0, 1, 2
+PMC_PRODUCTS_AUTO, PMC_PRODUCTS_F32, PMC_PRODUCTS_SPLIT16, PMC_PRODUCTS_REFINE = 0, 1, 2, 3
 
 
 class pmc_target_desc(C.Structure):

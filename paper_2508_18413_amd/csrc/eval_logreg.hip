@@ -234,7 +234,7 @@ template <int MK>
 __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs a, LdsArgs f)
 {
     extern __shared__ float s_x[];
-    if (a.glob && a.glob->n_active == 0) return;  // a sweep queued past the last active chain
+    if (a.glob && !eval_has_chains(a)) return;  // a sweep queued past the last active chain
     const int nrow = f.nr * 32;
     {
         const int nw = nrow * (kXS + 1) + 32;
@@ -261,7 +261,8 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 2) k_eval_logreg_lds(EvalArgs 
     for (int tix = blockIdx.x * kLdsWaves + (threadIdx.x >> 6); tix < a.n_tiles; tix += n_waves) {
         const SegTile tl = a.tiles[tix];
         const ChainStatus &cs = a.chains[tl.chain];
-        if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) continue;
+        if (!cs.active || !eval_takes(a, cs) || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end)
+            continue;
         const int64_t t = tl.start + i;
         const bool valid = i < tl.len && t >= cs.win_start && t < cs.win_end;
         const int64_t tt = i < tl.len ? t : tl.start;
@@ -590,7 +591,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
 {
     constexpr int KB = MK > 8 ? 2 : 1;
     extern __shared__ float4 s_img[];
-    if (a.glob && a.glob->n_active == 0) return;  // a sweep queued past the last active chain
+    if (a.glob && !eval_has_chains(a)) return;  // a sweep queued past the last active chain
     const int nrow = f.nr * 32;
     {
         const int n4 = (int)(kHImageBytes(f.nr) / 16);
@@ -620,7 +621,8 @@ __global__ void __launch_bounds__(64 * kLdsWaves, 1) k_eval_logreg_h(EvalArgs a,
     for (int tix = blockIdx.x * kLdsWaves + (threadIdx.x >> 6); tix < a.n_tiles; tix += n_waves) {
         const SegTile tl = a.tiles[tix];
         const ChainStatus &cs = a.chains[tl.chain];
-        if (!cs.active || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end) continue;
+        if (!cs.active || !eval_takes(a, cs) || tl.start + tl.len <= cs.win_start || tl.start >= cs.win_end)
+            continue;
         const int64_t t = tl.start + i;
         const bool valid = i < tl.len && t >= cs.win_start && t < cs.win_end;
         const int64_t tt = i < tl.len ? t : tl.start;
@@ -1140,6 +1142,10 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
     const int nr = (t.n_data + 31) / 32, mk = (t.dim + 1) / 2;
     t.nr = nr;
     t.mk = mk <= 2 ? 2 : mk <= 4 ? 4 : mk <= 8 ? 8 : mk <= 13 ? 13 : 16;
+    if (t.products == PMC_PRODUCTS_REFINE && nr > kLdsMaxRowTiles) {
+        set_error("logreg target: refined products need n_data <= %d", 32 * kLdsMaxRowTiles);
+        return PMC_ERR_UNSUPPORTED;
+    }
     if (t.products != PMC_PRODUCTS_F32) {
         // split-FP16 products need the image in LDS
         if (nr <= kHMaxRowTiles) {
@@ -1171,8 +1177,8 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
             return PMC_ERR_UNSUPPORTED;
         }
     }
-    if (!t.xh && nr <= kLdsMaxRowTiles) {
-        // LDS-resident path: one padded image of X and y
+    if ((!t.xh || t.products == PMC_PRODUCTS_REFINE) && nr <= kLdsMaxRowTiles) {
+        // LDS-resident path (FP32 products): one padded image of X and y
         const size_t bl = sizeof(float) * (size_t)kLdsImageFloats(nr);
         PMC_TRY_HIP(hipMalloc(&t.xl, bl));
         hipLaunchKernelGGL(k_logreg_lds_image, dim3(64), dim3(256), 0, ctx->stream, (const float *)t.X, t.ldx,
@@ -1202,9 +1208,16 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t)
     return PMC_OK;
 }
 
-pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a)
+pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalArgs &a_in)
 {
-    if (a.n_tiles <= 0) return PMC_OK;
+    if (a_in.n_tiles <= 0) return PMC_OK;
+    EvalArgs a = a_in;
+    if (t.xh && t.xl) {
+        // refined products: the split-FP16 kernel takes the chains still in
+        // their first phase, the FP32 kernel the others (each returns at
+        // once when it has no chain)
+        a.fine_sel = 0;
+    }
     if (t.xh) {
         HArgs f{t.xh, t.nr, (float)(1.0 / t.prior_var)};
         const size_t lds = kHImageBytes(t.nr);
@@ -1219,7 +1232,8 @@ pmc_status launch_eval_logreg(pmc_context *ctx, const DevTarget &t, const EvalAr
         default: set_error("logreg eval: unsupported dimension"); return PMC_ERR_UNSUPPORTED;
         }
         PMC_TRY_HIP(hipGetLastError());
-        return PMC_OK;
+        if (!t.xl) return PMC_OK;
+        a.fine_sel = 1;
     }
     if (t.xl) {
         LdsArgs f{(const float *)t.xl, t.nr, (float)(1.0 / t.prior_var)};

@@ -75,6 +75,8 @@ struct ChainStatus {
     float best_ratio;
     uint32_t nonfinite;
     int32_t at_floor;    // 1 if stopped at the rounding floor
+    int32_t fine;        // 1 once the evaluation uses the final arithmetic (refined products:
+                         // 0 while the split-FP16 products drive the iteration)
     int64_t best_front;  // furthest converged front seen
     int64_t fb_prev;     // first_bad of the sweep before (the window starts at the earlier of
                          // the two: a step is frozen once it met the tolerance twice in a row)
@@ -96,7 +98,7 @@ struct GlobalStatus {
     int64_t next_steps;  // steps the next sweep evaluates (active chains, from their windows)
     int64_t eval_steps;  // steps evaluated by all sweeps so far
     uint32_t fold_ctr;   // status-fold completion counter; zero between launches
-    uint32_t pad;
+    int32_t n_fine;      // active chains with fine = 1
 };
 
 // Synchronisation words of the single-pass scans.  A one-thread kernel after
@@ -303,12 +305,25 @@ struct EvalArgs {
     int hmc_L = 0;                // > 0: f_t is a whole HMC step with this many leapfrog steps
     const void *inv_mass = nullptr;  // HMC: [D] diagonal of M^-1, or nullptr = identity
     int ksplit = 1;               // logistic D > 32: K slices of the GEMMs (wide_ksplit)
+    int fine_sel = -1;            // evaluate only chains with ChainStatus::fine == fine_sel (-1: all)
     // fixed-width windows (logistic D > 32): the width, the chain count and
     // each chain's first eval tile [n_chains + 1]
     int64_t window_width = 0;
     int n_chains = 0;
     const int32_t *chain_etile_begin = nullptr;
 };
+
+// Whether an evaluation launch has chains to take (from the global status
+// the last status fold wrote), and whether it takes chain cs.
+__device__ __forceinline__ bool eval_has_chains(const EvalArgs &a)
+{
+    const int n = a.glob->n_active, nf = a.glob->n_fine;
+    return a.fine_sel < 0 ? n > 0 : a.fine_sel ? nf > 0 : n > nf;
+}
+__device__ __forceinline__ bool eval_takes(const EvalArgs &a, const ChainStatus &cs)
+{
+    return a.fine_sel < 0 || cs.fine == a.fine_sel;
+}
 pmc_status launch_eval(pmc_context *ctx, const DevTarget &tg, const EvalArgs &a);
 
 // A decision whose gate lies within the tie band keeps the previous sweep's

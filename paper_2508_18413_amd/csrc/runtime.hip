@@ -436,12 +436,12 @@ pmc_status pmc_target_create(pmc_context *ctx, const pmc_target_desc *d, pmc_tar
                 set_error("logreg target: dim <= %d (got %d)", kWideMaxDim, d->dim);
                 return PMC_ERR_UNSUPPORTED;
             }
-            PMC_REQUIRE(d->products != PMC_PRODUCTS_SPLIT16,
+            PMC_REQUIRE(d->products != PMC_PRODUCTS_SPLIT16 && d->products != PMC_PRODUCTS_REFINE,
                         "logreg target: dim > 32 evaluates with FP32 matrix products only");
             PMC_REQUIRE(d->n_data <= (1 << 24), "logreg target: n_data <= 2^24 (got %d)", d->n_data);
             ldx = wide_pad(d->dim);
         }
-        PMC_REQUIRE(d->products >= PMC_PRODUCTS_AUTO && d->products <= PMC_PRODUCTS_SPLIT16,
+        PMC_REQUIRE(d->products >= PMC_PRODUCTS_AUTO && d->products <= PMC_PRODUCTS_REFINE,
                     "logreg target: unknown products mode %d", (int)d->products);
         t.ldx = ldx;
         t.n_data = d->n_data;

@@ -1571,6 +1571,21 @@ __device__ void chain_update(ChainStatus &cs, const Fold &v, const StatusArgs &a
     } else {
         cs.stall += 1;
     }
+    // Refined products: the tolerance met (or the rounding floor reached)
+    // with the split-FP16 evaluation starts the final phase instead of
+    // stopping: FP32 products from the chain's first step, with the window
+    // and the plateau detection started afresh, until the tolerance is met
+    // again under them.
+    const bool floor_hit = a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f;
+    if (!cs.fine && ((r <= 1.f && cs.win_end >= cend) || floor_hit)) {
+        cs.fine = 1;
+        cs.win_start = off;
+        cs.fb_prev = off;
+        cs.best_front = off;
+        cs.best_ratio = INFINITY;
+        cs.stall = 0;
+        return;
+    }
     if (r <= 1.f && cs.win_end >= cend) {
         cs.converged = 1;
         cs.active = 0;
@@ -1582,7 +1597,7 @@ __device__ void chain_update(ChainStatus &cs, const Fold &v, const StatusArgs &a
         cs.fb_prev = cs.win_start;
     } else if (cs.sweeps >= a.max_iter) {
         cs.active = 0;
-    } else if (a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f) {
+    } else if (floor_hit) {
         // rounding floor: no progress for floor_stall sweeps with the last change within
         // twice the tolerance (the state error of a change-based stop is a few times the
         // last change, so this keeps it near the converged chains' error)
@@ -1639,9 +1654,9 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
     __syncthreads();
     if (!s_last) return;
     if (!single) __threadfence();
-    __shared__ int s_cnt[kStatusThreads / 64][4];
+    __shared__ int s_cnt[kStatusThreads / 64][5];
     Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
-    int nact = 0, nconv = 0, nfloor = 0, sweeps = 0;
+    int nact = 0, nconv = 0, nfloor = 0, sweeps = 0, nfine = 0;
     int64_t nsteps = 0;
     for (int i = tid; i < a.n_chains; i += kStatusThreads) {
         const ChainStatus &o = a.chains[i];
@@ -1654,11 +1669,13 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         v.r = fmaxf(v.r, o.max_ratio);
         v.f += o.nonfinite;
         nact += o.active;
+        nfine += o.active && o.fine;
         nconv += o.converged;
         nfloor += o.at_floor;
         sweeps = max(sweeps, o.sweeps);
     }
     nact = wave::reduce_sum(nact);
+    nfine = wave::reduce_sum(nfine);
     nconv = wave::reduce_sum(nconv);
     nfloor = wave::reduce_sum(nfloor);
     sweeps = wave::reduce_max(sweeps, INT32_MIN);
@@ -1669,6 +1686,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         s_cnt[tid >> 6][1] = nconv;
         s_cnt[tid >> 6][2] = nfloor;
         s_cnt[tid >> 6][3] = sweeps;
+        s_cnt[tid >> 6][4] = nfine;
         s_steps[tid >> 6] = nsteps;
     }
     v = block_fold(v);
@@ -1678,10 +1696,12 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
             nconv += s_cnt[w][1];
             nfloor += s_cnt[w][2];
             sweeps = max(sweeps, s_cnt[w][3]);
+            nfine += s_cnt[w][4];
             nsteps += s_steps[w];
         }
         GlobalStatus *g = a.global;
         g->n_active = nact;
+        g->n_fine = nfine;
         g->n_converged = nconv;
         g->n_floor = nfloor;
         g->sweeps = sweeps;
@@ -1738,6 +1758,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status_one(StatusArgs a)
     }
     GlobalStatus *g = a.global;
     g->n_active = cs.active;
+    g->n_fine = cs.active && cs.fine;
     g->n_converged = cs.converged;
     g->n_floor = cs.at_floor;
     g->sweeps = cs.sweeps;

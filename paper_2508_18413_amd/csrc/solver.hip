@@ -55,6 +55,7 @@ struct Plan {
     size_t o_hpair = 0;
     bool logreg_wide = false;     // logistic regression with D > 32 (matrix-core GEMM evaluation)
     int wide_ks = 1;              // K slices of its GEMMs (fixed-width windows)
+    bool refine = false;          // split-FP16 products until convergence, then FP32 products
     size_t o_wide = 0;
     std::vector<int32_t> ectb;    // each chain's first eval tile (wide, fixed-width windows)
     size_t o_ectb = 0;
@@ -132,6 +133,10 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
         return PMC_ERR_UNSUPPORTED;
     }
     pl.logreg_wide = t.kind == PMC_TARGET_LOGREG && pl.D >= kWideMinDim;
+    // refined products drive the per-step evaluation of MALA / ULA on the
+    // logistic posterior; fixed-width windows start with the final products
+    pl.refine = t.kind == PMC_TARGET_LOGREG && t.products == PMC_PRODUCTS_REFINE && !pl.logreg_wide &&
+                !pl.hmc && o->window_width == 0;
     if (pl.logreg_wide &&
         (pl.hmc || (o->variant != PMC_QDEER_DIAG && o->variant != PMC_PICARD) || o->jac_probes ||
          (o->gate == PMC_GATE_SURROGATE && p->sampler == PMC_SAMPLER_MALA))) {
@@ -575,6 +580,7 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
         cs.best_ratio = INFINITY;
         cs.best_front = pl.offs[c];
         cs.fb_prev = pl.offs[c];
+        cs.fine = !pl.refine;
     }
     PMC_TRY_HIP(hipMemcpyAsync(d_et, pl.etiles.data(), sizeof(SegTile) * pl.etiles.size(),
                                hipMemcpyHostToDevice, st));
@@ -592,6 +598,7 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
         memset(g0, 0, sizeof(*g0));
         for (int c = 0; c < pl.n_chains; c++) {
             g0->n_active += hc[c].active;
+            g0->n_fine += hc[c].active && hc[c].fine;
             g0->n_converged += hc[c].converged;
         }
         g0->next_steps = 0;

@@ -513,7 +513,7 @@ def _check_mala(orc, tg, ch, s0, got_states, got_acc, tol=1e-5, label=None):
     return err, rep
 
 
-@pytest.mark.parametrize("products", ["split16", "f32"])
+@pytest.mark.parametrize("products", ["split16", "f32", "refine"])
 @pytest.mark.parametrize("T", [4096, 5000])
 def test_logreg_diag_fp32(ctx, pm, orc, T, products):
     _say(f"logreg diag fp32 T={T} products={products}")
@@ -560,6 +560,46 @@ def test_logreg_gate_precision(ctx, pm, orc):
         err = np.abs(rs.gtilde.cpu().numpy().astype(np.float64) - ref)
         _say(f"  seed {seed} sequential: max |g~ - g~*| = {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}")
         assert err.max() <= F32_GATE_ERR
+
+
+def test_logreg_refined_products(ctx, pm, orc):
+    """Refined products: split-FP16 sweeps until the chain meets the tolerance,
+    then FP32-product sweeps from its first step until it meets it again.
+    The result is a converged point of the FP32-product iteration: one more
+    FP32-product sweep started from it moves no step by more than the
+    tolerance (this chain has no decision within the FP32 error of g~ of its
+    threshold, where a further sweep could take the other side).  With a fixed-width window the chains use FP32 products
+    throughout, bit for bit what FP32 products give; more data points than
+    the FP32 image holds are refused at target creation."""
+    _say("logreg refined products")
+    from paper_2508_18413_amd._binding import PMCError
+    T = 8192
+    ch, tg, s0 = _logreg_case(orc, T, 0.0015, seed=2)
+    gr = pm.Target(ctx, dict(ch.target, products="refine"))
+    gf = pm.Target(ctx, dict(ch.target, products="f32"))
+    gs = pm.Target(ctx, dict(ch.target, products="split16"))
+    a = (_t(s0), _t(ch.xi), _t(ch.u))
+    kw = dict(variant="diag", max_iter=T + 1)
+    rr = pm.solve(ctx, gr, ch.eps, *a, **kw)
+    rf = pm.solve(ctx, gf, ch.eps, *a, **kw)
+    rs = pm.solve(ctx, gs, ch.eps, *a, **kw)
+    _say(f"  sweeps refine {rr.sweeps} (split16 alone {rs.sweeps}, f32 alone {rf.sweeps}); "
+         f"max |refine - f32| {(rr.states - rf.states).abs().max().item():.3e}")
+    assert rr.status == 0 and rr.sweeps > rs.sweeps
+    one = pm.solve(ctx, gf, ch.eps, *a, **dict(kw, max_iter=1), init_guess=rr.states)
+    _say(f"  one FP32 sweep from the refined result: ratio {one.max_ratio:.3g}")
+    assert one.status == 0 and one.max_ratio <= 1.0
+    clear = one.gtilde.abs() > F32_GATE_ERR
+    assert torch.equal(one.accept[clear], rr.accept[clear])
+    _check_mala(orc, tg, ch, s0, rr.states.cpu().numpy(), rr.accept.cpu().numpy())
+    # fixed-width windows: FP32 products from the start
+    wkw = dict(kw, window_width=1024)
+    w1 = pm.solve(ctx, gr, ch.eps, *a, **wkw)
+    w2 = pm.solve(ctx, gf, ch.eps, *a, **wkw)
+    assert torch.equal(w1.states, w2.states) and w1.sweeps == w2.sweeps
+    big = W.logreg_chain(T=64, seed=5, eps=0.001, n_data=1200, dim=8)
+    with pytest.raises(PMCError, match="refined products"):
+        pm.Target(ctx, dict(big.target, products="refine"))
 
 
 def test_logreg_products_routing(ctx, pm):
@@ -665,13 +705,14 @@ def test_surrogate_gate(ctx, pm, orc, kind):
     _check_mala(orc, tg, ch, np.asarray(x0), r.states.cpu().numpy(), r.accept.cpu().numpy(), tol)
 
 
-def test_batched_uneven_chains(ctx, pm, orc):
-    _say("batched uneven chains")
+@pytest.mark.parametrize("products", ["auto", "refine"])
+def test_batched_uneven_chains(ctx, pm, orc, products):
+    _say(f"batched uneven chains products={products}")
     b = W.logreg_batch(seed=3, n_chains=6, lo=1, hi=9000, eps=0.0015)
     lens = np.diff(b.offsets)
     tg = oracle_target(b.target)
     s0 = np.stack([oracle_burnin(tg, _as_chain(b, c)) for c in range(b.n_chains)]).astype(np.float32)
-    g = pm.Target(ctx, b.target)
+    g = pm.Target(ctx, dict(b.target, products=products))
     r = pm.solve(ctx, g, b.eps, _t(s0), _t(b.xi), _t(b.u), offsets=list(b.offsets),
                  variant="diag", max_iter=int(lens.max()) + 1)
     _say(f"  lens={lens.tolist()} sweeps/chain={r.sweeps_per_chain}")
