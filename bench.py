@@ -567,10 +567,12 @@ def other_workload(args, pm, W, np, torch):
                         "sequential")
         res["sequential"] = {"ms": 1e3 * ts, "chain_steps_per_s": n / ts}
         pm.autotune(ctx, g, b.eps, s0, xi, u, offsets=off)
-        for name, kw in [("diag_window_graph8", dict(variant="diag", graph_sweeps=8)),
-                         ("diag_window", dict(variant="diag")),
-                         ("diag_no_window", dict(variant="diag", skip_converged_prefix=False))]:
-            r, tp = _timed(lambda: pm.solve(ctx, g, b.eps, s0, xi, u, offsets=off, max_iter=400, **kw), 1,
+        gr = pm.Target(ctx, dict(b.target, products="refine"))
+        for name, gg, kw in [("diag_window_graph8", g, dict(variant="diag", graph_sweeps=8)),
+                             ("diag_window", g, dict(variant="diag")),
+                             ("diag_no_window", g, dict(variant="diag", skip_converged_prefix=False)),
+                             ("refine_diag_window_graph8", gr, dict(variant="diag", graph_sweeps=8))]:
+            r, tp = _timed(lambda: pm.solve(ctx, gg, b.eps, s0, xi, u, offsets=off, max_iter=400, **kw), 1,
                            torch, name)
             spc = np.array(r.sweeps_per_chain)
             res[name] = {"ms": 1e3 * tp, "chain_steps_per_s": n / tp, "vs_sequential": ts / tp,

@@ -941,21 +941,22 @@ def test_autotune_and_cache(ctx, pm, orc, tmp_path):
     _check_mala(orc, tg, ch, s0, r.states.cpu().numpy(), r.accept.cpu().numpy())
 
 
-def test_batched_full_size_sampled(ctx, pm, orc):
+@pytest.mark.parametrize("products", ["auto", "refine"])
+def test_batched_full_size_sampled(ctx, pm, orc, products):
     """512 burned-in chains, lengths log-uniform in [4096, 131072] (sum ~ 1.9e7
     steps) in one graph-replayed solve.  Compared step by step with the
     oracle: the three shortest chains, the three longest (~131072 steps) and
     every chain that stopped at its rounding floor (reported as not converged,
     so the call's status is PMC_NOT_CONVERGED exactly when such a chain
-    exists).  Every chain starts from its 3 burn-in steps run by the GPU
+    exists); with the default (split-FP16) and the refined products.  Every chain starts from its 3 burn-in steps run by the GPU
     sequential sampler; the oracle runs each compared chain from that same
     FP32 start."""
     import concurrent.futures as cf
-    _say("batched full size (512 chains)")
+    _say(f"batched full size (512 chains) products={products}")
     b = W.logreg_batch(seed=0, n_chains=512, lo=4096, hi=131072, eps=0.0015)
     lens = np.diff(b.offsets)
     tg = oracle_target(b.target)
-    g = pm.Target(ctx, b.target)
+    g = pm.Target(ctx, dict(b.target, products=products))
     D = b.x0.shape[1]
     bx = pm.sample_sequential(ctx, g, b.eps, _t(b.x0), _t(b.burn_xi.reshape(-1, D)),
                               _t(b.burn_u.reshape(-1)), offsets=list(range(0, 3 * b.n_chains + 1, 3)))
