@@ -85,10 +85,11 @@ struct WideGemm {
     int want_j;
     // split K (narrow windows, where a launch has few output tiles): the
     // kernel's phase 1 computes slice blockIdx.y of ksplit slices of K into
-    // kpart planes [ksplit][ipad][ld]; phase 2 sums the slices in order and
+    // kpart planes [ksplit][ipad][ldk], whose columns are the compact grid's
+    // (column kBJ s + j of window tile slot s); phase 2 sums the slices in order and
     // runs the epilogue; phase 0 is the whole product in one launch
     int ksplit;
-    int64_t ipad;
+    int64_t ipad, ldk;
     float *kpart;
     // fixed-width windows: with win_tiles > 0 the grid covers only the
     // win_tiles evaluation tiles of each chain from the one holding its
@@ -145,11 +146,12 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
     // same XCD and share its L2 copy of the column panel
     const int n_it = (g.I + kBI - 1) / kBI;
     int it;
-    int64_t jt;
+    int64_t jt, kslot = 0;
     if (g.win_tiles > 0) {
         // compact grid: workgroup -> (row tile, chain, k-th tile of its window)
         it = (int)(blockIdx.x % n_it);
         const int64_t rest = blockIdx.x / n_it;
+        kslot = rest;
         const int c = (int)(rest / g.win_tiles);
         const ChainStatus &cs = g.chains[c];
         if (!cs.active) return;
@@ -339,7 +341,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
                     const int i = i0 + 64 * wi + 32 * a + crow(r, h);
-                    if (i < g.I) g.kpart[((size_t)blockIdx.y * g.ipad + i) * g.ld + cc.t] = acc[a][b][r];
+                    if (i < g.I)
+                        g.kpart[((size_t)blockIdx.y * g.ipad + i) * g.ldk + kslot * kBJ + 64 * wj + 32 * b + jl] =
+                            acc[a][b][r];
                 }
         }
         return;
@@ -351,16 +355,16 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
         // in flight together instead of one branch and one round trip each.
         // (rows past I lie inside the slice planes, which have ipad rows)
         for (int ks = 0; ks < g.ksplit; ks++) {
-            const float *src = g.kpart + (size_t)ks * g.ipad * g.ld;
+            const float *src = g.kpart + (size_t)ks * g.ipad * g.ldk;
 #pragma unroll
             for (int b = 0; b < 2; b++) {
                 const ColCtx cc = s_col[64 * wj + 32 * b + jl];
-                const float *col = src + (cc.valid ? cc.t : j0) + (size_t)(i0 + 64 * wi + 4 * h) * g.ld;
+                const float *col = src + kslot * kBJ + 64 * wj + 32 * b + jl + (size_t)(i0 + 64 * wi + 4 * h) * g.ldk;
                 float v[2][16];
 #pragma unroll
                 for (int a = 0; a < 2; a++)
 #pragma unroll
-                    for (int r = 0; r < 16; r++) v[a][r] = col[(size_t)(32 * a + crow(r, 0)) * g.ld];
+                    for (int r = 0; r < 16; r++) v[a][r] = col[(size_t)(32 * a + crow(r, 0)) * g.ldk];
 #pragma unroll
                 for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -614,7 +618,7 @@ pmc_status launch_gemm(pmc_context *ctx, WideGemm g, int64_t n_jtiles)
         g.win_tiles > 0 ? (int64_t)g.n_chains * g.win_tiles * n_it : (n_jtiles + 7) / 8 * 8 * n_it;
     PMC_REQUIRE(blocks <= 0x7fffffff, "wide logistic: %lld workgroups exceed the launch limit", (long long)blocks);
     g.n_jtiles = n_jtiles;
-    if (g.ksplit > 1 && g.kpart) {
+    if (g.ksplit > 1 && g.kpart && g.win_tiles > 0) {
         PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_wide_gemm<MODE, QF, 1>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_lds()));
         PMC_TRY_HIP(hipFuncSetAttribute((const void *)k_wide_gemm<MODE, QF, 2>,
@@ -643,10 +647,10 @@ namespace {
 struct WideWs {
     float *A, *R, *W, *G, *Dl, *xi;
     double *part_dll, *part_q;
-    float *kpart;  // split-K slices [ksplit][max(Np, Dp)][ld], or nullptr
+    float *kpart;  // split-K slices [ksplit][max(Np, Dp)][kcols], or nullptr
     size_t total;
 };
-WideWs wide_layout(void *base, const DevTarget &t, int64_t ld, int ksplit)
+WideWs wide_layout(void *base, const DevTarget &t, int64_t ld, int ksplit, int64_t kcols)
 {
     const size_t np = (size_t)wide_pad(t.n_data), D = (size_t)t.dim;
     const size_t nid = (size_t)(wide_pad(t.dim) / kBI), nin = np / kBI;
@@ -667,19 +671,25 @@ WideWs wide_layout(void *base, const DevTarget &t, int64_t ld, int ksplit)
     w.xi = (float *)take(4 * D * ld);
     w.part_dll = (double *)take(8 * nin * ld);
     w.part_q = (double *)take(8 * 3 * nid * ld);
-    w.kpart = ksplit > 1 ? (float *)take(4 * (size_t)ksplit * std::max(np, (size_t)t.ldx) * ld) : nullptr;
+    w.kpart = ksplit > 1 && kcols > 0 ? (float *)take(4 * (size_t)ksplit * std::max(np, (size_t)t.ldx) * kcols)
+                                      : nullptr;
     w.total = off;
     return w;
 }
 }  // namespace
 
-size_t wide_workspace_bytes(const DevTarget &t, int64_t ld, int ksplit)
+// columns of the compact window grid: each chain's window tiles
+int64_t wide_window_cols(int64_t window_width, int n_chains)
 {
-    return wide_layout(nullptr, t, ld, ksplit).total;
+    return window_width > 0 ? (int64_t)n_chains * ((window_width + kBJ - 1) / kBJ + 1) * kBJ : 0;
 }
-float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld, int ksplit)
+size_t wide_workspace_bytes(const DevTarget &t, int64_t ld, int ksplit, int64_t window_width, int n_chains)
 {
-    return wide_layout(ws, t, ld, ksplit).xi;
+    return wide_layout(nullptr, t, ld, ksplit, wide_window_cols(window_width, n_chains)).total;
+}
+float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld, int ksplit, int64_t window_width, int n_chains)
+{
+    return wide_layout(ws, t, ld, ksplit, wide_window_cols(window_width, n_chains)).xi;
 }
 
 int wide_ksplit(const DevTarget &t, int64_t window_width, int n_chains)
@@ -746,7 +756,7 @@ pmc_status launch_eval_logreg_wide(pmc_context *ctx, const DevTarget &t, const E
     PMC_REQUIRE(t.xwt && t.x2wt && t.ldx % kBI == 0, "wide logistic: target tables missing");
     const int Np = wide_pad(t.n_data), D = t.dim;
     const int64_t ld = a.ld;
-    const WideWs w = wide_layout(ws, t, ld, a.ksplit);
+    const WideWs w = wide_layout(ws, t, ld, a.ksplit, wide_window_cols(a.window_width, a.n_chains));
     float *Abuf = w.A, *Rbuf = w.R, *Wbuf = w.W, *Gbuf = w.G, *Dbuf = w.Dl;
     const float *xi_planes = w.xi;
     const int n_it_n = Np / kBI, n_it_d = t.ldx / kBI;
@@ -781,6 +791,7 @@ pmc_status launch_eval_logreg_wide(pmc_context *ctx, const DevTarget &t, const E
     g.ksplit = w.kpart ? a.ksplit : 1;
     g.kpart = w.kpart;
     g.ipad = std::max(Np, t.ldx);
+    g.ldk = wide_window_cols(a.window_width, a.n_chains);
     if (a.window_width > 0 && a.chain_etile_begin) {
         g.ctile0 = a.chain_etile_begin;
         g.win_tiles = (int)((a.window_width + kBJ - 1) / kBJ + 1);

@@ -357,10 +357,10 @@ pmc_status logreg_build_frags(pmc_context *ctx, DevTarget &t);
 constexpr int kWideMinDim = 33, kWideMaxDim = 1024;
 int wide_pad(int n);          // rows and columns padded to the GEMM tile (128)
 int wide_tile_steps();        // evaluation tile (steps)
-size_t wide_workspace_bytes(const DevTarget &t, int64_t ld, int ksplit);
+size_t wide_workspace_bytes(const DevTarget &t, int64_t ld, int ksplit, int64_t window_width, int n_chains);
 // K slices of the wide GEMMs for fixed-width windows of this width (1: none)
 int wide_ksplit(const DevTarget &t, int64_t window_width, int n_chains);
-float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld, int ksplit);
+float *wide_xi_planes(void *ws, const DevTarget &t, int64_t ld, int ksplit, int64_t window_width, int n_chains);
 pmc_status logreg_wide_tables(pmc_context *ctx, DevTarget &t);
 pmc_status wide_rotate_rows(pmc_context *ctx, const float *in, int64_t rows, int64_t ld_in, const float *Q, int D,
                             bool transpose, float *out, int64_t ld_out);

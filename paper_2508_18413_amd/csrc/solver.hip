@@ -295,7 +295,7 @@ pmc_status make_plan(pmc_context *ctx, const pmc_problem *p, const pmc_options *
     if (pl.basis) pl.o_rot = take(plane * pl.D);
     if (pl.logreg_wide) {
         pl.wide_ks = wide_ksplit(t, o->window_width, pl.n_chains);
-        pl.o_wide = take(wide_workspace_bytes(t, pl.ld, pl.wide_ks));
+        pl.o_wide = take(wide_workspace_bytes(t, pl.ld, pl.wide_ks, o->window_width, pl.n_chains));
         if (!pl.ectb.empty()) pl.o_ectb = take(sizeof(int32_t) * pl.ectb.size());
     }
     pl.o_acc = take(std::max<int64_t>(pl.n, 1));
@@ -627,7 +627,8 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
         // the noise as planes, once per solve
         sw.wide = ws + pl.o_wide;
         PMC_TRY(wide_rows_to_planes(ctx, (const float *)prob->noise, pl.n, pl.D, pl.ld,
-                                    wide_xi_planes(sw.wide, *pl.tg, pl.ld, pl.wide_ks)));
+                                    wide_xi_planes(sw.wide, *pl.tg, pl.ld, pl.wide_ks, opts->window_width,
+                                                   pl.n_chains)));
     }
     if (pl.logreg_dense || pl.logreg_probe) {
         // operand tables: derived data of the target, built by its first
