@@ -36,6 +36,7 @@ namespace pmc {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBI = 128, kBJ = 128, kBK = 32;
 constexpr int kThreads = 256;
@@ -285,6 +286,33 @@ __global__ void __launch_bounds__(kThreads, 2) k_wide_gemm(WideGemm g)
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     auto compute = [&](int s) {
         const float *Ps = lds + s * kStageFloats, *Qs = Ps + kBI * kPS;
+        if constexpr (MODE == W_HESS) {
+            // the Hessian diagonal only enters the Jacobian, which sets the
+            // Newton step and not the fixed point: BF16 products with FP32
+            // accumulation, 16 k per instruction (lane half h takes k 8h..8h+7
+            // of both operands)
+#pragma unroll
+            for (int kk = 0; kk < kBK / 16; kk++) {
+                const int k0 = 16 * kk + 8 * h;
+                bf16x8 af[2], bf[2];
+#pragma unroll
+                for (int a = 0; a < 2; a++) {
+                    const float *pr = Ps + (64 * wi + 32 * a + jl) * kPS + k0;
+#pragma unroll
+                    for (int j = 0; j < 8; j++) af[a][j] = (__bf16)pr[j];
+                }
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+#pragma unroll
+                    for (int j = 0; j < 8; j++) bf[b][j] = (__bf16)Qs[(k0 + j) * kQS + 64 * wj + 32 * b + jl];
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < 2; b++)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+            }
+            return;
+        }
 #pragma unroll
         for (int kp = 0; kp < kBK / 2; kp++) {
             const int kk = 2 * kp + h;
