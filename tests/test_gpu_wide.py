@@ -169,6 +169,39 @@ def test_wide_sequential(pm, ctx, orc, case):
     _check(orc, case, r.states.cpu().numpy(), r.accept.cpu().numpy(), "wide D=768 sequential")
 
 
+def test_wide_jacobian_one_sweep(pm, ctx, orc, case):
+    """One ULA quasi-DEER sweep from a perturbed guess (first 16 steps of the
+    first chain): S1 = F + J d with the Jacobian diagonal that the path forms
+    from (X o X)^T W on BF16 matrix instructions, against the oracle's FP64
+    sweep with the exact diagonal.  The Jacobian's part of the update,
+    S1 - F, is matched to 1 %."""
+    _say("wide Jacobian diagonal, one sweep")
+    T = 16
+    ch = case["chains"][0]
+    tg = case["tg"]
+    x0 = ch.x0.astype(np.float64)
+    xi = ch.xi[:T].astype(np.float64)
+    ref, _, _ = orc.mala_chain(tg, ch.eps, x0, xi, None, ula=True)
+    guess = (ref + 0.02 * np.random.default_rng(3).standard_normal(ref.shape)).astype(np.float32)
+    g64 = guess.astype(np.float64)
+    g = pm.Target(ctx, case["b"].target)
+    r = pm.solve(ctx, g, ch.eps, _t(ch.x0[None, :]), _t(ch.xi[:T]), None, sampler="ula", variant="diag",
+                 init_guess=_t(guess), max_iter=1)
+    got = r.states.cpu().numpy().astype(np.float64)
+
+    def sj(t, s):
+        F, J, _ = orc.mala_jac(tg, ch.eps, s, xi[t], 0.5, ula=True)
+        return F, J
+    want, _, _ = orc.newton_reference(sj, x0, T, variant="diag", init=g64, max_iter=1, full_trace=False)
+    F = np.array([orc.mala_step(tg, ch.eps, x0 if t == 0 else g64[t - 1], xi[t], 0.5, ula=True)[0]
+                  for t in range(T)])
+    jterm = np.max(np.abs(want - F))
+    err = np.max(np.abs(got - want))
+    _say(f"  |J part| {jterm:.3e}  gpu error {err:.3e}")
+    assert jterm > 1e-3
+    assert err <= 0.01 * jterm
+
+
 def test_wide_refusals(pm, ctx, case):
     from paper_2508_18413_amd import _binding as B
     b = case["b"]
