@@ -248,6 +248,21 @@ def main():
                    "max_abs_parallel_minus_sequential": (rpb[-1].states - rs.states).abs().max().item()}
     del rpb, ppb
 
+    # the same probed solve with the stop-gradient gate of Sec. 3.2 (the
+    # relaxed gate's term in the Jacobian diagonal) beside the frozen gate
+    pks = dict(pk, gate="surrogate")
+    pm.solve(ctx, tg, eps, s0, xi, u, **pks)
+    torch.cuda.synchronize()
+    t7 = time.perf_counter()
+    rps = [pm.solve(ctx, tg, eps, s0, xi, u, **pks) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wallps = (time.perf_counter() - t7) / args.steps
+    diag_probed_surrogate = {"value": T / wallps, "unit": "chain-steps/s", "ms_per_step": 1e3 * wallps,
+                             "speedup_vs_sequential": (T / wallps) / seq_value, "newton_iters": rps[-1].sweeps,
+                             "status": rps[-1].status, "gate": "surrogate",
+                             "max_abs_minus_quasi_deer": (rps[-1].states - r.states).abs().max().item()}
+    del rps
+
     # roofline of the dominant kernel (the evaluation kernel), live HIP events
     N, D = ch.target["X"].shape
     eval_avg_ms = sum(x.eval_ms for x in results) / sum(x.sweeps for x in results)
@@ -285,6 +300,7 @@ def main():
         "refine_products": refine_products,
         "dense_deer": dense_deer,
         "diag_probed": diag_probed,
+        "diag_probed_surrogate_gate": diag_probed_surrogate,
         "acceptance": r.n_accept / T,
         "roofline": _eval_roofline(args.products, N, D, eval_avg_ms, steps_per_launch,
                                    _traffic(eval_kernel), eval_kernel),
