@@ -112,3 +112,26 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(name, "size")] == C.sizeof(st), name
         for f in st._fields_:
             assert got[(name, f[0])] == getattr(st, f[0]).offset, (name, f[0])
+
+
+def test_enum_values_match_header(tmp_path):
+    """The binding's enum constants are the header's values (gcc on this host)."""
+    import shutil
+    import subprocess
+    from paper_2508_18413_amd import _binding as B
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    names = [n for n in dir(B) if n.startswith(("PMC_PRODUCTS_", "PMC_GATE_", "PMC_SAMPLER_", "PMC_QDEER_"))
+             and isinstance(getattr(B, n), int)]
+    assert "PMC_PRODUCTS_REFINE" in names
+    lines = ["#include <stdio.h>", '#include "pmcmc.h"', "int main(void) {"]
+    lines += [f'  printf("{n} %d\\n", (int){n});' for n in names]
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "enums.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "enums"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict((l.split()[0], int(l.split()[1])) for l in out if l)
+    for n in names:
+        assert got[n] == getattr(B, n), n
