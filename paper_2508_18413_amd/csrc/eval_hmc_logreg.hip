@@ -113,7 +113,7 @@ __device__ __forceinline__ void fwd_products(const Lds &l, int ldx, int D, int r
 
 // G (+ Gd) += X_tile^T R (+ Rd): lane (i = coordinate, h): A slot m =
 // X[32 rt + crow(m, h)][i]; B slot m = accumulator register m of R.
-template <bool tangent>
+template <bool tangent, bool grad = true>
 __device__ __forceinline__ void bwd_products(const Lds &l, int ldx, int D, int rt, int i, int h, const f32x16 &R,
                                              const f32x16 &Rd, f32x16 &G, f32x16 &Gd)
 {
@@ -121,7 +121,7 @@ __device__ __forceinline__ void bwd_products(const Lds &l, int ldx, int D, int r
 #pragma unroll
     for (int m = 0; m < 16; m++) {
         const float a = own ? l.X[(size_t)(32 * rt + crow(m, h)) * ldx + i] : 0.f;
-        G = __builtin_amdgcn_mfma_f32_32x32x2f32(a, R[m], G, 0, 0, 0);
+        if (grad) G = __builtin_amdgcn_mfma_f32_32x32x2f32(a, R[m], G, 0, 0, 0);
         if (tangent) Gd = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Rd[m], Gd, 0, 0, 0);
     }
 }
@@ -172,8 +172,9 @@ __device__ __forceinline__ void tree_reduce(const Lds &l, int w, int lane, f32x1
 
 // One batched evaluation at the positions in l.P (and directions in l.Pd):
 // G = X^T (y - sigma(X p)) and Gd = X^T (w o X d) per (coordinate, step);
-// wave w receives the entries of its coordinates (tree_reduce).
-template <int MK, bool tangent>
+// wave w receives the entries of its coordinates (tree_reduce).  Without
+// grad only Gd is formed (gs returns zeros).
+template <int MK, bool tangent, bool grad = true>
 __device__ __forceinline__ void evaluate(const Lds &l, const HmcLogregArgs &t, int NR, int w, int lane,
                                          float (&gs)[2], float (&hs)[2])
 {
@@ -190,9 +191,58 @@ __device__ __forceinline__ void evaluate(const Lds &l, const HmcLogregArgs &t, i
             R[r] = l.y[32 * rt + crow(r, h)] - s;
             Rd[r] = s * (1.f - s) * Zd[r];
         }
-        bwd_products<tangent>(l, t.ldx, t.D, rt, i, h, R, Rd, G, Gd);
+        bwd_products<tangent, grad>(l, t.ldx, t.D, rt, i, h, R, Rd, G, Gd);
     }
     tree_reduce<tangent>(l, w, lane, G, Gd, gs, hs);
+}
+
+// Three Hessian-vector products at the positions in l.P, in one pass over
+// the data: Gk = X^T (w o X dk) for the directions d1 = l.Pd, d2 and d3
+// (step-major [32][kPS] like l.Pd; d2 and d3 may lie in l.buf, which is
+// read here only before the reduction's first barrier).  Wave w receives the
+// entries of its coordinates as evaluate does.
+template <int MK>
+__device__ __forceinline__ void evaluate_hvp3(const Lds &l, const HmcLogregArgs &t, int NR, int w, int lane,
+                                              const float *d2, const float *d3, float (&h1)[2], float (&h2)[2],
+                                              float (&h3)[2])
+{
+    const int i = lane & 31, h = lane >> 5;
+    const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f32x16 G1 = zero, G2 = zero, G3 = zero;
+    for (int rt = w; 32 * rt < NR; rt += kW) {
+        f32x16 Z, Z1, Z2 = zero, Z3 = zero;
+        fwd_products<MK, true>(l, t.ldx, t.D, rt, i, h, Z, Z1);
+        const float *xr = l.X + (size_t)(32 * rt + i) * t.ldx;
+#pragma unroll
+        for (int m = 0; m < MK; m++) {
+            const int k = 2 * m + h;
+            const float a = k < t.D ? xr[k] : 0.f;
+            Z2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, d2[i * kPS + k], Z2, 0, 0, 0);
+            Z3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, d3[i * kPS + k], Z3, 0, 0, 0);
+        }
+        f32x16 R1, R2, R3;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const float sv = sigm(Z[r]);
+            const float sp = sv * (1.f - sv);
+            R1[r] = sp * Z1[r];
+            R2[r] = sp * Z2[r];
+            R3[r] = sp * Z3[r];
+        }
+        const bool own = i < t.D;
+#pragma unroll
+        for (int m = 0; m < 16; m++) {
+            const float a = own ? l.X[(size_t)(32 * rt + crow(m, h)) * t.ldx + i] : 0.f;
+            G1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, R1[m], G1, 0, 0, 0);
+            G2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, R2[m], G2, 0, 0, 0);
+            G3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, R3[m], G3, 0, 0, 0);
+        }
+    }
+    __syncthreads();  // every wave is done reading d2 and d3
+    tree_reduce<true>(l, w, lane, G1, G2, h1, h2);
+    f32x16 none = zero;
+    float unused[2];
+    tree_reduce<false>(l, w, lane, G3, none, h3, unused);
 }
 
 // Sum of the 16 registers and the two lane halves: a per-step total in every lane.
@@ -436,24 +486,33 @@ __global__ void __launch_bounds__(kNT, 1) k_logreg_surrogate(EvalArgs a, HmcLogr
             wv[q] = -dl[q] - eps * gt[q];
         }
         put(xt, wv);
-        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+        evaluate<MK, true, false>(l, t, NR, w, lane, gs, hs);  // the gradient at x~ is already in gt
 #pragma unroll
         for (int q = 0; q < 2; q++) {
             t1[q] = -hs[q] - pp * wv[q];                     // H(x~) w
             dll[q] = gt[q] - g[q];
         }
-        put(x, wv);
-        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+        // H(x) applied to w, g~ and H(x~) w in one pass over the data (the
+        // two later directions staged in the reduction buffer)
+        {
+            float *d2 = l.buf, *d3 = l.buf + 32 * kPS;
 #pragma unroll
-        for (int q = 0; q < 2; q++) dll[q] += 0.5f * (-hs[q] - pp * wv[q]);   // H(x) w / 2
-        put(x, gt);
-        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
+            for (int q = 0; q < 2; q++) {
+                l.P[i * kPS + dq[q]] = x[q];
+                l.Pd[i * kPS + dq[q]] = wv[q];
+                d2[i * kPS + dq[q]] = gt[q];
+                d3[i * kPS + dq[q]] = t1[q];
+            }
+            __syncthreads();
+            float hw[2], hg[2], ht[2];
+            evaluate_hvp3<MK>(l, t, NR, w, lane, d2, d3, hw, hg, ht);
 #pragma unroll
-        for (int q = 0; q < 2; q++) dll[q] += eps * (-hs[q] - pp * gt[q]);    // eps H(x) g~
-        put(x, t1);
-        evaluate<MK, true>(l, t, NR, w, lane, gs, hs);
-#pragma unroll
-        for (int q = 0; q < 2; q++) dll[q] += 0.5f * (t1[q] + eps * (-hs[q] - pp * t1[q]));  // M H(x~) w / 2
+            for (int q = 0; q < 2; q++) {
+                dll[q] += 0.5f * (-hw[q] - pp * wv[q]);                           // H(x) w / 2
+                dll[q] += eps * (-hg[q] - pp * gt[q]);                            // eps H(x) g~
+                dll[q] += 0.5f * (t1[q] + eps * (-ht[q] - pp * t1[q]));           // M H(x~) w / 2
+            }
+        }
         // the probe part needs dl/dx . z per step: a fixed-order sum over the waves
         float zq[2] = {0.f, 0.f};
         double dz = 0.0;
