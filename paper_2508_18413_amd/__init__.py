@@ -88,7 +88,13 @@ class Context:
 
 
 class Target:
-    """pmc_target_create from a workload target dictionary (arrays copied to the GPU)."""
+    """pmc_target_create from a workload target dictionary (arrays copied to the GPU).
+
+    A logistic-regression target may name its matrix-product arithmetic with
+    spec["products"]: "auto" (default), "f32", "split16" or "refine"
+    (split-FP16 sweeps until each chain meets the tolerance, then FP32-product
+    sweeps from its first step until it meets it again); see pmc_products in
+    include/pmcmc.h."""
 
     def __init__(self, ctx: Context, spec: dict, dtype=None):
         torch = _torch()
