@@ -37,6 +37,7 @@ namespace pmc {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kW = 8;               // waves per workgroup
 constexpr int kNT = 64 * kW;
@@ -95,7 +96,29 @@ size_t lds_bytes(int NR, int ldx)
 // Z (+ Zd) = X_tile P (+ Pd) for one 32-row tile; lane (i, h): A slot m =
 // X[32 rt + i][2 m + h], B slot m = P[step i][2 m + h]; accumulator register
 // r = row crow(r, h), column = step i.
-template <int MK, bool tangent>
+// With bft the tangent product is formed on BF16 matrix instructions (16 k
+// per instruction, lane half h taking k = 16 kb + 8 h + j): for directions
+// that only enter a Jacobian, never f.  The HMC transitions' probe tangents
+// take it; the relaxed MALA gate keeps FP32 (its rank-one term is a small
+// correction whose BF16 error would be a few per cent of it).
+template <int MK>
+__device__ __forceinline__ void fwd_dir_bf16(const float *xr, const float *dir, int D, int i, int h, f32x16 &Zd)
+{
+    constexpr int KB = (2 * MK + 15) / 16;
+#pragma unroll
+    for (int kb = 0; kb < KB; kb++) {
+        bf16x8 A, B;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int k = 16 * kb + 8 * h + j;
+            A[j] = (__bf16)(k < D ? xr[k] : 0.f);
+            B[j] = (__bf16)dir[i * kPS + k];
+        }
+        Zd = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, Zd, 0, 0, 0);
+    }
+}
+
+template <int MK, bool tangent, bool bft = false>
 __device__ __forceinline__ void fwd_products(const Lds &l, int ldx, int D, int rt, int i, int h, f32x16 &Z,
                                              f32x16 &Zd)
 {
@@ -107,23 +130,44 @@ __device__ __forceinline__ void fwd_products(const Lds &l, int ldx, int D, int r
         const int k = 2 * m + h;
         const float a = k < D ? xr[k] : 0.f;
         Z = __builtin_amdgcn_mfma_f32_32x32x2f32(a, l.P[i * kPS + k], Z, 0, 0, 0);
-        if (tangent) Zd = __builtin_amdgcn_mfma_f32_32x32x2f32(a, l.Pd[i * kPS + k], Zd, 0, 0, 0);
+        if (tangent && !bft) Zd = __builtin_amdgcn_mfma_f32_32x32x2f32(a, l.Pd[i * kPS + k], Zd, 0, 0, 0);
     }
+    if (tangent && bft) fwd_dir_bf16<MK>(xr, l.Pd, D, i, h, Zd);
 }
 
 // G (+ Gd) += X_tile^T R (+ Rd): lane (i = coordinate, h): A slot m =
 // X[32 rt + crow(m, h)][i]; B slot m = accumulator register m of R.
-template <bool tangent, bool grad = true>
+// BF16 form of Gd += X_tile^T Rd: k slot (kb, h, j) is row crow(8 kb + j, h),
+// so A is the lane's X column entries av[8 kb + j] and B its own accumulator
+// registers Rd[8 kb + j].
+__device__ __forceinline__ void bwd_dir_bf16(const float (&av)[16], const f32x16 &Rd, f32x16 &Gd)
+{
+#pragma unroll
+    for (int kb = 0; kb < 2; kb++) {
+        bf16x8 A, B;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            A[j] = (__bf16)av[8 * kb + j];
+            B[j] = (__bf16)Rd[8 * kb + j];
+        }
+        Gd = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, Gd, 0, 0, 0);
+    }
+}
+
+template <bool tangent, bool grad = true, bool bft = false>
 __device__ __forceinline__ void bwd_products(const Lds &l, int ldx, int D, int rt, int i, int h, const f32x16 &R,
                                              const f32x16 &Rd, f32x16 &G, f32x16 &Gd)
 {
     const bool own = i < D;
+    float av[16];
 #pragma unroll
     for (int m = 0; m < 16; m++) {
         const float a = own ? l.X[(size_t)(32 * rt + crow(m, h)) * ldx + i] : 0.f;
+        av[m] = a;
         if (grad) G = __builtin_amdgcn_mfma_f32_32x32x2f32(a, R[m], G, 0, 0, 0);
-        if (tangent) Gd = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Rd[m], Gd, 0, 0, 0);
+        if (tangent && !bft) Gd = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Rd[m], Gd, 0, 0, 0);
     }
+    if (tangent && bft) bwd_dir_bf16(av, Rd, Gd);
 }
 
 // Fixed-order tree over the 8 waves, then a broadcast: every wave w receives
@@ -173,8 +217,9 @@ __device__ __forceinline__ void tree_reduce(const Lds &l, int w, int lane, f32x1
 // One batched evaluation at the positions in l.P (and directions in l.Pd):
 // G = X^T (y - sigma(X p)) and Gd = X^T (w o X d) per (coordinate, step);
 // wave w receives the entries of its coordinates (tree_reduce).  Without
-// grad only Gd is formed (gs returns zeros).
-template <int MK, bool tangent, bool grad = true>
+// grad only Gd is formed (gs returns zeros); with bft the direction's
+// products run on BF16 matrix instructions (Jacobian directions only).
+template <int MK, bool tangent, bool grad = true, bool bft = false>
 __device__ __forceinline__ void evaluate(const Lds &l, const HmcLogregArgs &t, int NR, int w, int lane,
                                          float (&gs)[2], float (&hs)[2])
 {
@@ -183,7 +228,7 @@ __device__ __forceinline__ void evaluate(const Lds &l, const HmcLogregArgs &t, i
     f32x16 Gd = G;
     for (int rt = w; 32 * rt < NR; rt += kW) {
         f32x16 Z, Zd;
-        fwd_products<MK, tangent>(l, t.ldx, t.D, rt, i, h, Z, Zd);
+        fwd_products<MK, tangent, bft>(l, t.ldx, t.D, rt, i, h, Z, Zd);
         f32x16 R, Rd;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
@@ -191,7 +236,7 @@ __device__ __forceinline__ void evaluate(const Lds &l, const HmcLogregArgs &t, i
             R[r] = l.y[32 * rt + crow(r, h)] - s;
             Rd[r] = s * (1.f - s) * Zd[r];
         }
-        bwd_products<tangent, grad>(l, t.ldx, t.D, rt, i, h, R, Rd, G, Gd);
+        bwd_products<tangent, grad, bft>(l, t.ldx, t.D, rt, i, h, R, Rd, G, Gd);
     }
     tree_reduce<tangent>(l, w, lane, G, Gd, gs, hs);
 }
@@ -305,7 +350,7 @@ __global__ void __launch_bounds__(kNT, 1) k_eval_hmc_logreg(EvalArgs a, HmcLogre
         }
         __syncthreads();
         float gs[2], hs[2];
-        evaluate<MK, tangent>(l, t, NR, w, lane, gs, hs);
+        evaluate<MK, tangent, true, true>(l, t, NR, w, lane, gs, hs);
         double g0z = 0.0;  // g(x0) . z, for the relaxed gate's directional derivative
 #pragma unroll
         for (int q = 0; q < 2; q++) {
@@ -324,7 +369,7 @@ __global__ void __launch_bounds__(kNT, 1) k_eval_hmc_logreg(EvalArgs a, HmcLogre
                 l.Pd[i * kPS + dq[q]] = xd[q];
             }
             __syncthreads();
-            evaluate<MK, tangent>(l, t, NR, w, lane, gs, hs);
+            evaluate<MK, tangent, true, true>(l, t, NR, w, lane, gs, hs);
 #pragma unroll
             for (int q = 0; q < 2; q++) {
                 g[q] = gs[q] - pp * (x0[q] + dl[q]);
