@@ -482,6 +482,7 @@ struct StatusArgs {
     int64_t window_width;             // > 0: fixed-width sliding window (steps per chain and sweep)
     int64_t n_steps;
     ScanSync *bump_epoch;             // non-null: the last workgroup advances this scan epoch
+    int fold_only = 0;                // 1: re-fold the totals without updating any chain (after the last sweep)
 };
 pmc_status launch_status(pmc_context *ctx, const StatusArgs &a);
 // PMC_ERR_HIP if any scan's look-back gave up since the context was created.

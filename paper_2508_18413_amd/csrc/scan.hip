@@ -1578,6 +1578,10 @@ __device__ void chain_update(ChainStatus &cs, const Fold &v, const StatusArgs &a
     // again under them.
     const bool floor_hit = a.floor_stall > 0 && cs.stall >= a.floor_stall && r <= 2.f;
     if (!cs.fine && ((r <= 1.f && cs.win_end >= cend) || floor_hit)) {
+        if (cs.sweeps >= a.max_iter) {  // no sweep left for the final phase
+            cs.active = 0;
+            return;
+        }
         cs.fine = 1;
         cs.win_start = off;
         cs.fb_prev = off;
@@ -1623,7 +1627,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
 {
     const int c = blockIdx.x, tid = threadIdx.x;
     ChainStatus &cs = a.chains[c];
-    if (cs.active) {  // uniform per block
+    if (cs.active && !a.fold_only) {  // uniform per block
         const int k0 = a.chain_tile_begin[c], ntc = a.chain_tile_begin[c + 1] - k0;
         const int64_t cnt = (int64_t)a.n_lanes * ntc;
         Fold v{0.0, 0.0, 0.f, 0u, INT64_MAX};
@@ -1710,8 +1714,10 @@ __global__ void __launch_bounds__(kStatusThreads) k_status(StatusArgs a)
         g->max_ratio = v.r;
         g->nonfinite = v.f;
         g->n_accept = 0;
-        g->eval_steps += g->next_steps;  // what this sweep evaluated
-        g->next_steps = nsteps;
+        if (!a.fold_only) {
+            g->eval_steps += g->next_steps;  // what this sweep evaluated
+            g->next_steps = nsteps;
+        }
         if (a.bump_epoch) {
             ScanSync *sy = a.bump_epoch;
             const uint32_t e = __hip_atomic_load(&sy->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1752,7 +1758,7 @@ __global__ void __launch_bounds__(kStatusThreads) k_status_one(StatusArgs a)
     }
     v = block_fold(v);
     if (tid != 0) return;
-    if (cs.active) {
+    if (cs.active && !a.fold_only) {
         chain_update(cs, v, a, 0, cend);
         a.chains[0] = cs;
     }
@@ -1767,8 +1773,10 @@ __global__ void __launch_bounds__(kStatusThreads) k_status_one(StatusArgs a)
     g->max_ratio = cs.max_ratio;
     g->nonfinite = cs.nonfinite;
     g->n_accept = 0;
-    g->eval_steps = eval_steps + next_steps;  // what this sweep evaluated
-    g->next_steps = cs.active ? cs.win_end - (cs.win_start > 0 ? cs.win_start : 0) : 0;
+    if (!a.fold_only) {
+        g->eval_steps = eval_steps + next_steps;  // what this sweep evaluated
+        g->next_steps = cs.active ? cs.win_end - (cs.win_start > 0 ? cs.win_start : 0) : 0;
+    }
     if (a.bump_epoch)
         __hip_atomic_store(&a.bump_epoch->epoch, (epoch + 1) & 0x3fffffffu, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);

@@ -811,7 +811,8 @@ pmc_status solve_impl(pmc_context *ctx, const pmc_problem *prob, const pmc_optio
     PMC_TRY_HIP(hipEventRecord(ctx->ev1, st));
     // final accept count
     sta.accept = acc;
-    PMC_TRY(launch_status(ctx, sta));  // no active chain left or max_iter: only re-folds totals
+    sta.fold_only = 1;  // the totals and the accept count only: no chain is updated again
+    PMC_TRY(launch_status(ctx, sta));
     PMC_TRY_HIP(hipMemcpyAsync(hs, d_glob, sizeof(GlobalStatus), hipMemcpyDeviceToHost, st));
     PMC_TRY_HIP(hipMemcpyAsync(hc.data(), d_chains, sizeof(ChainStatus) * hc.size(),
                                hipMemcpyDeviceToHost, st));
