@@ -592,6 +592,11 @@ def test_logreg_refined_products(ctx, pm, orc):
     clear = one.gtilde.abs() > F32_GATE_ERR
     assert torch.equal(one.accept[clear], rr.accept[clear])
     _check_mala(orc, tg, ch, s0, rr.states.cpu().numpy(), rr.accept.cpu().numpy())
+    # max_iter reached by the split-FP16 phase itself: no FP32-product sweep
+    # is left, so the chain is reported not converged after exactly max_iter
+    short = pm.solve(ctx, gr, ch.eps, *a, **dict(kw, max_iter=rs.sweeps))
+    assert short.sweeps == rs.sweeps and short.status == pm.B.PMC_NOT_CONVERGED
+    assert list(short.chain_state) == [2]
     # fixed-width windows: FP32 products from the start
     wkw = dict(kw, window_width=1024)
     w1 = pm.solve(ctx, gr, ch.eps, *a, **wkw)
@@ -768,6 +773,28 @@ def test_sweep_batches_and_max_iter(ctx, pm):
     assert torch.equal(rp.states, r.states) and rp.sweeps == r.sweeps
     assert 0 < rp.eval_steps <= r.sweeps * 3000
     assert rp.eval_steps >= 3000  # the first sweep evaluates every step
+
+
+def test_max_iter_counts_with_fixed_windows(ctx, pm):
+    """A solve stopped by max_iter runs exactly max_iter sweeps on every chain
+    that was still iterating, also when the last sweep moved a fixed-width
+    window on; such a chain is reported as not converged."""
+    _say("max_iter with fixed-width windows")
+    b = W.logreg_batch(seed=4, n_chains=3, lo=600, hi=1500, eps=0.0015)
+    g = pm.Target(ctx, b.target)
+    args = (_t(b.x0), _t(b.xi), _t(b.u))
+    full = pm.solve(ctx, g, b.eps, *args, offsets=list(b.offsets), variant="diag", window_width=128,
+                    max_iter=20000)
+    assert full.status == 0
+    for m in range(3, 40, 3):
+        r = pm.solve(ctx, g, b.eps, *args, offsets=list(b.offsets), variant="diag", window_width=128, max_iter=m)
+        spc, cst = list(r.sweeps_per_chain), list(r.chain_state)
+        assert max(spc) <= m, (m, spc)
+        for c in range(b.n_chains):
+            if cst[c] == 0:  # converged: its count is the unlimited solve's
+                assert spc[c] == full.sweeps_per_chain[c], (m, c, spc, full.sweeps_per_chain)
+            elif cst[c] == 2:  # stopped by max_iter
+                assert spc[c] == m, (m, c, spc, cst)
 
 
 def test_sliding_window_prefix_skip(ctx, pm, orc):
