@@ -592,6 +592,10 @@ def test_logreg_refined_products(ctx, pm, orc):
     clear = one.gtilde.abs() > F32_GATE_ERR
     assert torch.equal(one.accept[clear], rr.accept[clear])
     _check_mala(orc, tg, ch, s0, rr.states.cpu().numpy(), rr.accept.cpu().numpy())
+    # the same solve from a graph of 8 sweeps: the phase switch happens on
+    # the device, so the replays give the eager result bit for bit
+    rg = pm.solve(ctx, gr, ch.eps, *a, **dict(kw, graph_sweeps=8))
+    assert rg.sweeps == rr.sweeps and torch.equal(rg.states, rr.states) and torch.equal(rg.accept, rr.accept)
     # max_iter reached by the split-FP16 phase itself: no FP32-product sweep
     # is left, so the chain is reported not converged after exactly max_iter
     short = pm.solve(ctx, gr, ch.eps, *a, **dict(kw, max_iter=rs.sweeps))
